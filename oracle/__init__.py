@@ -1,0 +1,219 @@
+"""FP64 CPU oracle for the electron collision step -- TEST INFRASTRUCTURE ONLY.
+
+Only the tests, the smoke check and the CPU-baseline leg of the benchmark
+import this package.  It shares no code with the GPU library: the C source
+``oracle.c`` is compiled on its own with gcc, and this module is a ctypes
+wrapper around it plus plain numpy routines in :mod:`oracle.physics`.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+GCC_CMD = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-std=c11",
+           "-Wall", "-Wextra", "-Wno-unused-parameter", "-shared", "-fPIC",
+           _SRC, "-o", _LIB, "-lm"]
+
+
+def build() -> str:
+    """Compile oracle.c into liboracle.so (always recompiles)."""
+    tmp = _LIB + ".tmp"
+    cmd = GCC_CMD[:-3] + ["-o", tmp, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        L = C.CDLL(_LIB)
+        u32p = np.ctypeslib.ndpointer(np.uint32, flags="C_CONTIGUOUS")
+        i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+        f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+        u8p = np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")
+        L.orc_philox.argtypes = [u32p, u32p, u32p]
+        L.orc_philox.restype = None
+        L.orc_philox_fill.argtypes = [C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint32, u32p,
+                                      C.c_int64, u32p]
+        L.orc_philox_fill.restype = None
+        L.orc_u01.argtypes = [C.c_uint32]
+        L.orc_u01.restype = C.c_double
+        L.orc_bin_cells.argtypes = [i32p, C.c_int64, C.c_int32, i32p, i32p]
+        L.orc_bin_cells.restype = C.c_int
+        L.orc_pairs.argtypes = [i32p, u32p, C.c_int32, C.c_uint64, C.c_uint64, i32p, i32p]
+        L.orc_pairs.restype = C.c_int
+        L.orc_ta_delta.argtypes = [f64p, C.c_double, C.c_double, C.c_double, C.c_double, f64p]
+        L.orc_ta_delta.restype = None
+        L.orc_ta_s2.argtypes = [C.c_double] * 4
+        L.orc_ta_s2.restype = C.c_double
+        L.orc_mcc_threshold.argtypes = [C.c_double, C.c_double, C.c_double]
+        L.orc_mcc_threshold.restype = C.c_uint64
+        L.orc_mcc.argtypes = [f64p, u32p, C.c_int64, C.c_double, C.c_double, C.c_double,
+                              C.c_double, C.c_uint64, C.c_uint64, C.c_void_p]
+        L.orc_mcc.restype = C.c_int
+        L.orc_step.argtypes = [f64p, i32p, u32p, C.c_int64, C.c_int32, C.POINTER(Params),
+                               C.c_void_p]
+        L.orc_step.restype = C.c_int
+        L.orc_conserve_cells.argtypes = [f64p, C.c_int64, i32p, C.c_int32, f64p]
+        L.orc_conserve_cells.restype = C.c_int
+        L.orc_cell_moments.argtypes = [f64p, C.c_int64, i32p, C.c_int32, f64p]
+        L.orc_cell_moments.restype = C.c_int
+        L.orc_repair_u.argtypes = [f64p, C.c_int64, i32p, C.c_int32, u32p, C.c_uint64,
+                                   C.c_uint64, C.c_uint32, f64p, i32p]
+        L.orc_repair_u.restype = C.c_int64
+        L.orc_num_threads.argtypes = []
+        L.orc_num_threads.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+class Params(C.Structure):
+    _fields_ = [("dt", C.c_double), ("lnL", C.c_double), ("density", C.c_void_p),
+                ("seed", C.c_uint64), ("step", C.c_uint64), ("conserve", C.c_int32),
+                ("mcc", C.c_int32), ("sigma0", C.c_double), ("n_neutral", C.c_double),
+                ("mass_ratio", C.c_double), ("dt_scale", C.c_void_p), ("skip", C.c_void_p)]
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+# ---------------------------------------------------------------- RNG
+def philox(ctr, key):
+    """One Philox4x32-10 block: ctr = 4 words, key = 2 words."""
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, np.uint32)
+    lib().orc_philox(c, k, out)
+    return out
+
+
+def philox_fill(seed: int, step: int, domain: int, c0, c3: int = 0) -> np.ndarray:
+    c0 = np.ascontiguousarray(c0, dtype=np.uint32)
+    out = np.zeros((c0.size, 4), np.uint32)
+    lib().orc_philox_fill(seed, step, domain, c3, c0, c0.size, out.reshape(-1))
+    return out
+
+
+def u01(x) -> np.ndarray:
+    """((x >> 9) + 0.5) * 2^-23 -- exact in binary32 and binary64."""
+    x = np.asarray(x, dtype=np.uint32)
+    return ((x >> np.uint32(9)).astype(np.float64) + 0.5) * 2.0 ** -23
+
+
+# ---------------------------------------------------------------- binning / pairing
+def bin_cells(cell_of, n_cells: int):
+    cell_of = np.ascontiguousarray(cell_of, dtype=np.int32)
+    cs = np.zeros(n_cells + 1, np.int32)
+    order = np.zeros(max(cell_of.size, 1), np.int32)
+    rc = lib().orc_bin_cells(cell_of, cell_of.size, n_cells, cs, order)
+    if rc:
+        raise ValueError(f"orc_bin_cells failed: {rc}")
+    return cs, order[:cell_of.size]
+
+
+def pairs(cell_start, pid, seed: int, step: int):
+    """Returns (sorted_slots, partner) for storage already in cell order."""
+    cs = np.ascontiguousarray(cell_start, dtype=np.int32)
+    pid = np.ascontiguousarray(pid, dtype=np.uint32)
+    n = int(cs[-1])
+    srt = np.zeros(max(n, 1), np.int32)
+    par = np.zeros(max(n, 1), np.int32)
+    rc = lib().orc_pairs(cs, pid, cs.size - 1, seed, step, srt, par)
+    if rc:
+        raise ValueError(f"orc_pairs failed: {rc}")
+    return srt[:n], par[:n]
+
+
+# ---------------------------------------------------------------- collision pieces
+def ta_delta(u, s2: float, U1: float, U2: float, U3: float) -> np.ndarray:
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    du = np.zeros(3, np.float64)
+    lib().orc_ta_delta(u, s2, U1, U2, U3, du)
+    return du
+
+
+def ta_s2(umag: float, density: float, lnL: float, dt: float) -> float:
+    return lib().orc_ta_s2(umag, density, lnL, dt)
+
+
+def mcc_threshold(dt: float, sigma0: float, n_neutral: float) -> int:
+    return int(lib().orc_mcc_threshold(dt, sigma0, n_neutral))
+
+
+def mcc(v, pid, dt, sigma0, n_neutral, mass_ratio, seed, step, return_flags=False):
+    """Stand-alone null-collision step, in place on v (3, n) float64."""
+    n = v.shape[1]
+    pid = np.ascontiguousarray(pid, dtype=np.uint32)
+    flags = np.zeros(max(n, 1), np.uint8) if return_flags else None
+    rc = lib().orc_mcc(v.reshape(-1), pid, n, dt, sigma0, n_neutral, mass_ratio, seed, step,
+                       _ptr(flags))
+    if rc:
+        raise ValueError(f"orc_mcc failed: {rc}")
+    return flags[:n] if return_flags else None
+
+
+def step(v, cell_of, pid, n_cells: int, *, dt: float, lnL: float, seed: int, step: int,
+         density=None, conserve=False, mcc=False, sigma0=0.0, n_neutral=0.0,
+         mass_ratio=0.0, dt_scale=None, skip=None):
+    """One full collision step in place.  v: (3, n) float64 C-contiguous,
+    cell_of int32, pid uint32 -- all permuted into stable cell order.
+    Returns cell_start."""
+    assert v.dtype == np.float64 and v.flags.c_contiguous and v.shape[0] == 3
+    n = v.shape[1]
+    assert cell_of.dtype == np.int32 and pid.dtype == np.uint32
+    dens = None if density is None else np.ascontiguousarray(density, np.float64)
+    dts = None if dt_scale is None else np.ascontiguousarray(dt_scale, np.float64)
+    sk = None if skip is None else np.ascontiguousarray(skip, np.uint8)
+    p = Params(dt, lnL, _ptr(dens), seed, step, int(bool(conserve)), int(bool(mcc)), sigma0,
+               n_neutral, mass_ratio, _ptr(dts), _ptr(sk))
+    cs = np.zeros(n_cells + 1, np.int32)
+    rc = lib().orc_step(v.reshape(-1), cell_of, pid, n, n_cells, C.byref(p), cs.ctypes.data)
+    if rc:
+        raise ValueError(f"orc_step failed: {rc}")
+    return cs
+
+
+def conserve_cells(v, cell_start, before):
+    """Per-cell correction in place; before = (M, 5) sums N, sum v (3), sum |v|^2."""
+    cs = np.ascontiguousarray(cell_start, dtype=np.int32)
+    lib().orc_conserve_cells(v.reshape(-1), v.shape[1], cs, cs.size - 1,
+                             np.ascontiguousarray(before, np.float64).reshape(-1))
+
+
+def cell_moments(v, cell_start) -> np.ndarray:
+    cs = np.ascontiguousarray(cell_start, dtype=np.int32)
+    out = np.zeros((cs.size - 1, 14), np.float64)
+    lib().orc_cell_moments(np.ascontiguousarray(v, np.float64).reshape(-1), v.shape[1], cs,
+                           cs.size - 1, out.reshape(-1))
+    return out
+
+
+def repair_u(v, cell_start, pid, seed: int, step: int, replica: int):
+    cs = np.ascontiguousarray(cell_start, dtype=np.int32)
+    n = v.shape[1]
+    u = np.zeros((max(n // 2, 1), 3), np.float64)
+    cell = np.zeros(max(n // 2, 1), np.int32)
+    k = lib().orc_repair_u(np.ascontiguousarray(v, np.float64).reshape(-1), n, cs, cs.size - 1,
+                           np.ascontiguousarray(pid, np.uint32), seed, step, replica,
+                           u.reshape(-1), cell)
+    if k < 0:
+        raise MemoryError("orc_repair_u")
+    return u[:k], cell[:k]
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
