@@ -1,0 +1,167 @@
+/*
+ * piccoll.h -- C ABI of the MI355X electron collision step.
+ *
+ * One time step of the electron collision operator of a PIC-DSMC solver for
+ * low-temperature plasmas (Almgren-Bell, Al Awar, Geethakrishnan, Gligoric,
+ * Biros, "A Portable Multi-GPU Solver for Collisional Plasmas with Coulombic
+ * Interactions"):
+ *   - step S1 of the PIC scheme table: electron-electron Coulomb collisions
+ *     (Sec. "Coulombic Collision Kernel", Table "Coulombic Collision Steps"
+ *     CCS1-CCS5, Takizuka & Abe binary collisions within a cell);
+ *   - the elastic part of step S2a run by the null-collision method (Sec.
+ *     "DSMC Collision Kernel", paragraph "Null Collision Method").
+ *
+ * Conventions shared by every entry point
+ *   - All array arguments are DEVICE pointers owned by the caller; the library
+ *     never frees them.  Velocities are structure-of-arrays
+ *     v = [vx(0..n-1) | vy(0..n-1) | vz(0..n-1)], element type given by a
+ *     pic_dtype.  Scratch memory belongs to the context and grows on demand.
+ *   - Every call is asynchronous on the context's stream (given at creation).
+ *     Argument errors are returned synchronously; errors found on the device
+ *     (a cell id out of range) are latched and returned by pic_sync.
+ *     Nothing throws across the ABI.  One context per host thread.
+ *   - Code units: m_e = 1, (e^2 / 4 pi eps0)^2 = 1, per-cell electron density
+ *     n_j (default 1).  Particles have uniform weights.
+ *   - Random numbers: Philox4x32-10 (Salmon et al., SC'11), key =
+ *     (lo32(seed), hi32(seed)), counter = (c0, lo32(step), domain, c3).
+ *     Domain 0, c0 = pid: word0 pairing key, word1 null-collision candidate
+ *     draw, word2/word3 Coulomb uniforms.  Domain 1, c0 = pid: uniforms of a
+ *     null-collision candidate.  Domain 2, c0 = cell: judge sampling.
+ *     Domain 3, c3 = replica: re-pairings for labels.  Uniform mapping
+ *     U(x) = ((x >> 9) + 1/2) 2^-23.  Results depend only on
+ *     (seed, step, pid, cell membership), never on storage order or launch
+ *     configuration, so runs are bitwise reproducible and resumable.
+ */
+#ifndef PICCOLL_H
+#define PICCOLL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pic_ctx pic_ctx;
+
+typedef enum {
+    PIC_OK = 0,
+    PIC_ERR_ARG = 1,    /* invalid argument (NULL pointer, n < 0, dt <= 0, ...) */
+    PIC_ERR_RANGE = 2,  /* a cell id outside [0, n_cells) was seen on the device */
+    PIC_ERR_HIP = 3,    /* a HIP runtime call failed */
+    PIC_ERR_NOMEM = 4,  /* scratch memory could not be allocated */
+    PIC_ERR_DTYPE = 5,  /* unknown pic_dtype */
+    PIC_ERR_STATE = 6   /* call not valid in the context's current state */
+} pic_status;
+
+typedef enum { PIC_F32 = 0, PIC_F64 = 1 } pic_dtype;
+
+/* flags of coulomb_collide / pic_run_steps */
+enum {
+    PIC_CONSERVE_FIX = 1u << 0,  /* restore each cell's FP64 momentum and thermal
+                                    energy after the Coulomb step */
+    PIC_FUSE_MCC = 1u << 1,      /* run the null-collision step (parameters from
+                                    pic_set_mcc) in the same pass, after Coulomb */
+    PIC_GATE = 1u << 2,          /* learned sub-cycling gate (pic_gate_*) */
+    PIC_ASSUME_SORTED = 1u << 3, /* caller asserts storage is already in cell
+                                    order: the re-binning kernels are not
+                                    launched; the check still runs and a
+                                    violation is reported as PIC_ERR_STATE */
+    PIC_MOMENTS = 1u << 4        /* write the 14 per-cell FP64 moment sums of the
+                                    post-step state to the pic_set_moments_out buffer */
+};
+
+/* Create a context on HIP device `device`, issuing work on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  *out receives the context. */
+int pic_create(pic_ctx **out, int device, void *hip_stream);
+/* Synchronises the stream and frees the context's scratch memory. */
+void pic_destroy(pic_ctx *ctx);
+/* Static string describing a pic_status. */
+const char *pic_strerror(int status);
+/* Waits for the context's stream, then returns (and clears) any latched
+ * device error: PIC_ERR_RANGE, PIC_ERR_STATE, or PIC_OK. */
+int pic_sync(pic_ctx *ctx);
+/* Changes the stream subsequent calls are issued on. */
+int pic_set_stream(pic_ctx *ctx, void *hip_stream);
+
+/* Binning, CCS1-CCS3 of the Coulombic collision steps.
+ * cell_of[n] in [0, n_cells).  Writes cell_start[n_cells+1] (exclusive prefix
+ * sum of the per-cell counts, cell_start[n_cells] = n) and order[n], the
+ * stable counting-sort permutation: order[k] = storage index of the k-th
+ * particle in cell order (ties in storage order).  Inputs are not modified.
+ * n_cells <= 2^24, n <= 2^31 - 1.  Out-of-range ids: PIC_ERR_RANGE at pic_sync
+ * and unspecified outputs. */
+int pic_bin_cells(pic_ctx *ctx, const int32_t *cell_of, int64_t n, int32_t n_cells,
+                  int32_t *cell_start, int32_t *order);
+
+/* One Coulomb collision step, in place (Table "Coulombic Collision Steps").
+ *  v        SoA velocities of `dtype`, n particles;
+ *  cell_of  cell id per particle; pid  particle identity (keys the RNG);
+ *  v, cell_of and pid are permuted jointly into stable cell order (callers
+ *  identify particles by pid, not by storage slot; pic_unsort restores the
+ *  order pid[l] = l).  Storage already in cell order is not moved.
+ *  Each cell's members are ordered by (word0 of the domain-0 draw, pid);
+ *  entries (2i, 2i+1) form pairs, a last odd member sits out.  Each pair
+ *  (a, b) turns its relative velocity u = v_a - v_b by the Takizuka & Abe
+ *  angle: tan(Theta/2) = s z with s^2 = 8 pi n_j lnLambda dt / |u|^3,
+ *  z = sqrt(-2 ln U1) cos(2 pi U2), azimuth 2 pi U3 (U1, U2 from words 2, 3
+ *  of a, U3 from word 2 of b); v_a += du/2, v_b -= du/2.
+ *  density: n_cells per-cell densities (device, nullable => 1).
+ *  step: low 32 bits enter the counter.  flags: PIC_* above.
+ *  Errors: PIC_ERR_ARG (NULL arrays with n > 0, n < 0, n_cells < 1,
+ *  dt <= 0, lnLambda <= 0), PIC_ERR_DTYPE, PIC_ERR_NOMEM. */
+int coulomb_collide(pic_ctx *ctx, int dtype, void *v, int32_t *cell_of, uint32_t *pid,
+                    int64_t n, int32_t n_cells, double dt, double lnLambda,
+                    const double *density, uint64_t seed, uint64_t step, uint32_t flags);
+
+/* Parameters of the fused null-collision step (PIC_FUSE_MCC):
+ * sigma(E) = sigma0 E^-1/2 with E = |v|^2/2, neutral density n_neutral,
+ * electron/neutral mass ratio mass_ratio (>= 0, < 0.5), same dt as Coulomb. */
+int pic_set_mcc(pic_ctx *ctx, double sigma0, double n_neutral, double mass_ratio);
+
+/* Stand-alone null-collision Monte Carlo step, in place (paragraph "Null
+ * Collision Method"; collision probability 1 - exp(-dt |v| sigma n_n) of the
+ * DSMC collision step).  For sigma = sigma0 E^-1/2 the frequency
+ * nu = n_n sigma0 sqrt(2) does not depend on speed, so nu_max = nu and every
+ * candidate is real.  A particle is a candidate iff word1 of its domain-0
+ * draw < floor(P_null 2^32), P_null = 1 - exp(-nu_max dt); candidates scatter
+ * elastically and isotropically (domain 1: cos theta = 1 - 2 U(w1),
+ * phi = 2 pi U(w2)) with |v'|^2 = |v|^2 (1 - 2 mass_ratio (1 - vhat.s)).
+ * Storage order is irrelevant and unchanged.  candidate_out (nullable,
+ * uint8[n]) receives the candidate flags. */
+int mcc_null_collide(pic_ctx *ctx, int dtype, void *v, const uint32_t *pid, int64_t n,
+                     double dt, double sigma0, double n_neutral, double mass_ratio,
+                     uint64_t seed, uint64_t step, uint8_t *candidate_out);
+
+/* Device buffer of n_cells * 14 doubles receiving the post-step moment sums
+ * (layout of pic_cell_moments) when PIC_MOMENTS is passed; NULL clears it. */
+int pic_set_moments_out(pic_ctx *ctx, double *out);
+
+/* ---------------------------------------------------------------- test exports */
+
+/* out[4*i + w] = word w of Philox4x32-10 with counter (c0[i], lo32(step),
+ * domain, c3) and key (lo32(seed), hi32(seed)). */
+int pic_philox(pic_ctx *ctx, uint64_t seed, uint64_t step, uint32_t domain, uint32_t c3,
+               const uint32_t *c0, int64_t n, uint32_t *out);
+
+/* Pairing of storage already in cell order (cell_start from pic_bin_cells):
+ * sorted[cell_start[j] + r] = slot of the r-th member of cell j in
+ * (key, pid) order; partner[slot] = partner slot or -1 (idle). */
+int coulomb_pairs(pic_ctx *ctx, const int32_t *cell_start, const uint32_t *pid,
+                  int32_t n_cells, uint64_t seed, uint64_t step, int32_t *sorted,
+                  int32_t *partner);
+
+/* Per-cell FP64 raw moment sums of storage in cell order, out[14*j + k]:
+ * N, sum vx, vy, vz, sum vx^2, vy^2, vz^2, sum vx vy, vx vz, vy vz,
+ * sum |v|^2 vx, |v|^2 vy, |v|^2 vz, sum |v|^4. */
+int pic_cell_moments(pic_ctx *ctx, int dtype, const void *v, int64_t n,
+                     const int32_t *cell_start, int32_t n_cells, double *out);
+
+/* Restores storage to pid order (slot pid[k] receives particle k), i.e. the
+ * caller's original order when pid was 0..n-1.  pid must be a permutation of
+ * 0..n-1 (not checked). */
+int pic_unsort(pic_ctx *ctx, int dtype, void *v, uint32_t *pid, int32_t *cell_of, int64_t n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PICCOLL_H */

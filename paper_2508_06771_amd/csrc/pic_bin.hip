@@ -1,0 +1,340 @@
+// pic_bin.hip -- binning of particles into cells (Coulombic collision steps
+// CCS1-CCS3): order check, cell starts, and a stable LSD counting sort by
+// cell id that moves the particle data itself.
+//
+// The paper builds an index list with one atomic increment per particle and
+// notes that those atomics cost up to 40% of its Coulomb kernel.  Here the
+// storage is kept in cell order between steps, so the steady state is a
+// single streaming check of cell_of (4 B per particle); only unsorted input
+// runs the sort passes, which rank elements inside a wave with ballots
+// instead of atomics, so the result is stable and deterministic.
+#include "pic_internal.hpp"
+
+#define HIP_OK(x) do { if ((x) != hipSuccess) return PIC_ERR_HIP; } while (0)
+
+namespace {
+
+constexpr int RS_THREADS = 256;   // radix kernels: 4 waves
+constexpr int RS_ITEMS = 16;      // rounds per tile
+constexpr int RS_TILE = RS_THREADS * RS_ITEMS;
+constexpr int SCAN_THREADS = 1024;
+constexpr int SCAN_ITEMS = 8;
+constexpr int SCAN_CHUNK = SCAN_THREADS * SCAN_ITEMS;
+
+__global__ void k_reset_flags(DevFlags *f)
+{
+    if (threadIdx.x == 0) {
+        f->unsorted = 0;
+        f->range_err = 0;
+        f->huge_total = 0;
+    }
+    if (threadIdx.x < 8) {
+        f->head[threadIdx.x] = 0;
+        f->count[threadIdx.x] = 0;
+    }
+}
+
+// One position i in [0, n]: the boundary between element i-1 and i.  Every
+// cell id j in (cell_of[i-1], cell_of[i]] starts at i; with sorted input each
+// entry of cell_start is written exactly once (empty cells included).
+__global__ void k_bin_check(const int32_t *__restrict__ cell_of, int64_t n, int32_t n_cells,
+                            int32_t *__restrict__ cell_start, DevFlags *f, int set_unsorted,
+                            const int *gate)
+{
+    if (gate && *gate == 0) return;
+    int bad = 0, uns = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i <= n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t prev = i > 0 ? cell_of[i - 1] : -1;
+        const int32_t cur = i < n ? cell_of[i] : n_cells;
+        if (i < n && (cur < 0 || cur >= n_cells)) {
+            bad = 1;
+            continue;
+        }
+        if (i > 0 && i < n && cur < prev) uns = 1;
+        int32_t lo = prev + 1 < 0 ? 0 : prev + 1;
+        for (int32_t j = lo; j <= cur && j <= n_cells; ++j) cell_start[j] = (int32_t)i;
+    }
+    const uint64_t wb = __ballot(bad), wu = __ballot(uns);
+    if ((threadIdx.x & (PIC_WAVE - 1)) == 0) {
+        if (wb) {
+            atomicOr(&f->range_err, 1);
+            atomicOr(&f->sticky_range, 1);
+        }
+        if (wu && set_unsorted) {
+            atomicOr(&f->unsorted, 1);
+            if (set_unsorted == 2) atomicOr(&f->sticky_state, 1);
+        }
+    }
+}
+
+__global__ void k_copy32(uint32_t *__restrict__ dst, const uint32_t *__restrict__ src, int64_t n,
+                         const int *gate)
+{
+    if (gate && *gate == 0) return;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+__device__ __forceinline__ uint32_t digit_of(int32_t key, int shift, int bits)
+{
+    return ((uint32_t)key >> shift) & ((1u << bits) - 1u);
+}
+
+// Per-tile digit counts: hist[d * nblocks + tile].
+__global__ __launch_bounds__(RS_THREADS) void k_radix_hist(RadixPass p, uint32_t *__restrict__ hist)
+{
+    if (p.gate && *p.gate == 0) return;
+    __shared__ uint32_t h[256];
+    const int R = 1 << p.bits;
+    for (int d = threadIdx.x; d < R; d += RS_THREADS) h[d] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    for (int r = 0; r < RS_ITEMS; ++r) {
+        const int64_t e = base + r * RS_THREADS + threadIdx.x;
+        if (e < p.n) atomicAdd(&h[digit_of(p.key_in[e], p.shift, p.bits)], 1u);
+    }
+    __syncthreads();
+    for (int d = threadIdx.x; d < R; d += RS_THREADS) hist[(int64_t)d * gridDim.x + blockIdx.x] = h[d];
+}
+
+// Exclusive scan of SCAN_ITEMS consecutive values per thread over the block;
+// returns the thread's exclusive prefix and (in *total) the block total.
+__device__ uint32_t block_excl_scan(uint32_t x, uint32_t *total)
+{
+    __shared__ uint32_t wtot[SCAN_THREADS / PIC_WAVE];
+    const int lane = threadIdx.x & (PIC_WAVE - 1), wid = threadIdx.x / PIC_WAVE;
+    const uint32_t inc = wave_incl_scan(x);
+    if (lane == PIC_WAVE - 1) wtot[wid] = inc;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+    for (int w = 0; w < SCAN_THREADS / PIC_WAVE; ++w) {
+        if (w < wid) off += wtot[w];
+        tot += wtot[w];
+    }
+    __syncthreads();
+    *total = tot;
+    return off + inc - x;
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_reduce(const uint32_t *__restrict__ a, int64_t L,
+                                                             uint32_t *__restrict__ bsum,
+                                                             const int *gate)
+{
+    if (gate && *gate == 0) return;
+    const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + threadIdx.x * SCAN_ITEMS;
+    uint32_t s = 0;
+    for (int k = 0; k < SCAN_ITEMS; ++k)
+        if (base + k < L) s += a[base + k];
+    uint32_t tot;
+    block_excl_scan(s, &tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_top(uint32_t *__restrict__ bsum, int64_t nb,
+                                                          const int *gate)
+{
+    if (gate && *gate == 0) return;
+    uint32_t carry = 0;
+    for (int64_t base = 0; base < nb; base += SCAN_CHUNK) {
+        const int64_t b0 = base + threadIdx.x * SCAN_ITEMS;
+        uint32_t v[SCAN_ITEMS], s = 0;
+        for (int k = 0; k < SCAN_ITEMS; ++k) {
+            v[k] = b0 + k < nb ? bsum[b0 + k] : 0u;
+            s += v[k];
+        }
+        uint32_t tot;
+        uint32_t off = block_excl_scan(s, &tot) + carry;
+        for (int k = 0; k < SCAN_ITEMS; ++k) {
+            if (b0 + k < nb) bsum[b0 + k] = off;
+            off += v[k];
+        }
+        carry += tot;
+    }
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_down(uint32_t *__restrict__ a, int64_t L,
+                                                           const uint32_t *__restrict__ bsum,
+                                                           const int *gate)
+{
+    if (gate && *gate == 0) return;
+    const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + threadIdx.x * SCAN_ITEMS;
+    uint32_t v[SCAN_ITEMS], s = 0;
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        v[k] = base + k < L ? a[base + k] : 0u;
+        s += v[k];
+    }
+    uint32_t tot;
+    uint32_t off = block_excl_scan(s, &tot) + bsum[blockIdx.x];
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        if (base + k < L) a[base + k] = off;
+        off += v[k];
+    }
+}
+
+// Stable scatter.  The tile is visited in element order, RS_THREADS elements
+// per round; within a round an element's rank among equal digits is
+// (count in earlier rounds) + (count in earlier waves) + (earlier lanes of
+// its own wave), the last found from ballots over the digit bits.
+__global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(RadixPass p,
+                                                              const uint32_t *__restrict__ offs)
+{
+    if (p.gate && *p.gate == 0) return;
+    constexpr int NW = RS_THREADS / PIC_WAVE;
+    __shared__ uint32_t base[256];
+    __shared__ uint32_t wc[NW * 256];
+    __shared__ uint32_t goff[256];
+    const int R = 1 << p.bits;
+    for (int d = threadIdx.x; d < R; d += RS_THREADS) {
+        base[d] = 0;
+        goff[d] = offs[(int64_t)d * gridDim.x + blockIdx.x];
+        for (int w = 0; w < NW; ++w) wc[w * 256 + d] = 0;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & (PIC_WAVE - 1), wid = threadIdx.x / PIC_WAVE;
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (PIC_WAVE - lane));
+    const int64_t tile = (int64_t)blockIdx.x * RS_TILE;
+    for (int r = 0; r < RS_ITEMS; ++r) {
+        const int64_t e = tile + r * RS_THREADS + threadIdx.x;
+        const bool valid = e < p.n;
+        const int32_t key = valid ? p.key_in[e] : 0;
+        const uint32_t d = digit_of(key, p.shift, p.bits);
+        uint64_t peers = __ballot(valid);
+        for (int b = 0; b < p.bits; ++b) {
+            const uint64_t m = __ballot((d >> b) & 1u);
+            peers &= ((d >> b) & 1u) ? m : ~m;
+        }
+        const uint32_t rank = __popcll(peers & lt);
+        if (valid && rank == 0) wc[wid * 256 + d] = __popcll(peers);
+        __syncthreads();
+        uint32_t pos = 0;
+        if (valid) {
+            pos = base[d] + rank;
+            for (int w = 0; w < wid; ++w) pos += wc[w * 256 + d];
+        }
+        __syncthreads();
+        for (int dd = threadIdx.x; dd < R; dd += RS_THREADS) {
+            uint32_t s = 0;
+            for (int w = 0; w < NW; ++w) {
+                s += wc[w * 256 + dd];
+                wc[w * 256 + dd] = 0;
+            }
+            base[dd] += s;
+        }
+        if (valid) {
+            const int64_t o = (int64_t)goff[d] + pos;
+            p.key_out[o] = key;
+            for (int s = 0; s < p.n32; ++s)
+                p.p32_out[s][o] = (s == p.iota_slot) ? (uint32_t)e : p.p32_in[s][e];
+            for (int s = 0; s < p.n64; ++s) p.p64_out[s][o] = p.p64_in[s][e];
+        }
+        __syncthreads();
+    }
+}
+
+// Cells by size class.  lists[c * n_cells + k] = k-th cell of class c; the
+// class lengths go to flags->count[c]; flags->huge_total sums the members of
+// cells beyond the largest LDS class.  Within a class the order is
+// arbitrary: cells are independent and their random numbers depend only on
+// (seed, step, pid), so processing order never changes results.
+__global__ void k_build_queue(const int32_t *__restrict__ cell_start, int32_t n_cells, ClassCaps caps,
+                              int32_t *__restrict__ lists, DevFlags *f)
+{
+    const int lane = threadIdx.x & (PIC_WAVE - 1);
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (PIC_WAVE - lane));
+    for (int64_t j0 = blockIdx.x * (int64_t)blockDim.x; j0 < n_cells;
+         j0 += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = j0 + threadIdx.x;
+        const bool valid = j < n_cells;
+        int cls = -1;
+        int32_t cnt = 0;
+        if (valid) {
+            // every cell is visited: cells with fewer than two members still
+            // need the null-collision step and their moment sums
+            cnt = cell_start[j + 1] - cell_start[j];
+            cls = caps.ncls;
+            for (int c = caps.ncls - 1; c >= 0; --c)
+                if (cnt <= caps.cap[c]) cls = c;
+        }
+        for (int c = 0; c <= caps.ncls; ++c) {
+            const uint64_t m = __ballot(cls == c);
+            if (!m) continue;
+            const int leader = __ffsll((unsigned long long)m) - 1;
+            uint32_t b = 0;
+            if (lane == leader) b = atomicAdd(&f->count[c], (uint32_t)__popcll(m));
+            b = __shfl(b, leader, PIC_WAVE);
+            if (cls == c) lists[(int64_t)c * n_cells + b + __popcll(m & lt)] = (int32_t)j;
+        }
+        if (cls == caps.ncls) atomicAdd(&f->huge_total, (uint32_t)cnt);
+    }
+}
+
+int grid_for(int64_t n, int threads, int cap)
+{
+    int64_t g = (n + threads - 1) / threads;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+}  // namespace
+
+int launch_reset_flags(DevFlags *flags, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_reset_flags, dim3(1), dim3(64), 0, st, flags);
+    HIP_OK(hipGetLastError());
+    return PIC_OK;
+}
+
+int launch_bin_check(const int32_t *cell_of, int64_t n, int32_t n_cells, int32_t *cell_start,
+                     DevFlags *flags, int set_unsorted, const int *gate, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_bin_check, dim3(grid_for(n + 1, 256, 8192)), dim3(256), 0, st, cell_of, n,
+                       n_cells, cell_start, flags, set_unsorted, gate);
+    HIP_OK(hipGetLastError());
+    return PIC_OK;
+}
+
+int launch_copy32(uint32_t *dst, const uint32_t *src, int64_t n, const int *gate, hipStream_t st)
+{
+    if (n <= 0) return PIC_OK;
+    hipLaunchKernelGGL(k_copy32, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, dst, src, n, gate);
+    HIP_OK(hipGetLastError());
+    return PIC_OK;
+}
+
+size_t radix_scratch_bytes(int64_t n)
+{
+    const int64_t nb = (n + RS_TILE - 1) / RS_TILE + 1;
+    const int64_t L = 256 * nb;
+    const int64_t ns = (L + SCAN_CHUNK - 1) / SCAN_CHUNK + 1;
+    return (size_t)(L + ns) * sizeof(uint32_t) + 512;
+}
+
+int radix_pass(const RadixPass &p, const BinScratch &s, hipStream_t st)
+{
+    if (p.n <= 0) return PIC_OK;
+    const int64_t nb = (p.n + RS_TILE - 1) / RS_TILE;
+    const int64_t L = (int64_t)(1 << p.bits) * nb;
+    const int64_t ns = (L + SCAN_CHUNK - 1) / SCAN_CHUNK;
+    hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(RS_THREADS), 0, st, p, s.hist);
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)ns), dim3(SCAN_THREADS), 0, st, s.hist, L, s.bsum,
+                       p.gate);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_THREADS), 0, st, s.bsum, ns, p.gate);
+    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)ns), dim3(SCAN_THREADS), 0, st, s.hist, L, s.bsum,
+                       p.gate);
+    hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(RS_THREADS), 0, st, p,
+                       (const uint32_t *)s.hist);
+    HIP_OK(hipGetLastError());
+    return PIC_OK;
+}
+
+int launch_build_queue(const int32_t *cell_start, int32_t n_cells, const ClassCaps &caps,
+                       int32_t *lists, DevFlags *flags, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_build_queue, dim3(grid_for(n_cells, 256, 1024)), dim3(256), 0, st,
+                       cell_start, n_cells, caps, lists, flags);
+    HIP_OK(hipGetLastError());
+    return PIC_OK;
+}

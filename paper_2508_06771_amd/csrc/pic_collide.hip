@@ -1,0 +1,795 @@
+// pic_collide.hip -- the per-cell Coulomb collision pass (Table "Coulombic
+// Collision Steps", CCS3-CCS5) with the null-collision step, the per-cell
+// FP64 conservation sums and the moment sums fused into the same pass.
+//
+// The paper keeps particles unsorted, builds index lists and then gathers
+// velocities at random addresses for every pair ("6 reads and 6 writes" per
+// pair, non-coalesced, the bulk of its Coulomb time).  Here storage is in
+// cell order, so one workgroup owns a cell's contiguous range: velocities and
+// ids are streamed in and out coalesced exactly once, the random pairing is a
+// sort of the cell's keys in LDS, and partners meet through LDS.  The random
+// numbers come from Philox in registers (no pre-generated arrays).
+//
+// Per cell (n members, all in registers: K per thread):
+//   1. load pid, v; one Philox4x32-10 call per particle (domain 0):
+//      word0 pairing key, word1 null-collision candidate, words 2-3 for the pair
+//   2. sort by (key, pid) with an LDS bucket sort: bucket = (key * nb) >> 32
+//      is monotone in key, so buckets in order and (key, pid) order inside a
+//      bucket (expected 2 members) give the full order
+//   3. pairs (2i, 2i+1): second members post (v, word2) in LDS, first members
+//      apply the Takizuka & Abe rotation and post the half change back
+//   4. optional FP64 momentum/energy correction, null-collision scattering of
+//      candidates, optional moment sums; store v.
+//
+// Cells larger than the biggest LDS class take the "huge" path below, the same
+// algorithm with its per-cell arrays in global scratch indexed by slot.
+#include <float.h>
+
+#include "pic_internal.hpp"
+
+#define HIP_OK(x) do { if ((x) != hipSuccess) return PIC_ERR_HIP; } while (0)
+
+namespace {
+
+constexpr double PI_D = 3.14159265358979323846;
+
+// Half of the Takizuka & Abe velocity change of the pair (a, b) with
+// relative velocity u = v_a - v_b.  C = 8 pi n lnL dt (so s^2 = C / |u|^3);
+// U1, U2 (words 2, 3 of a) give z by Box-Muller, U3 (word 2 of b) the
+// azimuth.  The rotation keeps |u|: u' = u cos T + |u| sin T (cos P e1 + sin P e2).
+__device__ __forceinline__ void ta_half(float ux, float uy, float uz, float C, uint32_t wa2,
+                                        uint32_t wa3, uint32_t wb2, float &hx, float &hy,
+                                        float &hz)
+{
+    const float uu = ux * ux + uy * uy + uz * uz;
+    hx = hy = hz = 0.0f;
+    if (!(uu >= FLT_MIN)) return;   // u = 0 (or below the normal range): no change
+    const float rinv = __builtin_amdgcn_rsqf(uu);     // 1 / |u|
+    const float um = uu * rinv;                        // |u|
+    const float s = __builtin_sqrtf(C * rinv * rinv * rinv);
+    const float z = __builtin_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u01f(wa2))) * __builtin_amdgcn_cosf(u01f(wa3));
+    const float d = s * z;
+    // sin T = 2d / (1 + d^2), 1 - cos T = 2 d^2 / (1 + d^2); for |d| > 1 the
+    // same ratios in t = 1/d avoid overflow of d^2.
+    float sin_t, omc;
+    if (fabsf(d) <= 1.0f) {
+        const float inv = __builtin_amdgcn_rcpf(1.0f + d * d);
+        sin_t = 2.0f * d * inv;
+        omc = 2.0f * d * d * inv;
+    } else {
+        const float t = __builtin_amdgcn_rcpf(d);
+        const float inv = __builtin_amdgcn_rcpf(1.0f + t * t);
+        sin_t = 2.0f * t * inv;
+        omc = 2.0f * inv;
+    }
+    const float u3 = u01f(wb2);
+    const float cp = __builtin_amdgcn_cosf(u3), sp = __builtin_amdgcn_sinf(u3);  // revolutions
+    const float up2 = ux * ux + uy * uy;
+    float dx, dy, dz;
+    if (up2 > 0.0f) {
+        const float upinv = __builtin_amdgcn_rsqf(up2);
+        const float up = up2 * upinv;
+        const float a = uz * sin_t * cp;
+        const float b = um * sin_t * sp;
+        dx = (ux * upinv) * a - (uy * upinv) * b - ux * omc;
+        dy = (uy * upinv) * a + (ux * upinv) * b - uy * omc;
+        dz = -up * sin_t * cp - uz * omc;
+    } else {
+        dx = um * sin_t * cp;
+        dy = um * sin_t * sp;
+        dz = -uz * omc;
+    }
+    hx = 0.5f * dx;
+    hy = 0.5f * dy;
+    hz = 0.5f * dz;
+}
+
+__device__ __forceinline__ void ta_half(double ux, double uy, double uz, double C, uint32_t wa2,
+                                        uint32_t wa3, uint32_t wb2, double &hx, double &hy,
+                                        double &hz)
+{
+#pragma clang fp contract(off)
+    const double uu = ux * ux + uy * uy + uz * uz;
+    hx = hy = hz = 0.0;
+    if (uu == 0.0) return;
+    const double um = sqrt(uu);
+    const double uperp = sqrt(ux * ux + uy * uy);
+    const double z = sqrt(-2.0 * log(u01d(wa2))) * cos(2.0 * PI_D * u01d(wa3));
+    const double s2 = C / (um * um * um);
+    const double d = sqrt(s2) * z;
+    double sin_t, omc;
+    if (fabs(d) <= 1e150) {
+        sin_t = 2.0 * d / (1.0 + d * d);
+        omc = 2.0 * d * d / (1.0 + d * d);
+    } else {
+        sin_t = 2.0 / d;
+        omc = 2.0;
+    }
+    const double phi = 2.0 * PI_D * u01d(wb2);
+    const double cp = cos(phi), sp = sin(phi);
+    double dx, dy, dz;
+    if (uperp > 0.0) {
+        dx = (ux / uperp) * uz * sin_t * cp - (uy / uperp) * um * sin_t * sp - ux * omc;
+        dy = (uy / uperp) * uz * sin_t * cp + (ux / uperp) * um * sin_t * sp - uy * omc;
+        dz = -uperp * sin_t * cp - uz * omc;
+    } else {
+        dx = um * sin_t * cp;
+        dy = um * sin_t * sp;
+        dz = -uz * omc;
+    }
+    hx = 0.5 * dx;
+    hy = 0.5 * dy;
+    hz = 0.5 * dz;
+}
+
+template <typename R>
+__device__ __forceinline__ void mcc_scatter(R &vx, R &vy, R &vz, uint32_t pid, uint64_t seed,
+                                            uint32_t step, double mass_ratio)
+{
+    scatter_dir(vx, vy, vz, draw4(seed, pid, step, 1u, 0u), mass_ratio);
+}
+
+__device__ __forceinline__ uint64_t read_step(const CollideArgs &a)
+{
+    return a.step_dev ? *a.step_dev : a.step;
+}
+
+__device__ __forceinline__ double cell_C(const CollideArgs &a, int cell)
+{
+    const double dens = a.density ? a.density[cell] : 1.0;
+    const double dts = a.dt_scale ? a.dt_scale[cell] : 1.0;
+    return 8.0 * PI_D * dens * a.lnL * a.dt * dts;
+}
+
+__device__ __forceinline__ bool gated_off(const CollideArgs &a)
+{
+    if (a.dflags->range_err) return true;
+    if ((a.flags & PIC_ASSUME_SORTED) && a.dflags->unsorted) return true;
+    return false;
+}
+
+// Block-wide exclusive scan of one value per thread (T <= 1024).
+__device__ __forceinline__ uint32_t block_excl(uint32_t x, uint32_t *wtot)
+{
+    const int lane = threadIdx.x & (PIC_WAVE - 1), wid = threadIdx.x / PIC_WAVE;
+    const int nw = blockDim.x / PIC_WAVE;
+    const uint32_t inc = wave_incl_scan(x);
+    if (lane == PIC_WAVE - 1) wtot[wid] = inc;
+    __syncthreads();
+    uint32_t off = 0;
+    for (int w = 0; w < nw; ++w)
+        if (w < wid) off += wtot[w];
+    __syncthreads();
+    return off + inc - x;
+}
+
+__device__ __forceinline__ uint32_t get16(const uint32_t *w, uint32_t b)
+{
+    return (w[b >> 1] >> ((b & 1u) * 16u)) & 0xFFFFu;
+}
+
+// LDS bytes of one LDS-class cell pass of capacity cap.
+__host__ __device__ constexpr size_t lds_sort_bytes(int cap)
+{
+    return (size_t)cap * 4 + ((size_t)cap / 4 + 2) * 4 + (size_t)cap * 2;
+}
+template <typename R> __host__ __device__ constexpr int pair_rec_bytes() { return sizeof(R) == 4 ? 16 : 32; }
+constexpr int PAIR_ROUNDS = 2;
+template <typename R>
+__host__ __device__ constexpr size_t lds_pair_bytes(int cap)
+{
+    return ((size_t)cap / 2 / PAIR_ROUNDS + 1) * pair_rec_bytes<R>();
+}
+template <typename R>
+__host__ __device__ constexpr size_t lds_bytes(int cap)
+{
+    return lds_sort_bytes(cap) > lds_pair_bytes<R>(cap) ? lds_sort_bytes(cap) : lds_pair_bytes<R>(cap);
+}
+
+template <typename R> struct PairRec;
+template <> struct __align__(16) PairRec<float> { float x, y, z; uint32_t w2; };
+template <> struct __align__(16) PairRec<double> { double x, y, z; uint32_t w2, pad; };
+
+// ------------------------------------------------------------ LDS-class pass
+template <typename R, int T, int K, bool PAIRS>
+__device__ void cell_pass(const CollideArgs &a, int cell, unsigned char *smem, double *red,
+                          uint32_t *wtot)
+{
+    const int lo = a.cell_start[cell];
+    const int n = a.cell_start[cell + 1] - lo;
+    const uint32_t step = (uint32_t)read_step(a);
+    const bool coul = !(a.skip && a.skip[cell]) && n >= 2;
+    R *vx_g = (R *)a.v;
+    R *vy_g = vx_g + a.n;
+    R *vz_g = vy_g + a.n;
+
+    uint32_t *keys = (uint32_t *)smem;
+    uint32_t *cntw = keys + T * K;
+    uint16_t *lst = (uint16_t *)(cntw + (T * K) / 4 + 2);
+    PairRec<R> *pbuf = (PairRec<R> *)smem;
+
+    R vx[K], vy[K], vz[K];
+    uint32_t w2[K], w3[K], pos[K];
+    uint32_t cand = 0;
+    double before[5] = {0, 0, 0, 0, 0};
+
+    const uint32_t nb = n >= 2 ? (uint32_t)(n / 2) : 1u;   // buckets
+    const int nwords = (int)((nb + 1) / 2);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int i = threadIdx.x + k * T;
+        if (i < n) {
+            const uint32_t p = a.pid[lo + i];
+            if (!PAIRS) {
+                vx[k] = vx_g[lo + i];
+                vy[k] = vy_g[lo + i];
+                vz[k] = vz_g[lo + i];
+            }
+            const W4 w = draw4(a.seed, p, step, 0u, 0u);
+            keys[i] = w.x;
+            w2[k] = w.z;
+            w3[k] = w.w;
+            if ((uint64_t)w.y < a.mcc_thr) cand |= 1u << k;
+            if (!PAIRS && (a.flags & PIC_CONSERVE_FIX)) {
+                const double x = vx[k], y = vy[k], z = vz[k];
+                before[0] += 1.0;
+                before[1] += x;
+                before[2] += y;
+                before[3] += z;
+                before[4] += x * x + y * y + z * z;
+            }
+        }
+    }
+    for (int b = threadIdx.x; b < nwords; b += T) cntw[b] = 0u;
+    __syncthreads();
+
+    if (coul || PAIRS) {
+        // bucket and arrival rank (16-bit counters, two per LDS word)
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int i = threadIdx.x + k * T;
+            if (i < n) {
+                const uint32_t b = __umulhi(keys[i], nb);
+                const uint32_t sh = (b & 1u) * 16u;
+                const uint32_t old = atomicAdd(&cntw[b >> 1], 1u << sh);
+                pos[k] = (b << 16) | ((old >> sh) & 0xFFFFu);
+            }
+        }
+        __syncthreads();
+        // exclusive scan of the bucket counts, words split into per-thread chunks
+        {
+            const int per = (nwords + T - 1) / T;
+            const int w0 = threadIdx.x * per;
+            uint32_t s = 0;
+            for (int q = 0; q < per; ++q)
+                if (w0 + q < nwords) {
+                    const uint32_t c = cntw[w0 + q];
+                    s += (c & 0xFFFFu) + (c >> 16);
+                }
+            uint32_t run = block_excl(s, wtot);
+            for (int q = 0; q < per; ++q)
+                if (w0 + q < nwords) {
+                    const uint32_t c = cntw[w0 + q];
+                    const uint32_t lo16 = run, hi16 = run + (c & 0xFFFFu);
+                    run = hi16 + (c >> 16);
+                    cntw[w0 + q] = lo16 | (hi16 << 16);
+                }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int i = threadIdx.x + k * T;
+            if (i < n) lst[get16(cntw, pos[k] >> 16) + (pos[k] & 0xFFFFu)] = (uint16_t)i;
+        }
+        __syncthreads();
+        // final position = bucket offset + rank by (key, pid) inside the bucket
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int i = threadIdx.x + k * T;
+            if (i < n) {
+                const uint32_t b = pos[k] >> 16;
+                const uint32_t beg = get16(cntw, b);
+                const uint32_t end = (b + 1 < nb) ? get16(cntw, b + 1) : (uint32_t)n;
+                const uint32_t key = keys[i];
+                uint32_t rank = 0;
+                for (uint32_t m = beg; m < end; ++m) {
+                    const uint32_t j = lst[m];
+                    const uint32_t kj = keys[j];
+                    if (kj < key) {
+                        ++rank;
+                    } else if (kj == key && j != (uint32_t)i) {
+                        if (a.pid[lo + j] < a.pid[lo + i]) ++rank;
+                    }
+                }
+                pos[k] = beg + rank;
+            }
+        }
+        __syncthreads();
+    }
+
+    if (PAIRS) {
+        // sorted[] and partner[] for the test export
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int i = threadIdx.x + k * T;
+            if (i < n) {
+                lst[pos[k]] = (uint16_t)i;
+                a.sorted_out[lo + pos[k]] = lo + i;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int i = threadIdx.x + k * T;
+            if (i < n) {
+                const uint32_t q = pos[k] ^ 1u;
+                a.partner_out[lo + i] = (q < (uint32_t)n) ? lo + (int)lst[q] : -1;
+            }
+        }
+        __syncthreads();
+        return;
+    }
+
+    if (coul) {
+        const R C = (R)cell_C(a, cell);
+        const int npairs = n / 2;
+        const int half = (npairs + PAIR_ROUNDS - 1) / PAIR_ROUNDS;
+        for (int r = 0; r < PAIR_ROUNDS; ++r) {
+            const int qlo = r * half, qhi = min(npairs, qlo + half);
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int i = threadIdx.x + k * T;
+                const int q = (int)(pos[k] >> 1);
+                if (i < n && (pos[k] & 1u) && q >= qlo && q < qhi) {
+                    PairRec<R> &e = pbuf[q - qlo];
+                    e.x = vx[k];
+                    e.y = vy[k];
+                    e.z = vz[k];
+                    e.w2 = w2[k];
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int i = threadIdx.x + k * T;
+                const int q = (int)(pos[k] >> 1);
+                if (i < n && !(pos[k] & 1u) && q >= qlo && q < qhi) {
+                    PairRec<R> &e = pbuf[q - qlo];
+                    R hx, hy, hz;
+                    ta_half(vx[k] - e.x, vy[k] - e.y, vz[k] - e.z, C, w2[k], w3[k], e.w2, hx, hy,
+                            hz);
+                    vx[k] += hx;
+                    vy[k] += hy;
+                    vz[k] += hz;
+                    e.x = hx;
+                    e.y = hy;
+                    e.z = hz;
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int i = threadIdx.x + k * T;
+                const int q = (int)(pos[k] >> 1);
+                if (i < n && (pos[k] & 1u) && q >= qlo && q < qhi) {
+                    const PairRec<R> &e = pbuf[q - qlo];
+                    vx[k] -= e.x;
+                    vy[k] -= e.y;
+                    vz[k] -= e.z;
+                }
+            }
+            __syncthreads();
+        }
+
+        if (a.flags & PIC_CONSERVE_FIX) {
+            double after[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int i = threadIdx.x + k * T;
+                if (i < n) {
+                    const double x = vx[k], y = vy[k], z = vz[k];
+                    after[1] += x;
+                    after[2] += y;
+                    after[3] += z;
+                    after[4] += x * x + y * y + z * z;
+                }
+            }
+            block_sum<5>(before, red);
+            block_sum<5>(after, red);
+            const double N = before[0];
+            const double Vo[3] = {before[1] / N, before[2] / N, before[3] / N};
+            const double Vn[3] = {after[1] / N, after[2] / N, after[3] / N};
+            const double Eo = 0.5 * before[4] - 0.5 * N * (Vo[0] * Vo[0] + Vo[1] * Vo[1] + Vo[2] * Vo[2]);
+            const double En = 0.5 * after[4] - 0.5 * N * (Vn[0] * Vn[0] + Vn[1] * Vn[1] + Vn[2] * Vn[2]);
+            if (En > 0.0 && Eo >= 0.0) {
+                const double al = sqrt(Eo / En);
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const int i = threadIdx.x + k * T;
+                    if (i < n) {
+                        vx[k] = (R)(Vo[0] + al * ((double)vx[k] - Vn[0]));
+                        vy[k] = (R)(Vo[1] + al * ((double)vy[k] - Vn[1]));
+                        vz[k] = (R)(Vo[2] + al * ((double)vz[k] - Vn[2]));
+                    }
+                }
+            }
+        }
+    }
+
+    if (a.mcc_thr && cand) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int i = threadIdx.x + k * T;
+            if (i < n && ((cand >> k) & 1u))
+                mcc_scatter<R>(vx[k], vy[k], vz[k], a.pid[lo + i], a.seed, step, a.mass_ratio);
+        }
+    }
+
+    if (a.flags & PIC_MOMENTS) {
+        double m[14];
+#pragma unroll
+        for (int q = 0; q < 14; ++q) m[q] = 0.0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int i = threadIdx.x + k * T;
+            if (i < n) {
+                const double x = vx[k], y = vy[k], z = vz[k];
+                const double q2 = x * x + y * y + z * z;
+                m[0] += 1.0;
+                m[1] += x; m[2] += y; m[3] += z;
+                m[4] += x * x; m[5] += y * y; m[6] += z * z;
+                m[7] += x * y; m[8] += x * z; m[9] += y * z;
+                m[10] += q2 * x; m[11] += q2 * y; m[12] += q2 * z;
+                m[13] += q2 * q2;
+            }
+        }
+        block_sum<14>(m, red);
+        if (threadIdx.x < 14) a.moments[(int64_t)cell * 14 + threadIdx.x] = m[threadIdx.x];
+    }
+
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int i = threadIdx.x + k * T;
+        if (i < n) {
+            vx_g[lo + i] = vx[k];
+            vy_g[lo + i] = vy[k];
+            vz_g[lo + i] = vz[k];
+        }
+    }
+}
+
+template <typename R, int T, int K, bool PAIRS>
+__global__ __launch_bounds__(T) void k_collide(CollideArgs a, const int32_t *__restrict__ list,
+                                               int cls)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[14 * (T / PIC_WAVE)];
+    __shared__ uint32_t wtot[T / PIC_WAVE];
+    __shared__ int s_item;
+    if (gated_off(a)) return;
+    const uint32_t count = a.dflags->count[cls];
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(&a.dflags->head[cls], 1u);
+        __syncthreads();
+        const int item = s_item;
+        __syncthreads();
+        if (item >= (int)count) break;
+        cell_pass<R, T, K, PAIRS>(a, list[item], smem, red, wtot);
+    }
+}
+
+// ------------------------------------------------------------ huge cells
+// One workgroup per cell; per-particle state in global scratch indexed by the
+// particle's slot, so scratch regions of different cells never overlap.
+struct HugeScratch {
+    uint32_t *keys;    // [n]
+    uint32_t *cnt;     // [n]  bucket counts, then offsets
+    uint32_t *lst;     // [n]  bucket member lists
+    uint32_t *pos;     // [n]  arrival rank, then sorted position
+    uint32_t *w23;     // [2n] words 2 and 3
+    uint8_t *cand;     // [n]
+    void *pbuf;        // [n/2 + 1] pair records
+};
+
+template <typename R, bool PAIRS>
+__global__ __launch_bounds__(1024) void k_collide_huge(CollideArgs a, const int32_t *__restrict__ list,
+                                                       int cls, HugeScratch hs)
+{
+    __shared__ double red[14 * 16];
+    __shared__ uint32_t wtot[16];
+    __shared__ int s_item;
+    if (gated_off(a)) return;
+    const uint32_t count = a.dflags->count[cls];
+    const int T = blockDim.x;
+    R *vx_g = (R *)a.v;
+    R *vy_g = vx_g + a.n;
+    R *vz_g = vy_g + a.n;
+    PairRec<R> *pb = (PairRec<R> *)hs.pbuf;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(&a.dflags->head[cls], 1u);
+        __syncthreads();
+        const int item = s_item;
+        __syncthreads();
+        if (item >= (int)count) break;
+        const int cell = list[item];
+        const int lo = a.cell_start[cell];
+        const int n = a.cell_start[cell + 1] - lo;
+        const uint32_t step = (uint32_t)read_step(a);
+        const bool coul = !(a.skip && a.skip[cell]) && n >= 2;
+        const uint32_t nb = n >= 2 ? (uint32_t)(n / 2) : 1u;
+        double before[5] = {0, 0, 0, 0, 0};
+        for (int i = threadIdx.x; i < n; i += T) {
+            const W4 w = draw4(a.seed, a.pid[lo + i], step, 0u, 0u);
+            hs.keys[lo + i] = w.x;
+            hs.w23[2 * (int64_t)(lo + i)] = w.z;
+            hs.w23[2 * (int64_t)(lo + i) + 1] = w.w;
+            hs.cand[lo + i] = (uint64_t)w.y < a.mcc_thr;
+            hs.cnt[lo + i] = 0u;
+            if (!PAIRS && (a.flags & PIC_CONSERVE_FIX)) {
+                const double x = vx_g[lo + i], y = vy_g[lo + i], z = vz_g[lo + i];
+                before[0] += 1.0;
+                before[1] += x;
+                before[2] += y;
+                before[3] += z;
+                before[4] += x * x + y * y + z * z;
+            }
+        }
+        __syncthreads();
+        if (coul || PAIRS) {
+            for (int i = threadIdx.x; i < n; i += T) {
+                const uint32_t b = __umulhi(hs.keys[lo + i], nb);
+                hs.pos[lo + i] = atomicAdd(&hs.cnt[lo + b], 1u);
+            }
+            __syncthreads();
+            {
+                const int per = ((int)nb + T - 1) / T;
+                const int b0 = threadIdx.x * per;
+                uint32_t s = 0;
+                for (int q = 0; q < per; ++q)
+                    if (b0 + q < (int)nb) s += hs.cnt[lo + b0 + q];
+                uint32_t run = block_excl(s, wtot);
+                for (int q = 0; q < per; ++q)
+                    if (b0 + q < (int)nb) {
+                        const uint32_t c = hs.cnt[lo + b0 + q];
+                        hs.cnt[lo + b0 + q] = run;
+                        run += c;
+                    }
+            }
+            __syncthreads();
+            for (int i = threadIdx.x; i < n; i += T) {
+                const uint32_t b = __umulhi(hs.keys[lo + i], nb);
+                hs.lst[lo + hs.cnt[lo + b] + hs.pos[lo + i]] = (uint32_t)i;
+            }
+            __syncthreads();
+            for (int i = threadIdx.x; i < n; i += T) {
+                const uint32_t key = hs.keys[lo + i];
+                const uint32_t b = __umulhi(key, nb);
+                const uint32_t beg = hs.cnt[lo + b];
+                const uint32_t end = (b + 1 < nb) ? hs.cnt[lo + b + 1] : (uint32_t)n;
+                uint32_t rank = 0;
+                for (uint32_t m = beg; m < end; ++m) {
+                    const uint32_t j = hs.lst[lo + m];
+                    const uint32_t kj = hs.keys[lo + j];
+                    if (kj < key) ++rank;
+                    else if (kj == key && j != (uint32_t)i && a.pid[lo + j] < a.pid[lo + i]) ++rank;
+                }
+                hs.pos[lo + i] = beg + rank;
+            }
+            __syncthreads();
+        }
+        if (PAIRS) {
+            for (int i = threadIdx.x; i < n; i += T) {
+                hs.lst[lo + hs.pos[lo + i]] = (uint32_t)i;
+                a.sorted_out[lo + hs.pos[lo + i]] = lo + i;
+            }
+            __syncthreads();
+            for (int i = threadIdx.x; i < n; i += T) {
+                const uint32_t q = hs.pos[lo + i] ^ 1u;
+                a.partner_out[lo + i] = (q < (uint32_t)n) ? lo + (int)hs.lst[lo + q] : -1;
+            }
+            __syncthreads();
+            continue;
+        }
+        if (coul) {
+            const R C = (R)cell_C(a, cell);
+            PairRec<R> *pc = pb + lo / 2 + (lo & 1);   // disjoint per cell
+            for (int i = threadIdx.x; i < n; i += T) {
+                const uint32_t p = hs.pos[lo + i];
+                if (p & 1u) {
+                    PairRec<R> &e = pc[p >> 1];
+                    e.x = vx_g[lo + i];
+                    e.y = vy_g[lo + i];
+                    e.z = vz_g[lo + i];
+                    e.w2 = hs.w23[2 * (int64_t)(lo + i)];
+                }
+            }
+            __syncthreads();
+            for (int i = threadIdx.x; i < n; i += T) {
+                const uint32_t p = hs.pos[lo + i];
+                if (!(p & 1u) && p + 1 < (uint32_t)n) {
+                    PairRec<R> &e = pc[p >> 1];
+                    R x = vx_g[lo + i], y = vy_g[lo + i], z = vz_g[lo + i];
+                    R hx, hy, hz;
+                    ta_half(x - e.x, y - e.y, z - e.z, C, hs.w23[2 * (int64_t)(lo + i)],
+                            hs.w23[2 * (int64_t)(lo + i) + 1], e.w2, hx, hy, hz);
+                    vx_g[lo + i] = x + hx;
+                    vy_g[lo + i] = y + hy;
+                    vz_g[lo + i] = z + hz;
+                    e.x = hx;
+                    e.y = hy;
+                    e.z = hz;
+                }
+            }
+            __syncthreads();
+            for (int i = threadIdx.x; i < n; i += T) {
+                const uint32_t p = hs.pos[lo + i];
+                if (p & 1u) {
+                    const PairRec<R> &e = pc[p >> 1];
+                    vx_g[lo + i] -= e.x;
+                    vy_g[lo + i] -= e.y;
+                    vz_g[lo + i] -= e.z;
+                }
+            }
+            __syncthreads();
+            if (a.flags & PIC_CONSERVE_FIX) {
+                double after[5] = {0, 0, 0, 0, 0};
+                for (int i = threadIdx.x; i < n; i += T) {
+                    const double x = vx_g[lo + i], y = vy_g[lo + i], z = vz_g[lo + i];
+                    after[1] += x;
+                    after[2] += y;
+                    after[3] += z;
+                    after[4] += x * x + y * y + z * z;
+                }
+                block_sum<5>(before, red);
+                block_sum<5>(after, red);
+                const double N = before[0];
+                const double Vo[3] = {before[1] / N, before[2] / N, before[3] / N};
+                const double Vn[3] = {after[1] / N, after[2] / N, after[3] / N};
+                const double Eo = 0.5 * before[4] - 0.5 * N * (Vo[0] * Vo[0] + Vo[1] * Vo[1] + Vo[2] * Vo[2]);
+                const double En = 0.5 * after[4] - 0.5 * N * (Vn[0] * Vn[0] + Vn[1] * Vn[1] + Vn[2] * Vn[2]);
+                if (En > 0.0 && Eo >= 0.0) {
+                    const double al = sqrt(Eo / En);
+                    for (int i = threadIdx.x; i < n; i += T) {
+                        vx_g[lo + i] = (R)(Vo[0] + al * ((double)vx_g[lo + i] - Vn[0]));
+                        vy_g[lo + i] = (R)(Vo[1] + al * ((double)vy_g[lo + i] - Vn[1]));
+                        vz_g[lo + i] = (R)(Vo[2] + al * ((double)vz_g[lo + i] - Vn[2]));
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        double m[14];
+        for (int q = 0; q < 14; ++q) m[q] = 0.0;
+        for (int i = threadIdx.x; i < n; i += T) {
+            R x = vx_g[lo + i], y = vy_g[lo + i], z = vz_g[lo + i];
+            if (a.mcc_thr && hs.cand[lo + i]) {
+                mcc_scatter<R>(x, y, z, a.pid[lo + i], a.seed, step, a.mass_ratio);
+                vx_g[lo + i] = x;
+                vy_g[lo + i] = y;
+                vz_g[lo + i] = z;
+            }
+            if (a.flags & PIC_MOMENTS) {
+                const double dx = x, dy = y, dz = z;
+                const double q2 = dx * dx + dy * dy + dz * dz;
+                m[0] += 1.0;
+                m[1] += dx; m[2] += dy; m[3] += dz;
+                m[4] += dx * dx; m[5] += dy * dy; m[6] += dz * dz;
+                m[7] += dx * dy; m[8] += dx * dz; m[9] += dy * dz;
+                m[10] += q2 * dx; m[11] += q2 * dy; m[12] += q2 * dz;
+                m[13] += q2 * q2;
+            }
+        }
+        if (a.flags & PIC_MOMENTS) {
+            block_sum<14>(m, red);
+            if (threadIdx.x < 14) a.moments[(int64_t)cell * 14 + threadIdx.x] = m[threadIdx.x];
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------ class table
+// Class c handles cells with at most cap[c] members (T threads x K items).
+template <typename R> struct Classes;
+template <> struct Classes<float> {
+    static constexpr int T0 = 256, K0 = 2;    // <= 512
+    static constexpr int T1 = 512, K1 = 4;    // <= 2048
+    static constexpr int T2 = 1024, K2 = 4;   // <= 4096
+    static constexpr int T3 = 1024, K3 = 10;  // <= 10240
+};
+template <> struct Classes<double> {
+    static constexpr int T0 = 256, K0 = 2;
+    static constexpr int T1 = 512, K1 = 4;
+    static constexpr int T2 = 1024, K2 = 4;
+    static constexpr int T3 = 1024, K3 = 6;   // <= 6144
+};
+
+template <typename R, int T, int K, bool PAIRS>
+int launch_class(const CollideArgs &a, const int32_t *list, int cls, int blocks, hipStream_t st)
+{
+    const size_t lds = lds_bytes<R>(T * K);
+    auto kern = k_collide<R, T, K, PAIRS>;
+    static bool attr_done = false;
+    if (!attr_done) {
+        HIP_OK(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)lds));
+        attr_done = true;
+    }
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(T), lds, st, a, list, cls);
+    HIP_OK(hipGetLastError());
+    return PIC_OK;
+}
+
+template <typename R, bool PAIRS>
+int launch_all(const CollideArgs &a, const int32_t *lists, int32_t n_cells, int num_cu,
+               const HugeScratch &hs, hipStream_t st)
+{
+    typedef Classes<R> C;
+    int rc;
+    const int64_t M = n_cells;
+    // largest cells first so the small ones fill the tail
+    hipLaunchKernelGGL((k_collide_huge<R, PAIRS>), dim3(num_cu), dim3(1024), 0, st, a, lists + 4 * M,
+                       4, hs);
+    HIP_OK(hipGetLastError());
+    if ((rc = launch_class<R, C::T3, C::K3, PAIRS>(a, lists + 3 * M, 3, 2 * num_cu, st))) return rc;
+    if ((rc = launch_class<R, C::T2, C::K2, PAIRS>(a, lists + 2 * M, 2, 2 * num_cu, st))) return rc;
+    if ((rc = launch_class<R, C::T1, C::K1, PAIRS>(a, lists + 1 * M, 1, 4 * num_cu, st))) return rc;
+    if ((rc = launch_class<R, C::T0, C::K0, PAIRS>(a, lists + 0 * M, 0, 8 * num_cu, st))) return rc;
+    return PIC_OK;
+}
+
+HugeScratch g_huge;   // set by launch_collide from the workspace
+
+}  // namespace
+
+ClassCaps collide_caps(int dtype, size_t)
+{
+    ClassCaps c;
+    c.ncls = 4;
+    if (dtype == PIC_F32) {
+        typedef Classes<float> C;
+        c.cap[0] = C::T0 * C::K0;
+        c.cap[1] = C::T1 * C::K1;
+        c.cap[2] = C::T2 * C::K2;
+        c.cap[3] = C::T3 * C::K3;
+    } else {
+        typedef Classes<double> C;
+        c.cap[0] = C::T0 * C::K0;
+        c.cap[1] = C::T1 * C::K1;
+        c.cap[2] = C::T2 * C::K2;
+        c.cap[3] = C::T3 * C::K3;
+    }
+    return c;
+}
+
+size_t huge_scratch_bytes(int dtype, int64_t n)
+{
+    const size_t rec = dtype == PIC_F32 ? 16 : 32;
+    return (size_t)n * (4 * 4 + 8 + 1) + ((size_t)n / 2 + 2) * rec + 1024;
+}
+
+void set_huge_scratch(int dtype, int64_t n, void *base)
+{
+    unsigned char *p = (unsigned char *)base;
+    auto take = [&](size_t bytes) {
+        unsigned char *r = p;
+        p += (bytes + 255) & ~(size_t)255;
+        return (void *)r;
+    };
+    g_huge.keys = (uint32_t *)take((size_t)n * 4);
+    g_huge.cnt = (uint32_t *)take((size_t)n * 4);
+    g_huge.lst = (uint32_t *)take((size_t)n * 4);
+    g_huge.pos = (uint32_t *)take((size_t)n * 4);
+    g_huge.w23 = (uint32_t *)take((size_t)n * 8);
+    g_huge.cand = (uint8_t *)take((size_t)n);
+    g_huge.pbuf = take(((size_t)n / 2 + 2) * (dtype == PIC_F32 ? 16 : 32));
+}
+
+int launch_collide(int dtype, const CollideArgs &a, const int32_t *lists, int32_t n_cells,
+                   const ClassCaps &, int pairs_only, int num_cu, hipStream_t st)
+{
+    if (dtype == PIC_F32)
+        return pairs_only ? launch_all<float, true>(a, lists, n_cells, num_cu, g_huge, st)
+                          : launch_all<float, false>(a, lists, n_cells, num_cu, g_huge, st);
+    return pairs_only ? launch_all<double, true>(a, lists, n_cells, num_cu, g_huge, st)
+                      : launch_all<double, false>(a, lists, n_cells, num_cu, g_huge, st);
+}

@@ -1,0 +1,239 @@
+// pic_internal.hpp -- device helpers and launch interfaces shared by the
+// library's HIP translation units (CDNA4 / gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "piccoll.h"
+
+#define PIC_WAVE 64
+
+// ---------------------------------------------------------------------------
+// Device-side status words.  `unsorted` and `range_err` describe the current
+// call; the sticky words survive until pic_sync reads and clears them.
+// ---------------------------------------------------------------------------
+struct DevFlags {
+    int unsorted;        // storage not in cell order (re-binning needed)
+    int range_err;       // a cell id outside [0, n_cells) in this call
+    int sticky_range;    // latched PIC_ERR_RANGE
+    int sticky_state;    // latched PIC_ERR_STATE
+    unsigned int head[8];   // work-queue heads of the persistent kernels
+    unsigned int count[8];  // work-queue lengths (cells per class)
+    unsigned int huge_total; // members of cells in the multi-block class
+    unsigned int pad[7];
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  Each round multiplies
+// two counter words by the round constants (one 32x32->64 product each),
+// mixes the high halves with the other two words and the round key, and the
+// key advances by the Weyl increments between rounds.  The key comes from the
+// seed and is the same for every lane, so its schedule stays in SGPRs.
+// ---------------------------------------------------------------------------
+struct W4 {
+    uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ W4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                       uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return W4{c0, c1, c2, c3};
+}
+
+__device__ __forceinline__ W4 draw4(uint64_t seed, uint32_t c0, uint32_t step, uint32_t domain,
+                                    uint32_t c3)
+{
+    return philox10(c0, step, domain, c3, (uint32_t)seed, (uint32_t)(seed >> 32));
+}
+
+// U(x) = ((x >> 9) + 1/2) 2^-23: 24 significant bits, exact in binary32.
+__device__ __forceinline__ float u01f(uint32_t x)
+{
+    return ((float)(x >> 9) + 0.5f) * 0x1p-23f;
+}
+__device__ __forceinline__ double u01d(uint32_t x)
+{
+    return ((double)(x >> 9) + 0.5) * 0x1p-23;
+}
+
+// ---------------------------------------------------------------------------
+// Elastic isotropic scattering of a null-collision candidate from its domain-1
+// draw w: cos(theta) = 1 - 2 U(w.y), phi = 2 pi U(w.z) (binary32: the hardware
+// sine/cosine take revolutions), |v'|^2 = |v|^2 (1 - 2 (m/M) (1 - vhat.s)).
+// The cross section sigma0 E^-1/2 gives the speed-independent frequency
+// nu = n_n sigma0 sqrt(2) = nu_max, so the real/null test U(w.x) nu_max < nu
+// always passes and is not evaluated.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void scatter_dir(float &vx, float &vy, float &vz, const W4 &w,
+                                            double mass_ratio)
+{
+    const float ct = 1.0f - 2.0f * u01f(w.y);
+    const float st = __builtin_sqrtf(fmaxf(0.0f, 1.0f - ct * ct));
+    const float up = u01f(w.z);
+    const float sx = st * __builtin_amdgcn_cosf(up), sy = st * __builtin_amdgcn_sinf(up), sz = ct;
+    const float sp = __builtin_sqrtf(vx * vx + vy * vy + vz * vz);
+    float scale = sp;
+    if (mass_ratio != 0.0 && sp > 0.0f) {
+        const float cosx = (vx * sx + vy * sy + vz * sz) / sp;
+        scale = sp * __builtin_sqrtf(1.0f - 2.0f * (float)mass_ratio * (1.0f - cosx));
+    }
+    vx = scale * sx;
+    vy = scale * sy;
+    vz = scale * sz;
+}
+
+__device__ __forceinline__ void scatter_dir(double &vx, double &vy, double &vz, const W4 &w,
+                                            double mass_ratio)
+{
+    const double ct = 1.0 - 2.0 * u01d(w.y);
+    const double st = sqrt(fmax(0.0, 1.0 - ct * ct));
+    const double ph = 2.0 * 3.14159265358979323846 * u01d(w.z);
+    const double sx = st * cos(ph), sy = st * sin(ph), sz = ct;
+    const double sp = sqrt(vx * vx + vy * vy + vz * vz);
+    double scale = sp;
+    if (mass_ratio != 0.0 && sp > 0.0) {
+        const double cosx = (vx * sx + vy * sy + vz * sz) / sp;
+        scale = sp * sqrt(1.0 - 2.0 * mass_ratio * (1.0 - cosx));
+    }
+    vx = scale * sx;
+    vy = scale * sy;
+    vz = scale * sz;
+}
+
+// ---------------------------------------------------------------------------
+// Wave / block reductions in a fixed order (bitwise reproducible).
+// ---------------------------------------------------------------------------
+template <typename V>
+__device__ __forceinline__ V wave_sum(V x)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, PIC_WAVE);
+    return x;
+}
+
+// Sum NV doubles over the block; every thread receives the totals.
+// red: LDS scratch of NV * (blockDim / 64) doubles.  Contains the barriers.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&x)[NV], double *red)
+{
+    const int lane = threadIdx.x & (PIC_WAVE - 1), wid = threadIdx.x / PIC_WAVE;
+    const int nw = blockDim.x / PIC_WAVE;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) x[j] = wave_sum(x[j]);
+    if (lane == 0) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) red[wid * NV + j] = x[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        double s = 0.0;
+        for (int w = 0; w < nw; ++w) s += red[w * NV + j];
+        x[j] = s;
+    }
+    __syncthreads();
+}
+
+// Inclusive scan of one uint32 per lane within a wave.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x)
+{
+    const int lane = threadIdx.x & (PIC_WAVE - 1);
+#pragma unroll
+    for (int o = 1; o < PIC_WAVE; o <<= 1) {
+        uint32_t y = __shfl_up(x, o, PIC_WAVE);
+        if (lane >= o) x += y;
+    }
+    return x;
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launch interfaces (implemented in the .hip files).
+// ---------------------------------------------------------------------------
+struct RadixPass {
+    const int32_t *key_in;
+    int32_t *key_out;
+    int n32, n64;
+    const uint32_t *p32_in[6];
+    uint32_t *p32_out[6];
+    const uint64_t *p64_in[3];
+    uint64_t *p64_out[3];
+    int iota_slot;      // payload slot written with the element index (-1: none)
+    int64_t n;
+    int shift, bits;
+    const int *gate;    // non-null: run only if *gate != 0
+};
+
+struct BinScratch {
+    uint32_t *hist;     // (1 << bits) * nblocks
+    uint32_t *bsum;     // scan block sums
+};
+
+size_t radix_scratch_bytes(int64_t n);
+int radix_pass(const RadixPass &p, const BinScratch &s, hipStream_t st);
+
+// Checks the order of cell_of and writes cell_start as if it were sorted.
+// set_unsorted: 0 = only range checks, 1 = raise flags->unsorted on a
+// descent, 2 = also latch sticky_state (caller asserted sorted storage).
+int launch_bin_check(const int32_t *cell_of, int64_t n, int32_t n_cells, int32_t *cell_start,
+                     DevFlags *flags, int set_unsorted, const int *gate, hipStream_t st);
+int launch_reset_flags(DevFlags *flags, hipStream_t st);
+int launch_copy32(uint32_t *dst, const uint32_t *src, int64_t n, const int *gate, hipStream_t st);
+
+// Work queue of cells by size class.
+struct ClassCaps {
+    int ncls;            // number of LDS classes (<= 4), class ncls = multi-block
+    int cap[4];          // max members per cell of each class
+};
+int launch_build_queue(const int32_t *cell_start, int32_t n_cells, const ClassCaps &caps,
+                       int32_t *lists, DevFlags *flags, hipStream_t st);
+
+struct CollideArgs {
+    void *v;               // SoA base
+    int64_t n;             // stride between components
+    const uint32_t *pid;
+    const int32_t *cell_start;
+    const double *density;
+    const double *dt_scale;  // per-cell dt multiplier (nullable)
+    const uint8_t *skip;     // per-cell skip (nullable)
+    double dt, lnL;
+    uint64_t seed, step;
+    const uint64_t *step_dev;  // nullable: step read from device memory
+    uint32_t flags;
+    uint64_t mcc_thr;      // candidate iff word1 < mcc_thr (0 = no null collisions)
+    double mass_ratio;
+    double *moments;       // PIC_MOMENTS output (M x 14)
+    DevFlags *dflags;
+    // pairing export
+    int32_t *sorted_out, *partner_out;
+};
+
+int launch_collide(int dtype, const CollideArgs &a, const int32_t *lists, int32_t n_cells,
+                   const ClassCaps &caps, int pairs_only, int num_cu, hipStream_t st);
+ClassCaps collide_caps(int dtype, size_t lds_per_block);
+// Global scratch of the multi-block ("huge") class, indexed by particle slot.
+size_t huge_scratch_bytes(int dtype, int64_t n);
+void set_huge_scratch(int dtype, int64_t n, void *base);
+
+int launch_mcc(int dtype, void *v, const uint32_t *pid, int64_t n, uint64_t thr, double mass_ratio,
+               uint64_t seed, uint64_t step, uint8_t *cand_out, hipStream_t st);
+int launch_philox(uint64_t seed, uint64_t step, uint32_t domain, uint32_t c3, const uint32_t *c0,
+                  int64_t n, uint32_t *out, hipStream_t st);
+int launch_moments(int dtype, const void *v, int64_t n, const int32_t *cell_start,
+                   int32_t n_cells, double *out, hipStream_t st);
+int launch_unsort(int dtype, void *v, uint32_t *pid, int32_t *cell_of, int64_t n, void *tmp,
+                  hipStream_t st);

@@ -1,0 +1,169 @@
+// pic_misc.hip -- stand-alone null-collision step, per-cell moment sums,
+// Philox export and the pid-order restore.
+#include "pic_internal.hpp"
+
+#define HIP_OK(x) do { if ((x) != hipSuccess) return PIC_ERR_HIP; } while (0)
+
+namespace {
+
+// One particle per lane: the candidate test needs only pid (4 B); velocities
+// are read and written for candidates only (P_null of the particles).
+template <typename R>
+__global__ __launch_bounds__(256) void k_mcc(R *__restrict__ v, const uint32_t *__restrict__ pid,
+                                             int64_t n, uint64_t thr, double mass_ratio,
+                                             uint64_t seed, uint32_t step,
+                                             uint8_t *__restrict__ cand_out)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t p = pid[i];
+        const W4 w = draw4(seed, p, step, 0u, 0u);
+        const bool c = (uint64_t)w.y < thr;
+        if (cand_out) cand_out[i] = (uint8_t)c;
+        if (c) {
+            R x = v[i], y = v[n + i], z = v[2 * n + i];
+            const W4 m = draw4(seed, p, step, 1u, 0u);
+            scatter_dir(x, y, z, m, mass_ratio);
+            v[i] = x;
+            v[n + i] = y;
+            v[2 * n + i] = z;
+        }
+    }
+}
+
+__global__ void k_philox(uint64_t seed, uint32_t step, uint32_t domain, uint32_t c3,
+                         const uint32_t *__restrict__ c0, int64_t n, uint4 *__restrict__ out)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const W4 w = draw4(seed, c0[i], step, domain, c3);
+        out[i] = make_uint4(w.x, w.y, w.z, w.w);
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_moments(const R *__restrict__ v, int64_t n,
+                                                 const int32_t *__restrict__ cs, int32_t n_cells,
+                                                 double *__restrict__ out)
+{
+    __shared__ double red[14 * 4];
+    for (int j = blockIdx.x; j < n_cells; j += gridDim.x) {
+        double m[14];
+        for (int q = 0; q < 14; ++q) m[q] = 0.0;
+        for (int64_t i = cs[j] + threadIdx.x; i < cs[j + 1]; i += blockDim.x) {
+            const double x = v[i], y = v[n + i], z = v[2 * n + i];
+            const double q2 = x * x + y * y + z * z;
+            m[0] += 1.0;
+            m[1] += x; m[2] += y; m[3] += z;
+            m[4] += x * x; m[5] += y * y; m[6] += z * z;
+            m[7] += x * y; m[8] += x * z; m[9] += y * z;
+            m[10] += q2 * x; m[11] += q2 * y; m[12] += q2 * z;
+            m[13] += q2 * q2;
+        }
+        block_sum<14>(m, red);
+        if (threadIdx.x < 14) out[(int64_t)j * 14 + threadIdx.x] = m[threadIdx.x];
+    }
+}
+
+template <typename R>
+__global__ void k_unsort_scatter(const R *__restrict__ v, const uint32_t *__restrict__ pid,
+                                 const int32_t *__restrict__ cell_of, int64_t n, R *__restrict__ tv,
+                                 int32_t *__restrict__ tc)
+{
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t d = pid[k];
+        if ((int64_t)d >= n) continue;
+        tv[d] = v[k];
+        tv[n + d] = v[n + k];
+        tv[2 * n + d] = v[2 * n + k];
+        tc[d] = cell_of[k];
+    }
+}
+
+template <typename R>
+__global__ void k_unsort_copy(R *__restrict__ v, uint32_t *__restrict__ pid, int32_t *__restrict__ cell_of,
+                              int64_t n, const R *__restrict__ tv, const int32_t *__restrict__ tc)
+{
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        v[k] = tv[k];
+        v[n + k] = tv[n + k];
+        v[2 * n + k] = tv[2 * n + k];
+        cell_of[k] = tc[k];
+        pid[k] = (uint32_t)k;
+    }
+}
+
+int grid_for(int64_t n, int threads, int cap)
+{
+    int64_t g = (n + threads - 1) / threads;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+}  // namespace
+
+int launch_mcc(int dtype, void *v, const uint32_t *pid, int64_t n, uint64_t thr, double mass_ratio,
+               uint64_t seed, uint64_t step, uint8_t *cand_out, hipStream_t st)
+{
+    if (n <= 0) return PIC_OK;
+    const int g = grid_for(n, 256, 65536);
+    if (dtype == PIC_F32)
+        hipLaunchKernelGGL(k_mcc<float>, dim3(g), dim3(256), 0, st, (float *)v, pid, n, thr,
+                           mass_ratio, seed, (uint32_t)step, cand_out);
+    else
+        hipLaunchKernelGGL(k_mcc<double>, dim3(g), dim3(256), 0, st, (double *)v, pid, n, thr,
+                           mass_ratio, seed, (uint32_t)step, cand_out);
+    HIP_OK(hipGetLastError());
+    return PIC_OK;
+}
+
+int launch_philox(uint64_t seed, uint64_t step, uint32_t domain, uint32_t c3, const uint32_t *c0,
+                  int64_t n, uint32_t *out, hipStream_t st)
+{
+    if (n <= 0) return PIC_OK;
+    hipLaunchKernelGGL(k_philox, dim3(grid_for(n, 256, 65536)), dim3(256), 0, st, seed,
+                       (uint32_t)step, domain, c3, c0, n, (uint4 *)out);
+    HIP_OK(hipGetLastError());
+    return PIC_OK;
+}
+
+int launch_moments(int dtype, const void *v, int64_t n, const int32_t *cell_start,
+                   int32_t n_cells, double *out, hipStream_t st)
+{
+    const int g = n_cells < 65536 ? n_cells : 65536;
+    if (dtype == PIC_F32)
+        hipLaunchKernelGGL(k_moments<float>, dim3(g), dim3(256), 0, st, (const float *)v, n,
+                           cell_start, n_cells, out);
+    else
+        hipLaunchKernelGGL(k_moments<double>, dim3(g), dim3(256), 0, st, (const double *)v, n,
+                           cell_start, n_cells, out);
+    HIP_OK(hipGetLastError());
+    return PIC_OK;
+}
+
+int launch_unsort(int dtype, void *v, uint32_t *pid, int32_t *cell_of, int64_t n, void *tmp,
+                  hipStream_t st)
+{
+    if (n <= 0) return PIC_OK;
+    const int g = grid_for(n, 256, 65536);
+    if (dtype == PIC_F32) {
+        float *tv = (float *)tmp;
+        int32_t *tc = (int32_t *)(tv + 3 * n);
+        hipLaunchKernelGGL(k_unsort_scatter<float>, dim3(g), dim3(256), 0, st, (const float *)v,
+                           pid, cell_of, n, tv, tc);
+        hipLaunchKernelGGL(k_unsort_copy<float>, dim3(g), dim3(256), 0, st, (float *)v, pid,
+                           cell_of, n, (const float *)tv, (const int32_t *)tc);
+    } else {
+        double *tv = (double *)tmp;
+        int32_t *tc = (int32_t *)(tv + 3 * n);
+        hipLaunchKernelGGL(k_unsort_scatter<double>, dim3(g), dim3(256), 0, st, (const double *)v,
+                           pid, cell_of, n, tv, tc);
+        hipLaunchKernelGGL(k_unsort_copy<double>, dim3(g), dim3(256), 0, st, (double *)v, pid,
+                           cell_of, n, (const double *)tv, (const int32_t *)tc);
+    }
+    HIP_OK(hipGetLastError());
+    return PIC_OK;
+}

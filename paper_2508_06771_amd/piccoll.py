@@ -1,0 +1,196 @@
+"""ctypes binding of libpiccoll.so -- argument marshalling only.
+
+Every step of the collision path runs in the HIP library; this module checks
+tensor dtypes, devices and contiguity, passes raw device pointers and the
+current torch stream, and turns status codes into exceptions.  There is no
+CPU fallback: if the library is missing the import fails.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libpiccoll.so")
+
+PIC_F32, PIC_F64 = 0, 1
+CONSERVE_FIX = 1 << 0
+FUSE_MCC = 1 << 1
+GATE = 1 << 2
+ASSUME_SORTED = 1 << 3
+MOMENTS = 1 << 4
+
+_STATUS = {0: "PIC_OK", 1: "PIC_ERR_ARG", 2: "PIC_ERR_RANGE", 3: "PIC_ERR_HIP",
+           4: "PIC_ERR_NOMEM", 5: "PIC_ERR_DTYPE", 6: "PIC_ERR_STATE"}
+
+
+class PicError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        super().__init__(f"{where}: {_STATUS.get(status, status)} ({status})")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} not built: run paper_2508_06771_amd/build.py "
+                          "(or __graft_entry__.build())")
+    L = C.CDLL(LIB_PATH)
+    vp, i64, i32, u64, u32, f64 = (C.c_void_p, C.c_int64, C.c_int32, C.c_uint64, C.c_uint32,
+                                   C.c_double)
+    sig = {
+        "pic_create": ([C.POINTER(vp), C.c_int, vp], C.c_int),
+        "pic_destroy": ([vp], None),
+        "pic_strerror": ([C.c_int], C.c_char_p),
+        "pic_sync": ([vp], C.c_int),
+        "pic_set_stream": ([vp, vp], C.c_int),
+        "pic_bin_cells": ([vp, vp, i64, i32, vp, vp], C.c_int),
+        "coulomb_collide": ([vp, C.c_int, vp, vp, vp, i64, i32, f64, f64, vp, u64, u64, u32],
+                            C.c_int),
+        "pic_set_mcc": ([vp, f64, f64, f64], C.c_int),
+        "pic_set_moments_out": ([vp, vp], C.c_int),
+        "mcc_null_collide": ([vp, C.c_int, vp, vp, i64, f64, f64, f64, f64, u64, u64, vp],
+                             C.c_int),
+        "pic_philox": ([vp, u64, u64, u32, u32, vp, i64, vp], C.c_int),
+        "coulomb_pairs": ([vp, vp, vp, i32, u64, u64, vp, vp], C.c_int),
+        "pic_cell_moments": ([vp, C.c_int, vp, i64, vp, i32, vp], C.c_int),
+        "pic_unsort": ([vp, C.c_int, vp, vp, vp, i64], C.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    return L
+
+
+lib = _load()
+
+EXPORTED = ["pic_create", "pic_destroy", "pic_strerror", "pic_sync", "pic_set_stream",
+            "pic_bin_cells", "coulomb_collide", "pic_set_mcc", "pic_set_moments_out",
+            "mcc_null_collide", "pic_philox", "coulomb_pairs", "pic_cell_moments", "pic_unsort"]
+
+
+def _dt(v: torch.Tensor) -> int:
+    if v.dtype == torch.float32:
+        return PIC_F32
+    if v.dtype == torch.float64:
+        return PIC_F64
+    raise TypeError(f"velocities must be float32 or float64, got {v.dtype}")
+
+
+def _p(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensor must be on a HIP device")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t.data_ptr()
+
+
+def _chk(rc: int, where: str):
+    if rc != 0:
+        raise PicError(rc, where)
+
+
+class Context:
+    """One library context bound to a device; calls go on torch's current stream."""
+
+    def __init__(self, device: int = 0):
+        self.device = device
+        h = C.c_void_p()
+        with torch.cuda.device(device):
+            s = torch.cuda.current_stream().cuda_stream
+            _chk(lib.pic_create(C.byref(h), device, C.c_void_p(s)), "pic_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.pic_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _stream(self):
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        _chk(lib.pic_set_stream(self._h, C.c_void_p(s)), "pic_set_stream")
+
+    def sync(self):
+        _chk(lib.pic_sync(self._h), "pic_sync")
+
+    # -------------------------------------------------------------- binning
+    def bin_cells(self, cell_of: torch.Tensor, n_cells: int):
+        assert cell_of.dtype == torch.int32
+        self._stream()
+        n = cell_of.numel()
+        cs = torch.empty(n_cells + 1, dtype=torch.int32, device=cell_of.device)
+        order = torch.empty(max(n, 1), dtype=torch.int32, device=cell_of.device)
+        _chk(lib.pic_bin_cells(self._h, _p(cell_of), n, n_cells, _p(cs), _p(order)),
+             "pic_bin_cells")
+        return cs, order[:n]
+
+    # -------------------------------------------------------------- collision step
+    def set_mcc(self, sigma0: float, n_neutral: float, mass_ratio: float = 0.0):
+        _chk(lib.pic_set_mcc(self._h, sigma0, n_neutral, mass_ratio), "pic_set_mcc")
+
+    def set_moments_out(self, out):
+        if out is not None:
+            assert out.dtype == torch.float64
+        _chk(lib.pic_set_moments_out(self._h, _p(out)), "pic_set_moments_out")
+
+    def coulomb_collide(self, v: torch.Tensor, cell_of: torch.Tensor, pid: torch.Tensor,
+                        n_cells: int, *, dt: float, lnL: float, seed: int, step: int,
+                        density=None, flags: int = 0):
+        assert v.dim() == 2 and v.shape[0] == 3
+        assert cell_of.dtype == torch.int32 and pid.dtype in (torch.int32, torch.uint32)
+        if density is not None:
+            assert density.dtype == torch.float64 and density.numel() == n_cells
+        self._stream()
+        _chk(lib.coulomb_collide(self._h, _dt(v), _p(v), _p(cell_of), _p(pid), v.shape[1],
+                                 n_cells, dt, lnL, _p(density), seed, step, flags),
+             "coulomb_collide")
+
+    def mcc_null_collide(self, v: torch.Tensor, pid: torch.Tensor, *, dt: float, sigma0: float,
+                         n_neutral: float, mass_ratio: float, seed: int, step: int,
+                         candidates: bool = False):
+        self._stream()
+        n = v.shape[1]
+        cand = torch.empty(max(n, 1), dtype=torch.uint8, device=v.device) if candidates else None
+        _chk(lib.mcc_null_collide(self._h, _dt(v), _p(v), _p(pid), n, dt, sigma0, n_neutral,
+                                  mass_ratio, seed, step, _p(cand)), "mcc_null_collide")
+        return cand[:n] if candidates else None
+
+    # -------------------------------------------------------------- test exports
+    def philox(self, seed: int, step: int, domain: int, c0: torch.Tensor, c3: int = 0):
+        self._stream()
+        out = torch.empty((max(c0.numel(), 1), 4), dtype=torch.int32, device=c0.device)
+        _chk(lib.pic_philox(self._h, seed, step, domain, c3, _p(c0), c0.numel(), _p(out)),
+             "pic_philox")
+        return out[:c0.numel()]
+
+    def pairs(self, cell_start: torch.Tensor, pid: torch.Tensor, seed: int, step: int):
+        self._stream()
+        n = pid.numel()
+        srt = torch.empty(max(n, 1), dtype=torch.int32, device=pid.device)
+        par = torch.empty(max(n, 1), dtype=torch.int32, device=pid.device)
+        _chk(lib.coulomb_pairs(self._h, _p(cell_start), _p(pid), cell_start.numel() - 1, seed,
+                               step, _p(srt), _p(par)), "coulomb_pairs")
+        return srt[:n], par[:n]
+
+    def cell_moments(self, v: torch.Tensor, cell_start: torch.Tensor):
+        self._stream()
+        M = cell_start.numel() - 1
+        out = torch.empty((M, 14), dtype=torch.float64, device=v.device)
+        _chk(lib.pic_cell_moments(self._h, _dt(v), _p(v), v.shape[1], _p(cell_start), M,
+                                  _p(out)), "pic_cell_moments")
+        return out
+
+    def unsort(self, v: torch.Tensor, pid: torch.Tensor, cell_of: torch.Tensor):
+        self._stream()
+        _chk(lib.pic_unsort(self._h, _dt(v), _p(v), _p(pid), _p(cell_of), v.shape[1]),
+             "pic_unsort")

@@ -1,0 +1,328 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle.
+
+Bars: bit-exact on Philox words, cell_start, orders, storage permutations,
+pairings and null-collision candidate flags; velocities within 1e-12
+relative in FP64 over 100 steps and within 1e-5 relative per step in FP32
+(metric max_l ||dv||_inf / max(||v||_2, 1e-3 v_th)) from identical inputs.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2508_06771_amd import workloads
+from tests.gpu_util import dev, host, host_u32, rel_err
+
+pytestmark = pytest.mark.gpu
+
+FP32_TOL = 1e-5
+FP64_TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2508_06771_amd import piccoll
+    assert torch.cuda.is_available()
+    c = piccoll.Context(0)
+    yield c
+    c.sync()
+    c.close()
+
+
+# ------------------------------------------------------------------ Philox
+def test_philox_bitexact(ctx):
+    rng = np.random.default_rng(0)
+    c0 = rng.integers(0, 2 ** 32, 1_000_000, dtype=np.uint64).astype(np.uint32)
+    for seed, step, dom, c3 in ((0, 0, 0, 0), (0xDEADBEEF12345678, 77, 1, 0), (5, 2 ** 32 + 3, 3, 7)):
+        g = host_u32(ctx.philox(seed, step, dom, dev(c0), c3))
+        ref = oracle.philox_fill(seed, step, dom, c0[:200_000], c3)
+        assert np.array_equal(g[:200_000], ref)
+    ctx.sync()
+
+
+# ------------------------------------------------------------------ binning
+def bin_case(ctx, cell_of, M):
+    cs, order = ctx.bin_cells(dev(cell_of), M)
+    ctx.sync()
+    rcs, rorder = oracle.bin_cells(cell_of, M)
+    assert np.array_equal(host(cs), rcs)
+    assert np.array_equal(host(order), rorder)
+
+
+@pytest.mark.parametrize("n,M", [(0, 1), (1, 1), (7, 1), (1000, 1), (5, 3), (1000, 7),
+                                 (4097, 64), (100_000, 4096), (300_000, 70_000), (50_000, 2)])
+def test_bin_random(ctx, n, M):
+    rng = np.random.default_rng(n + M)
+    bin_case(ctx, rng.integers(0, M, n).astype(np.int32), M)
+
+
+def test_bin_sorted_and_empty_cells(ctx):
+    cell = np.repeat(np.arange(0, 100, 3, dtype=np.int32), 17)   # every third cell used
+    bin_case(ctx, cell, 101)
+    bin_case(ctx, cell[::-1].copy(), 101)
+    bin_case(ctx, np.full(5000, 99, np.int32), 100)
+
+
+def test_bin_workloads(ctx):
+    for w in (workloads.c1(0), workloads.c2(0, n_cells=128, per_cell=2000)):
+        bin_case(ctx, w.cell_of, w.n_cells)
+
+
+def test_bin_out_of_range_reported(ctx):
+    from paper_2508_06771_amd.piccoll import PicError
+    ctx.bin_cells(dev(np.array([0, 5, 1], np.int32)), 3)
+    with pytest.raises(PicError) as e:
+        ctx.sync()
+    assert e.value.status == 2
+    ctx.sync()   # latched error was cleared
+
+
+# ------------------------------------------------------------------ pairing
+@pytest.mark.parametrize("sizes", [
+    [0, 1, 2, 3, 5, 64, 65, 255, 256, 257, 511, 512, 513],
+    [2048, 2049, 4096, 4097, 6000, 10240],
+    [10241, 20000, 3, 1, 0],
+])
+def test_pairs_bitexact(ctx, sizes):
+    rng = np.random.default_rng(len(sizes))
+    sizes = np.array(sizes)
+    cs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32)
+    n = int(cs[-1])
+    pid = rng.permutation(4 * n + 8)[:n].astype(np.uint32)
+    for step in (0, 9):
+        srt, par = ctx.pairs(dev(cs), dev(pid), seed=3, step=step)
+        ctx.sync()
+        rs, rp = oracle.pairs(cs, pid, seed=3, step=step)
+        assert np.array_equal(host(srt), rs)
+        assert np.array_equal(host(par), rp)
+
+
+def test_pairs_tie_break(ctx):
+    pids = np.arange(300000, dtype=np.uint32)
+    keys = oracle.philox_fill(0, 0, 0, pids)[:, 0]
+    o = np.argsort(keys, kind="stable")
+    d = np.flatnonzero(keys[o][1:] == keys[o][:-1])
+    a, b = sorted([int(o[d[0]]), int(o[d[0] + 1])])
+    pid = np.array([b, 11, a, 12, 13], np.uint32)
+    cs = np.array([0, 5], np.int32)
+    srt, par = ctx.pairs(dev(cs), dev(pid), seed=0, step=0)
+    rs, rp = oracle.pairs(cs, pid, 0, 0)
+    assert np.array_equal(host(srt), rs) and np.array_equal(host(par), rp)
+
+
+# ------------------------------------------------------------------ full step
+def run_gpu_step(ctx, w, v, dtype, step, flags=0, seed=0, density=None, mcc=False):
+    import torch
+    from paper_2508_06771_amd import piccoll
+    tv = dev(v, torch.float32 if dtype == "f32" else torch.float64)
+    tc, tp = dev(w.cell_of), dev(w.pid)
+    if mcc:
+        ctx.set_mcc(w.sigma0, w.n_neutral, w.mass_ratio)
+        flags |= piccoll.FUSE_MCC
+    dens = None if density is None else dev(density)
+    ctx.coulomb_collide(tv, tc, tp, w.n_cells, dt=w.dt, lnL=w.lnL, seed=seed, step=step,
+                        density=dens, flags=flags)
+    ctx.sync()
+    return host(tv).astype(np.float64), host(tc), host_u32(tp)
+
+
+def run_oracle_step(w, v64, step, seed=0, density=None, mcc=False, conserve=False, cell=None,
+                    pid=None):
+    v = np.ascontiguousarray(v64, dtype=np.float64).copy()
+    c = (w.cell_of if cell is None else cell).copy()
+    p = (w.pid if pid is None else pid).copy()
+    oracle.step(v, c, p, w.n_cells, dt=w.dt, lnL=w.lnL, seed=seed, step=step, density=density,
+                mcc=mcc, sigma0=w.sigma0, n_neutral=w.n_neutral, mass_ratio=w.mass_ratio,
+                conserve=conserve)
+    return v, c, p
+
+
+def test_fp64_c1_100_steps(ctx):
+    """c1 (64 x 256, FP64): 100 steps on the GPU match 100 oracle steps."""
+    import torch
+    w = workloads.c1(0)
+    tv = dev(w.v, torch.float64)
+    tc, tp = dev(w.cell_of), dev(w.pid)
+    v, c, p = w.v.copy(), w.cell_of.copy(), w.pid.copy()
+    for k in range(100):
+        ctx.coulomb_collide(tv, tc, tp, w.n_cells, dt=w.dt, lnL=w.lnL, seed=0, step=k)
+        oracle.step(v, c, p, w.n_cells, dt=w.dt, lnL=w.lnL, seed=0, step=k)
+    ctx.sync()
+    assert np.array_equal(host(tc), c) and np.array_equal(host_u32(tp), p)
+    err = rel_err(host(tv), v)
+    assert err < FP64_TOL, err
+
+
+@pytest.mark.parametrize("mcc", [False, True])
+def test_fp32_step_c2_small(ctx, mcc):
+    """c2 shape at 96 cells x 10,000 (a tile-multiple plus ragged tails via the
+    random storage order), one FP32 step from identical input."""
+    w = workloads.c2(0, n_cells=96, per_cell=10000)
+    for step in (0, 1):
+        vg, cg, pg = run_gpu_step(ctx, w, w.v, "f32", step, mcc=mcc)
+        vr, cr, pr = run_oracle_step(w, w.v.astype(np.float64), step, mcc=mcc)
+        assert np.array_equal(cg, cr) and np.array_equal(pg, pr)
+        assert rel_err(vg, vr) < FP32_TOL, rel_err(vg, vr)
+
+
+def ragged_workload(seed, sizes, dtype=np.float32):
+    rng = np.random.default_rng(seed)
+    sizes = np.asarray(sizes, dtype=np.int64)
+    v = workloads.maxwellian_beam(rng, sizes, dtype=dtype)
+    return workloads._finish(rng, "ragged", v, sizes, dtype, mcc=True)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_ragged_cells_all_classes(ctx, dtype):
+    """Cell sizes spanning every size class, empty and single-member cells and
+    cells beyond the largest LDS class, with density and MCC."""
+    sizes = [0, 1, 2, 3, 17, 64, 511, 512, 513, 2047, 2049, 4095, 4097, 6143, 6145, 10239,
+             10241, 25000, 0, 1]
+    w = ragged_workload(7, sizes, np.float32 if dtype == "f32" else np.float64)
+    dens = np.linspace(0.5, 2.0, w.n_cells)
+    vg, cg, pg = run_gpu_step(ctx, w, w.v, dtype, 3, density=dens, mcc=True)
+    vr, cr, pr = run_oracle_step(w, w.v.astype(np.float64), 3, density=dens, mcc=True)
+    assert np.array_equal(cg, cr) and np.array_equal(pg, pr)
+    tol = FP32_TOL if dtype == "f32" else FP64_TOL
+    assert rel_err(vg, vr) < tol, rel_err(vg, vr)
+
+
+def test_conservation_correction_fp32(ctx):
+    from paper_2508_06771_amd import piccoll
+    w = workloads.c2(1, n_cells=32, per_cell=10000)
+    vg, cg, _ = run_gpu_step(ctx, w, w.v, "f32", 0, flags=piccoll.CONSERVE_FIX)
+    vr, cr, _ = run_oracle_step(w, w.v.astype(np.float64), 0, conserve=True)
+    assert rel_err(vg, vr) < FP32_TOL
+    # FP64 sums of the FP32 output equal the sums of the (sorted) input
+    cs, order = oracle.bin_cells(w.cell_of, w.n_cells)
+    m0 = oracle.cell_moments(np.ascontiguousarray(w.v.astype(np.float64)[:, order]), cs)
+    m1 = oracle.cell_moments(vg, cs)
+    e0 = m0[:, 4] + m0[:, 5] + m0[:, 6]
+    e1 = m1[:, 4] + m1[:, 5] + m1[:, 6]
+    assert np.max(np.abs(e1 - e0) / e0) < 2e-7
+    assert np.max(np.abs(m1[:, 1:4] - m0[:, 1:4])) < 2e-7 * np.sqrt(e0.max())
+
+
+def test_assume_sorted_and_determinism(ctx):
+    import torch
+    from paper_2508_06771_amd import piccoll
+    w = workloads.c2(2, n_cells=64, per_cell=3000)
+    outs = []
+    for _ in range(2):
+        tv, tc, tp = dev(w.v, torch.float32), dev(w.cell_of), dev(w.pid)
+        ctx.coulomb_collide(tv, tc, tp, w.n_cells, dt=w.dt, lnL=w.lnL, seed=1, step=0)
+        ctx.coulomb_collide(tv, tc, tp, w.n_cells, dt=w.dt, lnL=w.lnL, seed=1, step=1,
+                            flags=piccoll.ASSUME_SORTED)
+        ctx.sync()
+        outs.append(host(tv).tobytes())
+    assert outs[0] == outs[1]
+    # asserting sorted storage that is not sorted is reported
+    tv, tc, tp = dev(w.v, torch.float32), dev(w.cell_of), dev(w.pid)
+    ctx.coulomb_collide(tv, tc, tp, w.n_cells, dt=w.dt, lnL=w.lnL, seed=1, step=0,
+                        flags=piccoll.ASSUME_SORTED)
+    with pytest.raises(piccoll.PicError) as e:
+        ctx.sync()
+    assert e.value.status == 6
+    assert np.array_equal(host(tv), w.v)    # nothing was modified
+
+
+def test_out_of_range_cell_reported(ctx):
+    import torch
+    from paper_2508_06771_amd import piccoll
+    w = workloads.c1(0, n_cells=4, per_cell=16)
+    bad = w.cell_of.copy()
+    bad[5] = 4
+    tv, tc, tp = dev(w.v, torch.float64), dev(bad), dev(w.pid)
+    ctx.coulomb_collide(tv, tc, tp, w.n_cells, dt=w.dt, lnL=w.lnL, seed=0, step=0)
+    with pytest.raises(piccoll.PicError) as e:
+        ctx.sync()
+    assert e.value.status == 2
+    with pytest.raises(piccoll.PicError):
+        ctx.coulomb_collide(tv, tc, tp, w.n_cells, dt=-1.0, lnL=w.lnL, seed=0, step=0)
+
+
+# ------------------------------------------------------------------ MCC alone
+@pytest.mark.parametrize("dtype,mr", [("f32", 0.0), ("f64", 0.0), ("f32", 1.373e-5), ("f64", 0.01)])
+def test_mcc_standalone(ctx, dtype, mr):
+    import torch
+    w = workloads.c2(3, n_cells=16, per_cell=5000)
+    tv = dev(w.v, torch.float32 if dtype == "f32" else torch.float64)
+    cand = ctx.mcc_null_collide(tv, dev(w.pid), dt=w.dt, sigma0=w.sigma0, n_neutral=1.0,
+                                mass_ratio=mr, seed=4, step=11, candidates=True)
+    ctx.sync()
+    v = w.v.astype(np.float64).copy()
+    rc = oracle.mcc(v, w.pid, w.dt, w.sigma0, 1.0, mr, 4, 11, return_flags=True)
+    assert np.array_equal(host(cand), rc)
+    tol = FP32_TOL if dtype == "f32" else 1e-14
+    assert rel_err(host(tv).astype(np.float64), v) < tol
+
+
+def test_fused_mcc_equals_standalone(ctx):
+    """Coulomb with fused MCC == Coulomb then stand-alone MCC (same kernels'
+    arithmetic for the scattering)."""
+    import torch
+    from paper_2508_06771_amd import piccoll
+    w = workloads.c2(4, n_cells=16, per_cell=4000)
+    tv, tc, tp = dev(w.v, torch.float32), dev(w.cell_of), dev(w.pid)
+    ctx.set_mcc(w.sigma0, 1.0, 0.0)
+    ctx.coulomb_collide(tv, tc, tp, w.n_cells, dt=w.dt, lnL=w.lnL, seed=0, step=5,
+                        flags=piccoll.FUSE_MCC)
+    tv2, tc2, tp2 = dev(w.v, torch.float32), dev(w.cell_of), dev(w.pid)
+    ctx.coulomb_collide(tv2, tc2, tp2, w.n_cells, dt=w.dt, lnL=w.lnL, seed=0, step=5)
+    ctx.mcc_null_collide(tv2, tp2, dt=w.dt, sigma0=w.sigma0, n_neutral=1.0, mass_ratio=0.0,
+                         seed=0, step=5)
+    ctx.sync()
+    assert np.array_equal(host(tv), host(tv2))
+
+
+# ------------------------------------------------------------------ moments / unsort
+def test_moments(ctx):
+    import torch
+    from paper_2508_06771_amd import piccoll
+    w = ragged_workload(9, [0, 1, 5, 600, 3000, 12000], np.float64)
+    cs, order = oracle.bin_cells(w.cell_of, w.n_cells)
+    vs = np.ascontiguousarray(w.v[:, order])
+    m = host(ctx.cell_moments(dev(vs, torch.float64), dev(cs)))
+    ctx.sync()
+    ref = oracle.cell_moments(vs, cs)
+    assert np.allclose(m, ref, rtol=1e-12, atol=1e-12)
+    # fused into the step: moments of the post-step state
+    out = torch.zeros((w.n_cells, 14), dtype=torch.float64, device="cuda")
+    ctx.set_moments_out(out)
+    vg, cg, pg = run_gpu_step(ctx, w, w.v, "f64", 2, flags=piccoll.MOMENTS)
+    ctx.set_moments_out(None)
+    assert np.allclose(host(out), oracle.cell_moments(vg, cs), rtol=1e-12, atol=1e-11)
+
+
+def test_unsort_restores_pid_order(ctx):
+    import torch
+    w = workloads.c2(5, n_cells=8, per_cell=1000)
+    tv, tc, tp = dev(w.v, torch.float32), dev(w.cell_of), dev(w.pid)
+    ctx.coulomb_collide(tv, tc, tp, w.n_cells, dt=w.dt, lnL=w.lnL, seed=0, step=0)
+    ctx.unsort(tv, tp, tc)
+    ctx.sync()
+    assert np.array_equal(host_u32(tp), np.arange(w.n, dtype=np.uint32))
+    assert np.array_equal(host(tc), w.cell_of)
+    vr, cr, pr = run_oracle_step(w, w.v.astype(np.float64), 0)
+    back = np.empty_like(vr)
+    back[:, pr] = vr
+    assert rel_err(host(tv).astype(np.float64), back) < FP32_TOL
+
+
+# ------------------------------------------------------------------ full size, sampled
+def test_c2_full_size_sampled_cells(ctx):
+    """The full c2 workload (4096 x 10,000, FP32, Coulomb + MCC) in one GPU step;
+    16 sampled cells re-run by the oracle (cells are independent)."""
+    w = workloads.c2(0)
+    vg, cg, pg = run_gpu_step(ctx, w, w.v, "f32", 0, mcc=True)
+    rng = np.random.default_rng(1)
+    cells = np.sort(rng.choice(w.n_cells, 16, replace=False))
+    sel = np.isin(w.cell_of, cells)
+    remap = np.full(w.n_cells, -1, np.int32)
+    remap[cells] = np.arange(cells.size, dtype=np.int32)
+    sub = workloads.Workload("sub", np.ascontiguousarray(w.v[:, sel]), remap[w.cell_of[sel]],
+                             w.pid[sel].copy(), cells.size, mcc=True)
+    vr, cr, pr = run_oracle_step(sub, sub.v.astype(np.float64), 0, mcc=True)
+    gsel = np.isin(cg, cells)
+    assert np.array_equal(pg[gsel], pr)
+    assert rel_err(vg[:, gsel], vr) < FP32_TOL
