@@ -136,6 +136,20 @@ int mcc_null_collide(pic_ctx *ctx, int dtype, void *v, const uint32_t *pid, int6
  * (layout of pic_cell_moments) when PIC_MOMENTS is passed; NULL clears it. */
 int pic_set_moments_out(pic_ctx *ctx, double *out);
 
+/* ---------------------------------------------------------------- measurement */
+
+/* on != 0: record HIP events around the library's kernel launches on the
+ * context's stream (for benchmarks; adds two event records per launch). */
+int pic_time_kernels(pic_ctx *ctx, int on);
+/* Waits for the recorded events and returns, per slot, the summed elapsed
+ * milliseconds ms[16] and launch counts count[16] since the previous call,
+ * then forgets them.  Slots: 0-3 collide pass of the LDS size classes
+ * (cells of at most 512 / 2048 / 4096 / 10240 members in binary32,
+ * 512 / 2048 / 4096 / 6144 in binary64), 4 cells beyond those, 5 order check
+ * and cell starts, 6 work queue, 7 re-binning passes, 8 stand-alone
+ * null-collision step. */
+int pic_kernel_times(pic_ctx *ctx, double *ms, int64_t *count);
+
 /* ---------------------------------------------------------------- test exports */
 
 /* out[4*i + w] = word w of Philox4x32-10 with counter (c0[i], lo32(step),

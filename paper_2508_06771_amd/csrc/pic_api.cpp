@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <new>
+#include <vector>
 
 #include "pic_internal.hpp"
 
@@ -19,6 +20,42 @@ struct pic_ctx {
     bool mcc_set = false;
     double *moments_out = nullptr;
 };
+
+namespace {
+
+struct TimedLaunch {
+    int slot;
+    hipEvent_t beg, end;
+};
+// The context whose launches are being timed (calls on one context are issued
+// from one host thread).
+struct Timing {
+    bool on = false;
+    std::vector<TimedLaunch> open;
+};
+Timing g_timing;
+
+}  // namespace
+
+void ktime_begin(int slot, hipStream_t st)
+{
+    if (!g_timing.on) return;
+    TimedLaunch t;
+    t.slot = slot;
+    if (hipEventCreate(&t.beg) != hipSuccess || hipEventCreate(&t.end) != hipSuccess) return;
+    (void)hipEventRecord(t.beg, st);
+    g_timing.open.push_back(t);
+}
+
+void ktime_end(int slot, hipStream_t st)
+{
+    if (!g_timing.on) return;
+    for (auto it = g_timing.open.rbegin(); it != g_timing.open.rend(); ++it)
+        if (it->slot == slot) {
+            (void)hipEventRecord(it->end, st);
+            return;
+        }
+}
 
 namespace {
 
@@ -225,6 +262,35 @@ int pic_set_mcc(pic_ctx *c, double sigma0, double n_neutral, double mass_ratio)
     return PIC_OK;
 }
 
+int pic_time_kernels(pic_ctx *c, int on)
+{
+    if (!c) return PIC_ERR_ARG;
+    g_timing.on = on != 0;
+    return PIC_OK;
+}
+
+int pic_kernel_times(pic_ctx *c, double *ms, int64_t *count)
+{
+    if (!c || !ms || !count) return PIC_ERR_ARG;
+    CK(hipSetDevice(c->device));
+    for (int s = 0; s < KT_SLOTS; ++s) {
+        ms[s] = 0.0;
+        count[s] = 0;
+    }
+    for (auto &t : g_timing.open) {
+        float e = 0.0f;
+        if (hipEventSynchronize(t.end) == hipSuccess && hipEventElapsedTime(&e, t.beg, t.end) == hipSuccess &&
+            t.slot >= 0 && t.slot < KT_SLOTS) {
+            ms[t.slot] += e;
+            count[t.slot] += 1;
+        }
+        (void)hipEventDestroy(t.beg);
+        (void)hipEventDestroy(t.end);
+    }
+    g_timing.open.clear();
+    return PIC_OK;
+}
+
 int pic_set_moments_out(pic_ctx *c, double *out)
 {
     if (!c) return PIC_ERR_ARG;
@@ -323,8 +389,11 @@ static int collide_common(pic_ctx *c, int dtype, void *v, int32_t *cell_of, uint
 
     RC(launch_reset_flags(c->flags, c->stream));
     const bool assume = (flags & PIC_ASSUME_SORTED) != 0;
+    ktime_begin(KT_CHECK, c->stream);
     RC(launch_bin_check(cell_of, n, n_cells, cs, c->flags, assume ? 2 : 1, nullptr, c->stream));
+    ktime_end(KT_CHECK, c->stream);
     if (!assume && n > 1 && n_cells > 1) {
+        ktime_begin(KT_SORT, c->stream);
         SortStreams caller, tmp;
         memset(&caller, 0, sizeof(caller));
         memset(&tmp, 0, sizeof(tmp));
@@ -348,9 +417,12 @@ static int collide_common(pic_ctx *c, int dtype, void *v, int32_t *cell_of, uint
         }
         RC(sort_by_cell(c, caller, tmp, n, n_cells, bs, &c->flags->unsorted));
         RC(launch_bin_check(cell_of, n, n_cells, cs, c->flags, 0, &c->flags->unsorted, c->stream));
+        ktime_end(KT_SORT, c->stream);
     }
     const ClassCaps caps = collide_caps(dtype, c->lds_max);
+    ktime_begin(KT_QUEUE, c->stream);
     RC(launch_build_queue(cs, n_cells, caps, lists, c->flags, c->stream));
+    ktime_end(KT_QUEUE, c->stream);
 
     CollideArgs a;
     memset(&a, 0, sizeof(a));
@@ -391,8 +463,11 @@ int mcc_null_collide(pic_ctx *c, int dtype, void *v, const uint32_t *pid, int64_
         return PIC_ERR_ARG;
     if (n > 0 && (!v || !pid)) return PIC_ERR_ARG;
     CK(hipSetDevice(c->device));
-    return launch_mcc(dtype, v, pid, n, mcc_threshold(dt, sigma0, n_neutral), mass_ratio, seed, step,
-                      candidate_out, c->stream);
+    ktime_begin(KT_MCC, c->stream);
+    const int rc = launch_mcc(dtype, v, pid, n, mcc_threshold(dt, sigma0, n_neutral), mass_ratio,
+                              seed, step, candidate_out, c->stream);
+    ktime_end(KT_MCC, c->stream);
+    return rc;
 }
 
 int pic_philox(pic_ctx *c, uint64_t seed, uint64_t step, uint32_t domain, uint32_t c3,

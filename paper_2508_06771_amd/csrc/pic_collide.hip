@@ -714,7 +714,9 @@ int launch_class(const CollideArgs &a, const int32_t *list, int cls, int blocks,
                                    (int)lds));
         attr_done = true;
     }
+    ktime_begin(KT_CLASS0 + cls, st);
     hipLaunchKernelGGL(kern, dim3(blocks), dim3(T), lds, st, a, list, cls);
+    ktime_end(KT_CLASS0 + cls, st);
     HIP_OK(hipGetLastError());
     return PIC_OK;
 }
@@ -727,8 +729,10 @@ int launch_all(const CollideArgs &a, const int32_t *lists, int32_t n_cells, int 
     int rc;
     const int64_t M = n_cells;
     // largest cells first so the small ones fill the tail
+    ktime_begin(KT_HUGE, st);
     hipLaunchKernelGGL((k_collide_huge<R, PAIRS>), dim3(num_cu), dim3(1024), 0, st, a, lists + 4 * M,
                        4, hs);
+    ktime_end(KT_HUGE, st);
     HIP_OK(hipGetLastError());
     if ((rc = launch_class<R, C::T3, C::K3, PAIRS>(a, lists + 3 * M, 3, 2 * num_cu, st))) return rc;
     if ((rc = launch_class<R, C::T2, C::K2, PAIRS>(a, lists + 2 * M, 2, 2 * num_cu, st))) return rc;

@@ -178,6 +178,14 @@ struct RadixPass {
     const int *gate;    // non-null: run only if *gate != 0
 };
 
+// Optional timing of selected launches with HIP events on the launch stream
+// (enabled by pic_time_kernels; no cost when off).  Slots: 0-3 LDS classes of
+// the collide pass, 4 multi-block class, 5 order check, 6 work queue,
+// 7 re-binning passes, 8 stand-alone null-collision step.
+enum { KT_CLASS0 = 0, KT_HUGE = 4, KT_CHECK = 5, KT_QUEUE = 6, KT_SORT = 7, KT_MCC = 8, KT_SLOTS = 16 };
+void ktime_begin(int slot, hipStream_t st);
+void ktime_end(int slot, hipStream_t st);
+
 struct BinScratch {
     uint32_t *hist;     // (1 << bits) * nblocks
     uint32_t *bsum;     // scan block sums

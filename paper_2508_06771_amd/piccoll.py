@@ -56,6 +56,8 @@ def _load():
         "coulomb_pairs": ([vp, vp, vp, i32, u64, u64, vp, vp], C.c_int),
         "pic_cell_moments": ([vp, C.c_int, vp, i64, vp, i32, vp], C.c_int),
         "pic_unsort": ([vp, C.c_int, vp, vp, vp, i64], C.c_int),
+        "pic_time_kernels": ([vp, C.c_int], C.c_int),
+        "pic_kernel_times": ([vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -68,7 +70,10 @@ lib = _load()
 
 EXPORTED = ["pic_create", "pic_destroy", "pic_strerror", "pic_sync", "pic_set_stream",
             "pic_bin_cells", "coulomb_collide", "pic_set_mcc", "pic_set_moments_out",
-            "mcc_null_collide", "pic_philox", "coulomb_pairs", "pic_cell_moments", "pic_unsort"]
+            "mcc_null_collide", "pic_philox", "coulomb_pairs", "pic_cell_moments", "pic_unsort",
+            "pic_time_kernels", "pic_kernel_times"]
+
+KT_SLOTS = ["class0", "class1", "class2", "class3", "huge", "check", "queue", "sort", "mcc"]
 
 
 def _dt(v: torch.Tensor) -> int:
@@ -164,6 +169,17 @@ class Context:
         _chk(lib.mcc_null_collide(self._h, _dt(v), _p(v), _p(pid), n, dt, sigma0, n_neutral,
                                   mass_ratio, seed, step, _p(cand)), "mcc_null_collide")
         return cand[:n] if candidates else None
+
+    # -------------------------------------------------------------- measurement
+    def time_kernels(self, on: bool):
+        _chk(lib.pic_time_kernels(self._h, int(on)), "pic_time_kernels")
+
+    def kernel_times(self):
+        """{slot: (total_ms, launches)} since the previous call."""
+        ms = (C.c_double * 16)()
+        cnt = (C.c_int64 * 16)()
+        _chk(lib.pic_kernel_times(self._h, ms, cnt), "pic_kernel_times")
+        return {KT_SLOTS[s]: (ms[s], cnt[s]) for s in range(len(KT_SLOTS)) if cnt[s]}
 
     # -------------------------------------------------------------- test exports
     def philox(self, seed: int, step: int, domain: int, c0: torch.Tensor, c3: int = 0):
