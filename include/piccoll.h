@@ -113,6 +113,20 @@ int coulomb_collide(pic_ctx *ctx, int dtype, void *v, int32_t *cell_of, uint32_t
                     int64_t n, int32_t n_cells, double dt, double lnLambda,
                     const double *density, uint64_t seed, uint64_t step, uint32_t flags);
 
+/* nsteps consecutive steps step0, step0+1, ... with the arguments of
+ * coulomb_collide (the operator split of the PIC scheme runs several collision
+ * steps between field solves, paragraph "Operator Splitting Algorithms").  The
+ * first step re-bins unsorted storage; the collision step never changes cell
+ * membership, so the following steps run as one captured HIP graph of a
+ * steady-state step (order check, work queue, collide pass, step counter
+ * increment in device memory) replayed nsteps - 1 times.  The graph is kept in
+ * the context and captured again when any argument, the MCC parameters, the
+ * moments buffer or the scratch memory changes.  A violated order (cell ids
+ * changed between replays) latches PIC_ERR_STATE and leaves v unchanged. */
+int pic_run_steps(pic_ctx *ctx, int dtype, void *v, int32_t *cell_of, uint32_t *pid, int64_t n,
+                  int32_t n_cells, double dt, double lnLambda, const double *density,
+                  uint64_t seed, uint64_t step0, int64_t nsteps, uint32_t flags);
+
 /* Parameters of the fused null-collision step (PIC_FUSE_MCC):
  * sigma(E) = sigma0 E^-1/2 with E = |v|^2/2, neutral density n_neutral,
  * electron/neutral mass ratio mass_ratio (>= 0, < 0.5), same dt as Coulomb. */
@@ -135,6 +149,71 @@ int mcc_null_collide(pic_ctx *ctx, int dtype, void *v, const uint32_t *pid, int6
 /* Device buffer of n_cells * 14 doubles receiving the post-step moment sums
  * (layout of pic_cell_moments) when PIC_MOMENTS is passed; NULL clears it. */
 int pic_set_moments_out(pic_ctx *ctx, double *out);
+
+/* ---------------------------------------------------------------- learned gate */
+/* A per-cell network decides which cells may defer their Coulomb collision
+ * (sub-cycling): a deferred cell keeps its velocities apart from null
+ * collisions, counts k, and later collides once with dt_eff = (k + 1) dt.
+ * Not part of the paper; its method is the plain operator, which stays the
+ * fallback and the judge. */
+
+#define PIC_MLP_PARAMS 4801
+/* Parameter layout (binary32): W1[8][64] at 0, b1[64] at 512, W2[64][64] at
+ * 576, b2[64] at 4672, W3[64] at 4736, b3 at 4800; logit =
+ * W3 . relu(W2^T relu(W1^T x + b1) + b2) + b3, probability = logistic(logit).
+ * bf16 != 0: products of bfloat16-rounded weights, inputs and activations
+ * with binary32 accumulation. */
+
+/* Features from per-cell raw sums (layout of pic_cell_moments), feat[8*j..]:
+ * ln N, ln T, T_xx/T, T_yy/T, T_zz/T, ||offdiag T||_F/T, |q|/(N T^1.5),
+ * <|c|^4>/(15 T^2) - 1 with c = v - V, T_ab = <c_a c_b>, T = tr/3,
+ * q = 1/2 sum |c|^2 c.  Cells with N < 2 or T <= 0: zeros, valid[j] = 0
+ * (valid nullable). */
+int pic_features(pic_ctx *ctx, const double *moments, int32_t n_cells, float *feat, uint8_t *valid);
+
+/* Expected relative one-step relaxation of each cell's temperature tensor
+ * (storage in cell order): r_j = ||(1/K) sum over K re-pairings (domain 3,
+ * c3 = replica) of sum_pairs 1/4 h(s^2) (|u|^2 I - 3 u u^T)||_F / (N_j T_j),
+ * h(s^2) = E[sin^2 Theta] of the Takizuka & Abe angle, s^2 from dt times
+ * dt_scale[j] (nullable => 1).  Cells with fewer than 2 members: 0. */
+int pic_relaxation(pic_ctx *ctx, int dtype, const void *v, int64_t n, const int32_t *cell_start,
+                   const uint32_t *pid, int32_t n_cells, double dt, double lnLambda,
+                   const double *density, const double *dt_scale, uint64_t seed, uint64_t step,
+                   int32_t replicas, double *r_out);
+
+/* prob[b] = network output for x[8*b .. 8*b+7]. */
+int pic_mlp_forward(pic_ctx *ctx, const float *params, const float *x, int32_t batch, int bf16,
+                    float *prob);
+/* Gradient of the mean binary cross-entropy of the logits against y[batch]
+ * (0/1) with respect to the 4801 parameters; loss (device, nullable) gets the
+ * mean loss.  Summation order is fixed (bitwise reproducible). */
+int pic_mlp_grad(pic_ctx *ctx, const float *params, const float *x, const float *y, int32_t batch,
+                 int bf16, float *grad, float *loss);
+/* pic_mlp_grad followed by one Adam step (beta1 0.9, beta2 0.999, eps 1e-8,
+ * bias-corrected with step t >= 1) on the binary32 master parameters. */
+int pic_mlp_train_step(pic_ctx *ctx, float *params, float *adam_m, float *adam_v, int32_t t,
+                       float lr, const float *x, const float *y, int32_t batch, int bf16,
+                       float *loss);
+
+/* Enables PIC_GATE steps: params (device, kept by pointer), skip when the
+ * probability exceeds threshold and the cell has deferred fewer than k_max
+ * steps; a judge_fraction of cells (domain-2 draw per cell and step) always
+ * collides and is scored: a judged cell the network wanted to skip is a false
+ * skip if its relaxation (replicas re-pairings) reaches tolerance.  When more
+ * than 10% of at least 20 judged skips are false the gate switches itself off
+ * (all cells collide).  The first gated step collides every cell and records
+ * the moments the next step decides from. */
+int pic_gate_config(pic_ctx *ctx, const float *params, float threshold, int32_t k_max,
+                    double judge_fraction, double tolerance, int32_t replicas, int bf16);
+/* Forgets deferred counts, moments and statistics. */
+int pic_gate_reset(pic_ctx *ctx);
+/* Host int64 out[8]: gated steps, cells skipped, cells collided, cells
+ * judged, judged cells the network wanted to skip, false skips, switched off,
+ * moments present.  Synchronises. */
+int pic_gate_stats(pic_ctx *ctx, int64_t *out);
+/* Device copies of the last gate decisions (each nullable): skip[n_cells],
+ * k_acc[n_cells], prob[n_cells], moments[14 n_cells]. */
+int pic_gate_state(pic_ctx *ctx, uint8_t *skip, int32_t *k_acc, float *prob, double *moments);
 
 /* ---------------------------------------------------------------- measurement */
 

@@ -148,7 +148,88 @@ def expected_pair_change(u: np.ndarray, s2: np.ndarray) -> np.ndarray:
     return 0.25 * h[:, None, None] * t
 
 
+def relaxation(v, cell_start, pid, *, dt, lnL, seed, step, replicas, density=None,
+               dt_scale=None):
+    """r_j = ||(1/K) sum over K re-pairings of sum_pairs 1/4 h(s2) (|u|^2 I - 3 u u^T)||_F
+    / (N_j T_j), with the oracle's re-pairings (domain 3, c3 = replica) and h by
+    quadrature.  Plain loops; meant for small inputs."""
+    import oracle
+    M = cell_start.size - 1
+    acc = np.zeros((M, 3, 3))
+    for rep in range(replicas):
+        u, cell = oracle.repair_u(v, cell_start, pid, seed, step, rep)
+        for k in range(u.shape[0]):
+            j = int(cell[k])
+            dens = 1.0 if density is None else float(density[j])
+            dts = 1.0 if dt_scale is None else float(dt_scale[j])
+            uu = float(u[k] @ u[k])
+            if uu == 0.0:
+                continue
+            s2 = 8 * math.pi * dens * lnL * dt * dts / uu ** 1.5
+            acc[j] += expected_pair_change(u[k:k + 1], np.array([s2]))[0]
+    r = np.zeros(M)
+    for j in range(M):
+        lo, hi = int(cell_start[j]), int(cell_start[j + 1])
+        N = hi - lo
+        if N < 2:
+            continue
+        c = v[:, lo:hi] - v[:, lo:hi].mean(axis=1, keepdims=True)
+        T = float((c * c).sum()) / (3 * N)
+        r[j] = np.linalg.norm(acc[j] / replicas) / (N * T)
+    return r
+
+
 # ---------------------------------------------------------------- gate MLP (FP64)
+
+
+def bf16_round(a):
+    """Round to bfloat16 (nearest, ties to even) via binary32, returned as float64."""
+    f = np.asarray(a, dtype=np.float64).astype(np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def unpack_params(flat):
+    flat = np.asarray(flat, dtype=np.float64)
+    W1 = flat[0:512].reshape(8, 64)
+    b1 = flat[512:576]
+    W2 = flat[576:4672].reshape(64, 64)
+    b2 = flat[4672:4736]
+    W3 = flat[4736:4800].reshape(64, 1)
+    b3 = flat[4800:4801]
+    return [W1, b1, W2, b2, W3, b3]
+
+
+def pack_params(params):
+    return np.concatenate([p.reshape(-1) for p in params])
+
+
+def mlp_bce_grad_bf16(flat, x, y):
+    """Mean BCE and gradient with the products of bfloat16-rounded operands
+    (weights, inputs, activations and back-propagated deltas), FP64 arithmetic."""
+    W1, b1, W2, b2, W3, b3 = unpack_params(flat)
+    r = bf16_round
+    W1r, W2r, W3r = r(W1), r(W2), r(W3)
+    B = x.shape[0]
+    xr = r(x)
+    z1 = xr @ W1r + b1
+    a1 = r(np.maximum(z1, 0.0))
+    z2 = a1 @ W2r + b2
+    a2 = r(np.maximum(z2, 0.0))
+    z3 = (a2 @ W3r + b3)[:, 0]
+    p = 1.0 / (1.0 + np.exp(-z3))
+    loss = np.mean(np.maximum(z3, 0) - z3 * y + np.log1p(np.exp(-np.abs(z3))))
+    d3 = r((p - y) / B)
+    gW3 = a2.T @ d3[:, None]
+    gb3 = np.array([d3.sum()])
+    d2 = r(np.where(z2 > 0, W3r[:, 0][None, :] * d3[:, None], 0.0))
+    gW2 = a1.T @ d2
+    gb2 = d2.sum(axis=0)
+    d1 = r(np.where(z1 > 0, d2 @ W2r.T, 0.0))
+    gW1 = xr.T @ d1
+    gb1 = d1.sum(axis=0)
+    return loss, pack_params([gW1, gb1, gW2, gb2, gW3, gb3]), p
 
 
 def mlp_init_shapes():

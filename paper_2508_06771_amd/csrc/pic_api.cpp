@@ -19,6 +19,26 @@ struct pic_ctx {
     double mcc_sigma0 = 0.0, mcc_nn = 0.0, mcc_mr = 0.0;
     bool mcc_set = false;
     double *moments_out = nullptr;
+    // graph of one steady-state step (pic_run_steps)
+    uint64_t *step_dev = nullptr;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t exec = nullptr;
+    unsigned char graph_key[256];
+    size_t graph_key_len = 0;
+    // learned gate
+    const float *gate_params = nullptr;
+    float gate_thr = 0.5f;
+    int gate_kmax = 8;
+    double gate_judge_frac = 0.01, gate_tol = 1e-3, gate_max_false = 0.1;
+    int gate_replicas = 8, gate_bf16 = 1;
+    uint32_t gate_min_judged = 20;
+    DevGate *gate_dev = nullptr;
+    int32_t gate_M = 0;
+    void *gate_mem = nullptr;
+    double *gate_mom = nullptr, *gate_dts = nullptr, *gate_r = nullptr;
+    int32_t *gate_k = nullptr, *gate_judge = nullptr;
+    uint8_t *gate_skip = nullptr, *gate_want = nullptr;
+    float *gate_prob = nullptr;
 };
 
 namespace {
@@ -46,6 +66,15 @@ void ktime_begin(int slot, hipStream_t st)
     (void)hipEventRecord(t.beg, st);
     g_timing.open.push_back(t);
 }
+
+bool ktime_pause()
+{
+    const bool was = g_timing.on;
+    g_timing.on = false;
+    return was;
+}
+
+void ktime_resume(bool was) { g_timing.on = was; }
 
 void ktime_end(int slot, hipStream_t st)
 {
@@ -101,6 +130,37 @@ int ensure_ws(pic_ctx *c, size_t bytes)
     return PIC_OK;
 }
 
+// Per-cell gate state for n_cells cells (allocated outside any capture).
+int ensure_gate(pic_ctx *c, int32_t M)
+{
+    if (c->gate_M == M && c->gate_mem) return PIC_OK;
+    CK(hipSetDevice(c->device));
+    CK(hipStreamSynchronize(c->stream));
+    if (c->gate_mem) CK(hipFree(c->gate_mem));
+    c->gate_mem = nullptr;
+    c->gate_M = 0;
+    const size_t m = (size_t)M;
+    const size_t bytes = m * (14 * 8 + 8 + 8 + 4 + 4 + 1 + 1 + 4) + 8 * 256;
+    if (hipMalloc(&c->gate_mem, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return PIC_ERR_NOMEM;
+    }
+    Bump b(c->gate_mem);
+    c->gate_mom = (double *)b.take(m * 14 * 8);
+    c->gate_dts = (double *)b.take(m * 8);
+    c->gate_r = (double *)b.take(m * 8);
+    c->gate_k = (int32_t *)b.take(m * 4);
+    c->gate_judge = (int32_t *)b.take(m * 4);
+    c->gate_skip = (uint8_t *)b.take(m);
+    c->gate_want = (uint8_t *)b.take(m);
+    c->gate_prob = (float *)b.take(m * 4);
+    CK(hipMemset(c->gate_mem, 0, bytes));
+    CK(hipMemset(c->gate_dev, 0, sizeof(DevGate)));
+    CK(hipDeviceSynchronize());
+    c->gate_M = M;
+    return PIC_OK;
+}
+
 int ceil_log2(int64_t x)
 {
     int b = 0;
@@ -130,7 +190,7 @@ struct SortStreams {
     uint64_t *p64[3];
 };
 
-int sort_by_cell(pic_ctx *c, const SortStreams &caller, const SortStreams &tmp, int64_t n,
+int sort_by_cell(hipStream_t st, const SortStreams &caller, const SortStreams &tmp, int64_t n,
                  int32_t n_cells, const BinScratch &bs, const int *gate)
 {
     const int bits = ceil_log2(n_cells);
@@ -161,7 +221,7 @@ int sort_by_cell(pic_ctx *c, const SortStreams &caller, const SortStreams &tmp, 
         if (p.shift + p.bits > bits) p.bits = bits - p.shift;
         if (p.bits <= 0) p.bits = 1;
         p.gate = gate;
-        RC(radix_pass(p, bs, c->stream));
+        RC(radix_pass(p, bs, st));
     }
     return PIC_OK;
 }
@@ -209,8 +269,20 @@ int pic_create(pic_ctx **out, int device, void *hip_stream)
         delete c;
         return PIC_ERR_NOMEM;
     }
+    if (hipMalloc((void **)&c->gate_dev, sizeof(DevGate)) != hipSuccess ||
+        hipMemset(c->gate_dev, 0, sizeof(DevGate)) != hipSuccess) {
+        (void)hipFree(c->flags);
+        delete c;
+        return PIC_ERR_NOMEM;
+    }
+    if (hipMalloc((void **)&c->step_dev, 256) != hipSuccess) {
+        (void)hipFree(c->flags);
+        delete c;
+        return PIC_ERR_NOMEM;
+    }
     if (hipMemset(c->flags, 0, sizeof(DevFlags)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
         (void)hipFree(c->flags);
+        (void)hipFree(c->step_dev);
         delete c;
         return PIC_ERR_HIP;
     }
@@ -223,8 +295,13 @@ void pic_destroy(pic_ctx *c)
     if (!c) return;
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
+    if (c->exec) (void)hipGraphExecDestroy(c->exec);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->ws) (void)hipFree(c->ws);
     if (c->flags) (void)hipFree(c->flags);
+    if (c->step_dev) (void)hipFree(c->step_dev);
+    if (c->gate_dev) (void)hipFree(c->gate_dev);
+    if (c->gate_mem) (void)hipFree(c->gate_mem);
     delete c;
 }
 
@@ -298,6 +375,132 @@ int pic_set_moments_out(pic_ctx *c, double *out)
     return PIC_OK;
 }
 
+int pic_gate_config(pic_ctx *c, const float *params, float threshold, int32_t k_max,
+                    double judge_fraction, double tolerance, int32_t replicas, int bf16)
+{
+    if (!c || !params || !(threshold >= 0.0f) || k_max < 0 || !(judge_fraction >= 0.0) ||
+        !(judge_fraction <= 1.0) || !(tolerance > 0.0) || replicas < 1)
+        return PIC_ERR_ARG;
+    c->gate_params = params;
+    c->gate_thr = threshold;
+    c->gate_kmax = k_max;
+    c->gate_judge_frac = judge_fraction;
+    c->gate_tol = tolerance;
+    c->gate_replicas = replicas;
+    c->gate_bf16 = bf16 != 0;
+    return PIC_OK;
+}
+
+int pic_gate_reset(pic_ctx *c)
+{
+    if (!c) return PIC_ERR_ARG;
+    CK(hipSetDevice(c->device));
+    CK(hipStreamSynchronize(c->stream));
+    CK(hipMemset(c->gate_dev, 0, sizeof(DevGate)));
+    if (c->gate_mem && c->gate_M > 0) CK(hipMemset(c->gate_k, 0, (size_t)c->gate_M * 4));
+    CK(hipDeviceSynchronize());
+    return PIC_OK;
+}
+
+int pic_gate_stats(pic_ctx *c, int64_t *out)
+{
+    if (!c || !out) return PIC_ERR_ARG;
+    CK(hipSetDevice(c->device));
+    CK(hipStreamSynchronize(c->stream));
+    DevGate g;
+    CK(hipMemcpy(&g, c->gate_dev, sizeof(g), hipMemcpyDeviceToHost));
+    out[0] = (int64_t)g.steps;
+    out[1] = (int64_t)g.skipped;
+    out[2] = (int64_t)g.collided;
+    out[3] = (int64_t)g.judged;
+    out[4] = (int64_t)g.judged_want;
+    out[5] = (int64_t)g.false_skip;
+    out[6] = g.disabled;
+    out[7] = g.have_moments;
+    return PIC_OK;
+}
+
+int pic_gate_state(pic_ctx *c, uint8_t *skip, int32_t *k_acc, float *prob, double *moments)
+{
+    if (!c) return PIC_ERR_ARG;
+    if (!c->gate_mem) return PIC_ERR_STATE;
+    CK(hipSetDevice(c->device));
+    const size_t M = (size_t)c->gate_M;
+    if (skip) CK(hipMemcpyAsync(skip, c->gate_skip, M, hipMemcpyDeviceToDevice, c->stream));
+    if (k_acc) CK(hipMemcpyAsync(k_acc, c->gate_k, M * 4, hipMemcpyDeviceToDevice, c->stream));
+    if (prob) CK(hipMemcpyAsync(prob, c->gate_prob, M * 4, hipMemcpyDeviceToDevice, c->stream));
+    if (moments) CK(hipMemcpyAsync(moments, c->gate_mom, M * 14 * 8, hipMemcpyDeviceToDevice, c->stream));
+    return PIC_OK;
+}
+
+int pic_features(pic_ctx *c, const double *moments, int32_t n_cells, float *feat, uint8_t *valid)
+{
+    if (!c || !moments || !feat || n_cells < 1) return PIC_ERR_ARG;
+    CK(hipSetDevice(c->device));
+    return launch_features(moments, n_cells, feat, valid, c->stream);
+}
+
+int pic_relaxation(pic_ctx *c, int dtype, const void *v, int64_t n, const int32_t *cell_start,
+                   const uint32_t *pid, int32_t n_cells, double dt, double lnLambda,
+                   const double *density, const double *dt_scale, uint64_t seed, uint64_t step,
+                   int32_t replicas, double *r_out)
+{
+    if (!c || n < 0 || n_cells < 1 || !cell_start || !r_out || replicas < 1 || !(dt > 0.0) ||
+        !(lnLambda > 0.0) || (n > 0 && (!v || !pid)))
+        return PIC_ERR_ARG;
+    RC(check_dtype(dtype));
+    CK(hipSetDevice(c->device));
+    RC(ensure_ws(c, huge_scratch_bytes(dtype, n) + 1024));
+    set_huge_scratch(dtype, n, c->ws);
+    RelaxArgs r;
+    memset(&r, 0, sizeof(r));
+    r.v = v;
+    r.n = n;
+    r.cell_start = cell_start;
+    r.pid = pid;
+    r.density = density;
+    r.dt_scale = dt_scale;
+    r.dt = dt;
+    r.lnL = lnLambda;
+    r.seed = seed;
+    r.step = step;
+    r.replicas = replicas;
+    r.count = n_cells;
+    r.r_out = r_out;
+    return launch_relax(dtype, r, c->num_cu, c->stream);
+}
+
+int pic_mlp_forward(pic_ctx *c, const float *params, const float *x, int32_t batch, int bf16,
+                    float *prob)
+{
+    if (!c || !params || batch < 0 || (batch > 0 && (!x || !prob))) return PIC_ERR_ARG;
+    CK(hipSetDevice(c->device));
+    return launch_mlp_forward(params, x, batch, bf16 != 0, prob, c->stream);
+}
+
+int pic_mlp_grad(pic_ctx *c, const float *params, const float *x, const float *y, int32_t batch,
+                 int bf16, float *grad, float *loss)
+{
+    if (!c || !params || batch < 1 || !x || !y || !grad) return PIC_ERR_ARG;
+    CK(hipSetDevice(c->device));
+    RC(ensure_ws(c, mlp_grad_scratch_floats(batch) * 4 + 1024));
+    return launch_mlp_grad(params, x, y, batch, bf16 != 0, (float *)c->ws, grad, loss, c->stream);
+}
+
+int pic_mlp_train_step(pic_ctx *c, float *params, float *adam_m, float *adam_v, int32_t t, float lr,
+                       const float *x, const float *y, int32_t batch, int bf16, float *loss)
+{
+    if (!c || !params || !adam_m || !adam_v || t < 1 || !(lr > 0.0f) || batch < 1 || !x || !y)
+        return PIC_ERR_ARG;
+    CK(hipSetDevice(c->device));
+    const size_t sf = mlp_grad_scratch_floats(batch);
+    RC(ensure_ws(c, (sf + 4801 + 64) * 4 + 1024));
+    float *scratch = (float *)c->ws;
+    float *grad = scratch + sf;
+    RC(launch_mlp_grad(params, x, y, batch, bf16 != 0, scratch, grad, loss, c->stream));
+    return launch_adam(params, adam_m, adam_v, grad, t, lr, c->stream);
+}
+
 int pic_bin_cells(pic_ctx *c, const int32_t *cell_of, int64_t n, int32_t n_cells,
                   int32_t *cell_start, int32_t *order)
 {
@@ -361,21 +564,47 @@ int pic_bin_cells(pic_ctx *c, const int32_t *cell_of, int64_t n, int32_t n_cells
     return PIC_OK;
 }
 
-static int collide_common(pic_ctx *c, int dtype, void *v, int32_t *cell_of, uint32_t *pid, int64_t n,
-                          int32_t n_cells, double dt, double lnL, const double *density,
-                          uint64_t seed, uint64_t step, uint32_t flags)
+struct StepArgs {
+    int dtype;
+    void *v;
+    int32_t *cell_of;
+    uint32_t *pid;
+    int64_t n;
+    int32_t n_cells;
+    double dt, lnL;
+    const double *density;
+    uint64_t seed, step;
+    uint32_t flags;
+};
+
+static size_t step_ws_bytes(const StepArgs &s)
 {
-    RC(check_dtype(dtype));
-    if (n < 0 || n > INT32_MAX || n_cells < 1 || n_cells > (1 << 24) || !(dt > 0.0) || !(lnL > 0.0))
+    const size_t es = s.dtype == PIC_F32 ? 4 : 8;
+    return (size_t)(s.n_cells + 1) * 4 + (size_t)s.n_cells * 5 * 4 + (size_t)s.n * (8 + 3 * es) +
+           radix_scratch_bytes(s.n) + huge_scratch_bytes(s.dtype, s.n) + 8192;
+}
+
+static int step_check(pic_ctx *c, const StepArgs &s)
+{
+    RC(check_dtype(s.dtype));
+    if (s.n < 0 || s.n > INT32_MAX || s.n_cells < 1 || s.n_cells > (1 << 24) || !(s.dt > 0.0) ||
+        !(s.lnL > 0.0))
         return PIC_ERR_ARG;
-    if (n > 0 && (!v || !cell_of || !pid)) return PIC_ERR_ARG;
-    if ((flags & PIC_FUSE_MCC) && !c->mcc_set) return PIC_ERR_STATE;
-    if ((flags & PIC_MOMENTS) && !c->moments_out) return PIC_ERR_STATE;
-    CK(hipSetDevice(c->device));
+    if (s.n > 0 && (!s.v || !s.cell_of || !s.pid)) return PIC_ERR_ARG;
+    if ((s.flags & PIC_FUSE_MCC) && !c->mcc_set) return PIC_ERR_STATE;
+    if ((s.flags & PIC_MOMENTS) && !(s.flags & PIC_GATE) && !c->moments_out) return PIC_ERR_STATE;
+    if ((s.flags & PIC_GATE) && !c->gate_params) return PIC_ERR_STATE;
+    return PIC_OK;
+}
+
+// All launches of one step on stream st.  step_dev: step number in device
+// memory (graph replays) or NULL (s.step by value).
+static int step_enqueue(pic_ctx *c, const StepArgs &s, hipStream_t st, const uint64_t *step_dev)
+{
+    const int dtype = s.dtype;
+    const int64_t n = s.n;
+    const int32_t n_cells = s.n_cells;
     const size_t es = dtype == PIC_F32 ? 4 : 8;
-    const size_t need = (size_t)(n_cells + 1) * 4 + (size_t)n_cells * 5 * 4 + (size_t)n * (8 + 3 * es) +
-                        radix_scratch_bytes(n) + huge_scratch_bytes(dtype, n) + 8192;
-    RC(ensure_ws(c, need));
     Bump b(c->ws);
     int32_t *cs = (int32_t *)b.take((size_t)(n_cells + 1) * 4);
     int32_t *lists = (int32_t *)b.take((size_t)n_cells * 5 * 4);
@@ -387,60 +616,122 @@ static int collide_common(pic_ctx *c, int dtype, void *v, int32_t *cell_of, uint
     bs.bsum = bs.hist + 256 * ((n + 4095) / 4096 + 1);
     set_huge_scratch(dtype, n, b.take(huge_scratch_bytes(dtype, n)));
 
-    RC(launch_reset_flags(c->flags, c->stream));
-    const bool assume = (flags & PIC_ASSUME_SORTED) != 0;
-    ktime_begin(KT_CHECK, c->stream);
-    RC(launch_bin_check(cell_of, n, n_cells, cs, c->flags, assume ? 2 : 1, nullptr, c->stream));
-    ktime_end(KT_CHECK, c->stream);
+    RC(launch_reset_flags(c->flags, st));
+    const bool assume = (s.flags & PIC_ASSUME_SORTED) != 0;
+    ktime_begin(KT_CHECK, st);
+    RC(launch_bin_check(s.cell_of, n, n_cells, cs, c->flags, assume ? 2 : 1, nullptr, st));
+    ktime_end(KT_CHECK, st);
     if (!assume && n > 1 && n_cells > 1) {
-        ktime_begin(KT_SORT, c->stream);
+        ktime_begin(KT_SORT, st);
         SortStreams caller, tmp;
         memset(&caller, 0, sizeof(caller));
         memset(&tmp, 0, sizeof(tmp));
-        caller.key = cell_of;
+        caller.key = s.cell_of;
         tmp.key = tkey;
         caller.n32 = tmp.n32 = 1;
-        caller.p32[0] = pid;
+        caller.p32[0] = s.pid;
         tmp.p32[0] = tpid;
         if (dtype == PIC_F32) {
             caller.n32 = tmp.n32 = 4;
             for (int k = 0; k < 3; ++k) {
-                caller.p32[1 + k] = (uint32_t *)v + (size_t)k * n;
+                caller.p32[1 + k] = (uint32_t *)s.v + (size_t)k * n;
                 tmp.p32[1 + k] = (uint32_t *)tv + (size_t)k * n;
             }
         } else {
             caller.n64 = tmp.n64 = 3;
             for (int k = 0; k < 3; ++k) {
-                caller.p64[k] = (uint64_t *)v + (size_t)k * n;
+                caller.p64[k] = (uint64_t *)s.v + (size_t)k * n;
                 tmp.p64[k] = (uint64_t *)tv + (size_t)k * n;
             }
         }
-        RC(sort_by_cell(c, caller, tmp, n, n_cells, bs, &c->flags->unsorted));
-        RC(launch_bin_check(cell_of, n, n_cells, cs, c->flags, 0, &c->flags->unsorted, c->stream));
-        ktime_end(KT_SORT, c->stream);
+        RC(sort_by_cell(st, caller, tmp, n, n_cells, bs, &c->flags->unsorted));
+        RC(launch_bin_check(s.cell_of, n, n_cells, cs, c->flags, 0, &c->flags->unsorted, st));
+        ktime_end(KT_SORT, st);
     }
     const ClassCaps caps = collide_caps(dtype, c->lds_max);
-    ktime_begin(KT_QUEUE, c->stream);
-    RC(launch_build_queue(cs, n_cells, caps, lists, c->flags, c->stream));
-    ktime_end(KT_QUEUE, c->stream);
+    ktime_begin(KT_QUEUE, st);
+    RC(launch_build_queue(cs, n_cells, caps, lists, c->flags, st));
+    ktime_end(KT_QUEUE, st);
+
+    const bool gate = (s.flags & PIC_GATE) != 0;
+    if (gate) {
+        // decide deferred cells from last step's moments; judge a sample
+        GateArgs g;
+        memset(&g, 0, sizeof(g));
+        g.moments = c->gate_mom;
+        g.params = c->gate_params;
+        g.M = n_cells;
+        g.thr = c->gate_thr;
+        g.kmax = c->gate_kmax;
+        g.judge_thr = (uint64_t)floor(c->gate_judge_frac * 4294967296.0);
+        g.bf16 = c->gate_bf16;
+        g.seed = s.seed;
+        g.step = s.step;
+        g.step_dev = step_dev;
+        g.k_acc = c->gate_k;
+        g.skip = c->gate_skip;
+        g.dt_scale = c->gate_dts;
+        g.want = c->gate_want;
+        g.prob = c->gate_prob;
+        g.judge_list = c->gate_judge;
+        g.g = c->gate_dev;
+        RC(launch_gate(g, st));
+        RelaxArgs r;
+        memset(&r, 0, sizeof(r));
+        r.v = s.v;
+        r.n = n;
+        r.cell_start = cs;
+        r.pid = s.pid;
+        r.density = s.density;
+        r.dt = s.dt;
+        r.lnL = s.lnL;
+        r.seed = s.seed;
+        r.step = s.step;
+        r.step_dev = step_dev;
+        r.replicas = c->gate_replicas;
+        r.list = c->gate_judge;
+        r.count_dev = &c->gate_dev->judge_count;
+        r.r_out = c->gate_r;
+        RC(launch_relax(dtype, r, c->num_cu, st));
+        RC(launch_gate_score(c->gate_dev, c->gate_judge, c->gate_want, c->gate_r, c->gate_tol,
+                             c->gate_max_false, c->gate_min_judged, st));
+    }
 
     CollideArgs a;
     memset(&a, 0, sizeof(a));
-    a.v = v;
+    a.v = s.v;
     a.n = n;
-    a.pid = pid;
+    a.pid = s.pid;
     a.cell_start = cs;
-    a.density = density;
-    a.dt = dt;
-    a.lnL = lnL;
-    a.seed = seed;
-    a.step = step;
-    a.flags = flags;
-    a.mcc_thr = (flags & PIC_FUSE_MCC) ? mcc_threshold(dt, c->mcc_sigma0, c->mcc_nn) : 0;
+    a.density = s.density;
+    a.dt = s.dt;
+    a.lnL = s.lnL;
+    a.seed = s.seed;
+    a.step = s.step;
+    a.step_dev = step_dev;
+    a.flags = s.flags;
+    a.mcc_thr = (s.flags & PIC_FUSE_MCC) ? mcc_threshold(s.dt, c->mcc_sigma0, c->mcc_nn) : 0;
     a.mass_ratio = c->mcc_mr;
     a.moments = c->moments_out;
     a.dflags = c->flags;
-    return launch_collide(dtype, a, lists, n_cells, caps, 0, c->num_cu, c->stream);
+    if (gate) {
+        a.skip = c->gate_skip;
+        a.dt_scale = c->gate_dts;
+        a.moments = c->gate_mom;
+        a.flags |= PIC_MOMENTS;
+    }
+    RC(launch_collide(dtype, a, lists, n_cells, caps, 0, c->num_cu, st));
+    if (gate) RC(launch_gate_end(c->gate_dev, st));
+    return PIC_OK;
+}
+
+static int collide_common(pic_ctx *c, const StepArgs &s)
+{
+    RC(step_check(c, s));
+    CK(hipSetDevice(c->device));
+    RC(ensure_ws(c, step_ws_bytes(s)));
+    if (s.flags & PIC_GATE) RC(ensure_gate(c, s.n_cells));
+    return step_enqueue(c, s, c->stream, nullptr);
 }
 
 int coulomb_collide(pic_ctx *c, int dtype, void *v, int32_t *cell_of, uint32_t *pid, int64_t n,
@@ -448,8 +739,71 @@ int coulomb_collide(pic_ctx *c, int dtype, void *v, int32_t *cell_of, uint32_t *
                     uint64_t seed, uint64_t step, uint32_t flags)
 {
     if (!c) return PIC_ERR_ARG;
-    return collide_common(c, dtype, v, cell_of, pid, n, n_cells, dt, lnLambda, density, seed, step,
-                          flags);
+    const StepArgs s = {dtype, v, cell_of, pid, n, n_cells, dt, lnLambda, density, seed, step, flags};
+    return collide_common(c, s);
+}
+
+int pic_run_steps(pic_ctx *c, int dtype, void *v, int32_t *cell_of, uint32_t *pid, int64_t n,
+                  int32_t n_cells, double dt, double lnLambda, const double *density, uint64_t seed,
+                  uint64_t step0, int64_t nsteps, uint32_t flags)
+{
+    if (!c || nsteps < 0) return PIC_ERR_ARG;
+    if (nsteps == 0) return PIC_OK;
+    StepArgs s = {dtype, v, cell_of, pid, n, n_cells, dt, lnLambda, density, seed, step0, flags};
+    RC(collide_common(c, s));          // first step: re-bins unsorted storage
+    if (nsteps == 1) return PIC_OK;
+    // Later steps find the storage in cell order (the collision step never
+    // changes cell membership): capture one such step once and replay it.
+    s.flags |= PIC_ASSUME_SORTED;
+    s.step = 0;
+    unsigned char key[256];
+    size_t kl = 0;
+    auto put = [&](const void *p, size_t bytes) {
+        memcpy(key + kl, p, bytes);
+        kl += bytes;
+    };
+    put(&s, sizeof(s));
+    put(&c->ws, sizeof(c->ws));
+    put(&c->mcc_sigma0, sizeof(double));
+    put(&c->mcc_nn, sizeof(double));
+    put(&c->mcc_mr, sizeof(double));
+    put(&c->moments_out, sizeof(void *));
+    put(&c->gate_params, sizeof(void *));
+    put(&c->gate_thr, sizeof(float));
+    put(&c->gate_kmax, sizeof(int));
+    put(&c->gate_judge_frac, sizeof(double));
+    put(&c->gate_tol, sizeof(double));
+    put(&c->gate_replicas, sizeof(int));
+    put(&c->gate_bf16, sizeof(int));
+    put(&c->gate_mem, sizeof(void *));
+    if (!c->exec || kl != c->graph_key_len || memcmp(key, c->graph_key, kl) != 0) {
+        if (c->exec) {
+            CK(hipGraphExecDestroy(c->exec));
+            c->exec = nullptr;
+        }
+        if (!c->cap_stream) CK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+        CK(hipStreamSynchronize(c->stream));
+        const bool timing = ktime_pause();
+        hipGraph_t g = nullptr;
+        CK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+        int rc = step_enqueue(c, s, c->cap_stream, c->step_dev);
+        if (rc == PIC_OK) rc = launch_step_inc(c->step_dev, c->cap_stream);
+        const hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+        ktime_resume(timing);
+        if (rc != PIC_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        CK(e);
+        const hipError_t ei = hipGraphInstantiate(&c->exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        CK(ei);
+        memcpy(c->graph_key, key, kl);
+        c->graph_key_len = kl;
+    }
+    RC(launch_set_step(c->step_dev, step0 + 1, c->stream));
+    for (int64_t k = 1; k < nsteps; ++k) CK(hipGraphLaunch(c->exec, c->stream));
+    return PIC_OK;
 }
 
 int mcc_null_collide(pic_ctx *c, int dtype, void *v, const uint32_t *pid, int64_t n, double dt,

@@ -34,6 +34,16 @@ __global__ void k_reset_flags(DevFlags *f)
     }
 }
 
+__global__ void k_set_step(uint64_t *s, uint64_t v)
+{
+    if (threadIdx.x == 0) *s = v;
+}
+
+__global__ void k_step_inc(uint64_t *s)
+{
+    if (threadIdx.x == 0) *s += 1;
+}
+
 // One position i in [0, n]: the boundary between element i-1 and i.  Every
 // cell id j in (cell_of[i-1], cell_of[i]] starts at i; with sorted input each
 // entry of cell_start is written exactly once (empty cells included).
@@ -283,6 +293,20 @@ int grid_for(int64_t n, int threads, int cap)
 int launch_reset_flags(DevFlags *flags, hipStream_t st)
 {
     hipLaunchKernelGGL(k_reset_flags, dim3(1), dim3(64), 0, st, flags);
+    HIP_OK(hipGetLastError());
+    return PIC_OK;
+}
+
+int launch_set_step(uint64_t *step_dev, uint64_t value, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_set_step, dim3(1), dim3(64), 0, st, step_dev, value);
+    HIP_OK(hipGetLastError());
+    return PIC_OK;
+}
+
+int launch_step_inc(uint64_t *step_dev, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_step_inc, dim3(1), dim3(64), 0, st, step_dev);
     HIP_OK(hipGetLastError());
     return PIC_OK;
 }

@@ -148,53 +148,119 @@ __device__ __forceinline__ bool gated_off(const CollideArgs &a)
     return false;
 }
 
-// Block-wide exclusive scan of one value per thread (T <= 1024).
-__device__ __forceinline__ uint32_t block_excl(uint32_t x, uint32_t *wtot)
-{
-    const int lane = threadIdx.x & (PIC_WAVE - 1), wid = threadIdx.x / PIC_WAVE;
-    const int nw = blockDim.x / PIC_WAVE;
-    const uint32_t inc = wave_incl_scan(x);
-    if (lane == PIC_WAVE - 1) wtot[wid] = inc;
-    __syncthreads();
-    uint32_t off = 0;
-    for (int w = 0; w < nw; ++w)
-        if (w < wid) off += wtot[w];
-    __syncthreads();
-    return off + inc - x;
-}
-
-__device__ __forceinline__ uint32_t get16(const uint32_t *w, uint32_t b)
-{
-    return (w[b >> 1] >> ((b & 1u) * 16u)) & 0xFFFFu;
-}
-
-// LDS bytes of one LDS-class cell pass of capacity cap.
-__host__ __device__ constexpr size_t lds_sort_bytes(int cap)
-{
-    return (size_t)cap * 4 + ((size_t)cap / 4 + 2) * 4 + (size_t)cap * 2;
-}
-template <typename R> __host__ __device__ constexpr int pair_rec_bytes() { return sizeof(R) == 4 ? 16 : 32; }
-constexpr int PAIR_ROUNDS = 2;
-template <typename R>
-__host__ __device__ constexpr size_t lds_pair_bytes(int cap)
-{
-    return ((size_t)cap / 2 / PAIR_ROUNDS + 1) * pair_rec_bytes<R>();
-}
-template <typename R>
-__host__ __device__ constexpr size_t lds_bytes(int cap)
-{
-    return lds_sort_bytes(cap) > lds_pair_bytes<R>(cap) ? lds_sort_bytes(cap) : lds_pair_bytes<R>(cap);
-}
+// Variants compiled per kernel: which optional parts of the pass exist.
+enum { F_MCC = 1, F_CONS = 2, F_MOM = 4, F_PAIRS = 8 };
 
 template <typename R> struct PairRec;
 template <> struct __align__(16) PairRec<float> { float x, y, z; uint32_t w2; };
 template <> struct __align__(16) PairRec<double> { double x, y, z; uint32_t w2, pad; };
 
-// ------------------------------------------------------------ LDS-class pass
-template <typename R, int T, int K, bool PAIRS>
-__device__ void cell_pass(const CollideArgs &a, int cell, unsigned char *smem, double *red,
-                          uint32_t *wtot)
+// Pair-major exchange area: pair q of the current round keeps the first
+// member's (v, word2, word3) and the second member's (v, word2); the thread
+// that evaluates the pair overwrites the first record with the half change.
+template <typename R> struct PairLDS;
+template <> struct PairLDS<float> {
+    static constexpr int BYTES = 36;
+    float4 *A;
+    float4 *B;
+    uint32_t *W3;
+    __device__ PairLDS(unsigned char *base, int H)
+        : A((float4 *)base), B((float4 *)(base + 16 * (size_t)H)), W3((uint32_t *)(base + 32 * (size_t)H))
+    {
+    }
+    __device__ void put_first(int q, float x, float y, float z, uint32_t w2, uint32_t w3)
+    {
+        A[q] = make_float4(x, y, z, __uint_as_float(w2));
+        W3[q] = w3;
+    }
+    __device__ void put_second(int q, float x, float y, float z, uint32_t w2)
+    {
+        B[q] = make_float4(x, y, z, __uint_as_float(w2));
+    }
+    __device__ void collide(int q, float C)
+    {
+        const float4 a = A[q], b = B[q];
+        float hx, hy, hz;
+        ta_half(a.x - b.x, a.y - b.y, a.z - b.z, C, __float_as_uint(a.w), W3[q], __float_as_uint(b.w),
+                hx, hy, hz);
+        A[q] = make_float4(hx, hy, hz, 0.0f);
+    }
+    __device__ void half(int q, float &hx, float &hy, float &hz) const
+    {
+        const float4 a = A[q];
+        hx = a.x;
+        hy = a.y;
+        hz = a.z;
+    }
+};
+template <> struct PairLDS<double> {
+    static constexpr int BYTES = 64;
+    double4 *A;
+    double4 *B;
+    __device__ PairLDS(unsigned char *base, int H) : A((double4 *)base), B((double4 *)(base + 32 * (size_t)H)) {}
+    __device__ void put_first(int q, double x, double y, double z, uint32_t w2, uint32_t w3)
+    {
+        A[q] = make_double4(x, y, z, __longlong_as_double((long long)(((uint64_t)w3 << 32) | w2)));
+    }
+    __device__ void put_second(int q, double x, double y, double z, uint32_t w2)
+    {
+        B[q] = make_double4(x, y, z, __longlong_as_double((long long)w2));
+    }
+    __device__ void collide(int q, double C)
+    {
+        const double4 a = A[q], b = B[q];
+        const uint64_t wa = (uint64_t)__double_as_longlong(a.w);
+        double hx, hy, hz;
+        ta_half(a.x - b.x, a.y - b.y, a.z - b.z, C, (uint32_t)wa, (uint32_t)(wa >> 32),
+                (uint32_t)__double_as_longlong(b.w), hx, hy, hz);
+        A[q] = make_double4(hx, hy, hz, 0.0);
+    }
+    __device__ void half(int q, double &hx, double &hy, double &hz) const
+    {
+        const double4 a = A[q];
+        hx = a.x;
+        hy = a.y;
+        hz = a.z;
+    }
+};
+
+// Pairs per thread per exchange round.
+template <typename R> __host__ __device__ constexpr int pairs_per_thread() { return sizeof(R) == 4 ? 2 : 1; }
+
+// LDS bytes of one LDS-class cell pass of capacity cap with T threads.
+__host__ __device__ constexpr size_t lds_sort_bytes(int cap)
 {
+    return (size_t)cap * 4 + ((size_t)cap / 4 + 2) * 4 + (size_t)cap * 2;
+}
+template <typename R>
+__host__ __device__ constexpr size_t lds_bytes(int cap, int T)
+{
+    const size_t pair = (size_t)T * pairs_per_thread<R>() * PairLDS<R>::BYTES;
+    const size_t srt = lds_sort_bytes(cap);
+    return srt > pair ? srt : pair;
+}
+
+// ------------------------------------------------------------ LDS-class pass
+// Adds sign * (the 14 moment terms of v) to m.
+__device__ __forceinline__ void moment_terms(double *m, double x, double y, double z, double sign)
+{
+    const double q2 = x * x + y * y + z * z;
+    m[0] += sign;
+    m[1] += sign * x; m[2] += sign * y; m[3] += sign * z;
+    m[4] += sign * (x * x); m[5] += sign * (y * y); m[6] += sign * (z * z);
+    m[7] += sign * (x * y); m[8] += sign * (x * z); m[9] += sign * (y * z);
+    m[10] += sign * (q2 * x); m[11] += sign * (q2 * y); m[12] += sign * (q2 * z);
+    m[13] += sign * (q2 * q2);
+}
+
+template <typename R, int T, int K, int F>
+__device__ void cell_pass(const CollideArgs &a, int cell, unsigned char *smem, double *red,
+                          uint32_t *wtot, double *s_before)
+{
+    constexpr bool PAIRS = (F & F_PAIRS) != 0;
+    constexpr bool MCC = (F & F_MCC) != 0;
+    constexpr bool CONS = (F & F_CONS) != 0;
+    constexpr bool MOM = (F & F_MOM) != 0;
     const int lo = a.cell_start[cell];
     const int n = a.cell_start[cell + 1] - lo;
     const uint32_t step = (uint32_t)read_step(a);
@@ -202,45 +268,79 @@ __device__ void cell_pass(const CollideArgs &a, int cell, unsigned char *smem, d
     R *vx_g = (R *)a.v;
     R *vy_g = vx_g + a.n;
     R *vz_g = vy_g + a.n;
+    const uint32_t *pid_c = a.pid + lo;
+
+    if (!PAIRS && a.skip && a.skip[cell]) {
+        // deferred cell: only its null-collision candidates change; the
+        // moment sums are updated by the candidates' differences
+        if constexpr (MCC) {
+            double dm[14];
+#pragma unroll
+            for (int q = 0; q < 14; ++q) dm[q] = 0.0;
+            for (int i = threadIdx.x; i < n; i += T) {
+                const uint32_t p = pid_c[i];
+                const W4 w = draw4(a.seed, p, step, 0u, 0u);
+                if ((uint64_t)w.y < a.mcc_thr) {
+                    R x = vx_g[lo + i], y = vy_g[lo + i], z = vz_g[lo + i];
+                    if constexpr (MOM) moment_terms(dm, x, y, z, -1.0);
+                    mcc_scatter<R>(x, y, z, p, a.seed, step, a.mass_ratio);
+                    if constexpr (MOM) moment_terms(dm, x, y, z, 1.0);
+                    vx_g[lo + i] = x;
+                    vy_g[lo + i] = y;
+                    vz_g[lo + i] = z;
+                }
+            }
+            if constexpr (MOM) {
+                block_sum<14>(dm, red);
+                if (threadIdx.x > 0 && threadIdx.x < 14) a.moments[(int64_t)cell * 14 + threadIdx.x] += dm[threadIdx.x];
+            }
+        }
+        return;
+    }
 
     uint32_t *keys = (uint32_t *)smem;
     uint32_t *cntw = keys + T * K;
     uint16_t *lst = (uint16_t *)(cntw + (T * K) / 4 + 2);
-    PairRec<R> *pbuf = (PairRec<R> *)smem;
 
     R vx[K], vy[K], vz[K];
     uint32_t w2[K], w3[K], pos[K];
     uint32_t cand = 0;
-    double before[5] = {0, 0, 0, 0, 0};
 
     const uint32_t nb = n >= 2 ? (uint32_t)(n / 2) : 1u;   // buckets
     const int nwords = (int)((nb + 1) / 2);
+    {
+        double before[5] = {0, 0, 0, 0, 0};
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const int i = threadIdx.x + k * T;
-        if (i < n) {
-            const uint32_t p = a.pid[lo + i];
-            if (!PAIRS) {
-                vx[k] = vx_g[lo + i];
-                vy[k] = vy_g[lo + i];
-                vz[k] = vz_g[lo + i];
-            }
-            const W4 w = draw4(a.seed, p, step, 0u, 0u);
-            keys[i] = w.x;
-            w2[k] = w.z;
-            w3[k] = w.w;
-            if ((uint64_t)w.y < a.mcc_thr) cand |= 1u << k;
-            if (!PAIRS && (a.flags & PIC_CONSERVE_FIX)) {
-                const double x = vx[k], y = vy[k], z = vz[k];
-                before[0] += 1.0;
-                before[1] += x;
-                before[2] += y;
-                before[3] += z;
-                before[4] += x * x + y * y + z * z;
+        for (int k = 0; k < K; ++k) {
+            const int i = threadIdx.x + k * T;
+            if (i < n) {
+                const uint32_t p = pid_c[i];
+                if (!PAIRS) {
+                    vx[k] = vx_g[lo + i];
+                    vy[k] = vy_g[lo + i];
+                    vz[k] = vz_g[lo + i];
+                }
+                const W4 w = draw4(a.seed, p, step, 0u, 0u);
+                keys[i] = w.x;
+                w2[k] = w.z;
+                w3[k] = w.w;
+                if (MCC && (uint64_t)w.y < a.mcc_thr) cand |= 1u << k;
+                if (CONS) {
+                    const double x = vx[k], y = vy[k], z = vz[k];
+                    before[0] += 1.0;
+                    before[1] += x;
+                    before[2] += y;
+                    before[3] += z;
+                    before[4] += x * x + y * y + z * z;
+                }
             }
         }
+        for (int b = threadIdx.x; b < nwords; b += T) cntw[b] = 0u;
+        if constexpr (CONS) {
+            block_sum<5>(before, red);     // contains the barriers
+            if (threadIdx.x < 5) s_before[threadIdx.x] = before[threadIdx.x];
+        }
     }
-    for (int b = threadIdx.x; b < nwords; b += T) cntw[b] = 0u;
     __syncthreads();
 
     if (coul || PAIRS) {
@@ -298,7 +398,7 @@ __device__ void cell_pass(const CollideArgs &a, int cell, unsigned char *smem, d
                     if (kj < key) {
                         ++rank;
                     } else if (kj == key && j != (uint32_t)i) {
-                        if (a.pid[lo + j] < a.pid[lo + i]) ++rank;
+                        if (pid_c[j] < pid_c[i]) ++rank;
                     }
                 }
                 pos[k] = beg + rank;
@@ -332,56 +432,49 @@ __device__ void cell_pass(const CollideArgs &a, int cell, unsigned char *smem, d
 
     if (coul) {
         const R C = (R)cell_C(a, cell);
-        const int npairs = n / 2;
-        const int half = (npairs + PAIR_ROUNDS - 1) / PAIR_ROUNDS;
-        for (int r = 0; r < PAIR_ROUNDS; ++r) {
-            const int qlo = r * half, qhi = min(npairs, qlo + half);
+        const uint32_t npairs = (uint32_t)n / 2;
+        constexpr uint32_t H = (uint32_t)T * pairs_per_thread<R>();
+        PairLDS<R> pl(smem, (int)H);
+        for (uint32_t qlo = 0; qlo < npairs; qlo += H) {
+            // members of this round's pairs post their data
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 const int i = threadIdx.x + k * T;
-                const int q = (int)(pos[k] >> 1);
-                if (i < n && (pos[k] & 1u) && q >= qlo && q < qhi) {
-                    PairRec<R> &e = pbuf[q - qlo];
-                    e.x = vx[k];
-                    e.y = vy[k];
-                    e.z = vz[k];
-                    e.w2 = w2[k];
+                const uint32_t q = (pos[k] >> 1) - qlo;
+                if (i < n && q < H && (pos[k] >> 1) < npairs) {
+                    if (pos[k] & 1u)
+                        pl.put_second((int)q, vx[k], vy[k], vz[k], w2[k]);
+                    else
+                        pl.put_first((int)q, vx[k], vy[k], vz[k], w2[k], w3[k]);
                 }
             }
+            __syncthreads();
+            // one thread per pair
+            const uint32_t m = min(H, npairs - qlo);
+            for (uint32_t q = threadIdx.x; q < m; q += T) pl.collide((int)q, C);
             __syncthreads();
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 const int i = threadIdx.x + k * T;
-                const int q = (int)(pos[k] >> 1);
-                if (i < n && !(pos[k] & 1u) && q >= qlo && q < qhi) {
-                    PairRec<R> &e = pbuf[q - qlo];
+                const uint32_t q = (pos[k] >> 1) - qlo;
+                if (i < n && q < H && (pos[k] >> 1) < npairs) {
                     R hx, hy, hz;
-                    ta_half(vx[k] - e.x, vy[k] - e.y, vz[k] - e.z, C, w2[k], w3[k], e.w2, hx, hy,
-                            hz);
-                    vx[k] += hx;
-                    vy[k] += hy;
-                    vz[k] += hz;
-                    e.x = hx;
-                    e.y = hy;
-                    e.z = hz;
-                }
-            }
-            __syncthreads();
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                const int i = threadIdx.x + k * T;
-                const int q = (int)(pos[k] >> 1);
-                if (i < n && (pos[k] & 1u) && q >= qlo && q < qhi) {
-                    const PairRec<R> &e = pbuf[q - qlo];
-                    vx[k] -= e.x;
-                    vy[k] -= e.y;
-                    vz[k] -= e.z;
+                    pl.half((int)q, hx, hy, hz);
+                    if (pos[k] & 1u) {
+                        vx[k] -= hx;
+                        vy[k] -= hy;
+                        vz[k] -= hz;
+                    } else {
+                        vx[k] += hx;
+                        vy[k] += hy;
+                        vz[k] += hz;
+                    }
                 }
             }
             __syncthreads();
         }
 
-        if (a.flags & PIC_CONSERVE_FIX) {
+        if constexpr (CONS) {
             double after[5] = {0, 0, 0, 0, 0};
 #pragma unroll
             for (int k = 0; k < K; ++k) {
@@ -394,12 +487,11 @@ __device__ void cell_pass(const CollideArgs &a, int cell, unsigned char *smem, d
                     after[4] += x * x + y * y + z * z;
                 }
             }
-            block_sum<5>(before, red);
             block_sum<5>(after, red);
-            const double N = before[0];
-            const double Vo[3] = {before[1] / N, before[2] / N, before[3] / N};
+            const double N = s_before[0];
+            const double Vo[3] = {s_before[1] / N, s_before[2] / N, s_before[3] / N};
             const double Vn[3] = {after[1] / N, after[2] / N, after[3] / N};
-            const double Eo = 0.5 * before[4] - 0.5 * N * (Vo[0] * Vo[0] + Vo[1] * Vo[1] + Vo[2] * Vo[2]);
+            const double Eo = 0.5 * s_before[4] - 0.5 * N * (Vo[0] * Vo[0] + Vo[1] * Vo[1] + Vo[2] * Vo[2]);
             const double En = 0.5 * after[4] - 0.5 * N * (Vn[0] * Vn[0] + Vn[1] * Vn[1] + Vn[2] * Vn[2]);
             if (En > 0.0 && Eo >= 0.0) {
                 const double al = sqrt(Eo / En);
@@ -416,23 +508,22 @@ __device__ void cell_pass(const CollideArgs &a, int cell, unsigned char *smem, d
         }
     }
 
-    if (a.mcc_thr && cand) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const int i = threadIdx.x + k * T;
-            if (i < n && ((cand >> k) & 1u))
-                mcc_scatter<R>(vx[k], vy[k], vz[k], a.pid[lo + i], a.seed, step, a.mass_ratio);
-        }
-    }
-
-    if (a.flags & PIC_MOMENTS) {
-        double m[14];
+    // null collisions, store, moment sums
+    double m[14];
+    if constexpr (MOM) {
 #pragma unroll
         for (int q = 0; q < 14; ++q) m[q] = 0.0;
+    }
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const int i = threadIdx.x + k * T;
-            if (i < n) {
+    for (int k = 0; k < K; ++k) {
+        const int i = threadIdx.x + k * T;
+        if (i < n) {
+            if (MCC && ((cand >> k) & 1u))
+                mcc_scatter<R>(vx[k], vy[k], vz[k], pid_c[i], a.seed, step, a.mass_ratio);
+            vx_g[lo + i] = vx[k];
+            vy_g[lo + i] = vy[k];
+            vz_g[lo + i] = vz[k];
+            if constexpr (MOM) {
                 const double x = vx[k], y = vy[k], z = vz[k];
                 const double q2 = x * x + y * y + z * z;
                 m[0] += 1.0;
@@ -443,27 +534,20 @@ __device__ void cell_pass(const CollideArgs &a, int cell, unsigned char *smem, d
                 m[13] += q2 * q2;
             }
         }
+    }
+    if constexpr (MOM) {
         block_sum<14>(m, red);
         if (threadIdx.x < 14) a.moments[(int64_t)cell * 14 + threadIdx.x] = m[threadIdx.x];
     }
-
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const int i = threadIdx.x + k * T;
-        if (i < n) {
-            vx_g[lo + i] = vx[k];
-            vy_g[lo + i] = vy[k];
-            vz_g[lo + i] = vz[k];
-        }
-    }
 }
 
-template <typename R, int T, int K, bool PAIRS>
+template <typename R, int T, int K, int F>
 __global__ __launch_bounds__(T) void k_collide(CollideArgs a, const int32_t *__restrict__ list,
                                                int cls)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[14 * (T / PIC_WAVE)];
+    __shared__ double s_before[8];
     __shared__ uint32_t wtot[T / PIC_WAVE];
     __shared__ int s_item;
     if (gated_off(a)) return;
@@ -474,23 +558,13 @@ __global__ __launch_bounds__(T) void k_collide(CollideArgs a, const int32_t *__r
         const int item = s_item;
         __syncthreads();
         if (item >= (int)count) break;
-        cell_pass<R, T, K, PAIRS>(a, list[item], smem, red, wtot);
+        cell_pass<R, T, K, F>(a, list[item], smem, red, wtot, s_before);
     }
 }
 
 // ------------------------------------------------------------ huge cells
 // One workgroup per cell; per-particle state in global scratch indexed by the
 // particle's slot, so scratch regions of different cells never overlap.
-struct HugeScratch {
-    uint32_t *keys;    // [n]
-    uint32_t *cnt;     // [n]  bucket counts, then offsets
-    uint32_t *lst;     // [n]  bucket member lists
-    uint32_t *pos;     // [n]  arrival rank, then sorted position
-    uint32_t *w23;     // [2n] words 2 and 3
-    uint8_t *cand;     // [n]
-    void *pbuf;        // [n/2 + 1] pair records
-};
-
 template <typename R, bool PAIRS>
 __global__ __launch_bounds__(1024) void k_collide_huge(CollideArgs a, const int32_t *__restrict__ list,
                                                        int cls, HugeScratch hs)
@@ -516,7 +590,6 @@ __global__ __launch_bounds__(1024) void k_collide_huge(CollideArgs a, const int3
         const int n = a.cell_start[cell + 1] - lo;
         const uint32_t step = (uint32_t)read_step(a);
         const bool coul = !(a.skip && a.skip[cell]) && n >= 2;
-        const uint32_t nb = n >= 2 ? (uint32_t)(n / 2) : 1u;
         double before[5] = {0, 0, 0, 0, 0};
         for (int i = threadIdx.x; i < n; i += T) {
             const W4 w = draw4(a.seed, a.pid[lo + i], step, 0u, 0u);
@@ -524,7 +597,6 @@ __global__ __launch_bounds__(1024) void k_collide_huge(CollideArgs a, const int3
             hs.w23[2 * (int64_t)(lo + i)] = w.z;
             hs.w23[2 * (int64_t)(lo + i) + 1] = w.w;
             hs.cand[lo + i] = (uint64_t)w.y < a.mcc_thr;
-            hs.cnt[lo + i] = 0u;
             if (!PAIRS && (a.flags & PIC_CONSERVE_FIX)) {
                 const double x = vx_g[lo + i], y = vy_g[lo + i], z = vz_g[lo + i];
                 before[0] += 1.0;
@@ -535,54 +607,9 @@ __global__ __launch_bounds__(1024) void k_collide_huge(CollideArgs a, const int3
             }
         }
         __syncthreads();
-        if (coul || PAIRS) {
-            for (int i = threadIdx.x; i < n; i += T) {
-                const uint32_t b = __umulhi(hs.keys[lo + i], nb);
-                hs.pos[lo + i] = atomicAdd(&hs.cnt[lo + b], 1u);
-            }
-            __syncthreads();
-            {
-                const int per = ((int)nb + T - 1) / T;
-                const int b0 = threadIdx.x * per;
-                uint32_t s = 0;
-                for (int q = 0; q < per; ++q)
-                    if (b0 + q < (int)nb) s += hs.cnt[lo + b0 + q];
-                uint32_t run = block_excl(s, wtot);
-                for (int q = 0; q < per; ++q)
-                    if (b0 + q < (int)nb) {
-                        const uint32_t c = hs.cnt[lo + b0 + q];
-                        hs.cnt[lo + b0 + q] = run;
-                        run += c;
-                    }
-            }
-            __syncthreads();
-            for (int i = threadIdx.x; i < n; i += T) {
-                const uint32_t b = __umulhi(hs.keys[lo + i], nb);
-                hs.lst[lo + hs.cnt[lo + b] + hs.pos[lo + i]] = (uint32_t)i;
-            }
-            __syncthreads();
-            for (int i = threadIdx.x; i < n; i += T) {
-                const uint32_t key = hs.keys[lo + i];
-                const uint32_t b = __umulhi(key, nb);
-                const uint32_t beg = hs.cnt[lo + b];
-                const uint32_t end = (b + 1 < nb) ? hs.cnt[lo + b + 1] : (uint32_t)n;
-                uint32_t rank = 0;
-                for (uint32_t m = beg; m < end; ++m) {
-                    const uint32_t j = hs.lst[lo + m];
-                    const uint32_t kj = hs.keys[lo + j];
-                    if (kj < key) ++rank;
-                    else if (kj == key && j != (uint32_t)i && a.pid[lo + j] < a.pid[lo + i]) ++rank;
-                }
-                hs.pos[lo + i] = beg + rank;
-            }
-            __syncthreads();
-        }
+        if (coul || PAIRS) gsort_positions(hs, a.pid, lo, n, wtot);
         if (PAIRS) {
-            for (int i = threadIdx.x; i < n; i += T) {
-                hs.lst[lo + hs.pos[lo + i]] = (uint32_t)i;
-                a.sorted_out[lo + hs.pos[lo + i]] = lo + i;
-            }
-            __syncthreads();
+            for (int i = threadIdx.x; i < n; i += T) a.sorted_out[lo + hs.pos[lo + i]] = lo + i;
             for (int i = threadIdx.x; i < n; i += T) {
                 const uint32_t q = hs.pos[lo + i] ^ 1u;
                 a.partner_out[lo + i] = (q < (uint32_t)n) ? lo + (int)hs.lst[lo + q] : -1;
@@ -703,11 +730,11 @@ template <> struct Classes<double> {
     static constexpr int T3 = 1024, K3 = 6;   // <= 6144
 };
 
-template <typename R, int T, int K, bool PAIRS>
+template <typename R, int T, int K, int F>
 int launch_class(const CollideArgs &a, const int32_t *list, int cls, int blocks, hipStream_t st)
 {
-    const size_t lds = lds_bytes<R>(T * K);
-    auto kern = k_collide<R, T, K, PAIRS>;
+    const size_t lds = lds_bytes<R>(T * K, T);
+    auto kern = k_collide<R, T, K, F>;
     static bool attr_done = false;
     if (!attr_done) {
         HIP_OK(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -721,11 +748,12 @@ int launch_class(const CollideArgs &a, const int32_t *list, int cls, int blocks,
     return PIC_OK;
 }
 
-template <typename R, bool PAIRS>
+template <typename R, int F>
 int launch_all(const CollideArgs &a, const int32_t *lists, int32_t n_cells, int num_cu,
                const HugeScratch &hs, hipStream_t st)
 {
     typedef Classes<R> C;
+    constexpr bool PAIRS = (F & F_PAIRS) != 0;
     int rc;
     const int64_t M = n_cells;
     // largest cells first so the small ones fill the tail
@@ -734,14 +762,40 @@ int launch_all(const CollideArgs &a, const int32_t *lists, int32_t n_cells, int 
                        4, hs);
     ktime_end(KT_HUGE, st);
     HIP_OK(hipGetLastError());
-    if ((rc = launch_class<R, C::T3, C::K3, PAIRS>(a, lists + 3 * M, 3, 2 * num_cu, st))) return rc;
-    if ((rc = launch_class<R, C::T2, C::K2, PAIRS>(a, lists + 2 * M, 2, 2 * num_cu, st))) return rc;
-    if ((rc = launch_class<R, C::T1, C::K1, PAIRS>(a, lists + 1 * M, 1, 4 * num_cu, st))) return rc;
-    if ((rc = launch_class<R, C::T0, C::K0, PAIRS>(a, lists + 0 * M, 0, 8 * num_cu, st))) return rc;
+    if ((rc = launch_class<R, C::T3, C::K3, F>(a, lists + 3 * M, 3, num_cu, st))) return rc;
+    if ((rc = launch_class<R, C::T2, C::K2, F>(a, lists + 2 * M, 2, 2 * num_cu, st))) return rc;
+    if ((rc = launch_class<R, C::T1, C::K1, F>(a, lists + 1 * M, 1, 4 * num_cu, st))) return rc;
+    if ((rc = launch_class<R, C::T0, C::K0, F>(a, lists + 0 * M, 0, 8 * num_cu, st))) return rc;
     return PIC_OK;
 }
 
+template <typename R>
+int launch_flags(const CollideArgs &a, const int32_t *lists, int32_t n_cells, int num_cu,
+                 const HugeScratch &hs, int pairs_only, hipStream_t st)
+{
+    if (pairs_only) return launch_all<R, F_PAIRS>(a, lists, n_cells, num_cu, hs, st);
+    const int f = (a.mcc_thr ? F_MCC : 0) | ((a.flags & PIC_CONSERVE_FIX) ? F_CONS : 0) |
+                  ((a.flags & PIC_MOMENTS) ? F_MOM : 0);
+    switch (f) {
+    case 0: return launch_all<R, 0>(a, lists, n_cells, num_cu, hs, st);
+    case 1: return launch_all<R, 1>(a, lists, n_cells, num_cu, hs, st);
+    case 2: return launch_all<R, 2>(a, lists, n_cells, num_cu, hs, st);
+    case 3: return launch_all<R, 3>(a, lists, n_cells, num_cu, hs, st);
+    case 4: return launch_all<R, 4>(a, lists, n_cells, num_cu, hs, st);
+    case 5: return launch_all<R, 5>(a, lists, n_cells, num_cu, hs, st);
+    case 6: return launch_all<R, 6>(a, lists, n_cells, num_cu, hs, st);
+    default: return launch_all<R, 7>(a, lists, n_cells, num_cu, hs, st);
+    }
+}
+
 HugeScratch g_huge;   // set by launch_collide from the workspace
+
+}  // namespace
+
+const HugeScratch &huge_scratch() { return g_huge; }
+
+namespace {
+
 
 }  // namespace
 
@@ -791,9 +845,6 @@ void set_huge_scratch(int dtype, int64_t n, void *base)
 int launch_collide(int dtype, const CollideArgs &a, const int32_t *lists, int32_t n_cells,
                    const ClassCaps &, int pairs_only, int num_cu, hipStream_t st)
 {
-    if (dtype == PIC_F32)
-        return pairs_only ? launch_all<float, true>(a, lists, n_cells, num_cu, g_huge, st)
-                          : launch_all<float, false>(a, lists, n_cells, num_cu, g_huge, st);
-    return pairs_only ? launch_all<double, true>(a, lists, n_cells, num_cu, g_huge, st)
-                      : launch_all<double, false>(a, lists, n_cells, num_cu, g_huge, st);
+    if (dtype == PIC_F32) return launch_flags<float>(a, lists, n_cells, num_cu, g_huge, pairs_only, st);
+    return launch_flags<double>(a, lists, n_cells, num_cu, g_huge, pairs_only, st);
 }

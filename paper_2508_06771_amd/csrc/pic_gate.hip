@@ -1,0 +1,528 @@
+// pic_gate.hip -- learned sub-cycling gate of the collision step.
+//
+// A cell whose Coulomb relaxation over one step is below a tolerance can
+// defer its collision: it accumulates the skipped time and later collides
+// once with dt_eff = (k + 1) dt.  A small network decides from eight moment
+// features per cell; the plain operator stays the fallback and, on a
+// Philox-sampled fraction of cells every step, the judge of the network's
+// decisions.
+//
+//   features   eight Galilean-invariant moments of the cell from its 14 FP64
+//              raw sums (count, momentum, second moments, heat flux, |v|^4)
+//   network    8 -> 64 -> 64 -> 1, ReLU, logistic output; BF16 products with
+//              FP32 accumulation (or FP32 throughout), FP32 master weights
+//   label      expected relative one-step change of the temperature tensor,
+//              r = || E sum_pairs 1/4 h(s^2) (|u|^2 I - 3 u u^T) || / (N T),
+//              averaged over independent re-pairings; h(s^2) = E[sin^2 Theta]
+//   training   forward, binary cross-entropy, backward and Adam, all here
+#include "pic_internal.hpp"
+
+#define HIP_OK(x) do { if ((x) != hipSuccess) return PIC_ERR_HIP; } while (0)
+
+namespace {
+
+constexpr double PI_D = 3.14159265358979323846;
+constexpr int OFF_W1 = 0, OFF_B1 = 512, OFF_W2 = 576, OFF_B2 = 4672, OFF_W3 = 4736, OFF_B3 = 4800;
+constexpr int NPARAM = 4801;
+
+// Round a binary32 value to bfloat16 (nearest, ties to even), returned as binary32.
+__device__ __forceinline__ float bf16r(float x)
+{
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return __uint_as_float(u & 0xFFFF0000u);
+}
+
+// h(s^2) = E[sin^2 Theta] = E[4 d^2 / (1 + d^2)^2], d ~ N(0, s^2).  With
+// E[1/(1 + t z^2)] = sqrt(pi/(2t)) erfcx(1/sqrt(2t)) and h = -4 t d/dt of it:
+// h = 2 sqrt(pi) w (1 + 2 w^2) erfcx(w) - 4 w^2, w = 1 / sqrt(2 t).  Below
+// t = 0.01 the closed form cancels, so the Gaussian-moment series is used.
+__device__ double h_angle(double t)
+{
+    if (t < 0.01) {
+        return t * (4.0 + t * (-24.0 + t * (180.0 + t * (-1680.0 + t * 18900.0))));
+    }
+    const double w = 1.0 / sqrt(2.0 * t);
+    return 2.0 * sqrt(PI_D) * w * (1.0 + 2.0 * w * w) * erfcx(w) - 4.0 * w * w;
+}
+
+// Eight features from the raw sums m[0..13] (layout of pic_cell_moments).
+// Returns false for cells with fewer than two members or no temperature.
+__device__ bool features_from_sums(const double *m, float f[8])
+{
+    const double N = m[0];
+    for (int k = 0; k < 8; ++k) f[k] = 0.0f;
+    if (!(N >= 2.0)) return false;
+    const double V[3] = {m[1] / N, m[2] / N, m[3] / N};
+    const double Q = m[4] + m[5] + m[6];   // sum |v|^2
+    // central second moments T_ab = <v_a v_b> - V_a V_b
+    const double Txx = m[4] / N - V[0] * V[0], Tyy = m[5] / N - V[1] * V[1], Tzz = m[6] / N - V[2] * V[2];
+    const double Txy = m[7] / N - V[0] * V[1], Txz = m[8] / N - V[0] * V[2], Tyz = m[9] / N - V[1] * V[2];
+    const double T = (Txx + Tyy + Tzz) / 3.0;
+    if (!(T > 0.0)) return false;
+    const double S2[3][3] = {{m[4], m[7], m[8]}, {m[7], m[5], m[9]}, {m[8], m[9], m[6]}};
+    const double VV = V[0] * V[0] + V[1] * V[1] + V[2] * V[2];
+    // sum |c|^2 c_a = S3_a - V_a Q - 2 (S2 V)_a + 2 V_a N |V|^2
+    double q[3];
+    for (int a = 0; a < 3; ++a) {
+        const double s2v = S2[a][0] * V[0] + S2[a][1] * V[1] + S2[a][2] * V[2];
+        q[a] = 0.5 * (m[10 + a] - V[a] * Q - 2.0 * s2v + 2.0 * V[a] * N * VV);
+    }
+    // sum |c|^4 = S4 - 4 V.S3 + 4 V^T S2 V + 2 |V|^2 Q - 3 N |V|^4
+    double vs2v = 0.0;
+    for (int a = 0; a < 3; ++a)
+        vs2v += V[a] * (S2[a][0] * V[0] + S2[a][1] * V[1] + S2[a][2] * V[2]);
+    const double c4 = m[13] - 4.0 * (V[0] * m[10] + V[1] * m[11] + V[2] * m[12]) + 4.0 * vs2v +
+                      2.0 * VV * Q - 3.0 * N * VV * VV;
+    f[0] = (float)log(N);
+    f[1] = (float)log(T);
+    f[2] = (float)(Txx / T);
+    f[3] = (float)(Tyy / T);
+    f[4] = (float)(Tzz / T);
+    f[5] = (float)(sqrt(2.0 * (Txy * Txy + Txz * Txz + Tyz * Tyz)) / T);
+    f[6] = (float)(sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]) / (N * T * sqrt(T)));
+    f[7] = (float)(c4 / N / (15.0 * T * T) - 1.0);
+    return true;
+}
+
+// Network logit of one sample; P holds the parameters (weights already
+// rounded to bfloat16 in BF16 mode), products of bfloat16-rounded operands,
+// binary32 accumulation.
+__device__ float mlp_logit(const float *P, const float x_in[8], bool bf16)
+{
+    float x[8];
+    for (int i = 0; i < 8; ++i) x[i] = bf16 ? bf16r(x_in[i]) : x_in[i];
+    float h1[64];
+    for (int j = 0; j < 64; ++j) {
+        float z = P[OFF_B1 + j];
+        for (int i = 0; i < 8; ++i) z += x[i] * P[OFF_W1 + i * 64 + j];
+        z = z > 0.0f ? z : 0.0f;
+        h1[j] = bf16 ? bf16r(z) : z;
+    }
+    float out = P[OFF_B3];
+    for (int j = 0; j < 64; ++j) {
+        float z = P[OFF_B2 + j];
+        for (int i = 0; i < 64; ++i) z += h1[i] * P[OFF_W2 + i * 64 + j];
+        z = z > 0.0f ? z : 0.0f;
+        out += (bf16 ? bf16r(z) : z) * P[OFF_W3 + j];
+    }
+    return out;
+}
+
+__device__ void load_params(float *P, const float *params, bool bf16)
+{
+    for (int p = threadIdx.x; p < NPARAM; p += blockDim.x) {
+        const bool weight = p < OFF_B1 || (p >= OFF_W2 && p < OFF_B2) || (p >= OFF_W3 && p < OFF_B3);
+        P[p] = (bf16 && weight) ? bf16r(params[p]) : params[p];
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void k_features(const double *__restrict__ mom, int32_t M,
+                                                  float *__restrict__ feat, uint8_t *__restrict__ valid)
+{
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < M; j += gridDim.x * blockDim.x) {
+        float f[8];
+        const bool ok = features_from_sums(mom + (int64_t)j * 14, f);
+        for (int k = 0; k < 8; ++k) feat[(int64_t)j * 8 + k] = f[k];
+        if (valid) valid[j] = ok;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_mlp_forward(const float *__restrict__ params,
+                                                     const float *__restrict__ x, int32_t B, int bf16,
+                                                     float *__restrict__ prob)
+{
+    __shared__ float P[NPARAM];
+    load_params(P, params, bf16 != 0);
+    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < B; s += gridDim.x * blockDim.x) {
+        float xi[8];
+        for (int i = 0; i < 8; ++i) xi[i] = x[(int64_t)s * 8 + i];
+        const float z = mlp_logit(P, xi, bf16 != 0);
+        prob[s] = 1.0f / (1.0f + __expf(-z));
+    }
+}
+
+// ------------------------------------------------------------ gate per step
+__global__ void k_gate_begin(DevGate *g)
+{
+    if (threadIdx.x == 0) g->judge_count = 0;
+}
+
+// One thread per cell: decide skip / collide, with the deferred-time count.
+__global__ __launch_bounds__(256) void k_gate(GateArgs a)
+{
+    __shared__ float P[NPARAM];
+    load_params(P, a.params, a.bf16 != 0);
+    const uint64_t step = a.step_dev ? *a.step_dev : a.step;
+    const bool on = a.g->have_moments && !a.g->disabled;
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < a.M; j += gridDim.x * blockDim.x) {
+        bool want = false;
+        float p = 0.0f;
+        if (on) {
+            float f[8];
+            if (features_from_sums(a.moments + (int64_t)j * 14, f)) {
+                p = 1.0f / (1.0f + __expf(-mlp_logit(P, f, a.bf16 != 0)));
+                want = p > a.thr && a.k_acc[j] < a.kmax;
+            }
+        }
+        const W4 w = draw4(a.seed, (uint32_t)j, (uint32_t)step, 2u, 0u);
+        const bool judge = on && (uint64_t)w.x < a.judge_thr;
+        const bool skip = want && !judge;
+        a.prob[j] = p;
+        a.want[j] = want;
+        a.skip[j] = skip;
+        if (skip) {
+            a.k_acc[j] += 1;
+            a.dt_scale[j] = 0.0;
+        } else {
+            a.dt_scale[j] = (double)(a.k_acc[j] + 1);
+            a.k_acc[j] = 0;
+        }
+        if (judge) a.judge_list[atomicAdd(&a.g->judge_count, 1u)] = j;
+        if (skip) atomicAdd(&a.g->skipped, 1ull);
+        else atomicAdd(&a.g->collided, 1ull);
+    }
+}
+
+// ------------------------------------------------------------ relaxation label
+// One workgroup per listed cell: r = || (1/K) sum_replicas sum_pairs
+// 1/4 h(s^2) (|u|^2 I - 3 u u^T) ||_F / (N T), pairs from independent
+// re-pairings (domain 3, c3 = replica); s^2 = 8 pi n lnL dt dt_scale / |u|^3.
+template <typename R>
+__global__ __launch_bounds__(1024) void k_relax(RelaxArgs a, HugeScratch hs)
+{
+    __shared__ double red[6 * 16];
+    __shared__ uint32_t wtot[16];
+    const uint32_t count = a.count_dev ? *a.count_dev : (uint32_t)a.count;
+    const uint64_t step = a.step_dev ? *a.step_dev : a.step;
+    const R *vx = (const R *)a.v;
+    const R *vy = vx + a.n;
+    const R *vz = vy + a.n;
+    for (uint32_t item = blockIdx.x; item < count; item += gridDim.x) {
+        const int cell = a.list ? a.list[item] : (int)item;
+        const int lo = a.cell_start[cell];
+        const int n = a.cell_start[cell + 1] - lo;
+        if (n < 2) {
+            if (threadIdx.x == 0) a.r_out[cell] = 0.0;
+            continue;
+        }
+        // temperature of the cell
+        double s5[5] = {0, 0, 0, 0, 0};
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            const double x = vx[lo + i], y = vy[lo + i], z = vz[lo + i];
+            s5[1] += x;
+            s5[2] += y;
+            s5[3] += z;
+            s5[4] += x * x + y * y + z * z;
+        }
+        block_sum<5>(s5, red);
+        const double N = (double)n;
+        const double T = (s5[4] / N - (s5[1] * s5[1] + s5[2] * s5[2] + s5[3] * s5[3]) / (N * N)) / 3.0;
+        const double dens = a.density ? a.density[cell] : 1.0;
+        const double dts = a.dt_scale ? a.dt_scale[cell] : 1.0;
+        const double C = 8.0 * PI_D * dens * a.lnL * a.dt * dts;
+        double acc[6] = {0, 0, 0, 0, 0, 0};   // xx yy zz xy xz yz
+        for (int rep = 0; rep < a.replicas; ++rep) {
+            for (int i = threadIdx.x; i < n; i += blockDim.x)
+                hs.keys[lo + i] = draw4(a.seed, a.pid[lo + i], (uint32_t)step, 3u, (uint32_t)rep).x;
+            __syncthreads();
+            gsort_positions(hs, a.pid, lo, n, wtot);
+            for (int q = threadIdx.x; q < n / 2; q += blockDim.x) {
+                const int ia = lo + (int)hs.lst[lo + 2 * q], ib = lo + (int)hs.lst[lo + 2 * q + 1];
+                const double ux = (double)vx[ia] - (double)vx[ib];
+                const double uy = (double)vy[ia] - (double)vy[ib];
+                const double uz = (double)vz[ia] - (double)vz[ib];
+                const double uu = ux * ux + uy * uy + uz * uz;
+                if (uu == 0.0) continue;
+                const double hq = 0.25 * h_angle(C / (uu * sqrt(uu)));
+                acc[0] += hq * (uu - 3.0 * ux * ux);
+                acc[1] += hq * (uu - 3.0 * uy * uy);
+                acc[2] += hq * (uu - 3.0 * uz * uz);
+                acc[3] += hq * (-3.0 * ux * uy);
+                acc[4] += hq * (-3.0 * ux * uz);
+                acc[5] += hq * (-3.0 * uy * uz);
+            }
+            __syncthreads();
+        }
+        block_sum<6>(acc, red);
+        if (threadIdx.x == 0) {
+            const double K = (double)a.replicas;
+            double f2 = 0.0;
+            for (int c = 0; c < 3; ++c) f2 += (acc[c] / K) * (acc[c] / K);
+            for (int c = 3; c < 6; ++c) f2 += 2.0 * (acc[c] / K) * (acc[c] / K);
+            a.r_out[cell] = T > 0.0 ? sqrt(f2) / (N * T) : 0.0;
+        }
+        __syncthreads();
+    }
+}
+
+// Scores the judged cells: a judged cell the network wanted to skip is a
+// false skip when its relaxation reaches the tolerance.  With enough judged
+// skips and a false-skip fraction above max_false the gate switches itself off.
+__global__ void k_gate_score(DevGate *g, const int32_t *__restrict__ judge_list,
+                             const uint8_t *__restrict__ want, const double *__restrict__ r,
+                             double tol, double max_false, uint32_t min_judged)
+{
+    __shared__ unsigned long long s_w, s_f;
+    if (threadIdx.x == 0) {
+        s_w = 0;
+        s_f = 0;
+    }
+    __syncthreads();
+    const uint32_t cnt = g->judge_count;
+    for (uint32_t k = threadIdx.x; k < cnt; k += blockDim.x) {
+        const int j = judge_list[k];
+        if (want[j]) {
+            atomicAdd(&s_w, 1ull);
+            if (r[j] >= tol) atomicAdd(&s_f, 1ull);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        g->judged += cnt;
+        g->judged_want += s_w;
+        g->false_skip += s_f;
+        if (g->judged_want >= min_judged && (double)g->false_skip > max_false * (double)g->judged_want)
+            g->disabled = 1;
+        g->steps += 1;
+    }
+}
+
+__global__ void k_gate_end(DevGate *g)
+{
+    if (threadIdx.x == 0) g->have_moments = 1;
+}
+
+// ------------------------------------------------------------ training
+// One block: a tile of TS samples; forward, loss and backward with the
+// activations in LDS, partial gradients written per tile and summed in a
+// fixed order by k_reduce_grads (bitwise reproducible).
+constexpr int TS = 64;
+
+__global__ __launch_bounds__(256) void k_mlp_grad_tile(const float *__restrict__ params,
+                                                      const float *__restrict__ x,
+                                                      const float *__restrict__ y, int32_t B,
+                                                      int bf16, float *__restrict__ partial,
+                                                      float *__restrict__ loss_partial)
+{
+    __shared__ float P[NPARAM];
+    __shared__ float X[TS * 8];
+    __shared__ float Z1[TS * 64], A1[TS * 64], Z2[TS * 64], A2[TS * 64];
+    __shared__ float D3[TS];
+    __shared__ float Ls[TS];
+    const bool b16 = bf16 != 0;
+    load_params(P, params, b16);
+    const int s0 = blockIdx.x * TS;
+    const int ns = min(TS, B - s0);
+    for (int e = threadIdx.x; e < TS * 8; e += blockDim.x) {
+        const int s = e / 8;
+        const float v = s < ns ? x[(int64_t)(s0 + s) * 8 + (e % 8)] : 0.0f;
+        X[e] = b16 ? bf16r(v) : v;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < TS * 64; e += blockDim.x) {
+        const int s = e / 64, j = e % 64;
+        float z = P[OFF_B1 + j];
+        for (int i = 0; i < 8; ++i) z += X[s * 8 + i] * P[OFF_W1 + i * 64 + j];
+        Z1[e] = z;
+        const float r = z > 0.0f ? z : 0.0f;
+        A1[e] = b16 ? bf16r(r) : r;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < TS * 64; e += blockDim.x) {
+        const int s = e / 64, j = e % 64;
+        float z = P[OFF_B2 + j];
+        for (int i = 0; i < 64; ++i) z += A1[s * 64 + i] * P[OFF_W2 + i * 64 + j];
+        Z2[e] = z;
+        const float r = z > 0.0f ? z : 0.0f;
+        A2[e] = b16 ? bf16r(r) : r;
+    }
+    __syncthreads();
+    if (threadIdx.x < TS) {
+        const int s = threadIdx.x;
+        float d = 0.0f, l = 0.0f;
+        if (s < ns) {
+            float z = P[OFF_B3];
+            for (int j = 0; j < 64; ++j) z += A2[s * 64 + j] * P[OFF_W3 + j];
+            const float p = 1.0f / (1.0f + __expf(-z));
+            const float t = y[s0 + s];
+            l = fmaxf(z, 0.0f) - z * t + log1pf(__expf(-fabsf(z)));
+            d = (p - t) / (float)B;
+        }
+        D3[s] = b16 ? bf16r(d) : d;
+        Ls[s] = l;
+    }
+    __syncthreads();
+    float *G = partial + (int64_t)blockIdx.x * NPARAM;
+    // layer 3
+    if (threadIdx.x < 64) {
+        const int j = threadIdx.x;
+        float g = 0.0f;
+        for (int s = 0; s < TS; ++s) g += A2[s * 64 + j] * D3[s];
+        G[OFF_W3 + j] = g;
+    }
+    if (threadIdx.x == 64) {
+        float g = 0.0f, l = 0.0f;
+        for (int s = 0; s < TS; ++s) {
+            g += D3[s];
+            l += Ls[s];
+        }
+        G[OFF_B3] = g;
+        loss_partial[blockIdx.x] = l;
+    }
+    __syncthreads();
+    // delta of layer 2 (overwrites Z2)
+    for (int e = threadIdx.x; e < TS * 64; e += blockDim.x) {
+        const int s = e / 64, j = e % 64;
+        const float d = Z2[e] > 0.0f ? P[OFF_W3 + j] * D3[s] : 0.0f;
+        Z2[e] = b16 ? bf16r(d) : d;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
+        const int i = e / 64, j = e % 64;
+        float g = 0.0f;
+        for (int s = 0; s < TS; ++s) g += A1[s * 64 + i] * Z2[s * 64 + j];
+        G[OFF_W2 + e] = g;
+    }
+    if (threadIdx.x < 64) {
+        float g = 0.0f;
+        for (int s = 0; s < TS; ++s) g += Z2[s * 64 + threadIdx.x];
+        G[OFF_B2 + threadIdx.x] = g;
+    }
+    // delta of layer 1 (overwrites Z1)
+    for (int e = threadIdx.x; e < TS * 64; e += blockDim.x) {
+        const int s = e / 64, i = e % 64;
+        float d = 0.0f;
+        if (Z1[e] > 0.0f) {
+            for (int j = 0; j < 64; ++j) d += P[OFF_W2 + i * 64 + j] * Z2[s * 64 + j];
+        }
+        Z1[e] = b16 ? bf16r(d) : d;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 8 * 64; e += blockDim.x) {
+        const int i = e / 64, j = e % 64;
+        float g = 0.0f;
+        for (int s = 0; s < TS; ++s) g += X[s * 8 + i] * Z1[s * 64 + j];
+        G[OFF_W1 + e] = g;
+    }
+    if (threadIdx.x < 64) {
+        float g = 0.0f;
+        for (int s = 0; s < TS; ++s) g += Z1[s * 64 + threadIdx.x];
+        G[OFF_B1 + threadIdx.x] = g;
+    }
+}
+
+__global__ void k_reduce_grads(const float *__restrict__ partial, const float *__restrict__ loss_partial,
+                               int tiles, int32_t B, float *__restrict__ grad, float *__restrict__ loss)
+{
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < NPARAM; p += gridDim.x * blockDim.x) {
+        float g = 0.0f;
+        for (int t = 0; t < tiles; ++t) g += partial[(int64_t)t * NPARAM + p];
+        grad[p] = g;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && loss) {
+        float l = 0.0f;
+        for (int t = 0; t < tiles; ++t) l += loss_partial[t];
+        *loss = l / (float)B;
+    }
+}
+
+// Adam (Kingma & Ba) with bias correction, step t >= 1.
+__global__ void k_adam(float *__restrict__ params, float *__restrict__ m, float *__restrict__ v,
+                       const float *__restrict__ grad, int32_t t, float lr, float b1, float b2, float eps)
+{
+    const float c1 = 1.0f - powf(b1, (float)t), c2 = 1.0f - powf(b2, (float)t);
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < NPARAM; p += gridDim.x * blockDim.x) {
+        const float g = grad[p];
+        const float mm = b1 * m[p] + (1.0f - b1) * g;
+        const float vv = b2 * v[p] + (1.0f - b2) * g * g;
+        m[p] = mm;
+        v[p] = vv;
+        params[p] -= lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+    }
+}
+
+}  // namespace
+
+int launch_features(const double *moments, int32_t M, float *feat, uint8_t *valid, hipStream_t st)
+{
+    const int g = (M + 255) / 256 < 4096 ? (M + 255) / 256 : 4096;
+    hipLaunchKernelGGL(k_features, dim3(g > 0 ? g : 1), dim3(256), 0, st, moments, M, feat, valid);
+    HIP_OK(hipGetLastError());
+    return PIC_OK;
+}
+
+int launch_mlp_forward(const float *params, const float *x, int32_t B, int bf16, float *prob,
+                       hipStream_t st)
+{
+    if (B <= 0) return PIC_OK;
+    const int g = (B + 255) / 256 < 1024 ? (B + 255) / 256 : 1024;
+    hipLaunchKernelGGL(k_mlp_forward, dim3(g), dim3(256), 0, st, params, x, B, bf16, prob);
+    HIP_OK(hipGetLastError());
+    return PIC_OK;
+}
+
+size_t mlp_grad_scratch_floats(int32_t B)
+{
+    const int tiles = (B + TS - 1) / TS;
+    return (size_t)tiles * NPARAM + tiles + NPARAM + 64;
+}
+
+int launch_mlp_grad(const float *params, const float *x, const float *y, int32_t B, int bf16,
+                    float *scratch, float *grad, float *loss, hipStream_t st)
+{
+    const int tiles = (B + TS - 1) / TS;
+    float *partial = scratch;
+    float *lp = scratch + (size_t)tiles * NPARAM;
+    hipLaunchKernelGGL(k_mlp_grad_tile, dim3(tiles), dim3(256), 0, st, params, x, y, B, bf16, partial, lp);
+    hipLaunchKernelGGL(k_reduce_grads, dim3((NPARAM + 255) / 256), dim3(256), 0, st, partial, lp, tiles,
+                       B, grad, loss);
+    HIP_OK(hipGetLastError());
+    return PIC_OK;
+}
+
+int launch_adam(float *params, float *m, float *v, const float *grad, int32_t t, float lr,
+                hipStream_t st)
+{
+    hipLaunchKernelGGL(k_adam, dim3((NPARAM + 255) / 256), dim3(256), 0, st, params, m, v, grad, t, lr,
+                       0.9f, 0.999f, 1e-8f);
+    HIP_OK(hipGetLastError());
+    return PIC_OK;
+}
+
+int launch_gate(const GateArgs &a, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_gate_begin, dim3(1), dim3(64), 0, st, a.g);
+    const int g = (a.M + 255) / 256 < 2048 ? (a.M + 255) / 256 : 2048;
+    hipLaunchKernelGGL(k_gate, dim3(g > 0 ? g : 1), dim3(256), 0, st, a);
+    HIP_OK(hipGetLastError());
+    return PIC_OK;
+}
+
+int launch_gate_score(DevGate *g, const int32_t *judge_list, const uint8_t *want, const double *r,
+                      double tol, double max_false, uint32_t min_judged, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_gate_score, dim3(1), dim3(256), 0, st, g, judge_list, want, r, tol, max_false,
+                       min_judged);
+    HIP_OK(hipGetLastError());
+    return PIC_OK;
+}
+
+int launch_gate_end(DevGate *g, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_gate_end, dim3(1), dim3(64), 0, st, g);
+    HIP_OK(hipGetLastError());
+    return PIC_OK;
+}
+
+int launch_relax(int dtype, const RelaxArgs &a, int num_cu, hipStream_t st)
+{
+    const int g = num_cu;
+    if (dtype == PIC_F32)
+        hipLaunchKernelGGL(k_relax<float>, dim3(g), dim3(1024), 0, st, a, huge_scratch());
+    else
+        hipLaunchKernelGGL(k_relax<double>, dim3(g), dim3(1024), 0, st, a, huge_scratch());
+    HIP_OK(hipGetLastError());
+    return PIC_OK;
+}

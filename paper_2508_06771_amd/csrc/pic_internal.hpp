@@ -58,7 +58,12 @@ __device__ __forceinline__ W4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, ui
 __device__ __forceinline__ W4 draw4(uint64_t seed, uint32_t c0, uint32_t step, uint32_t domain,
                                     uint32_t c3)
 {
-    return philox10(c0, step, domain, c3, (uint32_t)seed, (uint32_t)(seed >> 32));
+    uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    // The seed is uniform: keep its round keys in two SGPRs per call.  The
+    // empty asm hides the value from the optimiser so the ten round keys of
+    // unrolled call sites are not all hoisted and kept live at once.
+    asm volatile("" : "+s"(k0), "+s"(k1));
+    return philox10(c0, step, domain, c3, k0, k1);
 }
 
 // U(x) = ((x >> 9) + 1/2) 2^-23: 24 significant bits, exact in binary32.
@@ -82,6 +87,8 @@ __device__ __forceinline__ double u01d(uint32_t x)
 __device__ __forceinline__ void scatter_dir(float &vx, float &vy, float &vz, const W4 &w,
                                             double mass_ratio)
 {
+    // no contraction: the fused and the stand-alone step round identically
+#pragma clang fp contract(off)
     const float ct = 1.0f - 2.0f * u01f(w.y);
     const float st = __builtin_sqrtf(fmaxf(0.0f, 1.0f - ct * ct));
     const float up = u01f(w.z);
@@ -100,6 +107,7 @@ __device__ __forceinline__ void scatter_dir(float &vx, float &vy, float &vz, con
 __device__ __forceinline__ void scatter_dir(double &vx, double &vy, double &vz, const W4 &w,
                                             double mass_ratio)
 {
+#pragma clang fp contract(off)
     const double ct = 1.0 - 2.0 * u01d(w.y);
     const double st = sqrt(fmax(0.0, 1.0 - ct * ct));
     const double ph = 2.0 * 3.14159265358979323846 * u01d(w.z);
@@ -161,6 +169,99 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x)
     return x;
 }
 
+// Block-wide exclusive scan of one value per thread (blockDim <= 1024);
+// wtot: LDS scratch of blockDim / 64 words.  Contains two barriers.
+__device__ __forceinline__ uint32_t block_excl(uint32_t x, uint32_t *wtot)
+{
+    const int lane = threadIdx.x & (PIC_WAVE - 1), wid = threadIdx.x / PIC_WAVE;
+    const int nw = blockDim.x / PIC_WAVE;
+    const uint32_t inc = wave_incl_scan(x);
+    if (lane == PIC_WAVE - 1) wtot[wid] = inc;
+    __syncthreads();
+    uint32_t off = 0;
+    for (int w = 0; w < nw; ++w)
+        if (w < wid) off += wtot[w];
+    __syncthreads();
+    return off + inc - x;
+}
+
+__device__ __forceinline__ uint32_t get16(const uint32_t *w, uint32_t b)
+{
+    return (w[b >> 1] >> ((b & 1u) * 16u)) & 0xFFFFu;
+}
+
+// ---------------------------------------------------------------------------
+// Per-particle global scratch for cells handled by one workgroup without the
+// LDS capacity limit, indexed by storage slot (regions of different cells
+// never overlap).
+// ---------------------------------------------------------------------------
+struct HugeScratch {
+    uint32_t *keys;    // [n] sort keys
+    uint32_t *cnt;     // [n] bucket counts, then offsets
+    uint32_t *lst;     // [n] bucket member lists, then slots in sorted order
+    uint32_t *pos;     // [n] arrival rank, then sorted position
+    uint32_t *w23;     // [2n] words 2 and 3 of the particle draw
+    uint8_t *cand;     // [n] null-collision candidate flags
+    void *pbuf;        // [n/2 + 2] pair records
+};
+const HugeScratch &huge_scratch();
+
+// Sorted positions of the members [lo, lo+n) of one cell by (keys, pid):
+// bucket b = (key * nb) >> 32 is monotone in the key, so buckets in order and
+// (key, pid) order inside a bucket give the full order.  keys[lo..) must be
+// set; on return pos[lo + i] is member i's position and lst[lo + p] the
+// member at position p.  One workgroup; contains barriers.
+__device__ __forceinline__ void gsort_positions(const HugeScratch &hs, const uint32_t *pid, int lo,
+                                                int n, uint32_t *wtot)
+{
+    const int T = blockDim.x;
+    const uint32_t nb = n >= 2 ? (uint32_t)(n / 2) : 1u;
+    for (int i = threadIdx.x; i < (int)nb; i += T) hs.cnt[lo + i] = 0u;
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += T) {
+        const uint32_t b = __umulhi(hs.keys[lo + i], nb);
+        hs.pos[lo + i] = atomicAdd(&hs.cnt[lo + b], 1u);
+    }
+    __syncthreads();
+    {
+        const int per = ((int)nb + T - 1) / T;
+        const int b0 = threadIdx.x * per;
+        uint32_t s = 0;
+        for (int q = 0; q < per; ++q)
+            if (b0 + q < (int)nb) s += hs.cnt[lo + b0 + q];
+        uint32_t run = block_excl(s, wtot);
+        for (int q = 0; q < per; ++q)
+            if (b0 + q < (int)nb) {
+                const uint32_t c = hs.cnt[lo + b0 + q];
+                hs.cnt[lo + b0 + q] = run;
+                run += c;
+            }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += T) {
+        const uint32_t b = __umulhi(hs.keys[lo + i], nb);
+        hs.lst[lo + hs.cnt[lo + b] + hs.pos[lo + i]] = (uint32_t)i;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += T) {
+        const uint32_t key = hs.keys[lo + i];
+        const uint32_t b = __umulhi(key, nb);
+        const uint32_t beg = hs.cnt[lo + b];
+        const uint32_t end = (b + 1 < nb) ? hs.cnt[lo + b + 1] : (uint32_t)n;
+        uint32_t rank = 0;
+        for (uint32_t m = beg; m < end; ++m) {
+            const uint32_t j = hs.lst[lo + m];
+            const uint32_t kj = hs.keys[lo + j];
+            if (kj < key) ++rank;
+            else if (kj == key && j != (uint32_t)i && pid[lo + j] < pid[lo + i]) ++rank;
+        }
+        hs.pos[lo + i] = beg + rank;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += T) hs.lst[lo + hs.pos[lo + i]] = (uint32_t)i;
+    __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
 // Host-side launch interfaces (implemented in the .hip files).
 // ---------------------------------------------------------------------------
@@ -185,6 +286,8 @@ struct RadixPass {
 enum { KT_CLASS0 = 0, KT_HUGE = 4, KT_CHECK = 5, KT_QUEUE = 6, KT_SORT = 7, KT_MCC = 8, KT_SLOTS = 16 };
 void ktime_begin(int slot, hipStream_t st);
 void ktime_end(int slot, hipStream_t st);
+bool ktime_pause();            // returns whether timing was on
+void ktime_resume(bool was);
 
 struct BinScratch {
     uint32_t *hist;     // (1 << bits) * nblocks
@@ -200,6 +303,8 @@ int radix_pass(const RadixPass &p, const BinScratch &s, hipStream_t st);
 int launch_bin_check(const int32_t *cell_of, int64_t n, int32_t n_cells, int32_t *cell_start,
                      DevFlags *flags, int set_unsorted, const int *gate, hipStream_t st);
 int launch_reset_flags(DevFlags *flags, hipStream_t st);
+int launch_set_step(uint64_t *step_dev, uint64_t value, hipStream_t st);
+int launch_step_inc(uint64_t *step_dev, hipStream_t st);
 int launch_copy32(uint32_t *dst, const uint32_t *src, int64_t n, const int *gate, hipStream_t st);
 
 // Work queue of cells by size class.
@@ -236,6 +341,64 @@ ClassCaps collide_caps(int dtype, size_t lds_per_block);
 // Global scratch of the multi-block ("huge") class, indexed by particle slot.
 size_t huge_scratch_bytes(int dtype, int64_t n);
 void set_huge_scratch(int dtype, int64_t n, void *base);
+
+// ---------------------------------------------------------------- learned gate
+struct DevGate {
+    unsigned long long steps, skipped, collided, judged, judged_want, false_skip;
+    int disabled, have_moments;
+    unsigned int judge_count;
+    unsigned int pad[7];
+};
+
+struct GateArgs {
+    const double *moments;   // M x 14 post-step sums of the previous step
+    const float *params;     // 4801 binary32 master parameters
+    int32_t M;
+    float thr;               // skip when the network's probability exceeds thr
+    int32_t kmax;            // at most kmax deferred steps in a row
+    uint64_t judge_thr;      // judged iff word0 of the cell's domain-2 draw < judge_thr
+    int bf16;
+    uint64_t seed, step;
+    const uint64_t *step_dev;
+    int32_t *k_acc;
+    uint8_t *skip;
+    double *dt_scale;
+    uint8_t *want;
+    float *prob;
+    int32_t *judge_list;
+    DevGate *g;
+};
+
+struct RelaxArgs {
+    const void *v;
+    int64_t n;
+    const int32_t *cell_start;
+    const uint32_t *pid;
+    const double *density;
+    const double *dt_scale;
+    double dt, lnL;
+    uint64_t seed, step;
+    const uint64_t *step_dev;
+    int replicas;
+    const int32_t *list;        // cells to evaluate (NULL: cells 0..count-1)
+    const uint32_t *count_dev;  // device count of list entries (NULL: count)
+    int32_t count;
+    double *r_out;              // indexed by cell
+};
+
+int launch_features(const double *moments, int32_t M, float *feat, uint8_t *valid, hipStream_t st);
+int launch_mlp_forward(const float *params, const float *x, int32_t B, int bf16, float *prob,
+                       hipStream_t st);
+size_t mlp_grad_scratch_floats(int32_t B);
+int launch_mlp_grad(const float *params, const float *x, const float *y, int32_t B, int bf16,
+                    float *scratch, float *grad, float *loss, hipStream_t st);
+int launch_adam(float *params, float *m, float *v, const float *grad, int32_t t, float lr,
+                hipStream_t st);
+int launch_gate(const GateArgs &a, hipStream_t st);
+int launch_gate_score(DevGate *g, const int32_t *judge_list, const uint8_t *want, const double *r,
+                      double tol, double max_false, uint32_t min_judged, hipStream_t st);
+int launch_relax(int dtype, const RelaxArgs &a, int num_cu, hipStream_t st);
+int launch_gate_end(DevGate *g, hipStream_t st);
 
 int launch_mcc(int dtype, void *v, const uint32_t *pid, int64_t n, uint64_t thr, double mass_ratio,
                uint64_t seed, uint64_t step, uint8_t *cand_out, hipStream_t st);

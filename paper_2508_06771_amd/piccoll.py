@@ -56,6 +56,18 @@ def _load():
         "coulomb_pairs": ([vp, vp, vp, i32, u64, u64, vp, vp], C.c_int),
         "pic_cell_moments": ([vp, C.c_int, vp, i64, vp, i32, vp], C.c_int),
         "pic_unsort": ([vp, C.c_int, vp, vp, vp, i64], C.c_int),
+        "pic_run_steps": ([vp, C.c_int, vp, vp, vp, i64, i32, f64, f64, vp, u64, u64, i64, u32],
+                          C.c_int),
+        "pic_features": ([vp, vp, i32, vp, vp], C.c_int),
+        "pic_relaxation": ([vp, C.c_int, vp, i64, vp, vp, i32, f64, f64, vp, vp, u64, u64, i32, vp],
+                           C.c_int),
+        "pic_mlp_forward": ([vp, vp, vp, i32, C.c_int, vp], C.c_int),
+        "pic_mlp_grad": ([vp, vp, vp, vp, i32, C.c_int, vp, vp], C.c_int),
+        "pic_mlp_train_step": ([vp, vp, vp, vp, i32, C.c_float, vp, vp, i32, C.c_int, vp], C.c_int),
+        "pic_gate_config": ([vp, vp, C.c_float, i32, f64, f64, i32, C.c_int], C.c_int),
+        "pic_gate_reset": ([vp], C.c_int),
+        "pic_gate_stats": ([vp, C.POINTER(C.c_int64)], C.c_int),
+        "pic_gate_state": ([vp, vp, vp, vp, vp], C.c_int),
         "pic_time_kernels": ([vp, C.c_int], C.c_int),
         "pic_kernel_times": ([vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)], C.c_int),
     }
@@ -71,7 +83,13 @@ lib = _load()
 EXPORTED = ["pic_create", "pic_destroy", "pic_strerror", "pic_sync", "pic_set_stream",
             "pic_bin_cells", "coulomb_collide", "pic_set_mcc", "pic_set_moments_out",
             "mcc_null_collide", "pic_philox", "coulomb_pairs", "pic_cell_moments", "pic_unsort",
-            "pic_time_kernels", "pic_kernel_times"]
+            "pic_time_kernels", "pic_kernel_times", "pic_run_steps", "pic_features",
+            "pic_relaxation", "pic_mlp_forward", "pic_mlp_grad", "pic_mlp_train_step",
+            "pic_gate_config", "pic_gate_reset", "pic_gate_stats", "pic_gate_state"]
+
+MLP_PARAMS = 4801
+GATE_STATS = ["steps", "skipped", "collided", "judged", "judged_want", "false_skip", "disabled",
+              "have_moments"]
 
 KT_SLOTS = ["class0", "class1", "class2", "class3", "huge", "check", "queue", "sort", "mcc"]
 
@@ -160,6 +178,16 @@ class Context:
                                  n_cells, dt, lnL, _p(density), seed, step, flags),
              "coulomb_collide")
 
+    def run_steps(self, v: torch.Tensor, cell_of: torch.Tensor, pid: torch.Tensor, n_cells: int,
+                  *, dt: float, lnL: float, seed: int, step0: int, nsteps: int, density=None,
+                  flags: int = 0):
+        """nsteps steps; after the first, replays of a captured HIP graph."""
+        assert v.dim() == 2 and v.shape[0] == 3
+        assert cell_of.dtype == torch.int32 and pid.dtype in (torch.int32, torch.uint32)
+        self._stream()
+        _chk(lib.pic_run_steps(self._h, _dt(v), _p(v), _p(cell_of), _p(pid), v.shape[1], n_cells,
+                               dt, lnL, _p(density), seed, step0, nsteps, flags), "pic_run_steps")
+
     def mcc_null_collide(self, v: torch.Tensor, pid: torch.Tensor, *, dt: float, sigma0: float,
                          n_neutral: float, mass_ratio: float, seed: int, step: int,
                          candidates: bool = False):
@@ -169,6 +197,71 @@ class Context:
         _chk(lib.mcc_null_collide(self._h, _dt(v), _p(v), _p(pid), n, dt, sigma0, n_neutral,
                                   mass_ratio, seed, step, _p(cand)), "mcc_null_collide")
         return cand[:n] if candidates else None
+
+    # -------------------------------------------------------------- learned gate
+    def features(self, moments: torch.Tensor):
+        self._stream()
+        M = moments.shape[0]
+        feat = torch.empty((M, 8), dtype=torch.float32, device=moments.device)
+        valid = torch.empty(M, dtype=torch.uint8, device=moments.device)
+        _chk(lib.pic_features(self._h, _p(moments), M, _p(feat), _p(valid)), "pic_features")
+        return feat, valid
+
+    def relaxation(self, v: torch.Tensor, cell_start: torch.Tensor, pid: torch.Tensor, *, dt: float,
+                   lnL: float, seed: int, step: int, replicas: int = 8, density=None,
+                   dt_scale=None):
+        self._stream()
+        M = cell_start.numel() - 1
+        r = torch.empty(M, dtype=torch.float64, device=v.device)
+        _chk(lib.pic_relaxation(self._h, _dt(v), _p(v), v.shape[1], _p(cell_start), _p(pid), M, dt,
+                                lnL, _p(density), _p(dt_scale), seed, step, replicas, _p(r)),
+             "pic_relaxation")
+        return r
+
+    def mlp_forward(self, params: torch.Tensor, x: torch.Tensor, bf16: bool = True):
+        self._stream()
+        prob = torch.empty(x.shape[0], dtype=torch.float32, device=x.device)
+        _chk(lib.pic_mlp_forward(self._h, _p(params), _p(x), x.shape[0], int(bf16), _p(prob)),
+             "pic_mlp_forward")
+        return prob
+
+    def mlp_grad(self, params, x, y, bf16: bool = True):
+        self._stream()
+        grad = torch.empty(MLP_PARAMS, dtype=torch.float32, device=x.device)
+        loss = torch.empty(1, dtype=torch.float32, device=x.device)
+        _chk(lib.pic_mlp_grad(self._h, _p(params), _p(x), _p(y), x.shape[0], int(bf16), _p(grad),
+                              _p(loss)), "pic_mlp_grad")
+        return grad, loss
+
+    def mlp_train_step(self, params, m, v, t: int, lr: float, x, y, bf16: bool = True):
+        self._stream()
+        loss = torch.empty(1, dtype=torch.float32, device=x.device)
+        _chk(lib.pic_mlp_train_step(self._h, _p(params), _p(m), _p(v), t, lr, _p(x), _p(y),
+                                    x.shape[0], int(bf16), _p(loss)), "pic_mlp_train_step")
+        return loss
+
+    def gate_config(self, params, threshold: float, k_max: int = 8, judge_fraction: float = 0.01,
+                    tolerance: float = 1e-3, replicas: int = 8, bf16: bool = True):
+        self._gate_params = params     # the library keeps the pointer
+        _chk(lib.pic_gate_config(self._h, _p(params), threshold, k_max, judge_fraction, tolerance,
+                                 replicas, int(bf16)), "pic_gate_config")
+
+    def gate_reset(self):
+        _chk(lib.pic_gate_reset(self._h), "pic_gate_reset")
+
+    def gate_stats(self):
+        out = (C.c_int64 * 8)()
+        _chk(lib.pic_gate_stats(self._h, out), "pic_gate_stats")
+        return dict(zip(GATE_STATS, list(out)))
+
+    def gate_state(self, n_cells: int, device="cuda"):
+        self._stream()
+        skip = torch.empty(n_cells, dtype=torch.uint8, device=device)
+        k = torch.empty(n_cells, dtype=torch.int32, device=device)
+        prob = torch.empty(n_cells, dtype=torch.float32, device=device)
+        mom = torch.empty((n_cells, 14), dtype=torch.float64, device=device)
+        _chk(lib.pic_gate_state(self._h, _p(skip), _p(k), _p(prob), _p(mom)), "pic_gate_state")
+        return skip, k, prob, mom
 
     # -------------------------------------------------------------- measurement
     def time_kernels(self, on: bool):

@@ -1,0 +1,134 @@
+"""Pins of the oracle's learned-gate references (features, label, network).
+
+* Features are Galilean invariant and take their textbook values for
+  Maxwellian (isotropic, no heat flux, zero excess kurtosis) and
+  bi-Maxwellian samples.
+* The label's per-pair expectation 1/4 h (|u|^2 I - 3 u u^T) matches Monte
+  Carlo of the realized change of sum v v^T.
+* The FP64 backpropagation matches central finite differences; the bfloat16
+  variant stays within bfloat16 rounding of it; Adam's first step has its
+  closed form -lr g / (|g| + eps).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import physics
+from paper_2508_06771_amd import workloads
+
+
+def one_cell(v):
+    return np.array([0, v.shape[1]], np.int32)
+
+
+def test_features_galilean_invariance():
+    rng = np.random.default_rng(0)
+    v = rng.standard_normal((3, 5000)) * np.array([[1.0], [0.7], [1.3]])
+    f0 = physics.cell_features(v, one_cell(v))
+    f1 = physics.cell_features(v + np.array([[3.0], [-2.0], [0.5]]), one_cell(v))
+    assert np.allclose(f0, f1, rtol=1e-9, atol=1e-9)
+
+
+def test_features_maxwellian_and_bimaxwellian():
+    rng = np.random.default_rng(1)
+    N = 400_000
+    v = rng.standard_normal((3, N)) * 1.7
+    f = physics.cell_features(v, one_cell(v))[0]
+    assert abs(f[0] - math.log(N)) < 1e-12
+    assert abs(f[1] - math.log(1.7 ** 2)) < 5 * math.sqrt(2 / (3 * N))
+    for k in (2, 3, 4):
+        assert abs(f[k] - 1.0) < 5 * math.sqrt(2 / N) * 1.5
+    assert f[5] < 5 * math.sqrt(2 / N) * 2
+    assert f[6] < 5 * math.sqrt(15 / N)
+    assert abs(f[7]) < 5 * math.sqrt(96 / 225 / N) * 3
+    b = workloads.bi_maxwellian(rng, N)
+    fb = physics.cell_features(b, one_cell(b))[0]
+    assert abs(fb[4] - 1.5) < 0.01 and abs(fb[2] - 0.75) < 0.01
+    # <|c|^4> = 3 sum s_a^4 + sum_{a != b} s_a^2 s_b^2 = 15.75 for (0.75, 0.75, 1.5): 15.75/15 - 1
+    assert abs(fb[7] - 0.05) < 0.01
+    assert np.all(np.isnan(physics.cell_features(v[:, :1], one_cell(v[:, :1]))))
+
+
+@pytest.mark.parametrize("umag", [0.4, 1.2])
+def test_label_pair_expectation_monte_carlo(orc, umag):
+    """E[change of v_a v_a^T + v_b v_b^T] over one collision = 1/4 h (|u|^2 I - 3 u u^T)."""
+    u = np.array([0.2, 0.9, -0.4])
+    u = u / np.linalg.norm(u) * umag
+    n_cells = 300_000
+    dt = 20 * workloads.DT
+    v = np.zeros((3, 2 * n_cells))
+    v[:, 0::2] = (0.5 * u + np.array([0.1, 0.0, 0.3]))[:, None]
+    v[:, 1::2] = (-0.5 * u + np.array([0.1, 0.0, 0.3]))[:, None]
+    cell = np.repeat(np.arange(n_cells, dtype=np.int32), 2)
+    pid = np.arange(2 * n_cells, dtype=np.uint32)
+    v0 = v.copy()
+    orc.step(v, cell, pid, n_cells, dt=dt, lnL=10.0, seed=9, step=0)
+
+    def svv(x):
+        a, b = x[:, 0::2], x[:, 1::2]
+        return np.einsum("in,jn->nij", a, a) + np.einsum("in,jn->nij", b, b)
+
+    d = svv(v) - svv(v0)
+    s2 = orc.ta_s2(umag, 1.0, 10.0, dt)
+    ref = physics.expected_pair_change(u[None, :], np.array([s2]))[0]
+    mean = d.mean(axis=0)
+    sd = d.reshape(n_cells, 9).std(axis=0).reshape(3, 3) / math.sqrt(n_cells)
+    assert np.all(np.abs(mean - ref) < 5 * sd + 1e-14), (mean, ref)
+    assert abs(np.trace(ref)) < 1e-15
+
+
+def test_relaxation_orders_cells(orc):
+    """A near-isotropic cell relaxes less per step than a strongly anisotropic one."""
+    rng = np.random.default_rng(3)
+    iso = rng.standard_normal((3, 2000))
+    ani = workloads.bi_maxwellian(rng, 2000, t_par=2.0, t_perp=0.5)
+    v = np.ascontiguousarray(np.concatenate([iso, ani], axis=1))
+    cs = np.array([0, 2000, 4000], np.int32)
+    pid = np.arange(4000, dtype=np.uint32)
+    r = physics.relaxation(v, cs, pid, dt=workloads.DT, lnL=10.0, seed=0, step=0, replicas=2)
+    assert r[1] > 5 * r[0] and r[1] > 1e-3
+
+
+def rand_params(rng, scale=0.3):
+    return [rng.standard_normal(s) * scale for s in physics.mlp_init_shapes()]
+
+
+def test_backprop_matches_finite_differences():
+    rng = np.random.default_rng(4)
+    params = rand_params(rng)
+    x = rng.standard_normal((32, 8))
+    y = (rng.uniform(size=32) < 0.5).astype(float)
+    loss, grads = physics.mlp_bce_grad(params, x, y)
+    flat = physics.pack_params(params)
+    g = physics.pack_params(grads)
+    idx = rng.choice(flat.size, 60, replace=False)
+    eps = 1e-6
+    for i in idx:
+        fp, fm = flat.copy(), flat.copy()
+        fp[i] += eps
+        fm[i] -= eps
+        lp, _ = physics.mlp_bce_grad(physics.unpack_params(fp), x, y)
+        lm, _ = physics.mlp_bce_grad(physics.unpack_params(fm), x, y)
+        fd = (lp - lm) / (2 * eps)
+        assert abs(fd - g[i]) < 1e-7 + 1e-5 * abs(g[i]), (i, fd, g[i])
+
+
+def test_bf16_gradient_close_to_fp64():
+    rng = np.random.default_rng(5)
+    params = rand_params(rng)
+    x = rng.standard_normal((256, 8))
+    y = (rng.uniform(size=256) < 0.3).astype(float)
+    _, g64 = physics.mlp_bce_grad(params, x, y)
+    _, g16, _ = physics.mlp_bce_grad_bf16(physics.pack_params(params), x, y)
+    g64 = physics.pack_params(g64)
+    assert np.linalg.norm(g16 - g64) / np.linalg.norm(g64) < 3e-2
+
+
+def test_adam_first_step_closed_form():
+    rng = np.random.default_rng(6)
+    p = [rng.standard_normal(5)]
+    g = [rng.standard_normal(5)]
+    out, m, v = physics.adam_update(p, g, [np.zeros(5)], [np.zeros(5)], 1, 1e-3)
+    assert np.allclose(out[0], p[0] - 1e-3 * g[0] / (np.abs(g[0]) + 1e-8), rtol=1e-12)
+    assert np.allclose(m[0], 0.1 * g[0]) and np.allclose(v[0], 0.001 * g[0] ** 2)
