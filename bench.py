@@ -78,6 +78,227 @@ def cpu_baseline(target_s=10.0, n_cells=512):
                       f"{steps} steady-state steps in {el:.1f} s, Coulomb + MCC, FP64"}
 
 
+def _timed(torch, fn):
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    fn()
+    e.record()
+    torch.cuda.synchronize()
+    return s.elapsed_time(e)
+
+
+def _line(value, ms, args, dtype, config, **extra):
+    out = {"metric": METRIC, "value": value, "unit": "electron-updates/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+           "config": config}
+    out.update(extra)
+    return out
+
+
+def temperatures(torch, v, cell=None):
+    c = v.double() - v.double().mean(dim=1, keepdim=True)
+    tz = float((c[2] ** 2).mean())
+    tp = float(0.5 * ((c[0] ** 2).mean() + (c[1] ** 2).mean()))
+    return tz, tp
+
+
+def bench_c3(args):
+    """16,384 cells with log-normal populations (median 2000, clipped to
+    [10, 200000], ~50M electrons): default routing vs autotuned routing, eager
+    launches vs graph replays."""
+    import numpy as np
+    import torch
+
+    from paper_2508_06771_amd import piccoll, workloads
+    w = workloads.c3(0)
+    v = torch.from_numpy(w.v).cuda()
+    cell = torch.from_numpy(w.cell_of).cuda()
+    pid = torch.from_numpy(w.pid.view(np.int32)).cuda()
+    n = w.n
+    ctx = piccoll.Context(0)
+    ctx.set_mcc(w.sigma0, w.n_neutral, 0.0)
+    fl = piccoll.FUSE_MCC
+    k = [0]
+
+    def eager(nsteps):
+        for _ in range(nsteps):
+            ctx.coulomb_collide(v, cell, pid, w.n_cells, dt=w.dt, lnL=w.lnL, seed=0, step=k[0],
+                                flags=fl)
+            k[0] += 1
+
+    def graph(nsteps):
+        ctx.run_steps(v, cell, pid, w.n_cells, dt=w.dt, lnL=w.lnL, seed=0, step0=k[0],
+                      nsteps=nsteps, flags=fl | piccoll.ASSUME_SORTED)
+        k[0] += nsteps
+
+    rebin_ms = _timed(torch, lambda: eager(1))
+    eager(max(args.warmup - 1, 0))
+    ctx.time_kernels(True)
+    ctx.kernel_times()
+    ms_default = _timed(torch, lambda: eager(args.steps)) / args.steps
+    kt = ctx.kernel_times()
+    ctx.time_kernels(False)
+    choice = ctx.autotune(v, cell, pid, w.n_cells, dt=w.dt, lnL=w.lnL, flags=fl)
+    eager(2)
+    ms_tuned = _timed(torch, lambda: eager(args.steps)) / args.steps
+    graph(2)
+    ms_graph = _timed(torch, lambda: graph(args.steps)) / args.steps
+    ctx.sync()
+    counts = np.bincount(w.cell_of, minlength=w.n_cells)
+    best = min(ms_tuned, ms_graph)
+    hbm = n * (BYTES_CHECK + BYTES_COLLIDE) / (best * 1e-3) / 1e9
+    ctx.close()
+    return _line(n / (best * 1e-3), best, args, "f32",
+                 {"workload": f"16384 cells, log-normal counts (median 2000, clip 10..200000), "
+                              f"{n} electrons, FP32, Coulomb + fused MCC", "n_electrons": n,
+                  "max_cell": int(counts.max()),
+                  "share_in_cells_over_10240": float(counts[counts > 10240].sum() / n)},
+                 ms_default_routing_eager=ms_default, ms_autotuned_eager=ms_tuned,
+                 ms_autotuned_graph=ms_graph, autotune_choice=choice, rebin_step_ms=rebin_ms,
+                 hbm_frac_step=round(hbm / HBM_PEAK_GBS, 4),
+                 kernel_ms_per_step_default={kk: round(t / c, 5) for kk, (t, c) in kt.items()})
+
+
+def bench_c4(args):
+    """Precision study: 32,768 cells x 3,052 electrons (100M), c1's
+    bi-Maxwellian; binary32, binary32 + FP64 conservation correction, binary64.
+    Energy drift and the isotropisation T_par/T_perp after the timed steps;
+    64 sampled cells re-run by the FP64 oracle from the same initial state."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from oracle import physics
+    from paper_2508_06771_amd import piccoll, workloads
+    w = workloads.c4(0, dtype=np.float64)
+    n = w.n
+    rng = np.random.default_rng(0)
+    sample = np.sort(rng.choice(w.n_cells, 64, replace=False))
+    sel = np.isin(w.cell_of, sample)
+    remap = np.full(w.n_cells, -1, np.int32)
+    remap[sample] = np.arange(64, dtype=np.int32)
+    ov = np.ascontiguousarray(w.v[:, sel])
+    oc, op = remap[w.cell_of[sel]].copy(), w.pid[sel].copy()
+    S = args.steps
+    for k in range(S + 1):
+        oracle.step(ov, oc, op, 64, dt=w.dt, lnL=w.lnL, seed=0, step=k)
+    ctx = piccoll.Context(0)
+    results = {}
+    for name, dt_, fl in (("f32", torch.float32, 0), ("f32_fix", torch.float32, piccoll.CONSERVE_FIX),
+                          ("f64", torch.float64, 0)):
+        v = torch.from_numpy(w.v).to(dt_).cuda()
+        cell = torch.from_numpy(w.cell_of).cuda()
+        pid = torch.from_numpy(w.pid.view(np.int32)).cuda()
+        ctx.coulomb_collide(v, cell, pid, w.n_cells, dt=w.dt, lnL=w.lnL, seed=0, step=0, flags=fl)
+        ctx.sync()
+        E0 = energy(v)
+        t0 = temperatures(torch, v)
+        ms = _timed(torch, lambda: ctx.run_steps(v, cell, pid, w.n_cells, dt=w.dt, lnL=w.lnL, seed=0,
+                                                 step0=1, nsteps=S,
+                                                 flags=fl | piccoll.ASSUME_SORTED)) / S
+        ctx.sync()
+        E1 = energy(v)
+        t1 = temperatures(torch, v)
+        opa, ope = physics.isotropisation_rk4(t0[0], t0[1], w.dt, S)
+        gsel = torch.from_numpy(np.isin(cell.cpu().numpy(), sample)).cuda()
+        gv = v[:, gsel].double().cpu().numpy()
+        err = float(np.max(np.max(np.abs(gv - ov), axis=0) /
+                           np.maximum(np.linalg.norm(ov, axis=0), 1e-3)))
+        results[name] = {"ms_per_step": ms, "updates_per_s": n / (ms * 1e-3),
+                         "energy_drift": abs(E1 - E0) / E0,
+                         "tpar_over_tperp": t1[0] / t1[1], "ode_tpar_over_tperp": opa[-1] / ope[-1],
+                         "sampled_cells_max_rel_err_vs_oracle": err}
+        del v, cell, pid
+        torch.cuda.empty_cache()
+    ctx.close()
+    r = results["f32_fix"]
+    return _line(r["updates_per_s"], r["ms_per_step"], args, "f32",
+                 {"workload": f"32768 cells x 3052 electrons ({n}), bi-Maxwellian T_par = 2 T_perp, "
+                              f"{S} steps per variant, graph replays", "n_electrons": n},
+                 precision=results)
+
+
+def _cell_ratio(ctx, torch, v, cell, n_cells):
+    """Per-cell T_par / T_perp (z parallel) from the FP64 moment sums."""
+    cs, _ = ctx.bin_cells(cell, n_cells)
+    m = ctx.cell_moments(v, cs).cpu().numpy()
+    N = m[:, 0]
+    V = m[:, 1:4] / N[:, None]
+    T = m[:, 4:7] / N[:, None] - V ** 2
+    return T[:, 2] / (0.5 * (T[:, 0] + T[:, 1]))
+
+
+def bench_c5(args):
+    """Learned sub-cycling on 65,536 cells x 2,000 electrons (131M, FP32): 70%
+    near-Maxwellian cells, 15% Maxwellian + beam, 15% bi-Maxwellian with
+    anisotropy 1..4.  The same K steps from the same state with the plain
+    operator and with the gate (1% judged cells, at most 8 deferred steps);
+    speedup, judged false skips, energy drift and the per-cell T_par/T_perp
+    difference to the plain run."""
+    import numpy as np
+    import torch
+
+    from paper_2508_06771_amd import piccoll, workloads
+    path = args.gate_params or os.path.join(ROOT, "paper_2508_06771_amd", "gate_params.npy")
+    params = torch.from_numpy(np.load(path)).cuda()
+    meta = json.load(open(os.path.splitext(path)[0] + ".json"))
+    w = workloads.c5(0)
+    n = w.n
+    ctx = piccoll.Context(0)
+    K = args.steps
+    res = {}
+    for mode in ("plain", "gated"):
+        v = torch.from_numpy(w.v).cuda()
+        cell = torch.from_numpy(w.cell_of).cuda()
+        pid = torch.from_numpy(w.pid.view(np.int32)).cuda()
+        fl = 0
+        if mode == "gated":
+            ctx.gate_config(params, meta["threshold"], k_max=8, judge_fraction=0.01,
+                            tolerance=meta["tolerance"], replicas=8, bf16=True)
+            ctx.gate_reset()
+            fl = piccoll.GATE
+        ctx.coulomb_collide(v, cell, pid, w.n_cells, dt=w.dt, lnL=w.lnL, seed=0, step=0, flags=fl)
+        ctx.sync()
+        r0 = _cell_ratio(ctx, torch, v, cell, w.n_cells)
+        E0 = energy(v)
+        ctx.run_steps(v, cell, pid, w.n_cells, dt=w.dt, lnL=w.lnL, seed=0, step0=1, nsteps=2,
+                      flags=fl | piccoll.ASSUME_SORTED)
+        ms = _timed(torch, lambda: ctx.run_steps(v, cell, pid, w.n_cells, dt=w.dt, lnL=w.lnL,
+                                                 seed=0, step0=3, nsteps=K,
+                                                 flags=fl | piccoll.ASSUME_SORTED)) / K
+        ctx.sync()
+        res[mode] = {"ms_per_step": ms, "energy_drift": abs(energy(v) - E0) / E0,
+                     "ratio_start": r0, "ratio_end": _cell_ratio(ctx, torch, v, cell, w.n_cells)}
+        if mode == "gated":
+            res[mode]["gate"] = ctx.gate_stats()
+        del v, cell, pid
+        torch.cuda.empty_cache()
+    ctx.close()
+    kind = w.meta["kind"]
+    dr = np.abs(res["gated"]["ratio_end"] - res["plain"]["ratio_end"])
+    relax = np.abs(res["plain"]["ratio_start"] - res["plain"]["ratio_end"])
+    g = res["gated"]["gate"]
+    out_kind = {}
+    for k, name in enumerate(("near_maxwellian", "maxwellian_beam", "bi_maxwellian")):
+        sel = kind == k
+        out_kind[name] = {"mean_abs_ratio_diff_vs_plain": float(dr[sel].mean()),
+                          "mean_plain_relaxation_of_ratio": float(relax[sel].mean())}
+    speed = res["plain"]["ms_per_step"] / res["gated"]["ms_per_step"]
+    return _line(n / (res["gated"]["ms_per_step"] * 1e-3), res["gated"]["ms_per_step"], args,
+                 "f32", {"workload": f"65536 cells x 2000 electrons ({n}), mixed cells, FP32, "
+                                     f"Coulomb only, learned gate (threshold {meta['threshold']:.4f}, "
+                                     f"tolerance {meta['tolerance']}, 1% judged, k_max 8)",
+                         "n_electrons": n},
+                 speedup_over_plain=speed, ms_plain=res["plain"]["ms_per_step"],
+                 skipped_fraction=g["skipped"] / max(1, g["skipped"] + g["collided"]),
+                 judged=g["judged"], judged_false_skips=g["false_skip"],
+                 judged_want_skip=g["judged_want"], gate_switched_off=g["disabled"],
+                 energy_drift_plain=res["plain"]["energy_drift"],
+                 energy_drift_gated=res["gated"]["energy_drift"], by_cell_kind=out_kind)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +307,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"],
+                    help="c2: the headline configuration; c3: log-normal cell sizes, autotuned "
+                         "routing, graph replays; c4: precision study; c5: learned gate vs plain")
+    ap.add_argument("--graph", action="store_true", help="time graph replays (pic_run_steps)")
+    ap.add_argument("--gate-params", default=None, help="trained gate parameters (.npy) for c5")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the collision step has no cross-GPU exchange "
@@ -97,6 +323,11 @@ def main():
     import torch
 
     from paper_2508_06771_amd import piccoll, workloads
+
+    if args.workload != "c2":
+        out = {"c3": bench_c3, "c4": bench_c4, "c5": bench_c5}[args.workload](args)
+        print(json.dumps(out), flush=True)
+        return
 
     w = workloads.c2(0)
     v = torch.from_numpy(w.v).cuda()
@@ -125,15 +356,19 @@ def main():
     E0 = energy(v)
     k0 = max(args.warmup, 1)
 
-    timing = not args.no_kernel_timing
+    timing = not args.no_kernel_timing and not args.graph
     if timing:
         ctx.time_kernels(True)
         ctx.kernel_times()
     torch.cuda.synchronize()
     s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     s.record()
-    for k in range(args.steps):
-        step(k0 + k)
+    if args.graph:
+        ctx.run_steps(v, cell, pid, w.n_cells, dt=w.dt, lnL=w.lnL, seed=0, step0=k0,
+                      nsteps=args.steps, flags=flags | piccoll.ASSUME_SORTED)
+    else:
+        for k in range(args.steps):
+            step(k0 + k)
     e.record()
     torch.cuda.synchronize()
     ms_total = s.elapsed_time(e)
@@ -181,6 +416,7 @@ def main():
         "step_algorithmic_gbs": round(step_gbs, 1),
         "algorithmic_bytes_per_electron": BYTES_CHECK + BYTES_COLLIDE,
         "copy_probe_gbs": round(copy_gbs, 1),
+        "launch": "graph" if args.graph else "eager",
         "rebin_step_ms": round(rebin_ms, 4),
         "energy_drift": abs(E1 - E0) / E0,
         "kernel_ms_per_step": {k: round(t / c, 5) for k, (t, c) in kt.items()},

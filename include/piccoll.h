@@ -215,6 +215,22 @@ int pic_gate_stats(pic_ctx *ctx, int64_t *out);
  * k_acc[n_cells], prob[n_cells], moments[14 n_cells]. */
 int pic_gate_state(pic_ctx *ctx, uint8_t *skip, int32_t *k_acc, float *prob, double *moments);
 
+/* Batching.  Cells go to size classes (workgroup-per-cell kernels of 256,
+ * 512 and 1024 threads holding up to 512 / 2048 / 4096 / 10240 members in
+ * binary32, 512 / 2048 / 4096 / 6144 in binary64, and a multi-block class
+ * beyond), each a persistent kernel draining its work list.  pic_autotune
+ * times candidate routing thresholds and resident-workgroup counts for the
+ * given state on a scratch copy (the caller's arrays are not modified; it
+ * synchronises and allocates) and keeps the fastest for later steps of this
+ * dtype on the context.  If the environment variable PICCOLL_TUNE_CACHE
+ * names a file, choices are read from and appended to it as JSON lines keyed
+ * by (device architecture, dtype, n, n_cells, flags, histogram of log2 cell
+ * sizes).  *choice_out (nullable) receives the chosen candidate index.
+ * Flags PIC_GATE, PIC_MOMENTS and PIC_ASSUME_SORTED are ignored here. */
+int pic_autotune(pic_ctx *ctx, int dtype, const void *v, const int32_t *cell_of,
+                 const uint32_t *pid, int64_t n, int32_t n_cells, double dt, double lnLambda,
+                 uint32_t flags, int32_t *choice_out);
+
 /* ---------------------------------------------------------------- measurement */
 
 /* on != 0: record HIP events around the library's kernel launches on the

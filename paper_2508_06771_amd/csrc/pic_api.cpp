@@ -3,7 +3,11 @@
 #include <math.h>
 #include <string.h>
 
+#include <stdio.h>
+#include <stdlib.h>
+
 #include <new>
+#include <string>
 #include <vector>
 
 #include "pic_internal.hpp"
@@ -39,6 +43,9 @@ struct pic_ctx {
     int32_t *gate_k = nullptr, *gate_judge = nullptr;
     uint8_t *gate_skip = nullptr, *gate_want = nullptr;
     float *gate_prob = nullptr;
+    // autotuned class thresholds / grid sizes per dtype
+    ClassCaps tuned[2];
+    bool tuned_valid[2] = {false, false};
 };
 
 namespace {
@@ -648,7 +655,7 @@ static int step_enqueue(pic_ctx *c, const StepArgs &s, hipStream_t st, const uin
         RC(launch_bin_check(s.cell_of, n, n_cells, cs, c->flags, 0, &c->flags->unsorted, st));
         ktime_end(KT_SORT, st);
     }
-    const ClassCaps caps = collide_caps(dtype, c->lds_max);
+    const ClassCaps caps = c->tuned_valid[dtype] ? c->tuned[dtype] : collide_caps(dtype, c->lds_max);
     ktime_begin(KT_QUEUE, st);
     RC(launch_build_queue(cs, n_cells, caps, lists, c->flags, st));
     ktime_end(KT_QUEUE, st);
@@ -776,6 +783,8 @@ int pic_run_steps(pic_ctx *c, int dtype, void *v, int32_t *cell_of, uint32_t *pi
     put(&c->gate_replicas, sizeof(int));
     put(&c->gate_bf16, sizeof(int));
     put(&c->gate_mem, sizeof(void *));
+    put(&c->tuned_valid[dtype == PIC_F64], sizeof(bool));
+    put(&c->tuned[dtype == PIC_F64], sizeof(ClassCaps));
     if (!c->exec || kl != c->graph_key_len || memcmp(key, c->graph_key, kl) != 0) {
         if (c->exec) {
             CK(hipGraphExecDestroy(c->exec));
@@ -881,6 +890,170 @@ int pic_unsort(pic_ctx *c, int dtype, void *v, uint32_t *pid, int32_t *cell_of, 
     const size_t es = dtype == PIC_F32 ? 4 : 8;
     RC(ensure_ws(c, (size_t)n * (3 * es + 4) + 1024));
     return launch_unsort(dtype, v, pid, cell_of, n, c->ws, c->stream);
+}
+
+static std::vector<ClassCaps> tune_candidates(const ClassCaps &b)
+{
+    std::vector<ClassCaps> v;
+    auto add = [&](ClassCaps c) { v.push_back(c); };
+    add(b);
+    ClassCaps c = b;
+    c.cap[0] = b.cap[0] / 2;                  // fewer cells on the 256-thread class
+    add(c);
+    c = b;
+    c.cap[2] = b.cap[1];                      // 2049..4096-member cells on the largest class
+    add(c);
+    c = b;
+    c.cap[1] = b.cap[0];                      // 513..2048-member cells on the 1024-thread classes
+    add(c);
+    c = b;
+    c.blocks_per_cu[3] = 2;                   // two resident workgroups per CU on the largest class
+    add(c);
+    c = b;
+    c.blocks_per_cu[0] = 16;
+    c.blocks_per_cu[1] = 8;
+    add(c);
+    c = b;
+    c.blocks_per_cu[4] = 2;
+    add(c);
+    return v;
+}
+
+int pic_autotune(pic_ctx *c, int dtype, const void *v, const int32_t *cell_of, const uint32_t *pid,
+                 int64_t n, int32_t n_cells, double dt, double lnLambda, uint32_t flags,
+                 int32_t *choice_out)
+{
+    if (!c) return PIC_ERR_ARG;
+    flags &= ~(uint32_t)(PIC_GATE | PIC_MOMENTS | PIC_ASSUME_SORTED);
+    StepArgs s = {dtype, nullptr, nullptr, nullptr, n, n_cells, dt, lnLambda, nullptr, 0, 0, flags};
+    s.v = (void *)v;
+    s.cell_of = (int32_t *)cell_of;
+    s.pid = (uint32_t *)pid;
+    RC(step_check(c, s));
+    CK(hipSetDevice(c->device));
+    const size_t es = dtype == PIC_F32 ? 4 : 8;
+    const int di = dtype == PIC_F64;
+    // a scratch copy of the state: the caller's arrays are not modified
+    void *copy = nullptr;
+    const size_t vb = (size_t)n * 3 * es, ib = (size_t)n * 4;
+    if (hipMalloc(&copy, vb + 2 * ib + 1024) != hipSuccess) {
+        (void)hipGetLastError();
+        return PIC_ERR_NOMEM;
+    }
+    Bump b(copy);
+    StepArgs t = s;
+    t.v = b.take(vb);
+    t.cell_of = (int32_t *)b.take(ib);
+    t.pid = (uint32_t *)b.take(ib);
+    int rc = PIC_OK;
+    std::vector<int32_t> hcs((size_t)n_cells + 1);
+    std::string key;
+    const ClassCaps base = collide_caps(dtype, c->lds_max);
+    const std::vector<ClassCaps> cands = tune_candidates(base);
+    int best = 0;
+    float best_ms = 1e30f;
+    bool cached = false;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    do {
+        if (hipMemcpyAsync(t.v, v, vb, hipMemcpyDeviceToDevice, c->stream) != hipSuccess ||
+            hipMemcpyAsync(t.cell_of, cell_of, ib, hipMemcpyDeviceToDevice, c->stream) != hipSuccess ||
+            hipMemcpyAsync(t.pid, pid, ib, hipMemcpyDeviceToDevice, c->stream) != hipSuccess) {
+            rc = PIC_ERR_HIP;
+            break;
+        }
+        c->tuned_valid[di] = false;
+        if ((rc = collide_common(c, t)) != PIC_OK) break;     // re-bins the copy
+        // the histogram of log2 cell sizes keys the cache
+        int32_t *cs = (int32_t *)c->ws;
+        if (hipMemcpyAsync(hcs.data(), cs, hcs.size() * 4, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+            hipStreamSynchronize(c->stream) != hipSuccess) {
+            rc = PIC_ERR_HIP;
+            break;
+        }
+        long long hist[34] = {0};
+        for (int32_t j = 0; j < n_cells; ++j) {
+            const int64_t cnt = hcs[j + 1] - hcs[j];
+            int bkt = 0;
+            while (bkt < 33 && ((int64_t)1 << bkt) < cnt) ++bkt;
+            hist[bkt] += 1;
+        }
+        hipDeviceProp_t prop;
+        const char *arch = hipGetDeviceProperties(&prop, c->device) == hipSuccess ? prop.gcnArchName : "?";
+        char buf[512];
+        snprintf(buf, sizeof(buf), "%s|%d|%lld|%d|%u|", arch, dtype, (long long)n, n_cells, flags);
+        key = buf;
+        for (int k = 0; k < 34; ++k)
+            if (hist[k]) {
+                snprintf(buf, sizeof(buf), "%d:%lld,", k, hist[k]);
+                key += buf;
+            }
+        const char *path = getenv("PICCOLL_TUNE_CACHE");
+        if (path) {
+            FILE *f = fopen(path, "r");
+            if (f) {
+                char line[2048];
+                while (fgets(line, sizeof(line), f)) {
+                    // line: {"key": "<key>", "choice": <k>, "ms": <t>}
+                    const std::string ln(line);
+                    const std::string pre = "{\"key\": \"" + key + "\", \"choice\": ";
+                    if (ln.compare(0, pre.size(), pre) == 0) {
+                        const int ch = atoi(ln.c_str() + pre.size());
+                        if (ch >= 0 && ch < (int)cands.size()) {
+                            best = ch;
+                            cached = true;
+                        }
+                    }
+                }
+                fclose(f);
+            }
+        }
+        if (cached) break;
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+            rc = PIC_ERR_HIP;
+            break;
+        }
+        t.flags |= PIC_ASSUME_SORTED;
+        for (size_t k = 0; k < cands.size() && rc == PIC_OK; ++k) {
+            c->tuned[di] = cands[k];
+            c->tuned_valid[di] = true;
+            if ((rc = collide_common(c, t)) != PIC_OK) break;   // warm-up
+            (void)hipEventRecord(e0, c->stream);
+            for (int r = 0; r < 3 && rc == PIC_OK; ++r) {
+                t.step = 1 + r;
+                rc = collide_common(c, t);
+            }
+            (void)hipEventRecord(e1, c->stream);
+            float ms = 0.0f;
+            if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                rc = PIC_ERR_HIP;
+                break;
+            }
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = (int)k;
+            }
+        }
+        if (rc == PIC_OK && path) {
+            FILE *f = fopen(path, "a");
+            if (f) {
+                fprintf(f, "{\"key\": \"%s\", \"choice\": %d, \"ms\": %.5f}\n", key.c_str(), best,
+                        best_ms / 3.0f);
+                fclose(f);
+            }
+        }
+    } while (0);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(copy);
+    if (rc != PIC_OK) {
+        c->tuned_valid[di] = false;
+        return rc;
+    }
+    c->tuned[di] = cands[best];
+    c->tuned_valid[di] = true;
+    if (choice_out) *choice_out = best;
+    return PIC_OK;
 }
 
 }  // extern "C"

@@ -225,7 +225,7 @@ template <> struct PairLDS<double> {
 };
 
 // Pairs per thread per exchange round.
-template <typename R> __host__ __device__ constexpr int pairs_per_thread() { return sizeof(R) == 4 ? 2 : 1; }
+template <typename R> __host__ __device__ constexpr int pairs_per_thread() { return sizeof(R) == 4 ? 3 : 1; }
 
 // LDS bytes of one LDS-class cell pass of capacity cap with T threads.
 __host__ __device__ constexpr size_t lds_sort_bytes(int cap)
@@ -308,7 +308,11 @@ __device__ void cell_pass(const CollideArgs &a, int cell, unsigned char *smem, d
 
     const uint32_t nb = n >= 2 ? (uint32_t)(n / 2) : 1u;   // buckets
     const int nwords = (int)((nb + 1) / 2);
+    for (int b = threadIdx.x; b < nwords; b += T) cntw[b] = 0u;
+    __syncthreads();
     {
+        // load, one Philox call per particle, and the bucket count of its key
+        // with its arrival rank (16-bit counters, two per LDS word)
         double before[5] = {0, 0, 0, 0, 0};
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -325,6 +329,10 @@ __device__ void cell_pass(const CollideArgs &a, int cell, unsigned char *smem, d
                 w2[k] = w.z;
                 w3[k] = w.w;
                 if (MCC && (uint64_t)w.y < a.mcc_thr) cand |= 1u << k;
+                const uint32_t b = __umulhi(w.x, nb);
+                const uint32_t sh = (b & 1u) * 16u;
+                const uint32_t old = atomicAdd(&cntw[b >> 1], 1u << sh);
+                pos[k] = (b << 16) | ((old >> sh) & 0xFFFFu);
                 if (CONS) {
                     const double x = vx[k], y = vy[k], z = vz[k];
                     before[0] += 1.0;
@@ -335,7 +343,6 @@ __device__ void cell_pass(const CollideArgs &a, int cell, unsigned char *smem, d
                 }
             }
         }
-        for (int b = threadIdx.x; b < nwords; b += T) cntw[b] = 0u;
         if constexpr (CONS) {
             block_sum<5>(before, red);     // contains the barriers
             if (threadIdx.x < 5) s_before[threadIdx.x] = before[threadIdx.x];
@@ -344,18 +351,6 @@ __device__ void cell_pass(const CollideArgs &a, int cell, unsigned char *smem, d
     __syncthreads();
 
     if (coul || PAIRS) {
-        // bucket and arrival rank (16-bit counters, two per LDS word)
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const int i = threadIdx.x + k * T;
-            if (i < n) {
-                const uint32_t b = __umulhi(keys[i], nb);
-                const uint32_t sh = (b & 1u) * 16u;
-                const uint32_t old = atomicAdd(&cntw[b >> 1], 1u << sh);
-                pos[k] = (b << 16) | ((old >> sh) & 0xFFFFu);
-            }
-        }
-        __syncthreads();
         // exclusive scan of the bucket counts, words split into per-thread chunks
         {
             const int per = (nwords + T - 1) / T;
@@ -508,7 +503,36 @@ __device__ void cell_pass(const CollideArgs &a, int cell, unsigned char *smem, d
         }
     }
 
-    // null collisions, store, moment sums
+    // null collisions: about 1% of the particles are candidates, so each lane
+    // takes its candidates one at a time (selected out of its register slots)
+    // instead of branching per slot, which would run the scattering for every
+    // slot holding a candidate in any lane of the wave
+    if constexpr (MCC) {
+        uint32_t left = cand;
+        while (__ballot(left != 0u) != 0ull) {
+            if (left) {
+                const int kk = __builtin_ctz(left);
+                left &= left - 1u;
+                R x = vx[0], y = vy[0], z = vz[0];
+#pragma unroll
+                for (int k = 1; k < K; ++k)
+                    if (kk == k) {
+                        x = vx[k];
+                        y = vy[k];
+                        z = vz[k];
+                    }
+                mcc_scatter<R>(x, y, z, pid_c[threadIdx.x + kk * T], a.seed, step, a.mass_ratio);
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+                    if (kk == k) {
+                        vx[k] = x;
+                        vy[k] = y;
+                        vz[k] = z;
+                    }
+            }
+        }
+    }
+    // store, moment sums
     double m[14];
     if constexpr (MOM) {
 #pragma unroll
@@ -518,8 +542,6 @@ __device__ void cell_pass(const CollideArgs &a, int cell, unsigned char *smem, d
     for (int k = 0; k < K; ++k) {
         const int i = threadIdx.x + k * T;
         if (i < n) {
-            if (MCC && ((cand >> k) & 1u))
-                mcc_scatter<R>(vx[k], vy[k], vz[k], pid_c[i], a.seed, step, a.mass_ratio);
             vx_g[lo + i] = vx[k];
             vy_g[lo + i] = vy[k];
             vz_g[lo + i] = vz[k];
@@ -750,7 +772,7 @@ int launch_class(const CollideArgs &a, const int32_t *list, int cls, int blocks,
 
 template <typename R, int F>
 int launch_all(const CollideArgs &a, const int32_t *lists, int32_t n_cells, int num_cu,
-               const HugeScratch &hs, hipStream_t st)
+               const HugeScratch &hs, const ClassCaps &caps, hipStream_t st)
 {
     typedef Classes<R> C;
     constexpr bool PAIRS = (F & F_PAIRS) != 0;
@@ -758,33 +780,34 @@ int launch_all(const CollideArgs &a, const int32_t *lists, int32_t n_cells, int 
     const int64_t M = n_cells;
     // largest cells first so the small ones fill the tail
     ktime_begin(KT_HUGE, st);
-    hipLaunchKernelGGL((k_collide_huge<R, PAIRS>), dim3(num_cu), dim3(1024), 0, st, a, lists + 4 * M,
-                       4, hs);
+    hipLaunchKernelGGL((k_collide_huge<R, PAIRS>), dim3(num_cu * caps.blocks_per_cu[4]), dim3(1024), 0,
+                       st, a, lists + 4 * M, 4, hs);
     ktime_end(KT_HUGE, st);
     HIP_OK(hipGetLastError());
-    if ((rc = launch_class<R, C::T3, C::K3, F>(a, lists + 3 * M, 3, num_cu, st))) return rc;
-    if ((rc = launch_class<R, C::T2, C::K2, F>(a, lists + 2 * M, 2, 2 * num_cu, st))) return rc;
-    if ((rc = launch_class<R, C::T1, C::K1, F>(a, lists + 1 * M, 1, 4 * num_cu, st))) return rc;
-    if ((rc = launch_class<R, C::T0, C::K0, F>(a, lists + 0 * M, 0, 8 * num_cu, st))) return rc;
+    const int *bp = caps.blocks_per_cu;
+    if ((rc = launch_class<R, C::T3, C::K3, F>(a, lists + 3 * M, 3, bp[3] * num_cu, st))) return rc;
+    if ((rc = launch_class<R, C::T2, C::K2, F>(a, lists + 2 * M, 2, bp[2] * num_cu, st))) return rc;
+    if ((rc = launch_class<R, C::T1, C::K1, F>(a, lists + 1 * M, 1, bp[1] * num_cu, st))) return rc;
+    if ((rc = launch_class<R, C::T0, C::K0, F>(a, lists + 0 * M, 0, bp[0] * num_cu, st))) return rc;
     return PIC_OK;
 }
 
 template <typename R>
 int launch_flags(const CollideArgs &a, const int32_t *lists, int32_t n_cells, int num_cu,
-                 const HugeScratch &hs, int pairs_only, hipStream_t st)
+                 const HugeScratch &hs, const ClassCaps &cc, int pairs_only, hipStream_t st)
 {
-    if (pairs_only) return launch_all<R, F_PAIRS>(a, lists, n_cells, num_cu, hs, st);
+    if (pairs_only) return launch_all<R, F_PAIRS>(a, lists, n_cells, num_cu, hs, cc, st);
     const int f = (a.mcc_thr ? F_MCC : 0) | ((a.flags & PIC_CONSERVE_FIX) ? F_CONS : 0) |
                   ((a.flags & PIC_MOMENTS) ? F_MOM : 0);
     switch (f) {
-    case 0: return launch_all<R, 0>(a, lists, n_cells, num_cu, hs, st);
-    case 1: return launch_all<R, 1>(a, lists, n_cells, num_cu, hs, st);
-    case 2: return launch_all<R, 2>(a, lists, n_cells, num_cu, hs, st);
-    case 3: return launch_all<R, 3>(a, lists, n_cells, num_cu, hs, st);
-    case 4: return launch_all<R, 4>(a, lists, n_cells, num_cu, hs, st);
-    case 5: return launch_all<R, 5>(a, lists, n_cells, num_cu, hs, st);
-    case 6: return launch_all<R, 6>(a, lists, n_cells, num_cu, hs, st);
-    default: return launch_all<R, 7>(a, lists, n_cells, num_cu, hs, st);
+    case 0: return launch_all<R, 0>(a, lists, n_cells, num_cu, hs, cc, st);
+    case 1: return launch_all<R, 1>(a, lists, n_cells, num_cu, hs, cc, st);
+    case 2: return launch_all<R, 2>(a, lists, n_cells, num_cu, hs, cc, st);
+    case 3: return launch_all<R, 3>(a, lists, n_cells, num_cu, hs, cc, st);
+    case 4: return launch_all<R, 4>(a, lists, n_cells, num_cu, hs, cc, st);
+    case 5: return launch_all<R, 5>(a, lists, n_cells, num_cu, hs, cc, st);
+    case 6: return launch_all<R, 6>(a, lists, n_cells, num_cu, hs, cc, st);
+    default: return launch_all<R, 7>(a, lists, n_cells, num_cu, hs, cc, st);
     }
 }
 
@@ -803,6 +826,11 @@ ClassCaps collide_caps(int dtype, size_t)
 {
     ClassCaps c;
     c.ncls = 4;
+    c.blocks_per_cu[0] = 8;
+    c.blocks_per_cu[1] = 4;
+    c.blocks_per_cu[2] = 2;
+    c.blocks_per_cu[3] = 1;
+    c.blocks_per_cu[4] = 1;
     if (dtype == PIC_F32) {
         typedef Classes<float> C;
         c.cap[0] = C::T0 * C::K0;
@@ -843,8 +871,8 @@ void set_huge_scratch(int dtype, int64_t n, void *base)
 }
 
 int launch_collide(int dtype, const CollideArgs &a, const int32_t *lists, int32_t n_cells,
-                   const ClassCaps &, int pairs_only, int num_cu, hipStream_t st)
+                   const ClassCaps &cc, int pairs_only, int num_cu, hipStream_t st)
 {
-    if (dtype == PIC_F32) return launch_flags<float>(a, lists, n_cells, num_cu, g_huge, pairs_only, st);
-    return launch_flags<double>(a, lists, n_cells, num_cu, g_huge, pairs_only, st);
+    if (dtype == PIC_F32) return launch_flags<float>(a, lists, n_cells, num_cu, g_huge, cc, pairs_only, st);
+    return launch_flags<double>(a, lists, n_cells, num_cu, g_huge, cc, pairs_only, st);
 }

@@ -310,7 +310,8 @@ int launch_copy32(uint32_t *dst, const uint32_t *src, int64_t n, const int *gate
 // Work queue of cells by size class.
 struct ClassCaps {
     int ncls;            // number of LDS classes (<= 4), class ncls = multi-block
-    int cap[4];          // max members per cell of each class
+    int cap[4];          // max members per cell routed to each class (<= its capacity)
+    int blocks_per_cu[5];  // persistent workgroups per CU of classes 0-3 and the multi-block class
 };
 int launch_build_queue(const int32_t *cell_start, int32_t n_cells, const ClassCaps &caps,
                        int32_t *lists, DevFlags *flags, hipStream_t st);

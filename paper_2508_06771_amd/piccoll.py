@@ -68,6 +68,7 @@ def _load():
         "pic_gate_reset": ([vp], C.c_int),
         "pic_gate_stats": ([vp, C.POINTER(C.c_int64)], C.c_int),
         "pic_gate_state": ([vp, vp, vp, vp, vp], C.c_int),
+        "pic_autotune": ([vp, C.c_int, vp, vp, vp, i64, i32, f64, f64, u32, vp], C.c_int),
         "pic_time_kernels": ([vp, C.c_int], C.c_int),
         "pic_kernel_times": ([vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)], C.c_int),
     }
@@ -85,7 +86,7 @@ EXPORTED = ["pic_create", "pic_destroy", "pic_strerror", "pic_sync", "pic_set_st
             "mcc_null_collide", "pic_philox", "coulomb_pairs", "pic_cell_moments", "pic_unsort",
             "pic_time_kernels", "pic_kernel_times", "pic_run_steps", "pic_features",
             "pic_relaxation", "pic_mlp_forward", "pic_mlp_grad", "pic_mlp_train_step",
-            "pic_gate_config", "pic_gate_reset", "pic_gate_stats", "pic_gate_state"]
+            "pic_gate_config", "pic_gate_reset", "pic_gate_stats", "pic_gate_state", "pic_autotune"]
 
 MLP_PARAMS = 4801
 GATE_STATS = ["steps", "skipped", "collided", "judged", "judged_want", "false_skip", "disabled",
@@ -262,6 +263,14 @@ class Context:
         mom = torch.empty((n_cells, 14), dtype=torch.float64, device=device)
         _chk(lib.pic_gate_state(self._h, _p(skip), _p(k), _p(prob), _p(mom)), "pic_gate_state")
         return skip, k, prob, mom
+
+    def autotune(self, v, cell_of, pid, n_cells: int, *, dt: float, lnL: float, flags: int = 0):
+        """Picks class thresholds / grid sizes for this state (scratch copy); returns the index."""
+        self._stream()
+        ch = C.c_int32(-1)
+        _chk(lib.pic_autotune(self._h, _dt(v), _p(v), _p(cell_of), _p(pid), v.shape[1], n_cells, dt,
+                              lnL, flags, C.byref(ch)), "pic_autotune")
+        return ch.value
 
     # -------------------------------------------------------------- measurement
     def time_kernels(self, on: bool):
