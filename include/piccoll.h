@@ -58,7 +58,9 @@ typedef enum { PIC_F32 = 0, PIC_F64 = 1 } pic_dtype;
 /* flags of coulomb_collide / pic_run_steps */
 enum {
     PIC_CONSERVE_FIX = 1u << 0,  /* restore each cell's FP64 momentum and thermal
-                                    energy after the Coulomb step */
+                                    energy after the Coulomb step; the part the
+                                    output rounding leaves unmet is carried per
+                                    cell into the next step (pic_conserve_reset) */
     PIC_FUSE_MCC = 1u << 1,      /* run the null-collision step (parameters from
                                     pic_set_mcc) in the same pass, after Coulomb */
     PIC_GATE = 1u << 2,          /* learned sub-cycling gate (pic_gate_*) */
@@ -126,6 +128,10 @@ int coulomb_collide(pic_ctx *ctx, int dtype, void *v, int32_t *cell_of, uint32_t
 int pic_run_steps(pic_ctx *ctx, int dtype, void *v, int32_t *cell_of, uint32_t *pid, int64_t n,
                   int32_t n_cells, double dt, double lnLambda, const double *density,
                   uint64_t seed, uint64_t step0, int64_t nsteps, uint32_t flags);
+
+/* Forgets the per-cell momentum / energy shortfall carried between
+ * PIC_CONSERVE_FIX steps (use when the particle set changes). */
+int pic_conserve_reset(pic_ctx *ctx);
 
 /* Parameters of the fused null-collision step (PIC_FUSE_MCC):
  * sigma(E) = sigma0 E^-1/2 with E = |v|^2/2, neutral density n_neutral,

@@ -43,6 +43,9 @@ struct pic_ctx {
     int32_t *gate_k = nullptr, *gate_judge = nullptr;
     uint8_t *gate_skip = nullptr, *gate_want = nullptr;
     float *gate_prob = nullptr;
+    // per-cell conservation debt (PIC_CONSERVE_FIX)
+    double *debt = nullptr;
+    int32_t debt_M = 0;
     // autotuned class thresholds / grid sizes per dtype
     ClassCaps tuned[2];
     bool tuned_valid[2] = {false, false};
@@ -165,6 +168,24 @@ int ensure_gate(pic_ctx *c, int32_t M)
     CK(hipMemset(c->gate_dev, 0, sizeof(DevGate)));
     CK(hipDeviceSynchronize());
     c->gate_M = M;
+    return PIC_OK;
+}
+
+int ensure_debt(pic_ctx *c, int32_t M)
+{
+    if (c->debt_M == M && c->debt) return PIC_OK;
+    CK(hipSetDevice(c->device));
+    CK(hipStreamSynchronize(c->stream));
+    if (c->debt) CK(hipFree(c->debt));
+    c->debt = nullptr;
+    c->debt_M = 0;
+    if (hipMalloc((void **)&c->debt, (size_t)M * 4 * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        return PIC_ERR_NOMEM;
+    }
+    CK(hipMemset(c->debt, 0, (size_t)M * 4 * sizeof(double)));
+    CK(hipDeviceSynchronize());
+    c->debt_M = M;
     return PIC_OK;
 }
 
@@ -309,6 +330,7 @@ void pic_destroy(pic_ctx *c)
     if (c->step_dev) (void)hipFree(c->step_dev);
     if (c->gate_dev) (void)hipFree(c->gate_dev);
     if (c->gate_mem) (void)hipFree(c->gate_mem);
+    if (c->debt) (void)hipFree(c->debt);
     delete c;
 }
 
@@ -379,6 +401,17 @@ int pic_set_moments_out(pic_ctx *c, double *out)
 {
     if (!c) return PIC_ERR_ARG;
     c->moments_out = out;
+    return PIC_OK;
+}
+
+int pic_conserve_reset(pic_ctx *c)
+{
+    if (!c) return PIC_ERR_ARG;
+    if (!c->debt) return PIC_OK;
+    CK(hipSetDevice(c->device));
+    CK(hipStreamSynchronize(c->stream));
+    CK(hipMemset(c->debt, 0, (size_t)c->debt_M * 4 * sizeof(double)));
+    CK(hipDeviceSynchronize());
     return PIC_OK;
 }
 
@@ -699,6 +732,8 @@ static int step_enqueue(pic_ctx *c, const StepArgs &s, hipStream_t st, const uin
         r.list = c->gate_judge;
         r.count_dev = &c->gate_dev->judge_count;
         r.r_out = c->gate_r;
+        r.dflags = c->flags;
+        r.assume_sorted = assume ? 1 : 0;
         RC(launch_relax(dtype, r, c->num_cu, st));
         RC(launch_gate_score(c->gate_dev, c->gate_judge, c->gate_want, c->gate_r, c->gate_tol,
                              c->gate_max_false, c->gate_min_judged, st));
@@ -720,6 +755,7 @@ static int step_enqueue(pic_ctx *c, const StepArgs &s, hipStream_t st, const uin
     a.mcc_thr = (s.flags & PIC_FUSE_MCC) ? mcc_threshold(s.dt, c->mcc_sigma0, c->mcc_nn) : 0;
     a.mass_ratio = c->mcc_mr;
     a.moments = c->moments_out;
+    a.debt = (s.flags & PIC_CONSERVE_FIX) ? c->debt : nullptr;
     a.dflags = c->flags;
     if (gate) {
         a.skip = c->gate_skip;
@@ -738,6 +774,7 @@ static int collide_common(pic_ctx *c, const StepArgs &s)
     CK(hipSetDevice(c->device));
     RC(ensure_ws(c, step_ws_bytes(s)));
     if (s.flags & PIC_GATE) RC(ensure_gate(c, s.n_cells));
+    if (s.flags & PIC_CONSERVE_FIX) RC(ensure_debt(c, s.n_cells));
     return step_enqueue(c, s, c->stream, nullptr);
 }
 
@@ -783,6 +820,7 @@ int pic_run_steps(pic_ctx *c, int dtype, void *v, int32_t *cell_of, uint32_t *pi
     put(&c->gate_replicas, sizeof(int));
     put(&c->gate_bf16, sizeof(int));
     put(&c->gate_mem, sizeof(void *));
+    put(&c->debt, sizeof(void *));
     put(&c->tuned_valid[dtype == PIC_F64], sizeof(bool));
     put(&c->tuned[dtype == PIC_F64], sizeof(ClassCaps));
     if (!c->exec || kl != c->graph_key_len || memcmp(key, c->graph_key, kl) != 0) {
@@ -936,7 +974,8 @@ int pic_autotune(pic_ctx *c, int dtype, const void *v, const int32_t *cell_of, c
     // a scratch copy of the state: the caller's arrays are not modified
     void *copy = nullptr;
     const size_t vb = (size_t)n * 3 * es, ib = (size_t)n * 4;
-    if (hipMalloc(&copy, vb + 2 * ib + 1024) != hipSuccess) {
+    const size_t db = (size_t)n_cells * 4 * sizeof(double);
+    if (hipMalloc(&copy, vb + 2 * ib + db + 1024) != hipSuccess) {
         (void)hipGetLastError();
         return PIC_ERR_NOMEM;
     }
@@ -945,7 +984,13 @@ int pic_autotune(pic_ctx *c, int dtype, const void *v, const int32_t *cell_of, c
     t.v = b.take(vb);
     t.cell_of = (int32_t *)b.take(ib);
     t.pid = (uint32_t *)b.take(ib);
-    int rc = PIC_OK;
+    // trial steps carry their conservation shortfall in a scratch buffer, so
+    // the context's per-cell state is left as it was
+    double *const saved_debt = c->debt;
+    const int32_t saved_debt_M = c->debt_M;
+    c->debt = (double *)b.take(db);
+    c->debt_M = n_cells;
+    int rc = hipMemsetAsync(c->debt, 0, db, c->stream) == hipSuccess ? PIC_OK : PIC_ERR_HIP;
     std::vector<int32_t> hcs((size_t)n_cells + 1);
     std::string key;
     const ClassCaps base = collide_caps(dtype, c->lds_max);
@@ -955,6 +1000,7 @@ int pic_autotune(pic_ctx *c, int dtype, const void *v, const int32_t *cell_of, c
     bool cached = false;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     do {
+        if (rc != PIC_OK) break;
         if (hipMemcpyAsync(t.v, v, vb, hipMemcpyDeviceToDevice, c->stream) != hipSuccess ||
             hipMemcpyAsync(t.cell_of, cell_of, ib, hipMemcpyDeviceToDevice, c->stream) != hipSuccess ||
             hipMemcpyAsync(t.pid, pid, ib, hipMemcpyDeviceToDevice, c->stream) != hipSuccess) {
@@ -1045,6 +1091,8 @@ int pic_autotune(pic_ctx *c, int dtype, const void *v, const int32_t *cell_of, c
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     (void)hipStreamSynchronize(c->stream);
+    c->debt = saved_debt;
+    c->debt_M = saved_debt_M;
     (void)hipFree(copy);
     if (rc != PIC_OK) {
         c->tuned_valid[di] = false;

@@ -57,11 +57,16 @@ __global__ void k_bin_check(const int32_t *__restrict__ cell_of, int64_t n, int3
          i += (int64_t)gridDim.x * blockDim.x) {
         const int32_t prev = i > 0 ? cell_of[i - 1] : -1;
         const int32_t cur = i < n ? cell_of[i] : n_cells;
-        if (i < n && (cur < 0 || cur >= n_cells)) {
-            bad = 1;
-            continue;
-        }
-        if (i > 0 && i < n && cur < prev) uns = 1;
+        const bool out = i < n && (cur < 0 || cur >= n_cells);
+        const bool desc = i > 0 && i < n && cur < prev;
+        bad |= out;
+        uns |= desc;
+        // A wave whose elements are out of order writes no starts: the input
+        // is unsorted, gets sorted, and the starts are written by the check
+        // that follows the sort.  Without this, shuffled input would cost a
+        // write per cell for every ascending neighbour pair.
+        if (set_unsorted && __ballot(desc) != 0) continue;
+        if (out) continue;
         int32_t lo = prev + 1 < 0 ? 0 : prev + 1;
         for (int32_t j = lo; j <= cur && j <= n_cells; ++j) cell_start[j] = (int32_t)i;
     }

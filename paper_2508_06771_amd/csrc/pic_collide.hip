@@ -483,22 +483,27 @@ __device__ void cell_pass(const CollideArgs &a, int cell, unsigned char *smem, d
                 }
             }
             block_sum<5>(after, red);
-            const double N = s_before[0];
-            const double Vo[3] = {s_before[1] / N, s_before[2] / N, s_before[3] / N};
-            const double Vn[3] = {after[1] / N, after[2] / N, after[3] / N};
-            const double Eo = 0.5 * s_before[4] - 0.5 * N * (Vo[0] * Vo[0] + Vo[1] * Vo[1] + Vo[2] * Vo[2]);
-            const double En = 0.5 * after[4] - 0.5 * N * (Vn[0] * Vn[0] + Vn[1] * Vn[1] + Vn[2] * Vn[2]);
-            if (En > 0.0 && Eo >= 0.0) {
-                const double al = sqrt(Eo / En);
+            const Correction cr = make_correction(s_before, after, a.debt ? a.debt + (int64_t)cell * 4 : nullptr);
+            if (cr.ok) {
+                double real[5] = {0, 0, 0, 0, 0};
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
                     const int i = threadIdx.x + k * T;
                     if (i < n) {
-                        vx[k] = (R)(Vo[0] + al * ((double)vx[k] - Vn[0]));
-                        vy[k] = (R)(Vo[1] + al * ((double)vy[k] - Vn[1]));
-                        vz[k] = (R)(Vo[2] + al * ((double)vz[k] - Vn[2]));
+                        vx[k] = (R)(cr.Vt[0] + cr.al * ((double)vx[k] - cr.Vn[0]));
+                        vy[k] = (R)(cr.Vt[1] + cr.al * ((double)vy[k] - cr.Vn[1]));
+                        vz[k] = (R)(cr.Vt[2] + cr.al * ((double)vz[k] - cr.Vn[2]));
+                        const double x = vx[k], y = vy[k], z = vz[k];
+                        real[1] += x;
+                        real[2] += y;
+                        real[3] += z;
+                        real[4] += x * x + y * y + z * z;
                     }
                 }
+                block_sum<5>(real, red);
+                if (a.debt && threadIdx.x < 4)
+                    a.debt[(int64_t)cell * 4 + threadIdx.x] =
+                        threadIdx.x < 3 ? cr.P[threadIdx.x] - real[1 + threadIdx.x] : cr.Q - real[4];
             }
         }
     }
@@ -691,18 +696,25 @@ __global__ __launch_bounds__(1024) void k_collide_huge(CollideArgs a, const int3
                 }
                 block_sum<5>(before, red);
                 block_sum<5>(after, red);
-                const double N = before[0];
-                const double Vo[3] = {before[1] / N, before[2] / N, before[3] / N};
-                const double Vn[3] = {after[1] / N, after[2] / N, after[3] / N};
-                const double Eo = 0.5 * before[4] - 0.5 * N * (Vo[0] * Vo[0] + Vo[1] * Vo[1] + Vo[2] * Vo[2]);
-                const double En = 0.5 * after[4] - 0.5 * N * (Vn[0] * Vn[0] + Vn[1] * Vn[1] + Vn[2] * Vn[2]);
-                if (En > 0.0 && Eo >= 0.0) {
-                    const double al = sqrt(Eo / En);
+                const Correction cr = make_correction(before, after, a.debt ? a.debt + (int64_t)cell * 4 : nullptr);
+                if (cr.ok) {
+                    double real[5] = {0, 0, 0, 0, 0};
                     for (int i = threadIdx.x; i < n; i += T) {
-                        vx_g[lo + i] = (R)(Vo[0] + al * ((double)vx_g[lo + i] - Vn[0]));
-                        vy_g[lo + i] = (R)(Vo[1] + al * ((double)vy_g[lo + i] - Vn[1]));
-                        vz_g[lo + i] = (R)(Vo[2] + al * ((double)vz_g[lo + i] - Vn[2]));
+                        const R x = (R)(cr.Vt[0] + cr.al * ((double)vx_g[lo + i] - cr.Vn[0]));
+                        const R y = (R)(cr.Vt[1] + cr.al * ((double)vy_g[lo + i] - cr.Vn[1]));
+                        const R z = (R)(cr.Vt[2] + cr.al * ((double)vz_g[lo + i] - cr.Vn[2]));
+                        vx_g[lo + i] = x;
+                        vy_g[lo + i] = y;
+                        vz_g[lo + i] = z;
+                        real[1] += (double)x;
+                        real[2] += (double)y;
+                        real[3] += (double)z;
+                        real[4] += (double)x * x + (double)y * y + (double)z * z;
                     }
+                    block_sum<5>(real, red);
+                    if (a.debt && threadIdx.x < 4)
+                        a.debt[(int64_t)cell * 4 + threadIdx.x] =
+                            threadIdx.x < 3 ? cr.P[threadIdx.x] - real[1 + threadIdx.x] : cr.Q - real[4];
                 }
                 __syncthreads();
             }

@@ -196,6 +196,7 @@ __global__ __launch_bounds__(1024) void k_relax(RelaxArgs a, HugeScratch hs)
 {
     __shared__ double red[6 * 16];
     __shared__ uint32_t wtot[16];
+    if (a.dflags && (a.dflags->range_err || (a.assume_sorted && a.dflags->unsorted))) return;
     const uint32_t count = a.count_dev ? *a.count_dev : (uint32_t)a.count;
     const uint64_t step = a.step_dev ? *a.step_dev : a.step;
     const R *vx = (const R *)a.v;

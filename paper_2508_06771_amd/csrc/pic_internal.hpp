@@ -124,6 +124,51 @@ __device__ __forceinline__ void scatter_dir(double &vx, double &vy, double &vz, 
 }
 
 // ---------------------------------------------------------------------------
+// Compensated conservation correction of one cell.  b = (N, sum v, sum |v|^2)
+// before the Coulomb step, f = the same sums now (f[0] unused).  The targets
+// are b plus the cell's debt (momentum, sum |v|^2) that earlier steps' output
+// rounding left unmet: a binary32 step changes a cell's energy by far less
+// than one binary32 ulp, so a plain rescaling would round away and the error
+// would accumulate; carrying the shortfall makes it diffuse instead.
+// v <- Vt + alpha (v - Vn) with Vt the target mean velocity and alpha^2 the
+// ratio of target to current thermal energy.
+// ---------------------------------------------------------------------------
+struct Correction {
+    double Vt[3], Vn[3], al;
+    double P[3], Q;   // targets: momentum and sum |v|^2
+    bool ok;
+};
+
+__device__ __forceinline__ Correction make_correction(const double *b, const double *f,
+                                                      const double *debt)
+{
+    Correction c;
+    const double N = b[0];
+    c.P[0] = b[1];
+    c.P[1] = b[2];
+    c.P[2] = b[3];
+    c.Q = b[4];
+    if (debt) {
+        c.P[0] += debt[0];
+        c.P[1] += debt[1];
+        c.P[2] += debt[2];
+        c.Q += debt[3];
+    }
+    double vt2 = 0.0, vn2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        c.Vt[a] = c.P[a] / N;
+        c.Vn[a] = f[1 + a] / N;
+        vt2 += c.Vt[a] * c.Vt[a];
+        vn2 += c.Vn[a] * c.Vn[a];
+    }
+    const double Et = 0.5 * c.Q - 0.5 * N * vt2;
+    const double En = 0.5 * f[4] - 0.5 * N * vn2;
+    c.ok = N >= 2.0 && En > 0.0 && Et >= 0.0;
+    c.al = c.ok ? sqrt(Et / En) : 1.0;
+    return c;
+}
+
+// ---------------------------------------------------------------------------
 // Wave / block reductions in a fixed order (bitwise reproducible).
 // ---------------------------------------------------------------------------
 template <typename V>
@@ -331,6 +376,7 @@ struct CollideArgs {
     uint64_t mcc_thr;      // candidate iff word1 < mcc_thr (0 = no null collisions)
     double mass_ratio;
     double *moments;       // PIC_MOMENTS output (M x 14)
+    double *debt;          // PIC_CONSERVE_FIX: per-cell shortfall (M x 4) carried between steps
     DevFlags *dflags;
     // pairing export
     int32_t *sorted_out, *partner_out;
@@ -385,6 +431,8 @@ struct RelaxArgs {
     const uint32_t *count_dev;  // device count of list entries (NULL: count)
     int32_t count;
     double *r_out;              // indexed by cell
+    const DevFlags *dflags;     // in a collision step: skip when binning failed
+    int assume_sorted;
 };
 
 int launch_features(const double *moments, int32_t M, float *feat, uint8_t *valid, hipStream_t st);

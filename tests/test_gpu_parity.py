@@ -120,6 +120,7 @@ def run_gpu_step(ctx, w, v, dtype, step, flags=0, seed=0, density=None, mcc=Fals
         ctx.set_mcc(w.sigma0, w.n_neutral, w.mass_ratio)
         flags |= piccoll.FUSE_MCC
     dens = None if density is None else dev(density)
+    ctx.conserve_reset()
     ctx.coulomb_collide(tv, tc, tp, w.n_cells, dt=w.dt, lnL=w.lnL, seed=seed, step=step,
                         density=dens, flags=flags)
     ctx.sync()
@@ -341,21 +342,30 @@ def test_run_steps_graph_matches_eager(ctx, dtype):
     w = ragged_workload(11, [3000] * 40 + [0, 1, 700, 12000], np.float32 if dtype == "f32" else np.float64)
     ctx.set_mcc(w.sigma0, 1.0, 0.0)
     fl = piccoll.FUSE_MCC | piccoll.CONSERVE_FIX
+    # the per-cell conservation shortfall is context state: one context per
+    # particle population
+    eager = piccoll.Context(0)
+    eager.set_mcc(w.sigma0, 1.0, 0.0)
+    ctx.conserve_reset()
     A = [dev(w.v, td), dev(w.cell_of), dev(w.pid)]
     B = [dev(w.v, td), dev(w.cell_of), dev(w.pid)]
     ctx.run_steps(*A, w.n_cells, dt=w.dt, lnL=w.lnL, seed=2, step0=0, nsteps=6, flags=fl)
-    for k in range(6):
-        ctx.coulomb_collide(*B, w.n_cells, dt=w.dt, lnL=w.lnL, seed=2, step=k, flags=fl)
     ctx.sync()
+    for k in range(6):
+        eager.coulomb_collide(*B, w.n_cells, dt=w.dt, lnL=w.lnL, seed=2, step=k, flags=fl)
+    eager.sync()
     assert torch.equal(A[0], B[0]) and torch.equal(A[1], B[1]) and torch.equal(A[2], B[2])
     ctx.run_steps(*A, w.n_cells, dt=w.dt, lnL=w.lnL, seed=2, step0=6, nsteps=4, flags=fl)
-    for k in range(6, 10):
-        ctx.coulomb_collide(*B, w.n_cells, dt=w.dt, lnL=w.lnL, seed=2, step=k, flags=fl)
     ctx.sync()
+    for k in range(6, 10):
+        eager.coulomb_collide(*B, w.n_cells, dt=w.dt, lnL=w.lnL, seed=2, step=k, flags=fl)
+    eager.sync()
+    eager.close()
     assert torch.equal(A[0], B[0])
     # and against the oracle for the first of these steps from the same state
     vr, cr, pr = run_oracle_step(w, w.v.astype(np.float64), 0, seed=2, mcc=True, conserve=True)
     v1 = [dev(w.v, td), dev(w.cell_of), dev(w.pid)]
+    ctx.conserve_reset()
     ctx.run_steps(*v1, w.n_cells, dt=w.dt, lnL=w.lnL, seed=2, step0=0, nsteps=1, flags=fl)
     ctx.sync()
     tol = FP32_TOL if dtype == "f32" else FP64_TOL
@@ -375,12 +385,14 @@ def test_autotune_keeps_results_and_caches(ctx, tmp_path, monkeypatch):
     ctx.set_mcc(w.sigma0, 1.0, 0.0)
     fl = piccoll.FUSE_MCC | piccoll.CONSERVE_FIX
     ref = [dev(w.v, torch.float32), dev(w.cell_of), dev(w.pid)]
+    ctx.conserve_reset()
     ctx.coulomb_collide(*ref, w.n_cells, dt=w.dt, lnL=w.lnL, seed=4, step=0, flags=fl)
     cache = tmp_path / "tune.jsonl"
     monkeypatch.setenv("PICCOLL_TUNE_CACHE", str(cache))
     src = [dev(w.v, torch.float32), dev(w.cell_of), dev(w.pid)]
     choice = ctx.autotune(*src, w.n_cells, dt=w.dt, lnL=w.lnL, flags=fl)
     assert torch.equal(src[0], dev(w.v, torch.float32))        # caller's state untouched
+    ctx.conserve_reset()
     ctx.coulomb_collide(*src, w.n_cells, dt=w.dt, lnL=w.lnL, seed=4, step=0, flags=fl)
     ctx.sync()
     assert torch.equal(src[0], ref[0]) and torch.equal(src[2], ref[2])
