@@ -271,6 +271,15 @@ def bench_c5(args):
         ctx.sync()
         res[mode] = {"ms_per_step": ms, "energy_drift": abs(energy(v) - E0) / E0,
                      "ratio_start": r0, "ratio_end": _cell_ratio(ctx, torch, v, cell, w.n_cells)}
+        # per-kernel times of a few more eager steps (after the measured state)
+        ctx.time_kernels(True)
+        ctx.kernel_times()
+        for k in range(5):
+            ctx.coulomb_collide(v, cell, pid, w.n_cells, dt=w.dt, lnL=w.lnL, seed=0,
+                                step=3 + K + k, flags=fl | piccoll.ASSUME_SORTED)
+        ctx.sync()
+        res[mode]["kernel_ms"] = {k: round(t / 5, 5) for k, (t, c) in ctx.kernel_times().items()}
+        ctx.time_kernels(False)
         if mode == "gated":
             res[mode]["gate"] = ctx.gate_stats()
         del v, cell, pid
@@ -296,7 +305,9 @@ def bench_c5(args):
                  judged=g["judged"], judged_false_skips=g["false_skip"],
                  judged_want_skip=g["judged_want"], gate_switched_off=g["disabled"],
                  energy_drift_plain=res["plain"]["energy_drift"],
-                 energy_drift_gated=res["gated"]["energy_drift"], by_cell_kind=out_kind)
+                 energy_drift_gated=res["gated"]["energy_drift"], by_cell_kind=out_kind,
+                 kernel_ms_per_step_plain=res["plain"]["kernel_ms"],
+                 kernel_ms_per_step_gated=res["gated"]["kernel_ms"])
 
 
 def main():

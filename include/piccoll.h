@@ -248,7 +248,8 @@ int pic_time_kernels(pic_ctx *ctx, int on);
  * (cells of at most 512 / 2048 / 4096 / 10240 members in binary32,
  * 512 / 2048 / 4096 / 6144 in binary64), 4 cells beyond those, 5 order check
  * and cell starts, 6 work queue, 7 re-binning passes, 8 stand-alone
- * null-collision step. */
+ * null-collision step, 9 learned-gate decision, 10 relaxation of the
+ * judged cells (16 slots are reserved). */
 int pic_kernel_times(pic_ctx *ctx, double *ms, int64_t *count);
 
 /* ---------------------------------------------------------------- test exports */

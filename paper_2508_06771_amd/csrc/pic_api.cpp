@@ -715,7 +715,9 @@ static int step_enqueue(pic_ctx *c, const StepArgs &s, hipStream_t st, const uin
         g.prob = c->gate_prob;
         g.judge_list = c->gate_judge;
         g.g = c->gate_dev;
+        ktime_begin(KT_GATE, st);
         RC(launch_gate(g, st));
+        ktime_end(KT_GATE, st);
         RelaxArgs r;
         memset(&r, 0, sizeof(r));
         r.v = s.v;
@@ -734,7 +736,9 @@ static int step_enqueue(pic_ctx *c, const StepArgs &s, hipStream_t st, const uin
         r.r_out = c->gate_r;
         r.dflags = c->flags;
         r.assume_sorted = assume ? 1 : 0;
+        ktime_begin(KT_RELAX, st);
         RC(launch_relax(dtype, r, c->num_cu, st));
+        ktime_end(KT_RELAX, st);
         RC(launch_gate_score(c->gate_dev, c->gate_judge, c->gate_want, c->gate_r, c->gate_tol,
                              c->gate_max_false, c->gate_min_judged, st));
     }

@@ -151,93 +151,50 @@ __device__ __forceinline__ bool gated_off(const CollideArgs &a)
 // Variants compiled per kernel: which optional parts of the pass exist.
 enum { F_MCC = 1, F_CONS = 2, F_MOM = 4, F_PAIRS = 8 };
 
-template <typename R> struct PairRec;
-template <> struct __align__(16) PairRec<float> { float x, y, z; uint32_t w2; };
-template <> struct __align__(16) PairRec<double> { double x, y, z; uint32_t w2, pad; };
+// Pair-major exchange records.  In each round the members whose sorted
+// position falls in the round post their velocity and word 2 at that
+// position (first members also word 3, at the pair index); one thread per
+// pair applies the Takizuka & Abe rotation and writes both new velocities
+// back in place; each member then reads its own record.
+template <typename R> struct Rec;
+template <> struct __align__(16) Rec<float> { float x, y, z; uint32_t w2; };
+template <> struct __align__(16) Rec<double> { double x, y, z; uint32_t w2, pad; };
 
-// Pair-major exchange area: pair q of the current round keeps the first
-// member's (v, word2, word3) and the second member's (v, word2); the thread
-// that evaluates the pair overwrites the first record with the half change.
-template <typename R> struct PairLDS;
-template <> struct PairLDS<float> {
-    static constexpr int BYTES = 36;
-    float4 *A;
-    float4 *B;
-    uint32_t *W3;
-    __device__ PairLDS(unsigned char *base, int H)
-        : A((float4 *)base), B((float4 *)(base + 16 * (size_t)H)), W3((uint32_t *)(base + 32 * (size_t)H))
-    {
-    }
-    __device__ void put_first(int q, float x, float y, float z, uint32_t w2, uint32_t w3)
-    {
-        A[q] = make_float4(x, y, z, __uint_as_float(w2));
-        W3[q] = w3;
-    }
-    __device__ void put_second(int q, float x, float y, float z, uint32_t w2)
-    {
-        B[q] = make_float4(x, y, z, __uint_as_float(w2));
-    }
-    __device__ void collide(int q, float C)
-    {
-        const float4 a = A[q], b = B[q];
-        float hx, hy, hz;
-        ta_half(a.x - b.x, a.y - b.y, a.z - b.z, C, __float_as_uint(a.w), W3[q], __float_as_uint(b.w),
-                hx, hy, hz);
-        A[q] = make_float4(hx, hy, hz, 0.0f);
-    }
-    __device__ void half(int q, float &hx, float &hy, float &hz) const
-    {
-        const float4 a = A[q];
-        hx = a.x;
-        hy = a.y;
-        hz = a.z;
-    }
-};
-template <> struct PairLDS<double> {
-    static constexpr int BYTES = 64;
-    double4 *A;
-    double4 *B;
-    __device__ PairLDS(unsigned char *base, int H) : A((double4 *)base), B((double4 *)(base + 32 * (size_t)H)) {}
-    __device__ void put_first(int q, double x, double y, double z, uint32_t w2, uint32_t w3)
-    {
-        A[q] = make_double4(x, y, z, __longlong_as_double((long long)(((uint64_t)w3 << 32) | w2)));
-    }
-    __device__ void put_second(int q, double x, double y, double z, uint32_t w2)
-    {
-        B[q] = make_double4(x, y, z, __longlong_as_double((long long)w2));
-    }
-    __device__ void collide(int q, double C)
-    {
-        const double4 a = A[q], b = B[q];
-        const uint64_t wa = (uint64_t)__double_as_longlong(a.w);
-        double hx, hy, hz;
-        ta_half(a.x - b.x, a.y - b.y, a.z - b.z, C, (uint32_t)wa, (uint32_t)(wa >> 32),
-                (uint32_t)__double_as_longlong(b.w), hx, hy, hz);
-        A[q] = make_double4(hx, hy, hz, 0.0);
-    }
-    __device__ void half(int q, double &hx, double &hy, double &hz) const
-    {
-        const double4 a = A[q];
-        hx = a.x;
-        hy = a.y;
-        hz = a.z;
-    }
-};
-
-// Pairs per thread per exchange round.
-template <typename R> __host__ __device__ constexpr int pairs_per_thread() { return sizeof(R) == 4 ? 3 : 1; }
-
-// LDS bytes of one LDS-class cell pass of capacity cap with T threads.
-__host__ __device__ constexpr size_t lds_sort_bytes(int cap)
+__host__ __device__ constexpr uint32_t next_pow2(uint32_t x)
 {
-    return (size_t)cap * 4 + ((size_t)cap / 4 + 2) * 4 + (size_t)cap * 2;
+    uint32_t p = 1;
+    while (p < x) p <<= 1;
+    return p;
 }
-template <typename R>
-__host__ __device__ constexpr size_t lds_bytes(int cap, int T)
+
+// Dynamic LDS a cell pass may use (the static part is below 4 KB).
+constexpr size_t LDS_DYN_LIMIT = 152 * 1024;
+
+// Sort stage of a cell of capacity cap: keys by member, keys in bucket order
+// (padded for the 4-wide reads), 16-bit bucket counters, members in bucket
+// order.
+__host__ __device__ constexpr size_t sort_bytes(int cap)
 {
-    const size_t pair = (size_t)T * pairs_per_thread<R>() * PairLDS<R>::BYTES;
-    const size_t srt = lds_sort_bytes(cap);
-    return srt > pair ? srt : pair;
+    return (size_t)cap * 4 + ((size_t)cap + 4) * 4 + (size_t)next_pow2((uint32_t)cap) * 2 +
+           (size_t)cap * 2;
+}
+
+// Positions per exchange round: the whole cell when its records fit.
+template <typename R>
+__host__ __device__ constexpr uint32_t round_positions(int cap)
+{
+    const size_t per_pair = 2 * sizeof(Rec<R>) + 4;
+    const size_t want = ((size_t)cap + 1) / 2;
+    const size_t lim = (LDS_DYN_LIMIT / per_pair) & ~(size_t)63;
+    return (uint32_t)(2 * (want < lim ? want : lim));
+}
+
+template <typename R>
+__host__ __device__ constexpr size_t lds_bytes(int cap)
+{
+    const size_t ex = (size_t)round_positions<R>(cap) / 2 * (2 * sizeof(Rec<R>) + 4);
+    const size_t s = sort_bytes(cap);
+    return s > ex ? s : ex;
 }
 
 // ------------------------------------------------------------ LDS-class pass
@@ -261,13 +218,14 @@ __device__ void cell_pass(const CollideArgs &a, int cell, unsigned char *smem, d
     constexpr bool MCC = (F & F_MCC) != 0;
     constexpr bool CONS = (F & F_CONS) != 0;
     constexpr bool MOM = (F & F_MOM) != 0;
+    constexpr int CAP = T * K;
     const int lo = a.cell_start[cell];
     const int n = a.cell_start[cell + 1] - lo;
     const uint32_t step = (uint32_t)read_step(a);
     const bool coul = !(a.skip && a.skip[cell]) && n >= 2;
-    R *vx_g = (R *)a.v;
-    R *vy_g = vx_g + a.n;
-    R *vz_g = vy_g + a.n;
+    R *vx_g = (R *)a.v + lo;
+    R *vy_g = (R *)a.v + a.n + lo;
+    R *vz_g = (R *)a.v + 2 * a.n + lo;
     const uint32_t *pid_c = a.pid + lo;
 
     if (!PAIRS && a.skip && a.skip[cell]) {
@@ -281,13 +239,13 @@ __device__ void cell_pass(const CollideArgs &a, int cell, unsigned char *smem, d
                 const uint32_t p = pid_c[i];
                 const W4 w = draw4(a.seed, p, step, 0u, 0u);
                 if ((uint64_t)w.y < a.mcc_thr) {
-                    R x = vx_g[lo + i], y = vy_g[lo + i], z = vz_g[lo + i];
+                    R x = vx_g[i], y = vy_g[i], z = vz_g[i];
                     if constexpr (MOM) moment_terms(dm, x, y, z, -1.0);
                     mcc_scatter<R>(x, y, z, p, a.seed, step, a.mass_ratio);
                     if constexpr (MOM) moment_terms(dm, x, y, z, 1.0);
-                    vx_g[lo + i] = x;
-                    vy_g[lo + i] = y;
-                    vz_g[lo + i] = z;
+                    vx_g[i] = x;
+                    vy_g[i] = y;
+                    vz_g[i] = z;
                 }
             }
             if constexpr (MOM) {
@@ -298,17 +256,21 @@ __device__ void cell_pass(const CollideArgs &a, int cell, unsigned char *smem, d
         return;
     }
 
-    uint32_t *keys = (uint32_t *)smem;
-    uint32_t *cntw = keys + T * K;
-    uint16_t *lst = (uint16_t *)(cntw + (T * K) / 4 + 2);
+    uint32_t *keys = (uint32_t *)smem;          // [CAP] key of member i
+    uint32_t *sk = keys + CAP;                  // [CAP + 4] keys in bucket order
+    uint32_t *cnt = sk + CAP + 4;               // [nbk / 2] 16-bit bucket counters
+    uint16_t *lst = (uint16_t *)(cnt + next_pow2(CAP) / 2);   // [CAP] member in bucket order
 
     R vx[K], vy[K], vz[K];
     uint32_t w2[K], w3[K], pos[K];
     uint32_t cand = 0;
 
-    const uint32_t nb = n >= 2 ? (uint32_t)(n / 2) : 1u;   // buckets
-    const int nwords = (int)((nb + 1) / 2);
-    for (int b = threadIdx.x; b < nwords; b += T) cntw[b] = 0u;
+    // buckets: the top `bits` bits of the key, nbk = 2^bits >= n, so a
+    // bucket holds at most one member on average
+    const uint32_t bits = n >= 2 ? 32u - (uint32_t)__clz(n - 1) : 0u;
+    const uint32_t nbk = 1u << bits;
+    const int nwords = (int)((nbk + 1) / 2);
+    for (int w = threadIdx.x; w < nwords; w += T) cnt[w] = 0u;
     __syncthreads();
     {
         // load, one Philox call per particle, and the bucket count of its key
@@ -320,18 +282,18 @@ __device__ void cell_pass(const CollideArgs &a, int cell, unsigned char *smem, d
             if (i < n) {
                 const uint32_t p = pid_c[i];
                 if (!PAIRS) {
-                    vx[k] = vx_g[lo + i];
-                    vy[k] = vy_g[lo + i];
-                    vz[k] = vz_g[lo + i];
+                    vx[k] = vx_g[i];
+                    vy[k] = vy_g[i];
+                    vz[k] = vz_g[i];
                 }
                 const W4 w = draw4(a.seed, p, step, 0u, 0u);
                 keys[i] = w.x;
                 w2[k] = w.z;
                 w3[k] = w.w;
                 if (MCC && (uint64_t)w.y < a.mcc_thr) cand |= 1u << k;
-                const uint32_t b = __umulhi(w.x, nb);
-                const uint32_t sh = (b & 1u) * 16u;
-                const uint32_t old = atomicAdd(&cntw[b >> 1], 1u << sh);
+                const uint32_t b = __builtin_amdgcn_ubfe(w.x, (32u - bits) & 31u, bits);
+                const uint32_t sh = (b & 1u) << 4;
+                const uint32_t old = atomicAdd(&cnt[b >> 1], 1u << sh);
                 pos[k] = (b << 16) | ((old >> sh) & 0xFFFFu);
                 if (CONS) {
                     const double x = vx[k], y = vy[k], z = vz[k];
@@ -358,45 +320,60 @@ __device__ void cell_pass(const CollideArgs &a, int cell, unsigned char *smem, d
             uint32_t s = 0;
             for (int q = 0; q < per; ++q)
                 if (w0 + q < nwords) {
-                    const uint32_t c = cntw[w0 + q];
+                    const uint32_t c = cnt[w0 + q];
                     s += (c & 0xFFFFu) + (c >> 16);
                 }
             uint32_t run = block_excl(s, wtot);
             for (int q = 0; q < per; ++q)
                 if (w0 + q < nwords) {
-                    const uint32_t c = cntw[w0 + q];
+                    const uint32_t c = cnt[w0 + q];
                     const uint32_t lo16 = run, hi16 = run + (c & 0xFFFFu);
                     run = hi16 + (c >> 16);
-                    cntw[w0 + q] = lo16 | (hi16 << 16);
+                    cnt[w0 + q] = lo16 | (hi16 << 16);
                 }
         }
         __syncthreads();
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const int i = threadIdx.x + k * T;
-            if (i < n) lst[get16(cntw, pos[k] >> 16) + (pos[k] & 0xFFFFu)] = (uint16_t)i;
-        }
-        __syncthreads();
-        // final position = bucket offset + rank by (key, pid) inside the bucket
+        // keys and members in bucket order
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const int i = threadIdx.x + k * T;
             if (i < n) {
-                const uint32_t b = pos[k] >> 16;
-                const uint32_t beg = get16(cntw, b);
-                const uint32_t end = (b + 1 < nb) ? get16(cntw, b + 1) : (uint32_t)n;
-                const uint32_t key = keys[i];
-                uint32_t rank = 0;
-                for (uint32_t m = beg; m < end; ++m) {
-                    const uint32_t j = lst[m];
-                    const uint32_t kj = keys[j];
-                    if (kj < key) {
-                        ++rank;
-                    } else if (kj == key && j != (uint32_t)i) {
-                        if (pid_c[j] < pid_c[i]) ++rank;
-                    }
+                const uint32_t slot = get16(cnt, pos[k] >> 16) + (pos[k] & 0xFFFFu);
+                sk[slot] = keys[i];
+                lst[slot] = (uint16_t)i;
+            }
+        }
+        __syncthreads();
+        // final position = bucket start + rank by (key, pid) inside the
+        // bucket; the first four members are compared without a loop
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int i = threadIdx.x + k * T;
+            if (i < n) {
+                const uint32_t b = pos[k] >> 16, arr = pos[k] & 0xFFFFu;
+                const uint32_t beg = get16(cnt, b);
+                const uint32_t size = ((b + 1 < nbk) ? get16(cnt, b + 1) : (uint32_t)n) - beg;
+                const uint32_t key = sk[beg + arr];
+                uint32_t r = 0, tie = 0;
+#pragma unroll
+                for (uint32_t j = 0; j < 4; ++j) {
+                    const uint32_t kj = sk[beg + j];
+                    const bool in = j < size;
+                    r += (in && kj < key) ? 1u : 0u;
+                    tie |= (in && kj == key && j != arr) ? 1u : 0u;
                 }
-                pos[k] = beg + rank;
+                for (uint32_t j = 4; j < size; ++j) {
+                    const uint32_t kj = sk[beg + j];
+                    r += kj < key ? 1u : 0u;
+                    tie |= (kj == key && j != arr) ? 1u : 0u;
+                }
+                if (tie) {
+                    // equal keys: the smaller pid comes first
+                    const uint32_t pi = pid_c[i];
+                    for (uint32_t j = 0; j < size; ++j)
+                        if (j != arr && sk[beg + j] == key && pid_c[lst[beg + j]] < pi) ++r;
+                }
+                pos[k] = beg + r;
             }
         }
         __syncthreads();
@@ -427,46 +404,53 @@ __device__ void cell_pass(const CollideArgs &a, int cell, unsigned char *smem, d
 
     if (coul) {
         const R C = (R)cell_C(a, cell);
-        const uint32_t npairs = (uint32_t)n / 2;
-        constexpr uint32_t H = (uint32_t)T * pairs_per_thread<R>();
-        PairLDS<R> pl(smem, (int)H);
-        for (uint32_t qlo = 0; qlo < npairs; qlo += H) {
-            // members of this round's pairs post their data
+        const uint32_t np2 = (uint32_t)n & ~1u;     // positions with a partner
+        constexpr uint32_t P = round_positions<R>(CAP);
+        Rec<R> *rec = (Rec<R> *)smem;
+        uint32_t *w3s = (uint32_t *)(rec + P);
+        for (uint32_t base = 0; base < np2; base += P) {
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 const int i = threadIdx.x + k * T;
-                const uint32_t q = (pos[k] >> 1) - qlo;
-                if (i < n && q < H && (pos[k] >> 1) < npairs) {
-                    if (pos[k] & 1u)
-                        pl.put_second((int)q, vx[k], vy[k], vz[k], w2[k]);
-                    else
-                        pl.put_first((int)q, vx[k], vy[k], vz[k], w2[k], w3[k]);
+                const uint32_t q = pos[k] - base;
+                if (i < n && q < P && pos[k] < np2) {
+                    Rec<R> e;
+                    e.x = vx[k];
+                    e.y = vy[k];
+                    e.z = vz[k];
+                    e.w2 = w2[k];
+                    rec[q] = e;
+                    if (!(q & 1u)) w3s[q >> 1] = w3[k];
                 }
             }
             __syncthreads();
-            // one thread per pair
-            const uint32_t m = min(H, npairs - qlo);
-            for (uint32_t q = threadIdx.x; q < m; q += T) pl.collide((int)q, C);
+            const uint32_t m = min(P, np2 - base) / 2;
+            for (uint32_t j = threadIdx.x; j < m; j += T) {
+                Rec<R> A = rec[2 * j], B = rec[2 * j + 1];
+                R hx, hy, hz;
+                ta_half(A.x - B.x, A.y - B.y, A.z - B.z, C, A.w2, w3s[j], B.w2, hx, hy, hz);
+                A.x += hx;
+                A.y += hy;
+                A.z += hz;
+                B.x -= hx;
+                B.y -= hy;
+                B.z -= hz;
+                rec[2 * j] = A;
+                rec[2 * j + 1] = B;
+            }
             __syncthreads();
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 const int i = threadIdx.x + k * T;
-                const uint32_t q = (pos[k] >> 1) - qlo;
-                if (i < n && q < H && (pos[k] >> 1) < npairs) {
-                    R hx, hy, hz;
-                    pl.half((int)q, hx, hy, hz);
-                    if (pos[k] & 1u) {
-                        vx[k] -= hx;
-                        vy[k] -= hy;
-                        vz[k] -= hz;
-                    } else {
-                        vx[k] += hx;
-                        vy[k] += hy;
-                        vz[k] += hz;
-                    }
+                const uint32_t q = pos[k] - base;
+                if (i < n && q < P && pos[k] < np2) {
+                    const Rec<R> e = rec[q];
+                    vx[k] = e.x;
+                    vy[k] = e.y;
+                    vz[k] = e.z;
                 }
             }
-            __syncthreads();
+            if (base + P < np2) __syncthreads();
         }
 
         if constexpr (CONS) {
@@ -547,9 +531,9 @@ __device__ void cell_pass(const CollideArgs &a, int cell, unsigned char *smem, d
     for (int k = 0; k < K; ++k) {
         const int i = threadIdx.x + k * T;
         if (i < n) {
-            vx_g[lo + i] = vx[k];
-            vy_g[lo + i] = vy[k];
-            vz_g[lo + i] = vz[k];
+            vx_g[i] = vx[k];
+            vy_g[i] = vy[k];
+            vz_g[i] = vz[k];
             if constexpr (MOM) {
                 const double x = vx[k], y = vy[k], z = vz[k];
                 const double q2 = x * x + y * y + z * z;
@@ -605,7 +589,7 @@ __global__ __launch_bounds__(1024) void k_collide_huge(CollideArgs a, const int3
     R *vx_g = (R *)a.v;
     R *vy_g = vx_g + a.n;
     R *vz_g = vy_g + a.n;
-    PairRec<R> *pb = (PairRec<R> *)hs.pbuf;
+    Rec<R> *pb = (Rec<R> *)hs.pbuf;
     for (;;) {
         if (threadIdx.x == 0) s_item = (int)atomicAdd(&a.dflags->head[cls], 1u);
         __syncthreads();
@@ -646,11 +630,11 @@ __global__ __launch_bounds__(1024) void k_collide_huge(CollideArgs a, const int3
         }
         if (coul) {
             const R C = (R)cell_C(a, cell);
-            PairRec<R> *pc = pb + lo / 2 + (lo & 1);   // disjoint per cell
+            Rec<R> *pc = pb + lo / 2 + (lo & 1);   // disjoint per cell
             for (int i = threadIdx.x; i < n; i += T) {
                 const uint32_t p = hs.pos[lo + i];
                 if (p & 1u) {
-                    PairRec<R> &e = pc[p >> 1];
+                    Rec<R> &e = pc[p >> 1];
                     e.x = vx_g[lo + i];
                     e.y = vy_g[lo + i];
                     e.z = vz_g[lo + i];
@@ -661,7 +645,7 @@ __global__ __launch_bounds__(1024) void k_collide_huge(CollideArgs a, const int3
             for (int i = threadIdx.x; i < n; i += T) {
                 const uint32_t p = hs.pos[lo + i];
                 if (!(p & 1u) && p + 1 < (uint32_t)n) {
-                    PairRec<R> &e = pc[p >> 1];
+                    Rec<R> &e = pc[p >> 1];
                     R x = vx_g[lo + i], y = vy_g[lo + i], z = vz_g[lo + i];
                     R hx, hy, hz;
                     ta_half(x - e.x, y - e.y, z - e.z, C, hs.w23[2 * (int64_t)(lo + i)],
@@ -678,7 +662,7 @@ __global__ __launch_bounds__(1024) void k_collide_huge(CollideArgs a, const int3
             for (int i = threadIdx.x; i < n; i += T) {
                 const uint32_t p = hs.pos[lo + i];
                 if (p & 1u) {
-                    const PairRec<R> &e = pc[p >> 1];
+                    const Rec<R> &e = pc[p >> 1];
                     vx_g[lo + i] -= e.x;
                     vy_g[lo + i] -= e.y;
                     vz_g[lo + i] -= e.z;
@@ -767,7 +751,7 @@ template <> struct Classes<double> {
 template <typename R, int T, int K, int F>
 int launch_class(const CollideArgs &a, const int32_t *list, int cls, int blocks, hipStream_t st)
 {
-    const size_t lds = lds_bytes<R>(T * K, T);
+    const size_t lds = lds_bytes<R>(T * K);
     auto kern = k_collide<R, T, K, F>;
     static bool attr_done = false;
     if (!attr_done) {

@@ -327,8 +327,10 @@ struct RadixPass {
 // Optional timing of selected launches with HIP events on the launch stream
 // (enabled by pic_time_kernels; no cost when off).  Slots: 0-3 LDS classes of
 // the collide pass, 4 multi-block class, 5 order check, 6 work queue,
-// 7 re-binning passes, 8 stand-alone null-collision step.
-enum { KT_CLASS0 = 0, KT_HUGE = 4, KT_CHECK = 5, KT_QUEUE = 6, KT_SORT = 7, KT_MCC = 8, KT_SLOTS = 16 };
+// 7 re-binning passes, 8 stand-alone null-collision step, 9 learned gate
+// decision, 10 relaxation of the judged cells.
+enum { KT_CLASS0 = 0, KT_HUGE = 4, KT_CHECK = 5, KT_QUEUE = 6, KT_SORT = 7, KT_MCC = 8, KT_GATE = 9,
+       KT_RELAX = 10, KT_SLOTS = 16 };
 void ktime_begin(int slot, hipStream_t st);
 void ktime_end(int slot, hipStream_t st);
 bool ktime_pause();            // returns whether timing was on
