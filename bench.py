@@ -321,7 +321,10 @@ def main():
     ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"],
                     help="c2: the headline configuration; c3: log-normal cell sizes, autotuned "
                          "routing, graph replays; c4: precision study; c5: learned gate vs plain")
-    ap.add_argument("--graph", action="store_true", help="time graph replays (pic_run_steps)")
+    ap.add_argument("--eager", action="store_true",
+                    help="time one coulomb_collide call per step instead of graph replays")
+    ap.add_argument("--kernel-steps", type=int, default=10,
+                    help="extra eager steps after the timed region whose kernels are timed")
     ap.add_argument("--gate-params", default=None, help="trained gate parameters (.npy) for c5")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -367,26 +370,35 @@ def main():
     E0 = energy(v)
     k0 = max(args.warmup, 1)
 
-    timing = not args.no_kernel_timing and not args.graph
-    if timing:
-        ctx.time_kernels(True)
-        ctx.kernel_times()
     torch.cuda.synchronize()
     s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     s.record()
-    if args.graph:
-        ctx.run_steps(v, cell, pid, w.n_cells, dt=w.dt, lnL=w.lnL, seed=0, step0=k0,
-                      nsteps=args.steps, flags=flags | piccoll.ASSUME_SORTED)
-    else:
+    if args.eager:
         for k in range(args.steps):
             step(k0 + k)
+    else:
+        ctx.run_steps(v, cell, pid, w.n_cells, dt=w.dt, lnL=w.lnL, seed=0, step0=k0,
+                      nsteps=args.steps, flags=flags | piccoll.ASSUME_SORTED)
     e.record()
     torch.cuda.synchronize()
     ms_total = s.elapsed_time(e)
     ctx.sync()
-    kt = ctx.kernel_times() if timing else {}
-    ctx.time_kernels(False)
     E1 = energy(v)
+
+    # kernel durations: HIP events recorded by the library around each launch
+    # on its stream, over a few more steps of the same kind (outside the
+    # timed region; graph replays cannot carry per-kernel events)
+    kt = {}
+    if not args.no_kernel_timing and args.kernel_steps > 0:
+        ctx.time_kernels(True)
+        ctx.kernel_times()
+        k1 = k0 + args.steps
+        for k in range(args.kernel_steps):
+            ctx.coulomb_collide(v, cell, pid, w.n_cells, dt=w.dt, lnL=w.lnL, seed=0, step=k1 + k,
+                                flags=flags | piccoll.ASSUME_SORTED)
+        ctx.sync()
+        kt = ctx.kernel_times()
+        ctx.time_kernels(False)
 
     ms_step = ms_total / args.steps
     value = n / (ms_step * 1e-3)
@@ -427,7 +439,7 @@ def main():
         "step_algorithmic_gbs": round(step_gbs, 1),
         "algorithmic_bytes_per_electron": BYTES_CHECK + BYTES_COLLIDE,
         "copy_probe_gbs": round(copy_gbs, 1),
-        "launch": "graph" if args.graph else "eager",
+        "launch": "eager" if args.eager else "graph",
         "rebin_step_ms": round(rebin_ms, 4),
         "energy_drift": abs(E1 - E0) / E0,
         "kernel_ms_per_step": {k: round(t / c, 5) for k, (t, c) in kt.items()},

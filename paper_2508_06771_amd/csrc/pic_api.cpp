@@ -490,10 +490,13 @@ int pic_relaxation(pic_ctx *c, int dtype, const void *v, int64_t n, const int32_
         return PIC_ERR_ARG;
     RC(check_dtype(dtype));
     CK(hipSetDevice(c->device));
-    RC(ensure_ws(c, huge_scratch_bytes(dtype, n) + 1024));
-    set_huge_scratch(dtype, n, c->ws);
+    const size_t hb = huge_scratch_bytes(dtype, n);
+    RC(ensure_ws(c, hb + relax_part_bytes(n_cells, replicas) + 2048));
+    Bump b(c->ws);
+    set_huge_scratch(dtype, n, b.take(hb));
     RelaxArgs r;
     memset(&r, 0, sizeof(r));
+    r.part = (double *)b.take(relax_part_bytes(n_cells, replicas));
     r.v = v;
     r.n = n;
     r.cell_start = cell_start;
@@ -617,11 +620,12 @@ struct StepArgs {
     uint32_t flags;
 };
 
-static size_t step_ws_bytes(const StepArgs &s)
+static size_t step_ws_bytes(const pic_ctx *c, const StepArgs &s)
 {
     const size_t es = s.dtype == PIC_F32 ? 4 : 8;
+    const size_t part = (s.flags & PIC_GATE) ? relax_part_bytes(s.n_cells, c->gate_replicas) : 0;
     return (size_t)(s.n_cells + 1) * 4 + (size_t)s.n_cells * 5 * 4 + (size_t)s.n * (8 + 3 * es) +
-           radix_scratch_bytes(s.n) + huge_scratch_bytes(s.dtype, s.n) + 8192;
+           radix_scratch_bytes(s.n) + huge_scratch_bytes(s.dtype, s.n) + part + 8192;
 }
 
 static int step_check(pic_ctx *c, const StepArgs &s)
@@ -655,6 +659,9 @@ static int step_enqueue(pic_ctx *c, const StepArgs &s, hipStream_t st, const uin
     bs.hist = (uint32_t *)b.take(radix_scratch_bytes(n));
     bs.bsum = bs.hist + 256 * ((n + 4095) / 4096 + 1);
     set_huge_scratch(dtype, n, b.take(huge_scratch_bytes(dtype, n)));
+    double *relax_part = (s.flags & PIC_GATE)
+                             ? (double *)b.take(relax_part_bytes(n_cells, c->gate_replicas))
+                             : nullptr;
 
     RC(launch_reset_flags(c->flags, st));
     const bool assume = (s.flags & PIC_ASSUME_SORTED) != 0;
@@ -736,6 +743,7 @@ static int step_enqueue(pic_ctx *c, const StepArgs &s, hipStream_t st, const uin
         r.r_out = c->gate_r;
         r.dflags = c->flags;
         r.assume_sorted = assume ? 1 : 0;
+        r.part = relax_part;
         ktime_begin(KT_RELAX, st);
         RC(launch_relax(dtype, r, c->num_cu, st));
         ktime_end(KT_RELAX, st);
@@ -776,7 +784,7 @@ static int collide_common(pic_ctx *c, const StepArgs &s)
 {
     RC(step_check(c, s));
     CK(hipSetDevice(c->device));
-    RC(ensure_ws(c, step_ws_bytes(s)));
+    RC(ensure_ws(c, step_ws_bytes(c, s)));
     if (s.flags & PIC_GATE) RC(ensure_gate(c, s.n_cells));
     if (s.flags & PIC_CONSERVE_FIX) RC(ensure_debt(c, s.n_cells));
     return step_enqueue(c, s, c->stream, nullptr);

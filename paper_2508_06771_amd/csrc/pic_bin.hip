@@ -44,31 +44,55 @@ __global__ void k_step_inc(uint64_t *s)
     if (threadIdx.x == 0) *s += 1;
 }
 
-// One position i in [0, n]: the boundary between element i-1 and i.  Every
-// cell id j in (cell_of[i-1], cell_of[i]] starts at i; with sorted input each
-// entry of cell_start is written exactly once (empty cells included).
+// Position i in [0, n] is the boundary between element i-1 and i: every cell
+// id j in (cell_of[i-1], cell_of[i]] starts at i, so with sorted input each
+// entry of cell_start is written exactly once (empty cells included).  Each
+// thread takes four consecutive positions (one 16-byte load when aligned).
 __global__ void k_bin_check(const int32_t *__restrict__ cell_of, int64_t n, int32_t n_cells,
                             int32_t *__restrict__ cell_start, DevFlags *f, int set_unsorted,
                             const int *gate)
 {
     if (gate && *gate == 0) return;
     int bad = 0, uns = 0;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i <= n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t prev = i > 0 ? cell_of[i - 1] : -1;
-        const int32_t cur = i < n ? cell_of[i] : n_cells;
-        const bool out = i < n && (cur < 0 || cur >= n_cells);
-        const bool desc = i > 0 && i < n && cur < prev;
-        bad |= out;
+    const int64_t nq = n / 4 + 1;
+    const bool vec = ((uintptr_t)cell_of & 15u) == 0;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nq;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i0 = q * 4;
+        int32_t c[5];
+        c[0] = i0 > 0 ? cell_of[i0 - 1] : -1;
+        if (vec && i0 + 4 <= n) {
+            const int4 x = *(const int4 *)(cell_of + i0);
+            c[1] = x.x;
+            c[2] = x.y;
+            c[3] = x.z;
+            c[4] = x.w;
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) c[1 + j] = i0 + j < n ? cell_of[i0 + j] : n_cells;
+        }
+        bool out[4], desc = false;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t i = i0 + j;
+            out[j] = i < n && (c[1 + j] < 0 || c[1 + j] >= n_cells);
+            desc |= i > 0 && i < n && c[1 + j] < c[j];
+            bad |= out[j];
+        }
         uns |= desc;
         // A wave whose elements are out of order writes no starts: the input
         // is unsorted, gets sorted, and the starts are written by the check
         // that follows the sort.  Without this, shuffled input would cost a
         // write per cell for every ascending neighbour pair.
         if (set_unsorted && __ballot(desc) != 0) continue;
-        if (out) continue;
-        int32_t lo = prev + 1 < 0 ? 0 : prev + 1;
-        for (int32_t j = lo; j <= cur && j <= n_cells; ++j) cell_start[j] = (int32_t)i;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t i = i0 + j;
+            if (i > n || out[j]) continue;
+            const int32_t cur = c[1 + j];
+            const int32_t lo = c[j] + 1 < 0 ? 0 : c[j] + 1;
+            for (int32_t k = lo; k <= cur && k <= n_cells; ++k) cell_start[k] = (int32_t)i;
+        }
     }
     const uint64_t wb = __ballot(bad), wu = __ballot(uns);
     if ((threadIdx.x & (PIC_WAVE - 1)) == 0) {
@@ -319,7 +343,7 @@ int launch_step_inc(uint64_t *step_dev, hipStream_t st)
 int launch_bin_check(const int32_t *cell_of, int64_t n, int32_t n_cells, int32_t *cell_start,
                      DevFlags *flags, int set_unsorted, const int *gate, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_bin_check, dim3(grid_for(n + 1, 256, 8192)), dim3(256), 0, st, cell_of, n,
+    hipLaunchKernelGGL(k_bin_check, dim3(grid_for(n / 4 + 1, 256, 8192)), dim3(256), 0, st, cell_of, n,
                        n_cells, cell_start, flags, set_unsorted, gate);
     HIP_OK(hipGetLastError());
     return PIC_OK;

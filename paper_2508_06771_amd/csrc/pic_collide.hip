@@ -160,24 +160,8 @@ template <typename R> struct Rec;
 template <> struct __align__(16) Rec<float> { float x, y, z; uint32_t w2; };
 template <> struct __align__(16) Rec<double> { double x, y, z; uint32_t w2, pad; };
 
-__host__ __device__ constexpr uint32_t next_pow2(uint32_t x)
-{
-    uint32_t p = 1;
-    while (p < x) p <<= 1;
-    return p;
-}
-
 // Dynamic LDS a cell pass may use (the static part is below 4 KB).
 constexpr size_t LDS_DYN_LIMIT = 152 * 1024;
-
-// Sort stage of a cell of capacity cap: keys by member, keys in bucket order
-// (padded for the 4-wide reads), 16-bit bucket counters, members in bucket
-// order.
-__host__ __device__ constexpr size_t sort_bytes(int cap)
-{
-    return (size_t)cap * 4 + ((size_t)cap + 4) * 4 + (size_t)next_pow2((uint32_t)cap) * 2 +
-           (size_t)cap * 2;
-}
 
 // Positions per exchange round: the whole cell when its records fit.
 template <typename R>
@@ -250,31 +234,28 @@ __device__ void cell_pass(const CollideArgs &a, int cell, unsigned char *smem, d
             }
             if constexpr (MOM) {
                 block_sum<14>(dm, red);
-                if (threadIdx.x > 0 && threadIdx.x < 14) a.moments[(int64_t)cell * 14 + threadIdx.x] += dm[threadIdx.x];
+                if (threadIdx.x == 0) {
+#pragma unroll
+                    for (int q = 1; q < 14; ++q) a.moments[(int64_t)cell * 14 + q] += dm[q];
+                }
             }
         }
+        __syncthreads();
         return;
     }
 
-    uint32_t *keys = (uint32_t *)smem;          // [CAP] key of member i
-    uint32_t *sk = keys + CAP;                  // [CAP + 4] keys in bucket order
-    uint32_t *cnt = sk + CAP + 4;               // [nbk / 2] 16-bit bucket counters
-    uint16_t *lst = (uint16_t *)(cnt + next_pow2(CAP) / 2);   // [CAP] member in bucket order
+    const SortLDS<T, CAP> L(smem);
 
     R vx[K], vy[K], vz[K];
     uint32_t w2[K], w3[K], pos[K];
     uint32_t cand = 0;
 
-    // buckets: the top `bits` bits of the key, nbk = 2^bits >= n, so a
-    // bucket holds at most one member on average
-    const uint32_t bits = n >= 2 ? 32u - (uint32_t)__clz(n - 1) : 0u;
-    const uint32_t nbk = 1u << bits;
-    const int nwords = (int)((nbk + 1) / 2);
-    for (int w = threadIdx.x; w < nwords; w += T) cnt[w] = 0u;
+    const uint32_t bits = sort_bits(n);
+    L.clear();
     __syncthreads();
     {
         // load, one Philox call per particle, and the bucket count of its key
-        // with its arrival rank (16-bit counters, two per LDS word)
+        // with its arrival rank
         double before[5] = {0, 0, 0, 0, 0};
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -287,14 +268,10 @@ __device__ void cell_pass(const CollideArgs &a, int cell, unsigned char *smem, d
                     vz[k] = vz_g[i];
                 }
                 const W4 w = draw4(a.seed, p, step, 0u, 0u);
-                keys[i] = w.x;
                 w2[k] = w.z;
                 w3[k] = w.w;
                 if (MCC && (uint64_t)w.y < a.mcc_thr) cand |= 1u << k;
-                const uint32_t b = __builtin_amdgcn_ubfe(w.x, (32u - bits) & 31u, bits);
-                const uint32_t sh = (b & 1u) << 4;
-                const uint32_t old = atomicAdd(&cnt[b >> 1], 1u << sh);
-                pos[k] = (b << 16) | ((old >> sh) & 0xFFFFu);
+                pos[k] = L.count(i, w.x, bits);
                 if (CONS) {
                     const double x = vx[k], y = vy[k], z = vz[k];
                     before[0] += 1.0;
@@ -307,77 +284,15 @@ __device__ void cell_pass(const CollideArgs &a, int cell, unsigned char *smem, d
         }
         if constexpr (CONS) {
             block_sum<5>(before, red);     // contains the barriers
-            if (threadIdx.x < 5) s_before[threadIdx.x] = before[threadIdx.x];
+            if (threadIdx.x == 0) {
+#pragma unroll
+                for (int q = 0; q < 5; ++q) s_before[q] = before[q];
+            }
         }
     }
     __syncthreads();
 
-    if (coul || PAIRS) {
-        // exclusive scan of the bucket counts, words split into per-thread chunks
-        {
-            const int per = (nwords + T - 1) / T;
-            const int w0 = threadIdx.x * per;
-            uint32_t s = 0;
-            for (int q = 0; q < per; ++q)
-                if (w0 + q < nwords) {
-                    const uint32_t c = cnt[w0 + q];
-                    s += (c & 0xFFFFu) + (c >> 16);
-                }
-            uint32_t run = block_excl(s, wtot);
-            for (int q = 0; q < per; ++q)
-                if (w0 + q < nwords) {
-                    const uint32_t c = cnt[w0 + q];
-                    const uint32_t lo16 = run, hi16 = run + (c & 0xFFFFu);
-                    run = hi16 + (c >> 16);
-                    cnt[w0 + q] = lo16 | (hi16 << 16);
-                }
-        }
-        __syncthreads();
-        // keys and members in bucket order
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const int i = threadIdx.x + k * T;
-            if (i < n) {
-                const uint32_t slot = get16(cnt, pos[k] >> 16) + (pos[k] & 0xFFFFu);
-                sk[slot] = keys[i];
-                lst[slot] = (uint16_t)i;
-            }
-        }
-        __syncthreads();
-        // final position = bucket start + rank by (key, pid) inside the
-        // bucket; the first four members are compared without a loop
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const int i = threadIdx.x + k * T;
-            if (i < n) {
-                const uint32_t b = pos[k] >> 16, arr = pos[k] & 0xFFFFu;
-                const uint32_t beg = get16(cnt, b);
-                const uint32_t size = ((b + 1 < nbk) ? get16(cnt, b + 1) : (uint32_t)n) - beg;
-                const uint32_t key = sk[beg + arr];
-                uint32_t r = 0, tie = 0;
-#pragma unroll
-                for (uint32_t j = 0; j < 4; ++j) {
-                    const uint32_t kj = sk[beg + j];
-                    const bool in = j < size;
-                    r += (in && kj < key) ? 1u : 0u;
-                    tie |= (in && kj == key && j != arr) ? 1u : 0u;
-                }
-                for (uint32_t j = 4; j < size; ++j) {
-                    const uint32_t kj = sk[beg + j];
-                    r += kj < key ? 1u : 0u;
-                    tie |= (kj == key && j != arr) ? 1u : 0u;
-                }
-                if (tie) {
-                    // equal keys: the smaller pid comes first
-                    const uint32_t pi = pid_c[i];
-                    for (uint32_t j = 0; j < size; ++j)
-                        if (j != arr && sk[beg + j] == key && pid_c[lst[beg + j]] < pi) ++r;
-                }
-                pos[k] = beg + r;
-            }
-        }
-        __syncthreads();
-    }
+    if (coul || PAIRS) rank_in_lds<T, K, CAP>(pos, n, bits, L, pid_c, wtot);
 
     if (PAIRS) {
         // sorted[] and partner[] for the test export
@@ -385,7 +300,7 @@ __device__ void cell_pass(const CollideArgs &a, int cell, unsigned char *smem, d
         for (int k = 0; k < K; ++k) {
             const int i = threadIdx.x + k * T;
             if (i < n) {
-                lst[pos[k]] = (uint16_t)i;
+                L.lst[pos[k]] = (uint16_t)i;
                 a.sorted_out[lo + pos[k]] = lo + i;
             }
         }
@@ -395,7 +310,7 @@ __device__ void cell_pass(const CollideArgs &a, int cell, unsigned char *smem, d
             const int i = threadIdx.x + k * T;
             if (i < n) {
                 const uint32_t q = pos[k] ^ 1u;
-                a.partner_out[lo + i] = (q < (uint32_t)n) ? lo + (int)lst[q] : -1;
+                a.partner_out[lo + i] = (q < (uint32_t)n) ? lo + (int)L.lst[q] : -1;
             }
         }
         __syncthreads();
@@ -485,9 +400,7 @@ __device__ void cell_pass(const CollideArgs &a, int cell, unsigned char *smem, d
                     }
                 }
                 block_sum<5>(real, red);
-                if (a.debt && threadIdx.x < 4)
-                    a.debt[(int64_t)cell * 4 + threadIdx.x] =
-                        threadIdx.x < 3 ? cr.P[threadIdx.x] - real[1 + threadIdx.x] : cr.Q - real[4];
+                if (a.debt && threadIdx.x == 0) store_debt(a.debt + (int64_t)cell * 4, cr, real);
             }
         }
     }
@@ -548,8 +461,15 @@ __device__ void cell_pass(const CollideArgs &a, int cell, unsigned char *smem, d
     }
     if constexpr (MOM) {
         block_sum<14>(m, red);
-        if (threadIdx.x < 14) a.moments[(int64_t)cell * 14 + threadIdx.x] = m[threadIdx.x];
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int q = 0; q < 14; ++q) a.moments[(int64_t)cell * 14 + q] = m[q];
+        }
     }
+    // every thread leaves the pass together: the caller's loop starts with a
+    // thread-0 work fetch, and a thread-0 block just before it must not be
+    // merged with it or moved out of the loop
+    __syncthreads();
 }
 
 template <typename R, int T, int K, int F>
@@ -696,9 +616,7 @@ __global__ __launch_bounds__(1024) void k_collide_huge(CollideArgs a, const int3
                         real[4] += (double)x * x + (double)y * y + (double)z * z;
                     }
                     block_sum<5>(real, red);
-                    if (a.debt && threadIdx.x < 4)
-                        a.debt[(int64_t)cell * 4 + threadIdx.x] =
-                            threadIdx.x < 3 ? cr.P[threadIdx.x] - real[1 + threadIdx.x] : cr.Q - real[4];
+                    if (a.debt && threadIdx.x == 0) store_debt(a.debt + (int64_t)cell * 4, cr, real);
                 }
                 __syncthreads();
             }
@@ -726,7 +644,10 @@ __global__ __launch_bounds__(1024) void k_collide_huge(CollideArgs a, const int3
         }
         if (a.flags & PIC_MOMENTS) {
             block_sum<14>(m, red);
-            if (threadIdx.x < 14) a.moments[(int64_t)cell * 14 + threadIdx.x] = m[threadIdx.x];
+            if (threadIdx.x == 0) {
+#pragma unroll
+                for (int q = 0; q < 14; ++q) a.moments[(int64_t)cell * 14 + q] = m[q];
+            }
         }
         __syncthreads();
     }
@@ -846,7 +767,7 @@ ClassCaps collide_caps(int dtype, size_t)
 size_t huge_scratch_bytes(int dtype, int64_t n)
 {
     const size_t rec = dtype == PIC_F32 ? 16 : 32;
-    return (size_t)n * (4 * 4 + 8 + 1) + ((size_t)n / 2 + 2) * rec + 1024;
+    return (size_t)n * (4 * 4 + 8 + 1) + ((size_t)n / 2 + 2) * rec + 7 * 256;   // 7 aligned parts
 }
 
 void set_huge_scratch(int dtype, int64_t n, void *base)

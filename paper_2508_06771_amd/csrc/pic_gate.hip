@@ -145,50 +145,345 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float *__restrict__ p
     }
 }
 
+// ------------------------------------------------------------ matrix-core network
+// bfloat16 mode on the matrix cores: one wave evaluates 32 samples with
+// v_mfma_f32_32x32x8_bf16 (A 32x8 rows x k, B 8x32 k x columns, FP32
+// accumulation).  Operand layout of that instruction: A[i][k] sits in lane
+// i + 32 (k / 4), element k % 4; B[k][j] in lane j + 32 (k / 4), element
+// k % 4; D[i][j] in lane j + 32 ((i / 4) % 2), element 4 (i / 8) + i % 4.
+// Layer 1 is one product per 32 output columns; the hidden layer goes
+// through LDS to change from the D to the A layout; layer 2 is eight
+// products of k = 8 per 32 columns; the output layer is a lane reduction.
+// The rounding points are those of mlp_logit: bfloat16 inputs, weights and
+// hidden activations, binary32 sums (here in the matrix core's order).
+typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ short bf16_bits(float x)
+{
+    return (short)(__float_as_uint(bf16r(x)) >> 16);
+}
+
+constexpr int MLP_ROW = 64 + 4;   // padded LDS rows (bank spread)
+
+struct __align__(16) MlpLDS {
+    short w1t[64][8];           // W1 transposed, [column][k], bfloat16
+    short w2t[64][MLP_ROW];     // W2 transposed, [column][k], bfloat16
+    float b1[64], b2[64], w3[64], b3;
+};
+
+struct __align__(16) MlpWave {
+    short h1[32][MLP_ROW];      // hidden layer 1 of the wave's 32 samples
+};
+
+__device__ void load_mlp_lds(MlpLDS &P, const float *params)
+{
+    for (int p = threadIdx.x; p < 8 * 64; p += blockDim.x) {
+        const int i = p / 64, j = p % 64;
+        P.w1t[j][i] = bf16_bits(params[OFF_W1 + p]);
+    }
+    for (int p = threadIdx.x; p < 64 * 64; p += blockDim.x) {
+        const int i = p / 64, j = p % 64;
+        P.w2t[j][i] = bf16_bits(params[OFF_W2 + p]);
+    }
+    for (int j = threadIdx.x; j < 64; j += blockDim.x) {
+        P.b1[j] = params[OFF_B1 + j];
+        P.b2[j] = params[OFF_B2 + j];
+        P.w3[j] = bf16r(params[OFF_W3 + j]);
+    }
+    if (threadIdx.x == 0) P.b3 = params[OFF_B3];
+}
+
+__device__ __forceinline__ void wave_lds_order()
+{
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+}
+
+// Logit of sample (lane % 32) of the wave's 32; x: that sample's features
+// (both half-waves hold them).  Every lane of the wave must take part.
+__device__ float mlp_logit_mfma(const MlpLDS &P, const float x[8], MlpWave &W)
+{
+    const int lane = threadIdx.x & (PIC_WAVE - 1);
+    const int half = lane >> 5, c = lane & 31;
+    bf16x4_t a, b0, b1;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        a[j] = bf16_bits(half ? x[4 + j] : x[j]);
+        b0[j] = P.w1t[c][4 * half + j];
+        b1[j] = P.w1t[c + 32][4 * half + j];
+    }
+    f32x16_t d0, d1;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) d0[r] = d1[r] = 0.0f;
+    d0 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b0, d0, 0, 0, 0);
+    d1 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b1, d1, 0, 0, 0);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int row = 8 * (r / 4) + 4 * half + (r % 4);
+        const float z0 = d0[r] + P.b1[c], z1 = d1[r] + P.b1[c + 32];
+        W.h1[row][c] = bf16_bits(z0 > 0.0f ? z0 : 0.0f);
+        W.h1[row][c + 32] = bf16_bits(z1 > 0.0f ? z1 : 0.0f);
+    }
+    wave_lds_order();
+    f32x16_t e0, e1;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) e0[r] = e1[r] = 0.0f;
+#pragma unroll
+    for (int kc = 0; kc < 8; ++kc) {
+        const bf16x4_t ah = *(const bf16x4_t *)&W.h1[c][8 * kc + 4 * half];
+        const bf16x4_t w0 = *(const bf16x4_t *)&P.w2t[c][8 * kc + 4 * half];
+        const bf16x4_t w1 = *(const bf16x4_t *)&P.w2t[c + 32][8 * kc + 4 * half];
+        e0 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ah, w0, e0, 0, 0, 0);
+        e1 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ah, w1, e1, 0, 0, 0);
+    }
+    float sum[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const float z0 = e0[r] + P.b2[c], z1 = e1[r] + P.b2[c + 32];
+        sum[r] = bf16r(z0 > 0.0f ? z0 : 0.0f) * P.w3[c] + bf16r(z1 > 0.0f ? z1 : 0.0f) * P.w3[c + 32];
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+#pragma unroll
+        for (int o = 16; o >= 1; o >>= 1) sum[r] += __shfl_xor(sum[r], o, 32);
+    // every lane of a half-wave now holds the 16 row sums of rows
+    // 8 (r / 4) + 4 half + r % 4; sample c's row is among them when
+    // bit 2 of c equals half, else the other half-wave holds it
+    const int rc = 4 * (c / 8) + (c % 4);
+    float mine = sum[0];
+#pragma unroll
+    for (int r = 1; r < 16; ++r) mine = (rc == r) ? sum[r] : mine;
+    const float other = __shfl_xor(mine, 32, PIC_WAVE);
+    wave_lds_order();   // the next tile rewrites W
+    return (((c >> 2) & 1) == half ? mine : other) + P.b3;
+}
+
+__global__ __launch_bounds__(256) void k_mlp_forward_mfma(const float *__restrict__ params,
+                                                          const float *__restrict__ x, int32_t B,
+                                                          float *__restrict__ prob)
+{
+    __shared__ MlpLDS P;
+    __shared__ MlpWave Wv[4];
+    load_mlp_lds(P, params);
+    __syncthreads();
+    const int wid = threadIdx.x / PIC_WAVE, c = threadIdx.x & 31;
+    const int ntiles = (B + 31) / 32;
+    for (int tile = blockIdx.x * 4 + wid; tile < ntiles; tile += gridDim.x * 4) {
+        const int s = tile * 32 + c;
+        float xi[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) xi[i] = s < B ? x[(int64_t)s * 8 + i] : 0.0f;
+        const float z = mlp_logit_mfma(P, xi, Wv[wid]);
+        if ((threadIdx.x & 32) == 0 && s < B) prob[s] = 1.0f / (1.0f + __expf(-z));
+        __builtin_amdgcn_wave_barrier();   // the next tile needs the whole wave
+    }
+}
+
 // ------------------------------------------------------------ gate per step
 __global__ void k_gate_begin(DevGate *g)
 {
     if (threadIdx.x == 0) g->judge_count = 0;
 }
 
-// One thread per cell: decide skip / collide, with the deferred-time count.
+// Decision for cell j from the network's probability p (valid: the cell
+// has features and the gate is on).
+__device__ __forceinline__ void gate_decide(const GateArgs &a, int j, bool valid, float p, uint64_t step,
+                                            bool on)
+{
+    const bool want = valid && p > a.thr && a.k_acc[j] < a.kmax;
+    const W4 w = draw4(a.seed, (uint32_t)j, (uint32_t)step, 2u, 0u);
+    const bool judge = on && (uint64_t)w.x < a.judge_thr;
+    const bool skip = want && !judge;
+    a.prob[j] = valid ? p : 0.0f;
+    a.want[j] = want;
+    a.skip[j] = skip;
+    if (skip) {
+        a.k_acc[j] += 1;
+        a.dt_scale[j] = 0.0;
+    } else {
+        a.dt_scale[j] = (double)(a.k_acc[j] + 1);
+        a.k_acc[j] = 0;
+    }
+    if (judge) a.judge_list[atomicAdd(&a.g->judge_count, 1u)] = j;
+    if (skip) atomicAdd(&a.g->skipped, 1ull);
+    else atomicAdd(&a.g->collided, 1ull);
+}
+
+// One thread per cell (binary32 network): decide skip / collide, with the
+// deferred-time count.
 __global__ __launch_bounds__(256) void k_gate(GateArgs a)
 {
     __shared__ float P[NPARAM];
-    load_params(P, a.params, a.bf16 != 0);
+    load_params(P, a.params, false);
     const uint64_t step = a.step_dev ? *a.step_dev : a.step;
     const bool on = a.g->have_moments && !a.g->disabled;
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < a.M; j += gridDim.x * blockDim.x) {
-        bool want = false;
         float p = 0.0f;
+        bool valid = false;
         if (on) {
             float f[8];
-            if (features_from_sums(a.moments + (int64_t)j * 14, f)) {
-                p = 1.0f / (1.0f + __expf(-mlp_logit(P, f, a.bf16 != 0)));
-                want = p > a.thr && a.k_acc[j] < a.kmax;
-            }
+            valid = features_from_sums(a.moments + (int64_t)j * 14, f);
+            if (valid) p = 1.0f / (1.0f + __expf(-mlp_logit(P, f, false)));
         }
-        const W4 w = draw4(a.seed, (uint32_t)j, (uint32_t)step, 2u, 0u);
-        const bool judge = on && (uint64_t)w.x < a.judge_thr;
-        const bool skip = want && !judge;
-        a.prob[j] = p;
-        a.want[j] = want;
-        a.skip[j] = skip;
-        if (skip) {
-            a.k_acc[j] += 1;
-            a.dt_scale[j] = 0.0;
-        } else {
-            a.dt_scale[j] = (double)(a.k_acc[j] + 1);
-            a.k_acc[j] = 0;
+        gate_decide(a, j, valid, p, step, on);
+    }
+}
+
+// The same decision with the bfloat16 network on the matrix cores: one wave
+// per 32 cells.
+__global__ __launch_bounds__(256) void k_gate_mfma(GateArgs a)
+{
+    __shared__ MlpLDS P;
+    __shared__ MlpWave Wv[4];
+    load_mlp_lds(P, a.params);
+    __syncthreads();
+    const uint64_t step = a.step_dev ? *a.step_dev : a.step;
+    const bool on = a.g->have_moments && !a.g->disabled;
+    const int wid = threadIdx.x / PIC_WAVE, c = threadIdx.x & 31;
+    const int ntiles = (a.M + 31) / 32;
+    for (int tile = blockIdx.x * 4 + wid; tile < ntiles; tile += gridDim.x * 4) {
+        const int j = tile * 32 + c;
+        float f[8];
+        bool valid = false;
+        if (on && j < a.M) valid = features_from_sums(a.moments + (int64_t)j * 14, f);
+        if (!valid) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) f[i] = 0.0f;
         }
-        if (judge) a.judge_list[atomicAdd(&a.g->judge_count, 1u)] = j;
-        if (skip) atomicAdd(&a.g->skipped, 1ull);
-        else atomicAdd(&a.g->collided, 1ull);
+        float p = 0.0f;
+        if (on) p = 1.0f / (1.0f + __expf(-mlp_logit_mfma(P, f, Wv[wid])));
+        if ((threadIdx.x & 32) == 0 && j < a.M) gate_decide(a, j, valid, p, step, on);
+        __builtin_amdgcn_wave_barrier();   // the next tile needs the whole wave
     }
 }
 
 // ------------------------------------------------------------ relaxation label
-// One workgroup per listed cell: r = || (1/K) sum_replicas sum_pairs
+// Cells of at most RELAX_LDS_CAP members: one workgroup per (cell, replica)
+// sorts the replica's keys in LDS and sums the pair terms
+// 1/4 h(s^2) (|u|^2 I - 3 u u^T) into part[]; k_relax_finish adds the
+// replicas in order and normalises.  Larger cells take k_relax below.
+constexpr int RELAX_T0 = 256, RELAX_K0 = 8;      // <= 2048 members
+constexpr int RELAX_T1 = 1024, RELAX_K1 = 10;    // <= 10240 members
+constexpr int RELAX_LDS_CAP = RELAX_T1 * RELAX_K1;
+
+template <typename R, int T, int K>
+__global__ __launch_bounds__(T) void k_relax_lds(RelaxArgs a, int nmin)
+{
+    constexpr int CAP = T * K;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[6 * (T / PIC_WAVE)];
+    __shared__ uint32_t wtot[T / PIC_WAVE];
+    if (a.dflags && (a.dflags->range_err || (a.assume_sorted && a.dflags->unsorted))) return;
+    const uint32_t count = a.count_dev ? *a.count_dev : (uint32_t)a.count;
+    const uint32_t reps = (uint32_t)a.replicas;
+    const uint32_t items = count * reps;
+    const uint32_t step = (uint32_t)(a.step_dev ? *a.step_dev : a.step);
+    const SortLDS<T, CAP> L(smem);
+    for (uint32_t item = blockIdx.x; item < items; item += gridDim.x) {
+        const uint32_t which = item / reps, rep = item - which * reps;
+        const int cell = a.list ? a.list[which] : (int)which;
+        const int lo = a.cell_start[cell];
+        const int n = a.cell_start[cell + 1] - lo;
+        if (n < nmin || n > CAP) continue;
+        double acc[6] = {0, 0, 0, 0, 0, 0};   // xx yy zz xy xz yz
+        if (n >= 2) {
+            const uint32_t *pid_c = a.pid + lo;
+            const uint32_t bits = sort_bits(n);
+            uint32_t pos[K];
+            L.clear();
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int i = threadIdx.x + k * T;
+                if (i < n) pos[k] = L.count(i, draw4(a.seed, pid_c[i], step, 3u, rep).x, bits);
+            }
+            __syncthreads();
+            rank_in_lds<T, K, CAP>(pos, n, bits, L, pid_c, wtot);
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int i = threadIdx.x + k * T;
+                if (i < n) L.lst[pos[k]] = (uint16_t)i;
+            }
+            __syncthreads();
+            const R *vx = (const R *)a.v + lo;
+            const R *vy = (const R *)a.v + a.n + lo;
+            const R *vz = (const R *)a.v + 2 * a.n + lo;
+            const double dens = a.density ? a.density[cell] : 1.0;
+            const double dts = a.dt_scale ? a.dt_scale[cell] : 1.0;
+            const double C = 8.0 * PI_D * dens * a.lnL * a.dt * dts;
+            for (int q = threadIdx.x; q < n / 2; q += T) {
+                const int ia = L.lst[2 * q], ib = L.lst[2 * q + 1];
+                const double ux = (double)vx[ia] - (double)vx[ib];
+                const double uy = (double)vy[ia] - (double)vy[ib];
+                const double uz = (double)vz[ia] - (double)vz[ib];
+                const double uu = ux * ux + uy * uy + uz * uz;
+                if (uu == 0.0) continue;
+                const double hq = 0.25 * h_angle(C / (uu * sqrt(uu)));
+                acc[0] += hq * (uu - 3.0 * ux * ux);
+                acc[1] += hq * (uu - 3.0 * uy * uy);
+                acc[2] += hq * (uu - 3.0 * uz * uz);
+                acc[3] += hq * (-3.0 * ux * uy);
+                acc[4] += hq * (-3.0 * ux * uz);
+                acc[5] += hq * (-3.0 * uy * uz);
+            }
+        }
+        block_sum<6>(acc, red);     // its barriers also end this item's use of LDS
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) a.part[(size_t)item * 6 + c] = acc[c];
+        }
+        __syncthreads();   // reconverge before the next item (see cell_pass)
+    }
+}
+
+// One workgroup per listed cell of at most RELAX_LDS_CAP members: the cell's
+// temperature, the replica sums in replica order, r.
+template <typename R>
+__global__ __launch_bounds__(256) void k_relax_finish(RelaxArgs a)
+{
+    __shared__ double red[5 * 4];
+    if (a.dflags && (a.dflags->range_err || (a.assume_sorted && a.dflags->unsorted))) return;
+    const uint32_t count = a.count_dev ? *a.count_dev : (uint32_t)a.count;
+    for (uint32_t which = blockIdx.x; which < count; which += gridDim.x) {
+        const int cell = a.list ? a.list[which] : (int)which;
+        const int lo = a.cell_start[cell];
+        const int n = a.cell_start[cell + 1] - lo;
+        if (n > RELAX_LDS_CAP) continue;
+        if (n < 2) {
+            if (threadIdx.x == 0) a.r_out[cell] = 0.0;
+            __syncthreads();
+            continue;
+        }
+        const R *vx = (const R *)a.v + lo;
+        const R *vy = (const R *)a.v + a.n + lo;
+        const R *vz = (const R *)a.v + 2 * a.n + lo;
+        double s5[5] = {0, 0, 0, 0, 0};
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            const double x = vx[i], y = vy[i], z = vz[i];
+            s5[1] += x;
+            s5[2] += y;
+            s5[3] += z;
+            s5[4] += x * x + y * y + z * z;
+        }
+        block_sum<5>(s5, red);
+        if (threadIdx.x == 0) {
+            const double N = (double)n;
+            const double T = (s5[4] / N - (s5[1] * s5[1] + s5[2] * s5[2] + s5[3] * s5[3]) / (N * N)) / 3.0;
+            double acc[6] = {0, 0, 0, 0, 0, 0};
+            const double *pc = a.part + (size_t)which * a.replicas * 6;
+            for (int rep = 0; rep < a.replicas; ++rep)
+                for (int c = 0; c < 6; ++c) acc[c] += pc[rep * 6 + c];
+            const double K = (double)a.replicas;
+            double f2 = 0.0;
+            for (int c = 0; c < 3; ++c) f2 += (acc[c] / K) * (acc[c] / K);
+            for (int c = 3; c < 6; ++c) f2 += 2.0 * (acc[c] / K) * (acc[c] / K);
+            a.r_out[cell] = T > 0.0 ? sqrt(f2) / (N * T) : 0.0;
+        }
+        __syncthreads();
+    }
+}
+
+// Cells above RELAX_LDS_CAP members: one workgroup per listed cell: r = || (1/K) sum_replicas sum_pairs
 // 1/4 h(s^2) (|u|^2 I - 3 u u^T) ||_F / (N T), pairs from independent
 // re-pairings (domain 3, c3 = replica); s^2 = 8 pi n lnL dt dt_scale / |u|^3.
 template <typename R>
@@ -206,10 +501,7 @@ __global__ __launch_bounds__(1024) void k_relax(RelaxArgs a, HugeScratch hs)
         const int cell = a.list ? a.list[item] : (int)item;
         const int lo = a.cell_start[cell];
         const int n = a.cell_start[cell + 1] - lo;
-        if (n < 2) {
-            if (threadIdx.x == 0) a.r_out[cell] = 0.0;
-            continue;
-        }
+        if (n <= RELAX_LDS_CAP) continue;    // sorted in LDS by k_relax_lds
         // temperature of the cell
         double s5[5] = {0, 0, 0, 0, 0};
         for (int i = threadIdx.x; i < n; i += blockDim.x) {
@@ -460,8 +752,14 @@ int launch_mlp_forward(const float *params, const float *x, int32_t B, int bf16,
                        hipStream_t st)
 {
     if (B <= 0) return PIC_OK;
-    const int g = (B + 255) / 256 < 1024 ? (B + 255) / 256 : 1024;
-    hipLaunchKernelGGL(k_mlp_forward, dim3(g), dim3(256), 0, st, params, x, B, bf16, prob);
+    if (bf16) {
+        const int tiles = (B + 31) / 32;
+        const int g = (tiles + 3) / 4 < 1024 ? (tiles + 3) / 4 : 1024;
+        hipLaunchKernelGGL(k_mlp_forward_mfma, dim3(g), dim3(256), 0, st, params, x, B, prob);
+    } else {
+        const int g = (B + 255) / 256 < 1024 ? (B + 255) / 256 : 1024;
+        hipLaunchKernelGGL(k_mlp_forward, dim3(g), dim3(256), 0, st, params, x, B, bf16, prob);
+    }
     HIP_OK(hipGetLastError());
     return PIC_OK;
 }
@@ -497,8 +795,14 @@ int launch_adam(float *params, float *m, float *v, const float *grad, int32_t t,
 int launch_gate(const GateArgs &a, hipStream_t st)
 {
     hipLaunchKernelGGL(k_gate_begin, dim3(1), dim3(64), 0, st, a.g);
-    const int g = (a.M + 255) / 256 < 2048 ? (a.M + 255) / 256 : 2048;
-    hipLaunchKernelGGL(k_gate, dim3(g > 0 ? g : 1), dim3(256), 0, st, a);
+    if (a.bf16) {
+        const int tiles = (a.M + 31) / 32;
+        const int g = (tiles + 3) / 4 < 1024 ? (tiles + 3) / 4 : 1024;
+        hipLaunchKernelGGL(k_gate_mfma, dim3(g > 0 ? g : 1), dim3(256), 0, st, a);
+    } else {
+        const int g = (a.M + 255) / 256 < 2048 ? (a.M + 255) / 256 : 2048;
+        hipLaunchKernelGGL(k_gate, dim3(g > 0 ? g : 1), dim3(256), 0, st, a);
+    }
     HIP_OK(hipGetLastError());
     return PIC_OK;
 }
@@ -519,13 +823,41 @@ int launch_gate_end(DevGate *g, hipStream_t st)
     return PIC_OK;
 }
 
-int launch_relax(int dtype, const RelaxArgs &a, int num_cu, hipStream_t st)
+size_t relax_part_bytes(int64_t count, int replicas)
 {
-    const int g = num_cu;
-    if (dtype == PIC_F32)
-        hipLaunchKernelGGL(k_relax<float>, dim3(g), dim3(1024), 0, st, a, huge_scratch());
-    else
-        hipLaunchKernelGGL(k_relax<double>, dim3(g), dim3(1024), 0, st, a, huge_scratch());
+    return (size_t)count * (size_t)replicas * 6 * sizeof(double) + 256;
+}
+
+template <typename R, int T, int K>
+static int launch_relax_lds(const RelaxArgs &a, int nmin, int blocks, hipStream_t st)
+{
+    const size_t lds = sort_bytes(T * K);
+    auto kern = k_relax_lds<R, T, K>;
+    static bool attr_done = false;
+    if (!attr_done) {
+        HIP_OK(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)lds));
+        attr_done = true;
+    }
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(T), lds, st, a, nmin);
     HIP_OK(hipGetLastError());
     return PIC_OK;
+}
+
+template <typename R>
+static int launch_relax_t(const RelaxArgs &a, int num_cu, hipStream_t st)
+{
+    int rc;
+    if ((rc = launch_relax_lds<R, RELAX_T0, RELAX_K0>(a, 0, num_cu * 4, st))) return rc;
+    if ((rc = launch_relax_lds<R, RELAX_T1, RELAX_K1>(a, RELAX_T0 * RELAX_K0 + 1, num_cu, st)))
+        return rc;
+    hipLaunchKernelGGL(k_relax<R>, dim3(num_cu), dim3(1024), 0, st, a, huge_scratch());
+    hipLaunchKernelGGL(k_relax_finish<R>, dim3(num_cu * 4), dim3(256), 0, st, a);
+    HIP_OK(hipGetLastError());
+    return PIC_OK;
+}
+
+int launch_relax(int dtype, const RelaxArgs &a, int num_cu, hipStream_t st)
+{
+    return dtype == PIC_F32 ? launch_relax_t<float>(a, num_cu, st) : launch_relax_t<double>(a, num_cu, st);
 }

@@ -168,6 +168,16 @@ __device__ __forceinline__ Correction make_correction(const double *b, const dou
     return c;
 }
 
+// The shortfall left after the correction: target minus the realised sums
+// (real[1..3] momentum, real[4] sum |v|^2).
+__device__ __forceinline__ void store_debt(double *debt, const Correction &c, const double *real)
+{
+    debt[0] = c.P[0] - real[1];
+    debt[1] = c.P[1] - real[2];
+    debt[2] = c.P[2] - real[3];
+    debt[3] = c.Q - real[4];
+}
+
 // ---------------------------------------------------------------------------
 // Wave / block reductions in a fixed order (bitwise reproducible).
 // ---------------------------------------------------------------------------
@@ -233,6 +243,138 @@ __device__ __forceinline__ uint32_t block_excl(uint32_t x, uint32_t *wtot)
 __device__ __forceinline__ uint32_t get16(const uint32_t *w, uint32_t b)
 {
     return (w[b >> 1] >> ((b & 1u) * 16u)) & 0xFFFFu;
+}
+
+// ---------------------------------------------------------------------------
+// LDS sort of one cell's members by (key, pid).  Buckets are the top `bits`
+// bits of the key with nbk = 2^bits >= n buckets (so at most one member per
+// bucket on average); the bucket is monotone in the key, so bucket order and
+// then (key, pid) order inside a bucket give the full order.  Layout for a
+// cell capacity CAP: keys by member, keys in bucket order (padded for 4-wide
+// reads), 16-bit bucket counters (two per word), members in bucket order.
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr uint32_t next_pow2(uint32_t x)
+{
+    uint32_t p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+__host__ __device__ constexpr size_t sort_bytes(int cap)
+{
+    return (size_t)cap * 4 + ((size_t)cap + 4) * 4 + (size_t)next_pow2((uint32_t)cap) * 2 +
+           (size_t)cap * 2;
+}
+
+template <int T, int CAP>
+struct SortLDS {
+    static constexpr int WMAX = (int)(next_pow2(CAP) / 2);   // counter words
+    static constexpr int PERW = WMAX / T;                     // words per thread
+    static_assert(PERW >= 1 && PERW * T == WMAX, "counter table must split evenly");
+    uint32_t *keys;    // [CAP] key of member i
+    uint32_t *sk;      // [CAP + 4] keys in bucket order
+    uint32_t *cnt;     // [WMAX] bucket counters, then bucket starts
+    uint16_t *lst;     // [CAP] member in bucket order
+    __device__ explicit SortLDS(unsigned char *smem)
+        : keys((uint32_t *)smem), sk(keys + CAP), cnt(sk + CAP + 4), lst((uint16_t *)(cnt + WMAX))
+    {
+    }
+    __device__ uint32_t *own() const { return cnt + threadIdx.x * PERW; }
+    // zero the counters (the caller synchronises before counting)
+    __device__ void clear() const
+    {
+        uint32_t *c = own();
+#pragma unroll
+        for (int q = 0; q < PERW; ++q) c[q] = 0u;
+    }
+    // counts member i with key `key`; returns (bucket << 16) | arrival rank
+    __device__ uint32_t count(int i, uint32_t key, uint32_t bits) const
+    {
+        keys[i] = key;
+        const uint32_t b = __builtin_amdgcn_ubfe(key, (32u - bits) & 31u, bits);
+        const uint32_t sh = (b & 1u) << 4;
+        const uint32_t old = atomicAdd(&cnt[b >> 1], 1u << sh);
+        return (b << 16) | ((old >> sh) & 0xFFFFu);
+    }
+};
+
+__device__ __forceinline__ uint32_t sort_bits(int n)
+{
+    return n >= 2 ? 32u - (uint32_t)__clz(n - 1) : 0u;
+}
+
+// After counting (and a barrier): pos[k] of member i = threadIdx.x + k T goes
+// from (bucket << 16 | arrival) to the member's position in (key, pid)
+// order.  Ends with a barrier.
+template <int T, int K, int CAP>
+__device__ void rank_in_lds(uint32_t (&pos)[K], int n, uint32_t bits, const SortLDS<T, CAP> &L,
+                            const uint32_t *pid_c, uint32_t *wtot)
+{
+    constexpr int PERW = SortLDS<T, CAP>::PERW;
+    const uint32_t nbk = 1u << bits;
+    {
+        // exclusive scan of the bucket counts over the per-thread chunks
+        uint32_t *own = L.own();
+        uint32_t c[PERW], s = 0;
+#pragma unroll
+        for (int q = 0; q < PERW; ++q) {
+            c[q] = own[q];
+            s += (c[q] & 0xFFFFu) + (c[q] >> 16);
+        }
+        uint32_t run = block_excl(s, wtot);
+#pragma unroll
+        for (int q = 0; q < PERW; ++q) {
+            const uint32_t lo16 = run, hi16 = run + (c[q] & 0xFFFFu);
+            run = hi16 + (c[q] >> 16);
+            own[q] = lo16 | (hi16 << 16);
+        }
+    }
+    __syncthreads();
+    // keys and members in bucket order
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int i = threadIdx.x + k * T;
+        if (i < n) {
+            const uint32_t slot = get16(L.cnt, pos[k] >> 16) + (pos[k] & 0xFFFFu);
+            L.sk[slot] = L.keys[i];
+            L.lst[slot] = (uint16_t)i;
+        }
+    }
+    __syncthreads();
+    // position = bucket start + rank by (key, pid) inside the bucket; the
+    // first four members are compared without a loop
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int i = threadIdx.x + k * T;
+        if (i < n) {
+            const uint32_t b = pos[k] >> 16, arr = pos[k] & 0xFFFFu;
+            const uint32_t beg = get16(L.cnt, b);
+            const uint32_t size = ((b + 1 < nbk) ? get16(L.cnt, b + 1) : (uint32_t)n) - beg;
+            const uint32_t *skb = L.sk + beg;
+            const uint32_t key = skb[arr];
+            uint32_t r = 0, tie = 0;
+#pragma unroll
+            for (uint32_t j = 0; j < 4; ++j) {
+                const uint32_t kj = skb[j];
+                const bool in = j < size;
+                r += (in && kj < key) ? 1u : 0u;
+                tie |= (in && kj == key && j != arr) ? 1u : 0u;
+            }
+            for (uint32_t j = 4; j < size; ++j) {
+                const uint32_t kj = skb[j];
+                r += kj < key ? 1u : 0u;
+                tie |= (kj == key && j != arr) ? 1u : 0u;
+            }
+            if (tie) {
+                // equal keys: the smaller pid comes first
+                const uint32_t pi = pid_c[i];
+                for (uint32_t j = 0; j < size; ++j)
+                    if (j != arr && skb[j] == key && pid_c[L.lst[beg + j]] < pi) ++r;
+            }
+            pos[k] = beg + r;
+        }
+    }
+    __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
@@ -435,7 +577,10 @@ struct RelaxArgs {
     double *r_out;              // indexed by cell
     const DevFlags *dflags;     // in a collision step: skip when binning failed
     int assume_sorted;
+    double *part;               // [count * replicas * 6] per-replica tensor sums
 };
+// Scratch bytes of launch_relax for `count` cells.
+size_t relax_part_bytes(int64_t count, int replicas);
 
 int launch_features(const double *moments, int32_t M, float *feat, uint8_t *valid, hipStream_t st);
 int launch_mlp_forward(const float *params, const float *x, int32_t B, int bf16, float *prob,

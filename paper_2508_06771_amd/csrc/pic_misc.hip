@@ -61,7 +61,11 @@ __global__ __launch_bounds__(256) void k_moments(const R *__restrict__ v, int64_
             m[13] += q2 * q2;
         }
         block_sum<14>(m, red);
-        if (threadIdx.x < 14) out[(int64_t)j * 14 + threadIdx.x] = m[threadIdx.x];
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int q = 0; q < 14; ++q) out[(int64_t)j * 14 + q] = m[q];
+        }
+        __syncthreads();   // reconverge before the next cell's reduction
     }
 }
 

@@ -63,6 +63,19 @@ def test_relaxation_labels(ctx):
     assert np.allclose(host(r), ref, rtol=1e-8, atol=1e-14)
 
 
+def test_relaxation_labels_large_cells(ctx):
+    """Cells beyond the small LDS sort (2,048 members) and beyond the large one
+    (10,240 members, sorted in global scratch) give the oracle's label too."""
+    import torch
+    w, cs = sorted_workload(4, [2, 3000, 10300])
+    r = ctx.relaxation(dev(w.v, torch.float32), dev(cs), dev(w.pid), dt=w.dt, lnL=w.lnL, seed=6,
+                       step=2, replicas=1)
+    ctx.sync()
+    v32 = dev(w.v, torch.float32).cpu().numpy().astype(np.float64)
+    ref = physics.relaxation(v32, cs, w.pid, dt=w.dt, lnL=w.lnL, seed=6, step=2, replicas=1)
+    assert np.allclose(host(r), ref, rtol=1e-8, atol=1e-14)
+
+
 def rand_params(seed, scale=0.4):
     rng = np.random.default_rng(seed)
     return physics.pack_params([rng.standard_normal(s) * scale for s in physics.mlp_init_shapes()])
