@@ -32,6 +32,30 @@ BYTES_CHECK = 4          # order check: read cell_of
 BYTES_COLLIDE = 4 + 12 + 12   # collide pass: read pid + v, write v
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_collide_c2_hbm_traffic.md")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    summary (FETCH_SIZE and WRITE_SIZE passes scaled by a plain copy of known
+    size), or None when the kernel sources changed since it was taken."""
+    import hashlib
+    try:
+        fields = dict(line.split(": ", 1) for line in open(TRAFFIC_PROFILE).read().splitlines()
+                      if line.startswith(("traffic_bytes_per_launch:", "source_sha256:", "sources:")))
+    except OSError:
+        return None
+    h = hashlib.sha256()
+    for f in fields.get("sources", "").split():
+        try:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        except OSError:
+            return None
+    if h.hexdigest() != fields.get("source_sha256", "").strip():
+        return None
+    return int(fields["traffic_bytes_per_launch"])
+
+
 def energy(v):
     return float((v.double() ** 2).sum().item()) * 0.5
 
@@ -409,8 +433,11 @@ def main():
         kms, kcnt = kt["class3"]
         kavg = kms / kcnt
         achieved = n * BYTES_COLLIDE / (kavg * 1e-3) / 1e9
+        tb = measured_traffic()
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None if tb is None else round(tb / (kavg * 1e-3) / 1e9, 1),
+                "traffic_bytes_per_launch": tb,
                 "kernel": "k_collide<float,1024,10> (cells of 4097..10240 members)",
                 "kernel_avg_ms": round(kavg, 5),
                 "bytes_per_launch": n * BYTES_COLLIDE}

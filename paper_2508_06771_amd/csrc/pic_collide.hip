@@ -194,6 +194,56 @@ __device__ __forceinline__ void moment_terms(double *m, double x, double y, doub
     m[13] += sign * (q2 * q2);
 }
 
+// The 14 moment sums of the pass's members (layout of pic_cell_moments),
+// one sum at a time: each is summed over the thread's members, then the wave,
+// then the waves in order, so only one accumulator is live at once.  The
+// count is n.  Contains a barrier; threads 1..13 write the sums.
+template <typename R, int T, int K>
+__device__ __forceinline__ void cell_moments_out(double *out, const R (&vx)[K], const R (&vy)[K],
+                                                 const R (&vz)[K], int n, double *red)
+{
+    constexpr int NW = T / PIC_WAVE;
+    const int lane = threadIdx.x & (PIC_WAVE - 1), wid = threadIdx.x / PIC_WAVE;
+#pragma unroll
+    for (int q = 1; q < 14; ++q) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int i = threadIdx.x + k * T;
+            if (i < n) {
+                const double x = vx[k], y = vy[k], z = vz[k];
+                double t;
+                if (q == 1) t = x;
+                else if (q == 2) t = y;
+                else if (q == 3) t = z;
+                else if (q == 4) t = x * x;
+                else if (q == 5) t = y * y;
+                else if (q == 6) t = z * z;
+                else if (q == 7) t = x * y;
+                else if (q == 8) t = x * z;
+                else if (q == 9) t = y * z;
+                else {
+                    const double q2 = x * x + y * y + z * z;
+                    t = q == 10 ? q2 * x : q == 11 ? q2 * y : q == 12 ? q2 * z : q2 * q2;
+                }
+                s += t;
+            }
+        }
+        s = wave_sum(s);
+        if (lane == 0) red[wid * 14 + q] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < 14) {
+        double tot = 0.0;
+        if (threadIdx.x == 0) {
+            tot = (double)n;
+        } else {
+            for (int w = 0; w < NW; ++w) tot += red[w * 14 + threadIdx.x];
+        }
+        out[threadIdx.x] = tot;
+    }
+}
+
 template <typename R, int T, int K, int F>
 __device__ void cell_pass(const CollideArgs &a, int cell, unsigned char *smem, double *red,
                           uint32_t *wtot, double *s_before)
@@ -434,12 +484,6 @@ __device__ void cell_pass(const CollideArgs &a, int cell, unsigned char *smem, d
             }
         }
     }
-    // store, moment sums
-    double m[14];
-    if constexpr (MOM) {
-#pragma unroll
-        for (int q = 0; q < 14; ++q) m[q] = 0.0;
-    }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int i = threadIdx.x + k * T;
@@ -447,25 +491,9 @@ __device__ void cell_pass(const CollideArgs &a, int cell, unsigned char *smem, d
             vx_g[i] = vx[k];
             vy_g[i] = vy[k];
             vz_g[i] = vz[k];
-            if constexpr (MOM) {
-                const double x = vx[k], y = vy[k], z = vz[k];
-                const double q2 = x * x + y * y + z * z;
-                m[0] += 1.0;
-                m[1] += x; m[2] += y; m[3] += z;
-                m[4] += x * x; m[5] += y * y; m[6] += z * z;
-                m[7] += x * y; m[8] += x * z; m[9] += y * z;
-                m[10] += q2 * x; m[11] += q2 * y; m[12] += q2 * z;
-                m[13] += q2 * q2;
-            }
         }
     }
-    if constexpr (MOM) {
-        block_sum<14>(m, red);
-        if (threadIdx.x == 0) {
-#pragma unroll
-            for (int q = 0; q < 14; ++q) a.moments[(int64_t)cell * 14 + q] = m[q];
-        }
-    }
+    if constexpr (MOM) cell_moments_out<R, T, K>(a.moments + (int64_t)cell * 14, vx, vy, vz, n, red);
     // every thread leaves the pass together: the caller's loop starts with a
     // thread-0 work fetch, and a thread-0 block just before it must not be
     // merged with it or moved out of the loop
@@ -483,6 +511,7 @@ __global__ __launch_bounds__(T) void k_collide(CollideArgs a, const int32_t *__r
     __shared__ int s_item;
     if (gated_off(a)) return;
     const uint32_t count = a.dflags->count[cls];
+    if (blockIdx.x >= count) return;   // no work for this workgroup (nor a queue atomic)
     for (;;) {
         if (threadIdx.x == 0) s_item = (int)atomicAdd(&a.dflags->head[cls], 1u);
         __syncthreads();
@@ -505,6 +534,7 @@ __global__ __launch_bounds__(1024) void k_collide_huge(CollideArgs a, const int3
     __shared__ int s_item;
     if (gated_off(a)) return;
     const uint32_t count = a.dflags->count[cls];
+    if (blockIdx.x >= count) return;   // no work for this workgroup (nor a queue atomic)
     const int T = blockDim.x;
     R *vx_g = (R *)a.v;
     R *vy_g = vx_g + a.n;

@@ -280,11 +280,6 @@ __global__ __launch_bounds__(256) void k_mlp_forward_mfma(const float *__restric
 }
 
 // ------------------------------------------------------------ gate per step
-__global__ void k_gate_begin(DevGate *g)
-{
-    if (threadIdx.x == 0) g->judge_count = 0;
-}
-
 // Decision for cell j from the network's probability p (valid: the cell
 // has features and the gate is on).
 __device__ __forceinline__ void gate_decide(const GateArgs &a, int j, bool valid, float p, uint64_t step,
@@ -295,7 +290,7 @@ __device__ __forceinline__ void gate_decide(const GateArgs &a, int j, bool valid
     const bool judge = on && (uint64_t)w.x < a.judge_thr;
     const bool skip = want && !judge;
     a.prob[j] = valid ? p : 0.0f;
-    a.want[j] = want;
+    a.want[j] = (uint8_t)((want ? 1u : 0u) | (judge ? 2u : 0u));   // bit 1: judged
     a.skip[j] = skip;
     if (skip) {
         a.k_acc[j] += 1;
@@ -304,9 +299,58 @@ __device__ __forceinline__ void gate_decide(const GateArgs &a, int j, bool valid
         a.dt_scale[j] = (double)(a.k_acc[j] + 1);
         a.k_acc[j] = 0;
     }
-    if (judge) a.judge_list[atomicAdd(&a.g->judge_count, 1u)] = j;
-    if (skip) atomicAdd(&a.g->skipped, 1ull);
-    else atomicAdd(&a.g->collided, 1ull);
+}
+
+// One workgroup: the judged cells in ascending order (from bit 1 of want),
+// their count, and the step's skipped / collided totals.  No atomics: the
+// decision kernel writes flags only (contended counters across the chip's
+// L2 slices cost more than the network itself).
+__global__ __launch_bounds__(1024) void k_gate_list(DevGate *g, const uint8_t *__restrict__ want,
+                                                    const uint8_t *__restrict__ skip, int32_t M,
+                                                    int32_t *__restrict__ judge_list)
+{
+    __shared__ uint32_t wtot[16];
+    // each thread owns a contiguous run of 16-cell words (16-byte loads; the
+    // flag arrays are 256-byte aligned and padded, reads past M are masked)
+    const int words = (M + 15) / 16;
+    const int per = (words + (int)blockDim.x - 1) / (int)blockDim.x;
+    const int w0 = (int)threadIdx.x * per;
+    const uint4 *wv = (const uint4 *)want, *sv = (const uint4 *)skip;
+    uint32_t nj = 0, ns = 0;
+    for (int q = 0; q < per; ++q) {
+        const int w = w0 + q;
+        if (w < words) {
+            const uint4 a = wv[w], b = sv[w];
+            const uint32_t aw[4] = {a.x, a.y, a.z, a.w}, bw[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                if (w * 16 + e < M) {
+                    nj += (aw[e / 4] >> (8 * (e % 4) + 1)) & 1u;
+                    ns += (bw[e / 4] >> (8 * (e % 4))) & 1u;
+                }
+            }
+        }
+    }
+    uint32_t off = block_excl(nj, wtot);
+    const uint32_t sk_before = block_excl(ns, wtot);
+    if (nj) {
+        for (int q = 0; q < per; ++q) {
+            const int w = w0 + q;
+            if (w < words) {
+                const uint4 a = wv[w];
+                const uint32_t aw[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll
+                for (int e = 0; e < 16; ++e)
+                    if (w * 16 + e < M && ((aw[e / 4] >> (8 * (e % 4) + 1)) & 1u)) judge_list[off++] = w * 16 + e;
+            }
+        }
+    }
+    if (threadIdx.x == blockDim.x - 1) {
+        const uint32_t skipped = sk_before + ns;
+        g->judge_count = off;
+        g->skipped += skipped;
+        g->collided += (unsigned long long)M - skipped;
+    }
 }
 
 // One thread per cell (binary32 network): decide skip / collide, with the
@@ -568,7 +612,7 @@ __global__ void k_gate_score(DevGate *g, const int32_t *__restrict__ judge_list,
     const uint32_t cnt = g->judge_count;
     for (uint32_t k = threadIdx.x; k < cnt; k += blockDim.x) {
         const int j = judge_list[k];
-        if (want[j]) {
+        if (want[j] & 1u) {
             atomicAdd(&s_w, 1ull);
             if (r[j] >= tol) atomicAdd(&s_f, 1ull);
         }
@@ -794,7 +838,6 @@ int launch_adam(float *params, float *m, float *v, const float *grad, int32_t t,
 
 int launch_gate(const GateArgs &a, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_gate_begin, dim3(1), dim3(64), 0, st, a.g);
     if (a.bf16) {
         const int tiles = (a.M + 31) / 32;
         const int g = (tiles + 3) / 4 < 1024 ? (tiles + 3) / 4 : 1024;
@@ -803,6 +846,7 @@ int launch_gate(const GateArgs &a, hipStream_t st)
         const int g = (a.M + 255) / 256 < 2048 ? (a.M + 255) / 256 : 2048;
         hipLaunchKernelGGL(k_gate, dim3(g > 0 ? g : 1), dim3(256), 0, st, a);
     }
+    hipLaunchKernelGGL(k_gate_list, dim3(1), dim3(1024), 0, st, a.g, a.want, a.skip, a.M, a.judge_list);
     HIP_OK(hipGetLastError());
     return PIC_OK;
 }
