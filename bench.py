@@ -215,6 +215,7 @@ def bench_c4(args):
         v = torch.from_numpy(w.v).to(dt_).cuda()
         cell = torch.from_numpy(w.cell_of).cuda()
         pid = torch.from_numpy(w.pid.view(np.int32)).cuda()
+        ctx.conserve_reset()
         ctx.coulomb_collide(v, cell, pid, w.n_cells, dt=w.dt, lnL=w.lnL, seed=0, step=0, flags=fl)
         ctx.sync()
         E0 = energy(v)
@@ -280,7 +281,8 @@ def bench_c5(args):
         fl = 0
         if mode == "gated":
             ctx.gate_config(params, meta["threshold"], k_max=8, judge_fraction=0.01,
-                            tolerance=meta["tolerance"], replicas=8, bf16=True)
+                            tolerance=meta["tolerance"], replicas=args.gate_replicas, bf16=True)
+            ctx.gate_refresh(args.gate_refresh)
             ctx.gate_reset()
             fl = piccoll.GATE
         ctx.coulomb_collide(v, cell, pid, w.n_cells, dt=w.dt, lnL=w.lnL, seed=0, step=0, flags=fl)
@@ -322,7 +324,9 @@ def bench_c5(args):
     return _line(n / (res["gated"]["ms_per_step"] * 1e-3), res["gated"]["ms_per_step"], args,
                  "f32", {"workload": f"65536 cells x 2000 electrons ({n}), mixed cells, FP32, "
                                      f"Coulomb only, learned gate (threshold {meta['threshold']:.4f}, "
-                                     f"tolerance {meta['tolerance']}, 1% judged, k_max 8)",
+                                     f"tolerance {meta['tolerance']}, 1% judged with "
+                                     f"{args.gate_replicas} re-pairings, k_max 8, moments every "
+                                     f"{args.gate_refresh} steps)",
                          "n_electrons": n},
                  speedup_over_plain=speed, ms_plain=res["plain"]["ms_per_step"],
                  skipped_fraction=g["skipped"] / max(1, g["skipped"] + g["collided"]),
@@ -350,6 +354,10 @@ def main():
     ap.add_argument("--kernel-steps", type=int, default=10,
                     help="extra eager steps after the timed region whose kernels are timed")
     ap.add_argument("--gate-params", default=None, help="trained gate parameters (.npy) for c5")
+    ap.add_argument("--gate-refresh", type=int, default=4,
+                    help="c5: steps between refreshes of the gate's moment sums")
+    ap.add_argument("--gate-replicas", type=int, default=8,
+                    help="c5: re-pairings averaged by the judge's relaxation label")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the collision step has no cross-GPU exchange "

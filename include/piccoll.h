@@ -211,6 +211,12 @@ int pic_mlp_train_step(pic_ctx *ctx, float *params, float *adam_m, float *adam_v
  * the moments the next step decides from. */
 int pic_gate_config(pic_ctx *ctx, const float *params, float threshold, int32_t k_max,
                     double judge_fraction, double tolerance, int32_t replicas, int bf16);
+/* Moment refresh interval of the gate: the 14 moment sums its features come
+ * from are recomputed in the collide pass on the first gated step and then
+ * every `every` steps (default 1: every step); in between the network reads
+ * the last refresh and the pass runs without the sums.  The choice is made on
+ * the device, so graph replays follow it.  PIC_ERR_ARG if every < 1. */
+int pic_gate_refresh(pic_ctx *ctx, int32_t every);
 /* Forgets deferred counts, moments and statistics. */
 int pic_gate_reset(pic_ctx *ctx);
 /* Host int64 out[8]: gated steps, cells skipped, cells collided, cells

@@ -34,6 +34,7 @@ struct pic_ctx {
     float gate_thr = 0.5f;
     int gate_kmax = 8;
     double gate_judge_frac = 0.01, gate_tol = 1e-3, gate_max_false = 0.1;
+    int gate_mom_every = 1;
     int gate_replicas = 8, gate_bf16 = 1;
     uint32_t gate_min_judged = 20;
     DevGate *gate_dev = nullptr;
@@ -431,6 +432,13 @@ int pic_gate_config(pic_ctx *c, const float *params, float threshold, int32_t k_
     return PIC_OK;
 }
 
+int pic_gate_refresh(pic_ctx *c, int32_t every)
+{
+    if (!c || every < 1) return PIC_ERR_ARG;
+    c->gate_mom_every = every;
+    return PIC_OK;
+}
+
 int pic_gate_reset(pic_ctx *c)
 {
     if (!c) return PIC_ERR_ARG;
@@ -773,6 +781,17 @@ static int step_enqueue(pic_ctx *c, const StepArgs &s, hipStream_t st, const uin
         a.skip = c->gate_skip;
         a.dt_scale = c->gate_dts;
         a.moments = c->gate_mom;
+        a.mom_full = c->gate_mom_every > 1;
+        RC(launch_mom_select(c->gate_dev, step_dev, s.step, c->gate_mom_every, st));
+        if (c->gate_mom_every > 1) {
+            // both variants are enqueued; the device flag selects one
+            CollideArgs plain = a;
+            plain.run_if = &c->gate_dev->mom_now;
+            plain.run_val = 0;
+            RC(launch_collide(dtype, plain, lists, n_cells, caps, 0, c->num_cu, st));
+            a.run_if = &c->gate_dev->mom_now;
+            a.run_val = 1;
+        }
         a.flags |= PIC_MOMENTS;
     }
     RC(launch_collide(dtype, a, lists, n_cells, caps, 0, c->num_cu, st));
@@ -828,6 +847,7 @@ int pic_run_steps(pic_ctx *c, int dtype, void *v, int32_t *cell_of, uint32_t *pi
     put(&c->gate_thr, sizeof(float));
     put(&c->gate_kmax, sizeof(int));
     put(&c->gate_judge_frac, sizeof(double));
+    put(&c->gate_mom_every, sizeof(int));
     put(&c->gate_tol, sizeof(double));
     put(&c->gate_replicas, sizeof(int));
     put(&c->gate_bf16, sizeof(int));

@@ -263,30 +263,50 @@ __device__ void cell_pass(const CollideArgs &a, int cell, unsigned char *smem, d
     const uint32_t *pid_c = a.pid + lo;
 
     if (!PAIRS && a.skip && a.skip[cell]) {
-        // deferred cell: only its null-collision candidates change; the
-        // moment sums are updated by the candidates' differences
-        if constexpr (MCC) {
+        // deferred cell: only its null-collision candidates change.  Its
+        // moment sums are updated by the candidates' differences when they
+        // are current (refresh every step), else recomputed over all members
+        if constexpr (MCC || MOM) {
+            const bool full = MOM && a.mom_full;
             double dm[14];
 #pragma unroll
             for (int q = 0; q < 14; ++q) dm[q] = 0.0;
             for (int i = threadIdx.x; i < n; i += T) {
-                const uint32_t p = pid_c[i];
-                const W4 w = draw4(a.seed, p, step, 0u, 0u);
-                if ((uint64_t)w.y < a.mcc_thr) {
-                    R x = vx_g[i], y = vy_g[i], z = vz_g[i];
-                    if constexpr (MOM) moment_terms(dm, x, y, z, -1.0);
-                    mcc_scatter<R>(x, y, z, p, a.seed, step, a.mass_ratio);
-                    if constexpr (MOM) moment_terms(dm, x, y, z, 1.0);
-                    vx_g[i] = x;
-                    vy_g[i] = y;
-                    vz_g[i] = z;
+                R x = 0, y = 0, z = 0;
+                if (full) {
+                    x = vx_g[i];
+                    y = vy_g[i];
+                    z = vz_g[i];
                 }
+                if constexpr (MCC) {
+                    const uint32_t p = pid_c[i];
+                    const W4 w = draw4(a.seed, p, step, 0u, 0u);
+                    if ((uint64_t)w.y < a.mcc_thr) {
+                        if (!full) {
+                            x = vx_g[i];
+                            y = vy_g[i];
+                            z = vz_g[i];
+                        }
+                        if (MOM && !full) moment_terms(dm, x, y, z, -1.0);
+                        mcc_scatter<R>(x, y, z, p, a.seed, step, a.mass_ratio);
+                        if (MOM && !full) moment_terms(dm, x, y, z, 1.0);
+                        vx_g[i] = x;
+                        vy_g[i] = y;
+                        vz_g[i] = z;
+                    }
+                }
+                if (MOM && full) moment_terms(dm, x, y, z, 1.0);
             }
             if constexpr (MOM) {
                 block_sum<14>(dm, red);
                 if (threadIdx.x == 0) {
+                    if (full) {
 #pragma unroll
-                    for (int q = 1; q < 14; ++q) a.moments[(int64_t)cell * 14 + q] += dm[q];
+                        for (int q = 0; q < 14; ++q) a.moments[(int64_t)cell * 14 + q] = dm[q];
+                    } else {
+#pragma unroll
+                        for (int q = 1; q < 14; ++q) a.moments[(int64_t)cell * 14 + q] += dm[q];
+                    }
                 }
             }
         }
@@ -510,6 +530,7 @@ __global__ __launch_bounds__(T) void k_collide(CollideArgs a, const int32_t *__r
     __shared__ uint32_t wtot[T / PIC_WAVE];
     __shared__ int s_item;
     if (gated_off(a)) return;
+    if (a.run_if && *a.run_if != a.run_val) return;
     const uint32_t count = a.dflags->count[cls];
     if (blockIdx.x >= count) return;   // no work for this workgroup (nor a queue atomic)
     for (;;) {
@@ -533,6 +554,7 @@ __global__ __launch_bounds__(1024) void k_collide_huge(CollideArgs a, const int3
     __shared__ uint32_t wtot[16];
     __shared__ int s_item;
     if (gated_off(a)) return;
+    if (a.run_if && *a.run_if != a.run_val) return;
     const uint32_t count = a.dflags->count[cls];
     if (blockIdx.x >= count) return;   // no work for this workgroup (nor a queue atomic)
     const int T = blockDim.x;

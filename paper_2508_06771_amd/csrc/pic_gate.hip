@@ -630,7 +630,17 @@ __global__ void k_gate_score(DevGate *g, const int32_t *__restrict__ judge_list,
 
 __global__ void k_gate_end(DevGate *g)
 {
-    if (threadIdx.x == 0) g->have_moments = 1;
+    if (threadIdx.x == 0 && g->mom_now) g->have_moments = 1;
+}
+
+// The moment sums are refreshed on the first gated step and then every
+// mom_every steps; in between the network reads the last refresh.
+__global__ void k_mom_select(DevGate *g, const uint64_t *step_dev, uint64_t step, int every)
+{
+    if (threadIdx.x == 0) {
+        const uint64_t s = step_dev ? *step_dev : step;
+        g->mom_now = (!g->have_moments || every <= 1 || s % (uint64_t)every == 0) ? 1 : 0;
+    }
 }
 
 // ------------------------------------------------------------ training
@@ -856,6 +866,13 @@ int launch_gate_score(DevGate *g, const int32_t *judge_list, const uint8_t *want
 {
     hipLaunchKernelGGL(k_gate_score, dim3(1), dim3(256), 0, st, g, judge_list, want, r, tol, max_false,
                        min_judged);
+    HIP_OK(hipGetLastError());
+    return PIC_OK;
+}
+
+int launch_mom_select(DevGate *g, const uint64_t *step_dev, uint64_t step, int every, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_mom_select, dim3(1), dim3(64), 0, st, g, step_dev, step, every);
     HIP_OK(hipGetLastError());
     return PIC_OK;
 }

@@ -524,6 +524,11 @@ struct CollideArgs {
     DevFlags *dflags;
     // pairing export
     int32_t *sorted_out, *partner_out;
+    // nullable: the launch runs only if *run_if == run_val (variants chosen
+    // on the device, e.g. with or without the gate's moment refresh)
+    const int *run_if;
+    int run_val;
+    int mom_full;          // deferred cells recompute their moment sums (not differences)
 };
 
 int launch_collide(int dtype, const CollideArgs &a, const int32_t *lists, int32_t n_cells,
@@ -538,7 +543,8 @@ struct DevGate {
     unsigned long long steps, skipped, collided, judged, judged_want, false_skip;
     int disabled, have_moments;
     unsigned int judge_count;
-    unsigned int pad[7];
+    int mom_now;      // this step refreshes the moment sums
+    unsigned int pad[6];
 };
 
 struct GateArgs {
@@ -595,6 +601,9 @@ int launch_gate_score(DevGate *g, const int32_t *judge_list, const uint8_t *want
                       double tol, double max_false, uint32_t min_judged, hipStream_t st);
 int launch_relax(int dtype, const RelaxArgs &a, int num_cu, hipStream_t st);
 int launch_gate_end(DevGate *g, hipStream_t st);
+// Sets g->mom_now for this step (before the collide launches).
+int launch_mom_select(DevGate *g, const uint64_t *step_dev, uint64_t step, int every,
+                      hipStream_t st);
 
 int launch_mcc(int dtype, void *v, const uint32_t *pid, int64_t n, uint64_t thr, double mass_ratio,
                uint64_t seed, uint64_t step, uint8_t *cand_out, hipStream_t st);

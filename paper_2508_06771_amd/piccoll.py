@@ -69,6 +69,7 @@ def _load():
         "pic_gate_stats": ([vp, C.POINTER(C.c_int64)], C.c_int),
         "pic_gate_state": ([vp, vp, vp, vp, vp], C.c_int),
         "pic_conserve_reset": ([vp], C.c_int),
+        "pic_gate_refresh": ([vp, i32], C.c_int),
         "pic_autotune": ([vp, C.c_int, vp, vp, vp, i64, i32, f64, f64, u32, vp], C.c_int),
         "pic_time_kernels": ([vp, C.c_int], C.c_int),
         "pic_kernel_times": ([vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)], C.c_int),
@@ -87,7 +88,7 @@ EXPORTED = ["pic_create", "pic_destroy", "pic_strerror", "pic_sync", "pic_set_st
             "mcc_null_collide", "pic_philox", "coulomb_pairs", "pic_cell_moments", "pic_unsort",
             "pic_time_kernels", "pic_kernel_times", "pic_run_steps", "pic_features",
             "pic_relaxation", "pic_mlp_forward", "pic_mlp_grad", "pic_mlp_train_step",
-            "pic_gate_config", "pic_gate_reset", "pic_gate_stats", "pic_gate_state", "pic_autotune", "pic_conserve_reset"]
+            "pic_gate_config", "pic_gate_reset", "pic_gate_stats", "pic_gate_state", "pic_autotune", "pic_conserve_reset", "pic_gate_refresh"]
 
 MLP_PARAMS = 4801
 GATE_STATS = ["steps", "skipped", "collided", "judged", "judged_want", "false_skip", "disabled",
@@ -251,6 +252,9 @@ class Context:
         self._gate_params = params     # the library keeps the pointer
         _chk(lib.pic_gate_config(self._h, _p(params), threshold, k_max, judge_fraction, tolerance,
                                  replicas, int(bf16)), "pic_gate_config")
+
+    def gate_refresh(self, every: int):
+        _chk(lib.pic_gate_refresh(self._h, int(every)), "pic_gate_refresh")
 
     def gate_reset(self):
         _chk(lib.pic_gate_reset(self._h), "pic_gate_reset")

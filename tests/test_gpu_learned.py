@@ -202,6 +202,34 @@ def test_gated_graph_equals_eager(ctx):
     assert ctx.gate_stats() == sa
 
 
+def test_gate_moment_refresh_interval(ctx):
+    """With a refresh interval of 3 the gate's moment sums are those of the
+    post-step state on the first gated step and every third step, and are
+    left as they were in between."""
+    import torch
+    from paper_2508_06771_amd import piccoll
+    w, cs, params = gated_setup(ctx, threshold=0.3)
+    ctx.gate_refresh(3)
+    try:
+        fl = piccoll.GATE | piccoll.FUSE_MCC
+        tv, tc, tp = dev(w.v, torch.float32), dev(w.cell_of), dev(w.pid)
+        last = None
+        for step in range(7):
+            ctx.coulomb_collide(tv, tc, tp, w.n_cells, dt=w.dt, lnL=w.lnL, seed=1, step=step,
+                                flags=fl)
+            _, _, _, mom = ctx.gate_state(w.n_cells)
+            ctx.sync()
+            mom = host(mom)
+            if step == 0 or step % 3 == 0:
+                ref = oracle.cell_moments(host(tv).astype(np.float64), cs)
+                assert np.allclose(mom, ref, rtol=1e-9, atol=1e-6), step
+            else:
+                assert np.array_equal(mom, last), step
+            last = mom
+    finally:
+        ctx.gate_refresh(1)
+
+
 def test_gate_switches_off_on_false_skips(ctx):
     """A gate that skips everything (threshold 0) on anisotropic cells is
     judged wrong and switches itself off; then every cell collides."""
