@@ -203,19 +203,23 @@ int pic_mlp_train_step(pic_ctx *ctx, float *params, float *adam_m, float *adam_v
 
 /* Enables PIC_GATE steps: params (device, kept by pointer), skip when the
  * probability exceeds threshold and the cell has deferred fewer than k_max
- * steps; a judge_fraction of cells (domain-2 draw per cell and step) always
- * collides and is scored: a judged cell the network wanted to skip is a false
- * skip if its relaxation (replicas re-pairings) reaches tolerance.  When more
- * than 10% of at least 20 judged skips are false the gate switches itself off
- * (all cells collide).  The first gated step collides every cell and records
- * the moments the next step decides from. */
+ * steps; on the steps that refresh the moment sums (pic_gate_refresh) a
+ * judge_fraction of cells (domain-2 draw per cell and step) always collides
+ * and is scored: a judged cell the network wanted to skip is a false skip if
+ * its relaxation (replicas re-pairings) reaches tolerance.  When more than 10%
+ * of at least 20 judged skips are false the gate switches itself off (all
+ * cells collide).  The first gated step collides every cell and records the
+ * moments the next step decides from.  Deferred cells enter no collision
+ * queue; with PIC_FUSE_MCC their null collisions still run.  With
+ * PIC_MOMENTS the moment sums of every cell are written after the step. */
 int pic_gate_config(pic_ctx *ctx, const float *params, float threshold, int32_t k_max,
                     double judge_fraction, double tolerance, int32_t replicas, int bf16);
 /* Moment refresh interval of the gate: the 14 moment sums its features come
- * from are recomputed in the collide pass on the first gated step and then
- * every `every` steps (default 1: every step); in between the network reads
- * the last refresh and the pass runs without the sums.  The choice is made on
- * the device, so graph replays follow it.  PIC_ERR_ARG if every < 1. */
+ * from are recomputed (a streaming pass over the post-step velocities) on
+ * the first gated step and then on steps that are multiples of `every`
+ * (default 1: every step); in between the network reads the last refresh and
+ * no cell is judged.  The choice is made on the device, so graph replays
+ * follow it.  PIC_ERR_ARG if every < 1. */
 int pic_gate_refresh(pic_ctx *ctx, int32_t every);
 /* Forgets deferred counts, moments and statistics. */
 int pic_gate_reset(pic_ctx *ctx);
@@ -255,7 +259,8 @@ int pic_time_kernels(pic_ctx *ctx, int on);
  * 512 / 2048 / 4096 / 6144 in binary64), 4 cells beyond those, 5 order check
  * and cell starts, 6 work queue, 7 re-binning passes, 8 stand-alone
  * null-collision step, 9 learned-gate decision, 10 relaxation of the
- * judged cells (16 slots are reserved). */
+ * judged cells, 11 null collisions of deferred cells, 12 gate's moment
+ * pass (16 slots are reserved). */
 int pic_kernel_times(pic_ctx *ctx, double *ms, int64_t *count);
 
 /* ---------------------------------------------------------------- test exports */

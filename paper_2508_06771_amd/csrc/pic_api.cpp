@@ -517,6 +517,7 @@ int pic_relaxation(pic_ctx *c, int dtype, const void *v, int64_t n, const int32_
     r.step = step;
     r.replicas = replicas;
     r.count = n_cells;
+    r.cap = n_cells;
     r.r_out = r_out;
     return launch_relax(dtype, r, c->num_cu, c->stream);
 }
@@ -632,7 +633,7 @@ static size_t step_ws_bytes(const pic_ctx *c, const StepArgs &s)
 {
     const size_t es = s.dtype == PIC_F32 ? 4 : 8;
     const size_t part = (s.flags & PIC_GATE) ? relax_part_bytes(s.n_cells, c->gate_replicas) : 0;
-    return (size_t)(s.n_cells + 1) * 4 + (size_t)s.n_cells * 5 * 4 + (size_t)s.n * (8 + 3 * es) +
+    return (size_t)(s.n_cells + 1) * 4 + (size_t)s.n_cells * QUEUE_LISTS * 4 + (size_t)s.n * (8 + 3 * es) +
            radix_scratch_bytes(s.n) + huge_scratch_bytes(s.dtype, s.n) + part + 8192;
 }
 
@@ -659,7 +660,7 @@ static int step_enqueue(pic_ctx *c, const StepArgs &s, hipStream_t st, const uin
     const size_t es = dtype == PIC_F32 ? 4 : 8;
     Bump b(c->ws);
     int32_t *cs = (int32_t *)b.take((size_t)(n_cells + 1) * 4);
-    int32_t *lists = (int32_t *)b.take((size_t)n_cells * 5 * 4);
+    int32_t *lists = (int32_t *)b.take((size_t)n_cells * QUEUE_LISTS * 4);
     int32_t *tkey = (int32_t *)b.take((size_t)n * 4);
     uint32_t *tpid = (uint32_t *)b.take((size_t)n * 4);
     void *tv = b.take((size_t)n * 3 * es);
@@ -704,13 +705,13 @@ static int step_enqueue(pic_ctx *c, const StepArgs &s, hipStream_t st, const uin
         ktime_end(KT_SORT, st);
     }
     const ClassCaps caps = c->tuned_valid[dtype] ? c->tuned[dtype] : collide_caps(dtype, c->lds_max);
-    ktime_begin(KT_QUEUE, st);
-    RC(launch_build_queue(cs, n_cells, caps, lists, c->flags, st));
-    ktime_end(KT_QUEUE, st);
-
+    const uint64_t mcc_thr = (s.flags & PIC_FUSE_MCC) ? mcc_threshold(s.dt, c->mcc_sigma0, c->mcc_nn) : 0;
     const bool gate = (s.flags & PIC_GATE) != 0;
     if (gate) {
-        // decide deferred cells from last step's moments; judge a sample
+        // decide the deferred cells from the last refreshed moments and draw
+        // the judged sample; the queue then leaves deferred cells out of the
+        // classes
+        RC(launch_mom_select(c->gate_dev, step_dev, s.step, c->gate_mom_every, st));
         GateArgs g;
         memset(&g, 0, sizeof(g));
         g.moments = c->gate_mom;
@@ -733,6 +734,13 @@ static int step_enqueue(pic_ctx *c, const StepArgs &s, hipStream_t st, const uin
         ktime_begin(KT_GATE, st);
         RC(launch_gate(g, st));
         ktime_end(KT_GATE, st);
+    }
+    ktime_begin(KT_QUEUE, st);
+    RC(launch_build_queue(cs, n_cells, caps, lists, c->flags, gate ? c->gate_skip : nullptr,
+                          mcc_thr != 0, st));
+    ktime_end(KT_QUEUE, st);
+
+    if (gate) {
         RelaxArgs r;
         memset(&r, 0, sizeof(r));
         r.v = s.v;
@@ -752,6 +760,7 @@ static int step_enqueue(pic_ctx *c, const StepArgs &s, hipStream_t st, const uin
         r.dflags = c->flags;
         r.assume_sorted = assume ? 1 : 0;
         r.part = relax_part;
+        r.cap = n_cells;
         ktime_begin(KT_RELAX, st);
         RC(launch_relax(dtype, r, c->num_cu, st));
         ktime_end(KT_RELAX, st);
@@ -772,30 +781,33 @@ static int step_enqueue(pic_ctx *c, const StepArgs &s, hipStream_t st, const uin
     a.step = s.step;
     a.step_dev = step_dev;
     a.flags = s.flags;
-    a.mcc_thr = (s.flags & PIC_FUSE_MCC) ? mcc_threshold(s.dt, c->mcc_sigma0, c->mcc_nn) : 0;
+    a.mcc_thr = mcc_thr;
     a.mass_ratio = c->mcc_mr;
     a.moments = c->moments_out;
     a.debt = (s.flags & PIC_CONSERVE_FIX) ? c->debt : nullptr;
     a.dflags = c->flags;
     if (gate) {
-        a.skip = c->gate_skip;
+        // deferred cells are in no class queue: their null collisions run
+        // here, and moment sums come from the pass after the collisions
         a.dt_scale = c->gate_dts;
-        a.moments = c->gate_mom;
-        a.mom_full = c->gate_mom_every > 1;
-        RC(launch_mom_select(c->gate_dev, step_dev, s.step, c->gate_mom_every, st));
-        if (c->gate_mom_every > 1) {
-            // both variants are enqueued; the device flag selects one
-            CollideArgs plain = a;
-            plain.run_if = &c->gate_dev->mom_now;
-            plain.run_val = 0;
-            RC(launch_collide(dtype, plain, lists, n_cells, caps, 0, c->num_cu, st));
-            a.run_if = &c->gate_dev->mom_now;
-            a.run_val = 1;
+        a.flags &= ~(uint32_t)PIC_MOMENTS;
+        if (mcc_thr) {
+            ktime_begin(KT_DEFER, st);
+            RC(launch_deferred(dtype, a, lists, n_cells, c->num_cu, st));
+            ktime_end(KT_DEFER, st);
         }
-        a.flags |= PIC_MOMENTS;
     }
     RC(launch_collide(dtype, a, lists, n_cells, caps, 0, c->num_cu, st));
-    if (gate) RC(launch_gate_end(c->gate_dev, st));
+    if (gate) {
+        // the sums the next decision reads: post-step state, on refresh steps
+        ktime_begin(KT_MOMENTS, st);
+        RC(launch_moments(dtype, s.v, n, cs, n_cells, c->gate_mom, &c->gate_dev->mom_now, c->num_cu,
+                          st));
+        if ((s.flags & PIC_MOMENTS) && c->moments_out)
+            RC(launch_moments(dtype, s.v, n, cs, n_cells, c->moments_out, nullptr, c->num_cu, st));
+        ktime_end(KT_MOMENTS, st);
+        RC(launch_gate_end(c->gate_dev, st));
+    }
     return PIC_OK;
 }
 
@@ -920,14 +932,14 @@ int coulomb_pairs(pic_ctx *c, const int32_t *cell_start, const uint32_t *pid, in
     CK(hipMemcpyAsync(&nn, cell_start + n_cells, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
     CK(hipStreamSynchronize(c->stream));
     const int64_t n = nn;
-    const size_t need = (size_t)n_cells * 5 * 4 + huge_scratch_bytes(PIC_F32, n) + 4096;
+    const size_t need = (size_t)n_cells * QUEUE_LISTS * 4 + huge_scratch_bytes(PIC_F32, n) + 4096;
     RC(ensure_ws(c, need));
     Bump b(c->ws);
-    int32_t *lists = (int32_t *)b.take((size_t)n_cells * 5 * 4);
+    int32_t *lists = (int32_t *)b.take((size_t)n_cells * QUEUE_LISTS * 4);
     set_huge_scratch(PIC_F32, n, b.take(huge_scratch_bytes(PIC_F32, n)));
     RC(launch_reset_flags(c->flags, c->stream));
     const ClassCaps caps = collide_caps(PIC_F32, c->lds_max);
-    RC(launch_build_queue(cell_start, n_cells, caps, lists, c->flags, c->stream));
+    RC(launch_build_queue(cell_start, n_cells, caps, lists, c->flags, nullptr, 0, c->stream));
     CollideArgs a;
     memset(&a, 0, sizeof(a));
     a.n = n;
@@ -949,7 +961,7 @@ int pic_cell_moments(pic_ctx *c, int dtype, const void *v, int64_t n, const int3
     if (!c || n < 0 || n_cells < 1 || !cell_start || !out || (n > 0 && !v)) return PIC_ERR_ARG;
     RC(check_dtype(dtype));
     CK(hipSetDevice(c->device));
-    return launch_moments(dtype, v, n, cell_start, n_cells, out, c->stream);
+    return launch_moments(dtype, v, n, cell_start, n_cells, out, nullptr, c->num_cu, c->stream);
 }
 
 int pic_unsort(pic_ctx *c, int dtype, void *v, uint32_t *pid, int32_t *cell_of, int64_t n)

@@ -276,9 +276,11 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(RadixPass p,
 // class lengths go to flags->count[c]; flags->huge_total sums the members of
 // cells beyond the largest LDS class.  Within a class the order is
 // arbitrary: cells are independent and their random numbers depend only on
-// (seed, step, pid), so processing order never changes results.
+// (seed, step, pid), so processing order never changes results.  Cells the
+// gate defers go to the deferred list when they still need a visit.
 __global__ void k_build_queue(const int32_t *__restrict__ cell_start, int32_t n_cells, ClassCaps caps,
-                              int32_t *__restrict__ lists, DevFlags *f)
+                              int32_t *__restrict__ lists, DevFlags *f,
+                              const uint8_t *__restrict__ skip, int visit)
 {
     const int lane = threadIdx.x & (PIC_WAVE - 1);
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (PIC_WAVE - lane));
@@ -295,8 +297,9 @@ __global__ void k_build_queue(const int32_t *__restrict__ cell_start, int32_t n_
             cls = caps.ncls;
             for (int c = caps.ncls - 1; c >= 0; --c)
                 if (cnt <= caps.cap[c]) cls = c;
+            if (skip && skip[j]) cls = visit ? LIST_DEFERRED : -1;
         }
-        for (int c = 0; c <= caps.ncls; ++c) {
+        for (int c = 0; c < QUEUE_LISTS; ++c) {
             const uint64_t m = __ballot(cls == c);
             if (!m) continue;
             const int leader = __ffsll((unsigned long long)m) - 1;
@@ -384,10 +387,11 @@ int radix_pass(const RadixPass &p, const BinScratch &s, hipStream_t st)
 }
 
 int launch_build_queue(const int32_t *cell_start, int32_t n_cells, const ClassCaps &caps,
-                       int32_t *lists, DevFlags *flags, hipStream_t st)
+                       int32_t *lists, DevFlags *flags, const uint8_t *skip, int visit,
+                       hipStream_t st)
 {
     hipLaunchKernelGGL(k_build_queue, dim3(grid_for(n_cells, 256, 1024)), dim3(256), 0, st,
-                       cell_start, n_cells, caps, lists, flags);
+                       cell_start, n_cells, caps, lists, flags, skip, visit);
     HIP_OK(hipGetLastError());
     return PIC_OK;
 }

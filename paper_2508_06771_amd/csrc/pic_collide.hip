@@ -182,66 +182,61 @@ __host__ __device__ constexpr size_t lds_bytes(int cap)
 }
 
 // ------------------------------------------------------------ LDS-class pass
-// Adds sign * (the 14 moment terms of v) to m.
-__device__ __forceinline__ void moment_terms(double *m, double x, double y, double z, double sign)
+// Adds the 14 moment terms of v to m[0..13] (layout of pic_cell_moments:
+// count, sum v, the second-order products, sum |v|^2 v, sum |v|^4).
+__device__ __forceinline__ void moment_terms(double (&m)[16], double x, double y, double z)
 {
     const double q2 = x * x + y * y + z * z;
-    m[0] += sign;
-    m[1] += sign * x; m[2] += sign * y; m[3] += sign * z;
-    m[4] += sign * (x * x); m[5] += sign * (y * y); m[6] += sign * (z * z);
-    m[7] += sign * (x * y); m[8] += sign * (x * z); m[9] += sign * (y * z);
-    m[10] += sign * (q2 * x); m[11] += sign * (q2 * y); m[12] += sign * (q2 * z);
-    m[13] += sign * (q2 * q2);
+    m[0] += 1.0;
+    m[1] += x; m[2] += y; m[3] += z;
+    m[4] += x * x; m[5] += y * y; m[6] += z * z;
+    m[7] += x * y; m[8] += x * z; m[9] += y * z;
+    m[10] += q2 * x; m[11] += q2 * y; m[12] += q2 * z;
+    m[13] += q2 * q2;
 }
 
-// The 14 moment sums of the pass's members (layout of pic_cell_moments),
-// one sum at a time: each is summed over the thread's members, then the wave,
-// then the waves in order, so only one accumulator is live at once.  The
-// count is n.  Contains a barrier; threads 1..13 write the sums.
+// The 14 moment sums of the pass's members (layout of pic_cell_moments): four
+// wave reduce-scatters of 4 values (so at most 4 accumulators are live), each
+// into its own quarter of red, then one cross-wave pass.  The count is n.
+// red: 16 doubles per wave.  Contains the barriers; threads 0..13 write.
 template <typename R, int T, int K>
 __device__ __forceinline__ void cell_moments_out(double *out, const R (&vx)[K], const R (&vy)[K],
                                                  const R (&vz)[K], int n, double *red)
 {
     constexpr int NW = T / PIC_WAVE;
-    const int lane = threadIdx.x & (PIC_WAVE - 1), wid = threadIdx.x / PIC_WAVE;
 #pragma unroll
-    for (int q = 1; q < 14; ++q) {
-        double s = 0.0;
+    for (int part = 0; part < 4; ++part) {
+        double h[4] = {0, 0, 0, 0};
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const int i = threadIdx.x + k * T;
-            if (i < n) {
+            if (threadIdx.x + k * T < n) {
                 const double x = vx[k], y = vy[k], z = vz[k];
-                double t;
-                if (q == 1) t = x;
-                else if (q == 2) t = y;
-                else if (q == 3) t = z;
-                else if (q == 4) t = x * x;
-                else if (q == 5) t = y * y;
-                else if (q == 6) t = z * z;
-                else if (q == 7) t = x * y;
-                else if (q == 8) t = x * z;
-                else if (q == 9) t = y * z;
-                else {
+                if (part == 0) {
+                    h[0] += x; h[1] += y; h[2] += z; h[3] += x * x;
+                } else if (part == 1) {
+                    h[0] += y * y; h[1] += z * z; h[2] += x * y; h[3] += x * z;
+                } else {
                     const double q2 = x * x + y * y + z * z;
-                    t = q == 10 ? q2 * x : q == 11 ? q2 * y : q == 12 ? q2 * z : q2 * q2;
+                    if (part == 2) {
+                        h[0] += y * z; h[1] += q2 * x; h[2] += q2 * y; h[3] += q2 * z;
+                    } else {
+                        h[0] += q2 * q2;
+                    }
                 }
-                s += t;
             }
         }
-        s = wave_sum(s);
-        if (lane == 0) red[wid * 14 + q] = s;
+        wave_scatter_to<4>(h, red + part * 4 * NW);
     }
     __syncthreads();
-    if (threadIdx.x < 14) {
-        double tot = 0.0;
-        if (threadIdx.x == 0) {
-            tot = (double)n;
-        } else {
-            for (int w = 0; w < NW; ++w) tot += red[w * 14 + threadIdx.x];
-        }
-        out[threadIdx.x] = tot;
+    if (threadIdx.x < 13) {
+        const double *r = red + (threadIdx.x >> 2) * 4 * NW + (threadIdx.x & 3);
+        double t = 0.0;
+        for (int w = 0; w < NW; ++w) t += r[w * 4];
+        out[1 + threadIdx.x] = t;
+    } else if (threadIdx.x == 13) {
+        out[0] = (double)n;
     }
+    __syncthreads();
 }
 
 template <typename R, int T, int K, int F>
@@ -256,63 +251,11 @@ __device__ void cell_pass(const CollideArgs &a, int cell, unsigned char *smem, d
     const int lo = a.cell_start[cell];
     const int n = a.cell_start[cell + 1] - lo;
     const uint32_t step = (uint32_t)read_step(a);
-    const bool coul = !(a.skip && a.skip[cell]) && n >= 2;
+    const bool coul = n >= 2;
     R *vx_g = (R *)a.v + lo;
     R *vy_g = (R *)a.v + a.n + lo;
     R *vz_g = (R *)a.v + 2 * a.n + lo;
     const uint32_t *pid_c = a.pid + lo;
-
-    if (!PAIRS && a.skip && a.skip[cell]) {
-        // deferred cell: only its null-collision candidates change.  Its
-        // moment sums are updated by the candidates' differences when they
-        // are current (refresh every step), else recomputed over all members
-        if constexpr (MCC || MOM) {
-            const bool full = MOM && a.mom_full;
-            double dm[14];
-#pragma unroll
-            for (int q = 0; q < 14; ++q) dm[q] = 0.0;
-            for (int i = threadIdx.x; i < n; i += T) {
-                R x = 0, y = 0, z = 0;
-                if (full) {
-                    x = vx_g[i];
-                    y = vy_g[i];
-                    z = vz_g[i];
-                }
-                if constexpr (MCC) {
-                    const uint32_t p = pid_c[i];
-                    const W4 w = draw4(a.seed, p, step, 0u, 0u);
-                    if ((uint64_t)w.y < a.mcc_thr) {
-                        if (!full) {
-                            x = vx_g[i];
-                            y = vy_g[i];
-                            z = vz_g[i];
-                        }
-                        if (MOM && !full) moment_terms(dm, x, y, z, -1.0);
-                        mcc_scatter<R>(x, y, z, p, a.seed, step, a.mass_ratio);
-                        if (MOM && !full) moment_terms(dm, x, y, z, 1.0);
-                        vx_g[i] = x;
-                        vy_g[i] = y;
-                        vz_g[i] = z;
-                    }
-                }
-                if (MOM && full) moment_terms(dm, x, y, z, 1.0);
-            }
-            if constexpr (MOM) {
-                block_sum<14>(dm, red);
-                if (threadIdx.x == 0) {
-                    if (full) {
-#pragma unroll
-                        for (int q = 0; q < 14; ++q) a.moments[(int64_t)cell * 14 + q] = dm[q];
-                    } else {
-#pragma unroll
-                        for (int q = 1; q < 14; ++q) a.moments[(int64_t)cell * 14 + q] += dm[q];
-                    }
-                }
-            }
-        }
-        __syncthreads();
-        return;
-    }
 
     const SortLDS<T, CAP> L(smem);
 
@@ -326,7 +269,7 @@ __device__ void cell_pass(const CollideArgs &a, int cell, unsigned char *smem, d
     {
         // load, one Philox call per particle, and the bucket count of its key
         // with its arrival rank
-        double before[5] = {0, 0, 0, 0, 0};
+        double before[4] = {0, 0, 0, 0};   // sum v, sum |v|^2
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const int i = threadIdx.x + k * T;
@@ -344,20 +287,16 @@ __device__ void cell_pass(const CollideArgs &a, int cell, unsigned char *smem, d
                 pos[k] = L.count(i, w.x, bits);
                 if (CONS) {
                     const double x = vx[k], y = vy[k], z = vz[k];
-                    before[0] += 1.0;
-                    before[1] += x;
-                    before[2] += y;
-                    before[3] += z;
-                    before[4] += x * x + y * y + z * z;
+                    before[0] += x;
+                    before[1] += y;
+                    before[2] += z;
+                    before[3] += x * x + y * y + z * z;
                 }
             }
         }
         if constexpr (CONS) {
-            block_sum<5>(before, red);     // contains the barriers
-            if (threadIdx.x == 0) {
-#pragma unroll
-                for (int q = 0; q < 5; ++q) s_before[q] = before[q];
-            }
+            const double t = block_sum_scatter<4>(before, red);   // contains the barriers
+            if (threadIdx.x < 4) s_before[threadIdx.x] = t;
         }
     }
     __syncthreads();
@@ -439,22 +378,23 @@ __device__ void cell_pass(const CollideArgs &a, int cell, unsigned char *smem, d
         }
 
         if constexpr (CONS) {
-            double after[5] = {0, 0, 0, 0, 0};
+            double after[4] = {0, 0, 0, 0};
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 const int i = threadIdx.x + k * T;
                 if (i < n) {
                     const double x = vx[k], y = vy[k], z = vz[k];
-                    after[1] += x;
-                    after[2] += y;
-                    after[3] += z;
-                    after[4] += x * x + y * y + z * z;
+                    after[0] += x;
+                    after[1] += y;
+                    after[2] += z;
+                    after[3] += x * x + y * y + z * z;
                 }
             }
-            block_sum<5>(after, red);
-            const Correction cr = make_correction(s_before, after, a.debt ? a.debt + (int64_t)cell * 4 : nullptr);
+            block_sum_bcast<4>(after, red);
+            const Correction cr = make_correction((double)n, s_before, after,
+                                                  a.debt ? a.debt + (int64_t)cell * 4 : nullptr);
             if (cr.ok) {
-                double real[5] = {0, 0, 0, 0, 0};
+                double real[4] = {0, 0, 0, 0};
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
                     const int i = threadIdx.x + k * T;
@@ -463,14 +403,14 @@ __device__ void cell_pass(const CollideArgs &a, int cell, unsigned char *smem, d
                         vy[k] = (R)(cr.Vt[1] + cr.al * ((double)vy[k] - cr.Vn[1]));
                         vz[k] = (R)(cr.Vt[2] + cr.al * ((double)vz[k] - cr.Vn[2]));
                         const double x = vx[k], y = vy[k], z = vz[k];
-                        real[1] += x;
-                        real[2] += y;
-                        real[3] += z;
-                        real[4] += x * x + y * y + z * z;
+                        real[0] += x;
+                        real[1] += y;
+                        real[2] += z;
+                        real[3] += x * x + y * y + z * z;
                     }
                 }
-                block_sum<5>(real, red);
-                if (a.debt && threadIdx.x == 0) store_debt(a.debt + (int64_t)cell * 4, cr, real);
+                const double t = block_sum_scatter<4>(real, red);
+                if (a.debt) store_debt_lane(a.debt + (int64_t)cell * 4, cr, t);
             }
         }
     }
@@ -525,12 +465,11 @@ __global__ __launch_bounds__(T) void k_collide(CollideArgs a, const int32_t *__r
                                                int cls)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double red[14 * (T / PIC_WAVE)];
-    __shared__ double s_before[8];
+    __shared__ double red[16 * (T / PIC_WAVE)];
+    __shared__ double s_before[4];
     __shared__ uint32_t wtot[T / PIC_WAVE];
     __shared__ int s_item;
     if (gated_off(a)) return;
-    if (a.run_if && *a.run_if != a.run_val) return;
     const uint32_t count = a.dflags->count[cls];
     if (blockIdx.x >= count) return;   // no work for this workgroup (nor a queue atomic)
     for (;;) {
@@ -550,11 +489,10 @@ template <typename R, bool PAIRS>
 __global__ __launch_bounds__(1024) void k_collide_huge(CollideArgs a, const int32_t *__restrict__ list,
                                                        int cls, HugeScratch hs)
 {
-    __shared__ double red[14 * 16];
+    __shared__ double red[16 * 16];
     __shared__ uint32_t wtot[16];
     __shared__ int s_item;
     if (gated_off(a)) return;
-    if (a.run_if && *a.run_if != a.run_val) return;
     const uint32_t count = a.dflags->count[cls];
     if (blockIdx.x >= count) return;   // no work for this workgroup (nor a queue atomic)
     const int T = blockDim.x;
@@ -572,8 +510,8 @@ __global__ __launch_bounds__(1024) void k_collide_huge(CollideArgs a, const int3
         const int lo = a.cell_start[cell];
         const int n = a.cell_start[cell + 1] - lo;
         const uint32_t step = (uint32_t)read_step(a);
-        const bool coul = !(a.skip && a.skip[cell]) && n >= 2;
-        double before[5] = {0, 0, 0, 0, 0};
+        const bool coul = n >= 2;
+        double before[4] = {0, 0, 0, 0};   // sum v, sum |v|^2
         for (int i = threadIdx.x; i < n; i += T) {
             const W4 w = draw4(a.seed, a.pid[lo + i], step, 0u, 0u);
             hs.keys[lo + i] = w.x;
@@ -582,11 +520,10 @@ __global__ __launch_bounds__(1024) void k_collide_huge(CollideArgs a, const int3
             hs.cand[lo + i] = (uint64_t)w.y < a.mcc_thr;
             if (!PAIRS && (a.flags & PIC_CONSERVE_FIX)) {
                 const double x = vx_g[lo + i], y = vy_g[lo + i], z = vz_g[lo + i];
-                before[0] += 1.0;
-                before[1] += x;
-                before[2] += y;
-                before[3] += z;
-                before[4] += x * x + y * y + z * z;
+                before[0] += x;
+                before[1] += y;
+                before[2] += z;
+                before[3] += x * x + y * y + z * z;
             }
         }
         __syncthreads();
@@ -642,19 +579,20 @@ __global__ __launch_bounds__(1024) void k_collide_huge(CollideArgs a, const int3
             }
             __syncthreads();
             if (a.flags & PIC_CONSERVE_FIX) {
-                double after[5] = {0, 0, 0, 0, 0};
+                double after[4] = {0, 0, 0, 0};
                 for (int i = threadIdx.x; i < n; i += T) {
                     const double x = vx_g[lo + i], y = vy_g[lo + i], z = vz_g[lo + i];
-                    after[1] += x;
-                    after[2] += y;
-                    after[3] += z;
-                    after[4] += x * x + y * y + z * z;
+                    after[0] += x;
+                    after[1] += y;
+                    after[2] += z;
+                    after[3] += x * x + y * y + z * z;
                 }
-                block_sum<5>(before, red);
-                block_sum<5>(after, red);
-                const Correction cr = make_correction(before, after, a.debt ? a.debt + (int64_t)cell * 4 : nullptr);
+                block_sum<4>(before, red);
+                block_sum<4>(after, red);
+                const Correction cr = make_correction((double)n, before, after,
+                                                      a.debt ? a.debt + (int64_t)cell * 4 : nullptr);
                 if (cr.ok) {
-                    double real[5] = {0, 0, 0, 0, 0};
+                    double real[4] = {0, 0, 0, 0};
                     for (int i = threadIdx.x; i < n; i += T) {
                         const R x = (R)(cr.Vt[0] + cr.al * ((double)vx_g[lo + i] - cr.Vn[0]));
                         const R y = (R)(cr.Vt[1] + cr.al * ((double)vy_g[lo + i] - cr.Vn[1]));
@@ -662,19 +600,20 @@ __global__ __launch_bounds__(1024) void k_collide_huge(CollideArgs a, const int3
                         vx_g[lo + i] = x;
                         vy_g[lo + i] = y;
                         vz_g[lo + i] = z;
-                        real[1] += (double)x;
-                        real[2] += (double)y;
-                        real[3] += (double)z;
-                        real[4] += (double)x * x + (double)y * y + (double)z * z;
+                        real[0] += (double)x;
+                        real[1] += (double)y;
+                        real[2] += (double)z;
+                        real[3] += (double)x * x + (double)y * y + (double)z * z;
                     }
-                    block_sum<5>(real, red);
+                    block_sum<4>(real, red);
                     if (a.debt && threadIdx.x == 0) store_debt(a.debt + (int64_t)cell * 4, cr, real);
                 }
                 __syncthreads();
             }
         }
-        double m[14];
-        for (int q = 0; q < 14; ++q) m[q] = 0.0;
+        double m[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) m[q] = 0.0;
         for (int i = threadIdx.x; i < n; i += T) {
             R x = vx_g[lo + i], y = vy_g[lo + i], z = vz_g[lo + i];
             if (a.mcc_thr && hs.cand[lo + i]) {
@@ -683,25 +622,46 @@ __global__ __launch_bounds__(1024) void k_collide_huge(CollideArgs a, const int3
                 vy_g[lo + i] = y;
                 vz_g[lo + i] = z;
             }
-            if (a.flags & PIC_MOMENTS) {
-                const double dx = x, dy = y, dz = z;
-                const double q2 = dx * dx + dy * dy + dz * dz;
-                m[0] += 1.0;
-                m[1] += dx; m[2] += dy; m[3] += dz;
-                m[4] += dx * dx; m[5] += dy * dy; m[6] += dz * dz;
-                m[7] += dx * dy; m[8] += dx * dz; m[9] += dy * dz;
-                m[10] += q2 * dx; m[11] += q2 * dy; m[12] += q2 * dz;
-                m[13] += q2 * q2;
-            }
+            if (a.flags & PIC_MOMENTS) moment_terms(m, x, y, z);
         }
         if (a.flags & PIC_MOMENTS) {
-            block_sum<14>(m, red);
-            if (threadIdx.x == 0) {
-#pragma unroll
-                for (int q = 0; q < 14; ++q) a.moments[(int64_t)cell * 14 + q] = m[q];
-            }
+            const double t = block_sum_scatter<16>(m, red);
+            if (threadIdx.x < 14) a.moments[(int64_t)cell * 14 + threadIdx.x] = t;
         }
         __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------ deferred cells
+// A cell the gate defers skips the Coulomb step and enters no class queue.
+// When null collisions are on it is listed here for its candidates (about 1%
+// of the members: one Philox word per member decides).  One workgroup per
+// cell, cells dealt round-robin (no queue atomics).
+constexpr int DEFER_T = 256;
+
+template <typename R>
+__global__ __launch_bounds__(DEFER_T) void k_deferred(CollideArgs a, const int32_t *__restrict__ list)
+{
+    if (gated_off(a)) return;
+    const uint32_t count = a.dflags->count[LIST_DEFERRED];
+    const uint32_t step = (uint32_t)read_step(a);
+    for (uint32_t item = blockIdx.x; item < count; item += gridDim.x) {
+        const int cell = list[item];
+        const int lo = a.cell_start[cell];
+        const int n = a.cell_start[cell + 1] - lo;
+        R *vx_g = (R *)a.v + lo;
+        R *vy_g = (R *)a.v + a.n + lo;
+        R *vz_g = (R *)a.v + 2 * a.n + lo;
+        const uint32_t *pid_c = a.pid + lo;
+        for (int i = threadIdx.x; i < n; i += DEFER_T) {
+            if ((uint64_t)draw4(a.seed, pid_c[i], step, 0u, 0u).y < a.mcc_thr) {
+                R x = vx_g[i], y = vy_g[i], z = vz_g[i];
+                mcc_scatter<R>(x, y, z, pid_c[i], a.seed, step, a.mass_ratio);
+                vx_g[i] = x;
+                vy_g[i] = y;
+                vz_g[i] = z;
+            }
+        }
     }
 }
 
@@ -758,6 +718,17 @@ int launch_all(const CollideArgs &a, const int32_t *lists, int32_t n_cells, int 
     if ((rc = launch_class<R, C::T2, C::K2, F>(a, lists + 2 * M, 2, bp[2] * num_cu, st))) return rc;
     if ((rc = launch_class<R, C::T1, C::K1, F>(a, lists + 1 * M, 1, bp[1] * num_cu, st))) return rc;
     if ((rc = launch_class<R, C::T0, C::K0, F>(a, lists + 0 * M, 0, bp[0] * num_cu, st))) return rc;
+    return PIC_OK;
+}
+
+template <typename R>
+int launch_deferred_t(const CollideArgs &a, const int32_t *lists, int32_t n_cells, int num_cu,
+                      hipStream_t st)
+{
+    const int g = n_cells < num_cu * 8 ? n_cells : num_cu * 8;
+    hipLaunchKernelGGL(k_deferred<R>, dim3(g), dim3(DEFER_T), 0, st, a,
+                       lists + (int64_t)LIST_DEFERRED * n_cells);
+    HIP_OK(hipGetLastError());
     return PIC_OK;
 }
 
@@ -844,4 +815,11 @@ int launch_collide(int dtype, const CollideArgs &a, const int32_t *lists, int32_
 {
     if (dtype == PIC_F32) return launch_flags<float>(a, lists, n_cells, num_cu, g_huge, cc, pairs_only, st);
     return launch_flags<double>(a, lists, n_cells, num_cu, g_huge, cc, pairs_only, st);
+}
+
+int launch_deferred(int dtype, const CollideArgs &a, const int32_t *lists, int32_t n_cells,
+                    int num_cu, hipStream_t st)
+{
+    if (dtype == PIC_F32) return launch_deferred_t<float>(a, lists, n_cells, num_cu, st);
+    return launch_deferred_t<double>(a, lists, n_cells, num_cu, st);
 }

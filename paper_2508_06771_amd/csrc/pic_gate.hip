@@ -39,7 +39,7 @@ __device__ __forceinline__ float bf16r(float x)
 // t = 1e-3 the closed form cancels (relative error ~1e-16 / t), so the
 // asymptotic Gaussian-moment series is used there (next term ~ 2.5e5 t^6,
 // below 1e-10 relative).
-__device__ double h_angle(double t)
+__device__ __noinline__ double h_angle(double t)
 {
     if (t < 1e-3) {
         return t * (4.0 + t * (-24.0 + t * (180.0 + t * (-1680.0 + t * 18900.0))));
@@ -283,11 +283,11 @@ __global__ __launch_bounds__(256) void k_mlp_forward_mfma(const float *__restric
 // Decision for cell j from the network's probability p (valid: the cell
 // has features and the gate is on).
 __device__ __forceinline__ void gate_decide(const GateArgs &a, int j, bool valid, float p, uint64_t step,
-                                            bool on)
+                                            bool on, bool judge_now)
 {
     const bool want = valid && p > a.thr && a.k_acc[j] < a.kmax;
     const W4 w = draw4(a.seed, (uint32_t)j, (uint32_t)step, 2u, 0u);
-    const bool judge = on && (uint64_t)w.x < a.judge_thr;
+    const bool judge = on && judge_now && (uint64_t)w.x < a.judge_thr;
     const bool skip = want && !judge;
     a.prob[j] = valid ? p : 0.0f;
     a.want[j] = (uint8_t)((want ? 1u : 0u) | (judge ? 2u : 0u));   // bit 1: judged
@@ -361,6 +361,7 @@ __global__ __launch_bounds__(256) void k_gate(GateArgs a)
     load_params(P, a.params, false);
     const uint64_t step = a.step_dev ? *a.step_dev : a.step;
     const bool on = a.g->have_moments && !a.g->disabled;
+    const bool judge_now = a.g->mom_now != 0;
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < a.M; j += gridDim.x * blockDim.x) {
         float p = 0.0f;
         bool valid = false;
@@ -369,7 +370,7 @@ __global__ __launch_bounds__(256) void k_gate(GateArgs a)
             valid = features_from_sums(a.moments + (int64_t)j * 14, f);
             if (valid) p = 1.0f / (1.0f + __expf(-mlp_logit(P, f, false)));
         }
-        gate_decide(a, j, valid, p, step, on);
+        gate_decide(a, j, valid, p, step, on, judge_now);
     }
 }
 
@@ -383,6 +384,7 @@ __global__ __launch_bounds__(256) void k_gate_mfma(GateArgs a)
     __syncthreads();
     const uint64_t step = a.step_dev ? *a.step_dev : a.step;
     const bool on = a.g->have_moments && !a.g->disabled;
+    const bool judge_now = a.g->mom_now != 0;
     const int wid = threadIdx.x / PIC_WAVE, c = threadIdx.x & 31;
     const int ntiles = (a.M + 31) / 32;
     for (int tile = blockIdx.x * 4 + wid; tile < ntiles; tile += gridDim.x * 4) {
@@ -396,41 +398,88 @@ __global__ __launch_bounds__(256) void k_gate_mfma(GateArgs a)
         }
         float p = 0.0f;
         if (on) p = 1.0f / (1.0f + __expf(-mlp_logit_mfma(P, f, Wv[wid])));
-        if ((threadIdx.x & 32) == 0 && j < a.M) gate_decide(a, j, valid, p, step, on);
+        if ((threadIdx.x & 32) == 0 && j < a.M) gate_decide(a, j, valid, p, step, on, judge_now);
         __builtin_amdgcn_wave_barrier();   // the next tile needs the whole wave
     }
 }
 
 // ------------------------------------------------------------ relaxation label
-// Cells of at most RELAX_LDS_CAP members: one workgroup per (cell, replica)
-// sorts the replica's keys in LDS and sums the pair terms
-// 1/4 h(s^2) (|u|^2 I - 3 u u^T) into part[]; k_relax_finish adds the
-// replicas in order and normalises.  Larger cells take k_relax below.
+// The evaluated cells are first split by size (k_relax_classify).  Cells of
+// at most RELAX_LDS_CAP members: one workgroup per (cell, replica) sorts the
+// replica's keys in LDS and sums the pair terms 1/4 h(s^2) (|u|^2 I - 3 u u^T)
+// into part[]; k_relax_finish adds the replicas in order and normalises.
+// Larger cells take k_relax below.
 constexpr int RELAX_T0 = 256, RELAX_K0 = 8;      // <= 2048 members
 constexpr int RELAX_T1 = 1024, RELAX_K1 = 10;    // <= 10240 members
 constexpr int RELAX_LDS_CAP = RELAX_T1 * RELAX_K1;
+constexpr int RELAX_CLASSIFY_T = 512;            // class counts per pass fit 10 bits
+
+__device__ __forceinline__ bool relax_off(const RelaxArgs &a)
+{
+    return a.dflags && (a.dflags->range_err || (a.assume_sorted && a.dflags->unsorted));
+}
+
+__device__ __forceinline__ int relax_cell(const RelaxArgs &a, uint32_t which)
+{
+    return a.list ? a.list[which] : (int)which;
+}
+
+// One workgroup: positions in the evaluated list by size class (0: LDS sort
+// by RELAX_T0 threads, 1: by RELAX_T1 threads, 2: sort in global scratch), in
+// ascending order, and the class counts.  The three per-class flags are
+// packed into one scan (10 bits each).
+__global__ __launch_bounds__(RELAX_CLASSIFY_T) void k_relax_classify(RelaxArgs a)
+{
+    __shared__ uint32_t wtot[RELAX_CLASSIFY_T / PIC_WAVE];
+    __shared__ uint32_t s_tot;
+    if (relax_off(a)) return;
+    const uint32_t count = a.count_dev ? *a.count_dev : (uint32_t)a.count;
+    uint32_t base[3] = {0, 0, 0};
+    for (uint32_t c0 = 0; c0 < count; c0 += RELAX_CLASSIFY_T) {
+        const uint32_t which = c0 + threadIdx.x;
+        int cls = -1;
+        if (which < count) {
+            const int cell = relax_cell(a, which);
+            const int n = a.cell_start[cell + 1] - a.cell_start[cell];
+            cls = n <= RELAX_T0 * RELAX_K0 ? 0 : n <= RELAX_LDS_CAP ? 1 : 2;
+        }
+        const uint32_t flag = cls < 0 ? 0u : 1u << (10 * cls);
+        const uint32_t off = block_excl(flag, wtot);
+        if (threadIdx.x == RELAX_CLASSIFY_T - 1) s_tot = off + flag;
+        __syncthreads();
+        const uint32_t tot = s_tot;
+        if (cls >= 0) {
+            const uint32_t o = (off >> (10 * cls)) & 1023u;
+            a.cls_list[(int64_t)cls * a.cap + base[cls] + o] = (int32_t)which;
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) base[c] += (tot >> (10 * c)) & 1023u;
+        __syncthreads();   // s_tot is rewritten by the next pass
+    }
+    if (threadIdx.x < 3) a.cls_count[threadIdx.x] = base[threadIdx.x];
+}
 
 template <typename R, int T, int K>
-__global__ __launch_bounds__(T) void k_relax_lds(RelaxArgs a, int nmin)
+__global__ __launch_bounds__(T) void k_relax_lds(RelaxArgs a, int cls)
 {
     constexpr int CAP = T * K;
+    constexpr int PK = (CAP / 2 + T - 1) / T;    // pairs per thread
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double red[6 * (T / PIC_WAVE)];
+    __shared__ double red[8 * (T / PIC_WAVE)];
     __shared__ uint32_t wtot[T / PIC_WAVE];
-    if (a.dflags && (a.dflags->range_err || (a.assume_sorted && a.dflags->unsorted))) return;
-    const uint32_t count = a.count_dev ? *a.count_dev : (uint32_t)a.count;
+    if (relax_off(a)) return;
     const uint32_t reps = (uint32_t)a.replicas;
-    const uint32_t items = count * reps;
+    const uint32_t items = a.cls_count[cls] * reps;
+    const int32_t *mine = a.cls_list + (int64_t)cls * a.cap;
     const uint32_t step = (uint32_t)(a.step_dev ? *a.step_dev : a.step);
     const SortLDS<T, CAP> L(smem);
     for (uint32_t item = blockIdx.x; item < items; item += gridDim.x) {
-        const uint32_t which = item / reps, rep = item - which * reps;
-        const int cell = a.list ? a.list[which] : (int)which;
+        const uint32_t which = (uint32_t)mine[item / reps], rep = item % reps;
+        const int cell = relax_cell(a, which);
         const int lo = a.cell_start[cell];
         const int n = a.cell_start[cell + 1] - lo;
-        if (n < nmin || n > CAP) continue;
-        double acc[6] = {0, 0, 0, 0, 0, 0};   // xx yy zz xy xz yz
-        if (n >= 2) {
+        double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // xx yy zz xy xz yz
+        if (n >= 2 && n <= CAP) {
             const uint32_t *pid_c = a.pid + lo;
             const uint32_t bits = sort_bits(n);
             uint32_t pos[K];
@@ -455,28 +504,36 @@ __global__ __launch_bounds__(T) void k_relax_lds(RelaxArgs a, int nmin)
             const double dens = a.density ? a.density[cell] : 1.0;
             const double dts = a.dt_scale ? a.dt_scale[cell] : 1.0;
             const double C = 8.0 * PI_D * dens * a.lnL * a.dt * dts;
-            for (int q = threadIdx.x; q < n / 2; q += T) {
-                const int ia = L.lst[2 * q], ib = L.lst[2 * q + 1];
-                const double ux = (double)vx[ia] - (double)vx[ib];
-                const double uy = (double)vy[ia] - (double)vy[ib];
-                const double uz = (double)vz[ia] - (double)vz[ib];
-                const double uu = ux * ux + uy * uy + uz * uz;
-                if (uu == 0.0) continue;
+            // all of the thread's pairs are gathered before any is evaluated,
+            // so their loads are in flight together
+            double ux[PK], uy[PK], uz[PK];
+#pragma unroll
+            for (int k = 0; k < PK; ++k) {
+                const int q = threadIdx.x + k * T;
+                ux[k] = uy[k] = uz[k] = 0.0;
+                if (q < n / 2) {
+                    const int ia = L.lst[2 * q], ib = L.lst[2 * q + 1];
+                    ux[k] = (double)vx[ia] - (double)vx[ib];
+                    uy[k] = (double)vy[ia] - (double)vy[ib];
+                    uz[k] = (double)vz[ia] - (double)vz[ib];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < PK; ++k) {
+                const double uu = ux[k] * ux[k] + uy[k] * uy[k] + uz[k] * uz[k];
+                if (uu == 0.0) continue;   // also the slots past the last pair
                 const double hq = 0.25 * h_angle(C / (uu * sqrt(uu)));
-                acc[0] += hq * (uu - 3.0 * ux * ux);
-                acc[1] += hq * (uu - 3.0 * uy * uy);
-                acc[2] += hq * (uu - 3.0 * uz * uz);
-                acc[3] += hq * (-3.0 * ux * uy);
-                acc[4] += hq * (-3.0 * ux * uz);
-                acc[5] += hq * (-3.0 * uy * uz);
+                acc[0] += hq * (uu - 3.0 * ux[k] * ux[k]);
+                acc[1] += hq * (uu - 3.0 * uy[k] * uy[k]);
+                acc[2] += hq * (uu - 3.0 * uz[k] * uz[k]);
+                acc[3] += hq * (-3.0 * ux[k] * uy[k]);
+                acc[4] += hq * (-3.0 * ux[k] * uz[k]);
+                acc[5] += hq * (-3.0 * uy[k] * uz[k]);
             }
         }
-        block_sum<6>(acc, red);     // its barriers also end this item's use of LDS
-        if (threadIdx.x == 0) {
-#pragma unroll
-            for (int c = 0; c < 6; ++c) a.part[(size_t)item * 6 + c] = acc[c];
-        }
-        __syncthreads();   // reconverge before the next item (see cell_pass)
+        // its barriers also end this item's use of LDS
+        const double t = block_sum_scatter<8>(acc, red);
+        if (threadIdx.x < 6) a.part[((size_t)which * reps + rep) * 6 + threadIdx.x] = t;
     }
 }
 
@@ -535,17 +592,16 @@ __global__ __launch_bounds__(1024) void k_relax(RelaxArgs a, HugeScratch hs)
 {
     __shared__ double red[6 * 16];
     __shared__ uint32_t wtot[16];
-    if (a.dflags && (a.dflags->range_err || (a.assume_sorted && a.dflags->unsorted))) return;
-    const uint32_t count = a.count_dev ? *a.count_dev : (uint32_t)a.count;
+    if (relax_off(a)) return;
     const uint64_t step = a.step_dev ? *a.step_dev : a.step;
     const R *vx = (const R *)a.v;
     const R *vy = vx + a.n;
     const R *vz = vy + a.n;
-    for (uint32_t item = blockIdx.x; item < count; item += gridDim.x) {
-        const int cell = a.list ? a.list[item] : (int)item;
+    const int32_t *mine = a.cls_list + 2 * (int64_t)a.cap;
+    for (uint32_t item = blockIdx.x; item < a.cls_count[2]; item += gridDim.x) {
+        const int cell = relax_cell(a, (uint32_t)mine[item]);
         const int lo = a.cell_start[cell];
         const int n = a.cell_start[cell + 1] - lo;
-        if (n <= RELAX_LDS_CAP) continue;    // sorted in LDS by k_relax_lds
         // temperature of the cell
         double s5[5] = {0, 0, 0, 0, 0};
         for (int i = threadIdx.x; i < n; i += blockDim.x) {
@@ -886,11 +942,11 @@ int launch_gate_end(DevGate *g, hipStream_t st)
 
 size_t relax_part_bytes(int64_t count, int replicas)
 {
-    return (size_t)count * (size_t)replicas * 6 * sizeof(double) + 256;
+    return (size_t)count * (size_t)replicas * 6 * sizeof(double) + 3 * (size_t)count * 4 + 16 + 256;
 }
 
 template <typename R, int T, int K>
-static int launch_relax_lds(const RelaxArgs &a, int nmin, int blocks, hipStream_t st)
+static int launch_relax_lds(const RelaxArgs &a, int cls, int blocks, hipStream_t st)
 {
     const size_t lds = sort_bytes(T * K);
     auto kern = k_relax_lds<R, T, K>;
@@ -900,18 +956,22 @@ static int launch_relax_lds(const RelaxArgs &a, int nmin, int blocks, hipStream_
                                    (int)lds));
         attr_done = true;
     }
-    hipLaunchKernelGGL(kern, dim3(blocks), dim3(T), lds, st, a, nmin);
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(T), lds, st, a, cls);
     HIP_OK(hipGetLastError());
     return PIC_OK;
 }
 
 template <typename R>
-static int launch_relax_t(const RelaxArgs &a, int num_cu, hipStream_t st)
+static int launch_relax_t(const RelaxArgs &a0, int num_cu, hipStream_t st)
 {
     int rc;
-    if ((rc = launch_relax_lds<R, RELAX_T0, RELAX_K0>(a, 0, num_cu * 4, st))) return rc;
-    if ((rc = launch_relax_lds<R, RELAX_T1, RELAX_K1>(a, RELAX_T0 * RELAX_K0 + 1, num_cu, st)))
-        return rc;
+    // class lists and counts follow the per-replica sums in the scratch
+    RelaxArgs a = a0;
+    a.cls_list = (int32_t *)(a.part + (size_t)a.cap * a.replicas * 6);
+    a.cls_count = (uint32_t *)(a.cls_list + 3 * (size_t)a.cap);
+    hipLaunchKernelGGL(k_relax_classify, dim3(1), dim3(RELAX_CLASSIFY_T), 0, st, a);
+    if ((rc = launch_relax_lds<R, RELAX_T0, RELAX_K0>(a, 0, num_cu * 6, st))) return rc;
+    if ((rc = launch_relax_lds<R, RELAX_T1, RELAX_K1>(a, 1, num_cu, st))) return rc;
     hipLaunchKernelGGL(k_relax<R>, dim3(num_cu), dim3(1024), 0, st, a, huge_scratch());
     hipLaunchKernelGGL(k_relax_finish<R>, dim3(num_cu * 4), dim3(256), 0, st, a);
     HIP_OK(hipGetLastError());

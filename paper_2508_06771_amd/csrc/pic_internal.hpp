@@ -124,12 +124,12 @@ __device__ __forceinline__ void scatter_dir(double &vx, double &vy, double &vz, 
 }
 
 // ---------------------------------------------------------------------------
-// Compensated conservation correction of one cell.  b = (N, sum v, sum |v|^2)
-// before the Coulomb step, f = the same sums now (f[0] unused).  The targets
-// are b plus the cell's debt (momentum, sum |v|^2) that earlier steps' output
-// rounding left unmet: a binary32 step changes a cell's energy by far less
-// than one binary32 ulp, so a plain rescaling would round away and the error
-// would accumulate; carrying the shortfall makes it diffuse instead.
+// Compensated conservation correction of one cell of N members.
+// b = (sum v, sum |v|^2) before the Coulomb step, f = the same sums now.  The
+// targets are b plus the cell's debt (momentum, sum |v|^2) that earlier steps'
+// output rounding left unmet: a binary32 step changes a cell's energy by far
+// less than one binary32 ulp, so a plain rescaling would round away and the
+// error would accumulate; carrying the shortfall makes it diffuse instead.
 // v <- Vt + alpha (v - Vn) with Vt the target mean velocity and alpha^2 the
 // ratio of target to current thermal energy.
 // ---------------------------------------------------------------------------
@@ -139,15 +139,14 @@ struct Correction {
     bool ok;
 };
 
-__device__ __forceinline__ Correction make_correction(const double *b, const double *f,
+__device__ __forceinline__ Correction make_correction(double N, const double *b, const double *f,
                                                       const double *debt)
 {
     Correction c;
-    const double N = b[0];
-    c.P[0] = b[1];
-    c.P[1] = b[2];
-    c.P[2] = b[3];
-    c.Q = b[4];
+    c.P[0] = b[0];
+    c.P[1] = b[1];
+    c.P[2] = b[2];
+    c.Q = b[3];
     if (debt) {
         c.P[0] += debt[0];
         c.P[1] += debt[1];
@@ -157,25 +156,33 @@ __device__ __forceinline__ Correction make_correction(const double *b, const dou
     double vt2 = 0.0, vn2 = 0.0;
     for (int a = 0; a < 3; ++a) {
         c.Vt[a] = c.P[a] / N;
-        c.Vn[a] = f[1 + a] / N;
+        c.Vn[a] = f[a] / N;
         vt2 += c.Vt[a] * c.Vt[a];
         vn2 += c.Vn[a] * c.Vn[a];
     }
     const double Et = 0.5 * c.Q - 0.5 * N * vt2;
-    const double En = 0.5 * f[4] - 0.5 * N * vn2;
+    const double En = 0.5 * f[3] - 0.5 * N * vn2;
     c.ok = N >= 2.0 && En > 0.0 && Et >= 0.0;
     c.al = c.ok ? sqrt(Et / En) : 1.0;
     return c;
 }
 
 // The shortfall left after the correction: target minus the realised sums
-// (real[1..3] momentum, real[4] sum |v|^2).
+// (real[0..2] momentum, real[3] sum |v|^2).
 __device__ __forceinline__ void store_debt(double *debt, const Correction &c, const double *real)
 {
-    debt[0] = c.P[0] - real[1];
-    debt[1] = c.P[1] - real[2];
-    debt[2] = c.P[2] - real[3];
-    debt[3] = c.Q - real[4];
+    debt[0] = c.P[0] - real[0];
+    debt[1] = c.P[1] - real[1];
+    debt[2] = c.P[2] - real[2];
+    debt[3] = c.Q - real[3];
+}
+
+// The same from block_sum_scatter<4> totals: thread t < 4 holds realised sum
+// t and writes shortfall t.
+__device__ __forceinline__ void store_debt_lane(double *debt, const Correction &c, double real_t)
+{
+    const unsigned t = threadIdx.x;
+    if (t < 4) debt[t] = (t == 0 ? c.P[0] : t == 1 ? c.P[1] : t == 2 ? c.P[2] : c.Q) - real_t;
 }
 
 // ---------------------------------------------------------------------------
@@ -209,6 +216,122 @@ __device__ __forceinline__ void block_sum(double (&x)[NV], double *red)
         for (int w = 0; w < nw; ++w) s += red[w * NV + j];
         x[j] = s;
     }
+    __syncthreads();
+}
+
+// Reduce-scatter butterfly over a wave for NV doubles (NV a power of two
+// <= 64): each exchange step halves the values a lane holds (its partner
+// keeps the other half), so a wave exchanges NV - 1 + 6 - log2(NV) values
+// instead of 6 NV, in a dependent chain of 6 steps.  Lane L ends with the
+// wave total of value L >> (6 - log2 NV).  The order of additions is fixed.
+// The first two steps (partners 32 and 16 lanes apart) use the CDNA4 lane
+// swaps: v_permlane32_swap exchanges the upper half-wave of one register
+// with the lower half-wave of another, v_permlane16_swap the odd 16-lane rows
+// of one with the even rows of the other; after the swap of (lo, hi) a lane
+// in the lower half (rows 0, 2) holds both its own and its partner's lo, one
+// in the upper half both hi, and one add finishes the step -- no selects and
+// no LDS traffic.  The later steps shuffle.
+template <int NV>
+constexpr int log2_pow2()
+{
+    return NV == 1 ? 0 : NV == 2 ? 1 : NV == 4 ? 2 : NV == 8 ? 3 : NV == 16 ? 4 : NV == 32 ? 5 : 6;
+}
+
+template <int O>
+__device__ __forceinline__ void lane_swap(double &lo, double &hi)
+{
+    static_assert(O == 32 || O == 16, "lane swaps exist for 32 and 16");
+    const uint64_t a = __double_as_longlong(lo), b = __double_as_longlong(hi);
+    const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32), b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
+    uint32_t l0, l1, h0, h1;
+    if constexpr (O == 32) {
+        const auto r0 = __builtin_amdgcn_permlane32_swap(a0, b0, false, false);
+        const auto r1 = __builtin_amdgcn_permlane32_swap(a1, b1, false, false);
+        l0 = r0[0]; h0 = r0[1]; l1 = r1[0]; h1 = r1[1];
+    } else {
+        const auto r0 = __builtin_amdgcn_permlane16_swap(a0, b0, false, false);
+        const auto r1 = __builtin_amdgcn_permlane16_swap(a1, b1, false, false);
+        l0 = r0[0]; h0 = r0[1]; l1 = r1[0]; h1 = r1[1];
+    }
+    lo = __longlong_as_double((int64_t)(((uint64_t)l1 << 32) | l0));
+    hi = __longlong_as_double((int64_t)(((uint64_t)h1 << 32) | h0));
+}
+
+// All 64 lanes must be active.
+template <int NV>
+__device__ __forceinline__ double wave_scatter(double (&x)[NV])
+{
+    static_assert(NV >= 1 && NV <= PIC_WAVE && (NV & (NV - 1)) == 0, "NV: power of two <= 64");
+    constexpr int B = log2_pow2<NV>();
+    const int lane = threadIdx.x & (PIC_WAVE - 1);
+#pragma unroll
+    for (int s = 0; s < B; ++s) {
+        const int o = (PIC_WAVE / 2) >> s;
+        const int half = NV >> (s + 1);
+#pragma unroll
+        for (int j = 0; j < half; ++j) {
+            if (o == 32 || o == 16) {
+                // lower-half lanes: own lo + partner's lo; upper: both hi
+                double l = x[j], h = x[j + half];
+                if (o == 32) lane_swap<32>(l, h);
+                else lane_swap<16>(l, h);
+                x[j] = l + h;
+            } else {
+                const bool up = (lane & o) != 0;
+                const double give = up ? x[j] : x[j + half];
+                const double keep = up ? x[j + half] : x[j];
+                x[j] = keep + __shfl_xor(give, o, PIC_WAVE);
+            }
+        }
+    }
+    double v = x[0];
+#pragma unroll
+    for (int o = (PIC_WAVE >> 1) >> B; o >= 1; o >>= 1) v += __shfl_xor(v, o, PIC_WAVE);
+    return v;
+}
+
+template <int NV>
+__device__ __forceinline__ void wave_scatter_to(double (&x)[NV], double *red)
+{
+    constexpr int B = log2_pow2<NV>();
+    const int lane = threadIdx.x & (PIC_WAVE - 1), wid = threadIdx.x / PIC_WAVE;
+    const double v = wave_scatter<NV>(x);
+    if ((lane & ((PIC_WAVE >> B) - 1)) == 0) red[wid * NV + (lane >> (6 - B))] = v;
+}
+
+// Block totals of NV doubles: thread t < NV returns the total of value t
+// (waves added in order), other threads 0.  red: NV * (blockDim / 64)
+// doubles of LDS.  Contains the barriers (red is free again on return).
+template <int NV>
+__device__ __forceinline__ double block_sum_scatter(double (&x)[NV], double *red)
+{
+    wave_scatter_to<NV>(x, red);
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x < NV) {
+        const int nw = blockDim.x / PIC_WAVE;
+        for (int w = 0; w < nw; ++w) s += red[w * NV + threadIdx.x];
+    }
+    __syncthreads();
+    return s;
+}
+
+// Block totals of NV doubles, returned to every thread in x.  red:
+// NV * (blockDim / 64 + 1) doubles of LDS.  Contains the barriers.
+template <int NV>
+__device__ __forceinline__ void block_sum_bcast(double (&x)[NV], double *red)
+{
+    const int nw = blockDim.x / PIC_WAVE;
+    wave_scatter_to<NV>(x, red);
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        double s = 0.0;
+        for (int w = 0; w < nw; ++w) s += red[w * NV + threadIdx.x];
+        red[nw * NV + threadIdx.x] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NV; ++j) x[j] = red[nw * NV + j];
     __syncthreads();
 }
 
@@ -472,7 +595,7 @@ struct RadixPass {
 // 7 re-binning passes, 8 stand-alone null-collision step, 9 learned gate
 // decision, 10 relaxation of the judged cells.
 enum { KT_CLASS0 = 0, KT_HUGE = 4, KT_CHECK = 5, KT_QUEUE = 6, KT_SORT = 7, KT_MCC = 8, KT_GATE = 9,
-       KT_RELAX = 10, KT_SLOTS = 16 };
+       KT_RELAX = 10, KT_DEFER = 11, KT_MOMENTS = 12, KT_SLOTS = 16 };
 void ktime_begin(int slot, hipStream_t st);
 void ktime_end(int slot, hipStream_t st);
 bool ktime_pause();            // returns whether timing was on
@@ -502,8 +625,16 @@ struct ClassCaps {
     int cap[4];          // max members per cell routed to each class (<= its capacity)
     int blocks_per_cu[5];  // persistent workgroups per CU of classes 0-3 and the multi-block class
 };
+// lists holds QUEUE_LISTS runs of n_cells entries: the classes, the
+// multi-block class at index ncls, and the cells the gate defers at
+// LIST_DEFERRED.  With skip (nullable) a deferred cell enters no class; it
+// is listed as deferred when visit is set (its null collisions still touch
+// it), else left out.
+constexpr int LIST_DEFERRED = 5;
+constexpr int QUEUE_LISTS = 6;
 int launch_build_queue(const int32_t *cell_start, int32_t n_cells, const ClassCaps &caps,
-                       int32_t *lists, DevFlags *flags, hipStream_t st);
+                       int32_t *lists, DevFlags *flags, const uint8_t *skip, int visit,
+                       hipStream_t st);
 
 struct CollideArgs {
     void *v;               // SoA base
@@ -512,7 +643,6 @@ struct CollideArgs {
     const int32_t *cell_start;
     const double *density;
     const double *dt_scale;  // per-cell dt multiplier (nullable)
-    const uint8_t *skip;     // per-cell skip (nullable)
     double dt, lnL;
     uint64_t seed, step;
     const uint64_t *step_dev;  // nullable: step read from device memory
@@ -524,15 +654,13 @@ struct CollideArgs {
     DevFlags *dflags;
     // pairing export
     int32_t *sorted_out, *partner_out;
-    // nullable: the launch runs only if *run_if == run_val (variants chosen
-    // on the device, e.g. with or without the gate's moment refresh)
-    const int *run_if;
-    int run_val;
-    int mom_full;          // deferred cells recompute their moment sums (not differences)
 };
 
 int launch_collide(int dtype, const CollideArgs &a, const int32_t *lists, int32_t n_cells,
                    const ClassCaps &caps, int pairs_only, int num_cu, hipStream_t st);
+// Null collisions of the deferred list: see k_deferred.
+int launch_deferred(int dtype, const CollideArgs &a, const int32_t *lists, int32_t n_cells,
+                    int num_cu, hipStream_t st);
 ClassCaps collide_caps(int dtype, size_t lds_per_block);
 // Global scratch of the multi-block ("huge") class, indexed by particle slot.
 size_t huge_scratch_bytes(int dtype, int64_t n);
@@ -583,9 +711,15 @@ struct RelaxArgs {
     double *r_out;              // indexed by cell
     const DevFlags *dflags;     // in a collision step: skip when binning failed
     int assume_sorted;
-    double *part;               // [count * replicas * 6] per-replica tensor sums
+    double *part;               // scratch of relax_part_bytes(cap, replicas) bytes
+    int32_t cap;                // most entries the list can hold (scratch sizing)
+    // set by launch_relax inside the scratch: list positions by size class
+    // (3 runs of cap) and the class counts
+    int32_t *cls_list;
+    uint32_t *cls_count;
 };
-// Scratch bytes of launch_relax for `count` cells.
+// Scratch bytes of launch_relax for lists of up to `count` cells: the
+// per-replica tensor sums [count * replicas * 6] and the size-class lists.
 size_t relax_part_bytes(int64_t count, int replicas);
 
 int launch_features(const double *moments, int32_t M, float *feat, uint8_t *valid, hipStream_t st);
@@ -609,7 +743,9 @@ int launch_mcc(int dtype, void *v, const uint32_t *pid, int64_t n, uint64_t thr,
                uint64_t seed, uint64_t step, uint8_t *cand_out, hipStream_t st);
 int launch_philox(uint64_t seed, uint64_t step, uint32_t domain, uint32_t c3, const uint32_t *c0,
                   int64_t n, uint32_t *out, hipStream_t st);
+// Per-cell moment sums (layout of pic_cell_moments); with run_if (nullable)
+// the pass runs only when *run_if is nonzero.
 int launch_moments(int dtype, const void *v, int64_t n, const int32_t *cell_start,
-                   int32_t n_cells, double *out, hipStream_t st);
+                   int32_t n_cells, double *out, const int *run_if, int num_cu, hipStream_t st);
 int launch_unsort(int dtype, void *v, uint32_t *pid, int32_t *cell_of, int64_t n, void *tmp,
                   hipStream_t st);

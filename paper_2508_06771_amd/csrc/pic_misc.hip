@@ -41,31 +41,85 @@ __global__ void k_philox(uint64_t seed, uint32_t step, uint32_t domain, uint32_t
     }
 }
 
-template <typename R>
-__global__ __launch_bounds__(256) void k_moments(const R *__restrict__ v, int64_t n,
-                                                 const int32_t *__restrict__ cs, int32_t n_cells,
-                                                 double *__restrict__ out)
+// Per-cell moment sums, streamed.  A workgroup takes groups of four
+// consecutive cells (round-robin, no atomics): first each wave sums one cell
+// of at most MOM_WAVE_MAX members on its own (four members' loads in flight
+// per lane, a wave reduce-scatter, no barriers), then the whole workgroup
+// sums each larger cell of the group.
+constexpr int MOM_T = 256;
+constexpr int MOM_WAVE_MAX = 4096;
+
+__device__ __forceinline__ void mom_add(double (&m)[16], double x, double y, double z)
 {
-    __shared__ double red[14 * 4];
-    for (int j = blockIdx.x; j < n_cells; j += gridDim.x) {
-        double m[14];
-        for (int q = 0; q < 14; ++q) m[q] = 0.0;
-        for (int64_t i = cs[j] + threadIdx.x; i < cs[j + 1]; i += blockDim.x) {
-            const double x = v[i], y = v[n + i], z = v[2 * n + i];
-            const double q2 = x * x + y * y + z * z;
-            m[0] += 1.0;
-            m[1] += x; m[2] += y; m[3] += z;
-            m[4] += x * x; m[5] += y * y; m[6] += z * z;
-            m[7] += x * y; m[8] += x * z; m[9] += y * z;
-            m[10] += q2 * x; m[11] += q2 * y; m[12] += q2 * z;
-            m[13] += q2 * q2;
-        }
-        block_sum<14>(m, red);
-        if (threadIdx.x == 0) {
+    const double q2 = x * x + y * y + z * z;
+    m[1] += x; m[2] += y; m[3] += z;
+    m[4] += x * x; m[5] += y * y; m[6] += z * z;
+    m[7] += x * y; m[8] += x * z; m[9] += y * z;
+    m[10] += q2 * x; m[11] += q2 * y; m[12] += q2 * z;
+    m[13] += q2 * q2;
+}
+
+// Sums members [i, hi) with stride `stride` into m (m[0] is left alone).
+template <typename R>
+__device__ __forceinline__ void mom_range(double (&m)[16], const R *__restrict__ v, int64_t n,
+                                          int64_t i, int64_t hi, int stride)
+{
+    for (; i < hi; i += 4 * (int64_t)stride) {
+        R x[4], y[4], z[4];
 #pragma unroll
-            for (int q = 0; q < 14; ++q) out[(int64_t)j * 14 + q] = m[q];
+        for (int k = 0; k < 4; ++k) {
+            const int64_t e = i + (int64_t)k * stride;
+            x[k] = y[k] = z[k] = (R)0;
+            if (e < hi) {
+                x[k] = v[e];
+                y[k] = v[n + e];
+                z[k] = v[2 * n + e];
+            }
         }
-        __syncthreads();   // reconverge before the next cell's reduction
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (i + (int64_t)k * stride < hi) mom_add(m, x[k], y[k], z[k]);
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(MOM_T) void k_moments(const R *__restrict__ v, int64_t n,
+                                                   const int32_t *__restrict__ cs, int32_t n_cells,
+                                                   double *__restrict__ out, const int *run_if)
+{
+    __shared__ double red[16 * (MOM_T / PIC_WAVE)];
+    if (run_if && !*run_if) return;
+    const int lane = threadIdx.x & (PIC_WAVE - 1), wid = threadIdx.x / PIC_WAVE;
+    constexpr int CPG = MOM_T / PIC_WAVE;    // cells per group
+    const int groups = (n_cells + CPG - 1) / CPG;
+    for (int g = blockIdx.x; g < groups; g += gridDim.x) {
+        const int j = g * CPG + wid;
+        if (j < n_cells) {
+            const int lo = cs[j], cnt = cs[j + 1] - lo;
+            if (cnt <= MOM_WAVE_MAX) {
+                double m[16];
+#pragma unroll
+                for (int q = 0; q < 16; ++q) m[q] = 0.0;
+                mom_range<R>(m, v, n, lo + lane, (int64_t)lo + cnt, PIC_WAVE);
+                // lane L holds sum L / 4 of the wave
+                const double t = wave_scatter<16>(m);
+                const int q = lane >> 2;
+                if ((lane & 3) == 0 && q < 14) out[(int64_t)j * 14 + q] = q == 0 ? (double)cnt : t;
+            }
+        }
+        // the group's larger cells; the bounds are the same for every thread
+        for (int w = 0; w < CPG; ++w) {
+            const int jj = g * CPG + w;
+            if (jj >= n_cells) break;
+            const int lo = cs[jj], cnt = cs[jj + 1] - lo;
+            if (cnt <= MOM_WAVE_MAX) continue;
+            double m[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) m[q] = 0.0;
+            mom_range<R>(m, v, n, lo + threadIdx.x, (int64_t)lo + cnt, MOM_T);
+            const double t = block_sum_scatter<16>(m, red);   // its barriers end the cell
+            if (threadIdx.x < 14) out[(int64_t)jj * 14 + threadIdx.x] = threadIdx.x == 0 ? (double)cnt : t;
+        }
     }
 }
 
@@ -135,15 +189,16 @@ int launch_philox(uint64_t seed, uint64_t step, uint32_t domain, uint32_t c3, co
 }
 
 int launch_moments(int dtype, const void *v, int64_t n, const int32_t *cell_start,
-                   int32_t n_cells, double *out, hipStream_t st)
+                   int32_t n_cells, double *out, const int *run_if, int num_cu, hipStream_t st)
 {
-    const int g = n_cells < 65536 ? n_cells : 65536;
+    const int groups = (n_cells + MOM_T / PIC_WAVE - 1) / (MOM_T / PIC_WAVE);
+    const int g = groups < num_cu * 8 ? groups : num_cu * 8;
     if (dtype == PIC_F32)
-        hipLaunchKernelGGL(k_moments<float>, dim3(g), dim3(256), 0, st, (const float *)v, n,
-                           cell_start, n_cells, out);
+        hipLaunchKernelGGL(k_moments<float>, dim3(g), dim3(MOM_T), 0, st, (const float *)v, n,
+                           cell_start, n_cells, out, run_if);
     else
-        hipLaunchKernelGGL(k_moments<double>, dim3(g), dim3(256), 0, st, (const double *)v, n,
-                           cell_start, n_cells, out);
+        hipLaunchKernelGGL(k_moments<double>, dim3(g), dim3(MOM_T), 0, st, (const double *)v, n,
+                           cell_start, n_cells, out, run_if);
     HIP_OK(hipGetLastError());
     return PIC_OK;
 }

@@ -95,7 +95,7 @@ GATE_STATS = ["steps", "skipped", "collided", "judged", "judged_want", "false_sk
               "have_moments"]
 
 KT_SLOTS = ["class0", "class1", "class2", "class3", "huge", "check", "queue", "sort", "mcc", "gate",
-            "relax"]
+            "relax", "deferred", "moments"]
 
 
 def _dt(v: torch.Tensor) -> int:
