@@ -634,7 +634,8 @@ static size_t step_ws_bytes(const pic_ctx *c, const StepArgs &s)
     const size_t es = s.dtype == PIC_F32 ? 4 : 8;
     const size_t part = (s.flags & PIC_GATE) ? relax_part_bytes(s.n_cells, c->gate_replicas) : 0;
     return (size_t)(s.n_cells + 1) * 4 + (size_t)s.n_cells * QUEUE_LISTS * 4 + (size_t)s.n * (8 + 3 * es) +
-           radix_scratch_bytes(s.n) + huge_scratch_bytes(s.dtype, s.n) + part + 8192;
+           radix_scratch_bytes(s.n) + huge_scratch_bytes(s.dtype, s.n) +
+           seg_scratch_bytes(s.dtype, s.n, s.n_cells) + part + 8192;
 }
 
 static int step_check(pic_ctx *c, const StepArgs &s)
@@ -668,6 +669,9 @@ static int step_enqueue(pic_ctx *c, const StepArgs &s, hipStream_t st, const uin
     bs.hist = (uint32_t *)b.take(radix_scratch_bytes(n));
     bs.bsum = bs.hist + 256 * ((n + 4095) / 4096 + 1);
     set_huge_scratch(dtype, n, b.take(huge_scratch_bytes(dtype, n)));
+    // the re-binning buffers are free again by the collide pass: the
+    // segmented path of the largest cells copies members into them
+    set_seg_scratch(dtype, n, n_cells, b.take(seg_scratch_bytes(dtype, n, n_cells)), tkey, tpid, tv);
     double *relax_part = (s.flags & PIC_GATE)
                              ? (double *)b.take(relax_part_bytes(n_cells, c->gate_replicas))
                              : nullptr;
@@ -707,6 +711,9 @@ static int step_enqueue(pic_ctx *c, const StepArgs &s, hipStream_t st, const uin
     const ClassCaps caps = c->tuned_valid[dtype] ? c->tuned[dtype] : collide_caps(dtype, c->lds_max);
     const uint64_t mcc_thr = (s.flags & PIC_FUSE_MCC) ? mcc_threshold(s.dt, c->mcc_sigma0, c->mcc_nn) : 0;
     const bool gate = (s.flags & PIC_GATE) != 0;
+    // cells beyond the LDS classes: several workgroups each, unless the step
+    // needs whole-cell sums (conservation correction, fused moments)
+    const bool seg_path = !(s.flags & PIC_CONSERVE_FIX) && (gate || !(s.flags & PIC_MOMENTS));
     if (gate) {
         // decide the deferred cells from the last refreshed moments and draw
         // the judged sample; the queue then leaves deferred cells out of the
@@ -737,7 +744,7 @@ static int step_enqueue(pic_ctx *c, const StepArgs &s, hipStream_t st, const uin
     }
     ktime_begin(KT_QUEUE, st);
     RC(launch_build_queue(cs, n_cells, caps, lists, c->flags, gate ? c->gate_skip : nullptr,
-                          mcc_thr != 0, st));
+                          mcc_thr != 0, seg_path ? &seg_scratch() : nullptr, seg_target(dtype), st));
     ktime_end(KT_QUEUE, st);
 
     if (gate) {
@@ -797,7 +804,7 @@ static int step_enqueue(pic_ctx *c, const StepArgs &s, hipStream_t st, const uin
             ktime_end(KT_DEFER, st);
         }
     }
-    RC(launch_collide(dtype, a, lists, n_cells, caps, 0, c->num_cu, st));
+    RC(launch_collide(dtype, a, lists, n_cells, caps, 0, c->num_cu, st, seg_path));
     if (gate) {
         // the sums the next decision reads: post-step state, on refresh steps
         ktime_begin(KT_MOMENTS, st);
@@ -939,7 +946,8 @@ int coulomb_pairs(pic_ctx *c, const int32_t *cell_start, const uint32_t *pid, in
     set_huge_scratch(PIC_F32, n, b.take(huge_scratch_bytes(PIC_F32, n)));
     RC(launch_reset_flags(c->flags, c->stream));
     const ClassCaps caps = collide_caps(PIC_F32, c->lds_max);
-    RC(launch_build_queue(cell_start, n_cells, caps, lists, c->flags, nullptr, 0, c->stream));
+    RC(launch_build_queue(cell_start, n_cells, caps, lists, c->flags, nullptr, 0, nullptr, 0,
+                          c->stream));
     CollideArgs a;
     memset(&a, 0, sizeof(a));
     a.n = n;

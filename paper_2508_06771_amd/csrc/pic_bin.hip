@@ -8,6 +8,8 @@
 // single streaming check of cell_of (4 B per particle); only unsorted input
 // runs the sort passes, which rank elements inside a wave with ballots
 // instead of atomics, so the result is stable and deterministic.
+#include <string.h>
+
 #include "pic_internal.hpp"
 
 #define HIP_OK(x) do { if ((x) != hipSuccess) return PIC_ERR_HIP; } while (0)
@@ -278,9 +280,41 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(RadixPass p,
 // arbitrary: cells are independent and their random numbers depend only on
 // (seed, step, pid), so processing order never changes results.  Cells the
 // gate defers go to the deferred list when they still need a visit.
+// Segment plan of cell h of the multi-workgroup list with cnt members:
+// S = 2^lS segments of about `target` members, their table entries, and the
+// counting work items.  Segment and item ranges are reserved with atomics:
+// where a cell's entries sit never changes results.
+__device__ void plan_segments(const SegScratch &ss, DevFlags *f, int h, int32_t cnt, int target)
+{
+    const int64_t want = ((int64_t)cnt + target - 1) / target;
+    int lS = 0;
+    while (((int64_t)1 << lS) < want) ++lS;
+    if (lS > SEG_MAX_LOG2) {
+        ss.hc_fb[h] = 1;
+        ss.hc_lS[h] = 0;
+        return;
+    }
+    const uint32_t S = 1u << lS;
+    const uint32_t nch = (uint32_t)(((int64_t)cnt + SEG_CHUNK - 1) / SEG_CHUNK);
+    const uint32_t sb = atomicAdd(&f->count[SEG_SLOT], S);
+    const uint32_t cb = atomicAdd(&f->count[CHUNK_SLOT], nch);
+    ss.hc_fb[h] = 0;
+    ss.hc_lS[h] = (uint8_t)lS;
+    ss.hc_seg[h] = (int32_t)sb;
+    ss.hc_chunk[h] = (int32_t)cb;
+    for (uint32_t q = 0; q < S; ++q) {
+        ss.sg_cell[sb + q] = h;
+        ss.sg_cnt[sb + q] = 0;
+        ss.bnd_head[sb + q] = -1;
+        ss.bnd_tail[sb + q] = -1;
+    }
+    for (uint32_t q = 0; q < nch; ++q) ss.ch_owner[cb + q] = h;
+}
+
 __global__ void k_build_queue(const int32_t *__restrict__ cell_start, int32_t n_cells, ClassCaps caps,
                               int32_t *__restrict__ lists, DevFlags *f,
-                              const uint8_t *__restrict__ skip, int visit)
+                              const uint8_t *__restrict__ skip, int visit, SegScratch ss,
+                              int plan, int seg_target)
 {
     const int lane = threadIdx.x & (PIC_WAVE - 1);
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (PIC_WAVE - lane));
@@ -306,7 +340,11 @@ __global__ void k_build_queue(const int32_t *__restrict__ cell_start, int32_t n_
             uint32_t b = 0;
             if (lane == leader) b = atomicAdd(&f->count[c], (uint32_t)__popcll(m));
             b = __shfl(b, leader, PIC_WAVE);
-            if (cls == c) lists[(int64_t)c * n_cells + b + __popcll(m & lt)] = (int32_t)j;
+            if (cls == c) {
+                const int h = (int)b + __popcll(m & lt);
+                lists[(int64_t)c * n_cells + h] = (int32_t)j;
+                if (plan && c == caps.ncls) plan_segments(ss, f, h, cnt, seg_target);
+            }
         }
         if (cls == caps.ncls) atomicAdd(&f->huge_total, (uint32_t)cnt);
     }
@@ -388,10 +426,14 @@ int radix_pass(const RadixPass &p, const BinScratch &s, hipStream_t st)
 
 int launch_build_queue(const int32_t *cell_start, int32_t n_cells, const ClassCaps &caps,
                        int32_t *lists, DevFlags *flags, const uint8_t *skip, int visit,
-                       hipStream_t st)
+                       const SegScratch *seg, int seg_target, hipStream_t st)
 {
+    SegScratch ss;
+    memset(&ss, 0, sizeof(ss));
+    if (seg) ss = *seg;
     hipLaunchKernelGGL(k_build_queue, dim3(grid_for(n_cells, 256, 1024)), dim3(256), 0, st,
-                       cell_start, n_cells, caps, lists, flags, skip, visit);
+                       cell_start, n_cells, caps, lists, flags, skip, visit, ss, seg ? 1 : 0,
+                       seg_target);
     HIP_OK(hipGetLastError());
     return PIC_OK;
 }

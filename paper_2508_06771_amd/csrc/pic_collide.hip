@@ -264,23 +264,32 @@ __device__ void cell_pass(const CollideArgs &a, int cell, unsigned char *smem, d
     uint32_t cand = 0;
 
     const uint32_t bits = sort_bits(n);
+    // every load of the thread is issued before any is used, so they are in
+    // flight together and overlap the clearing of the counters (pos holds
+    // the pid until the key is counted)
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int i = threadIdx.x + k * T;
+        if (i < n) {
+            pos[k] = pid_c[i];
+            if (!PAIRS) {
+                vx[k] = vx_g[i];
+                vy[k] = vy_g[i];
+                vz[k] = vz_g[i];
+            }
+        }
+    }
     L.clear();
     __syncthreads();
     {
-        // load, one Philox call per particle, and the bucket count of its key
-        // with its arrival rank
+        // one Philox call per particle, and the bucket count of its key with
+        // its arrival rank
         double before[4] = {0, 0, 0, 0};   // sum v, sum |v|^2
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const int i = threadIdx.x + k * T;
             if (i < n) {
-                const uint32_t p = pid_c[i];
-                if (!PAIRS) {
-                    vx[k] = vx_g[i];
-                    vy[k] = vy_g[i];
-                    vz[k] = vz_g[i];
-                }
-                const W4 w = draw4(a.seed, p, step, 0u, 0u);
+                const W4 w = draw4(a.seed, pos[k], step, 0u, 0u);
                 w2[k] = w.z;
                 w3[k] = w.w;
                 if (MCC && (uint64_t)w.y < a.mcc_thr) cand |= 1u << k;
@@ -487,7 +496,8 @@ __global__ __launch_bounds__(T) void k_collide(CollideArgs a, const int32_t *__r
 // particle's slot, so scratch regions of different cells never overlap.
 template <typename R, bool PAIRS>
 __global__ __launch_bounds__(1024) void k_collide_huge(CollideArgs a, const int32_t *__restrict__ list,
-                                                       int cls, HugeScratch hs)
+                                                       int cls, HugeScratch hs,
+                                                       const uint8_t *__restrict__ only)
 {
     __shared__ double red[16 * 16];
     __shared__ uint32_t wtot[16];
@@ -506,6 +516,7 @@ __global__ __launch_bounds__(1024) void k_collide_huge(CollideArgs a, const int3
         const int item = s_item;
         __syncthreads();
         if (item >= (int)count) break;
+        if (only && !only[item]) continue;   // taken by the segmented path
         const int cell = list[item];
         const int lo = a.cell_start[cell];
         const int n = a.cell_start[cell + 1] - lo;
@@ -632,6 +643,387 @@ __global__ __launch_bounds__(1024) void k_collide_huge(CollideArgs a, const int3
     }
 }
 
+// ------------------------------------------------------------ segmented cells
+// Cells beyond the largest LDS class with several workgroups each (see
+// SegScratch): count members per segment, scan, copy members segment-major,
+// sort and pair each segment in LDS, then the pairs across segment edges.
+constexpr int SEG_CT = 256;   // threads of the counting and copying kernels
+
+__device__ __forceinline__ uint32_t seg_of(uint32_t key, uint32_t lS)
+{
+    return lS ? key >> (32u - lS) : 0u;
+}
+
+struct SegItem {
+    int h, lo, b, e;
+    uint32_t lS;
+};
+
+// Work item -> its cell h of the list, the cell's first slot and the item's
+// member range [b, e) inside the cell.
+__device__ __forceinline__ SegItem seg_item(const CollideArgs &a, const SegScratch &ss,
+                                            const int32_t *list, uint32_t item)
+{
+    SegItem it;
+    it.h = ss.ch_owner[item];
+    const int cell = list[it.h];
+    it.lo = a.cell_start[cell];
+    const int n = a.cell_start[cell + 1] - it.lo;
+    it.b = (int)(item - (uint32_t)ss.hc_chunk[it.h]) * SEG_CHUNK;
+    it.e = min(n, it.b + SEG_CHUNK);
+    it.lS = ss.hc_lS[it.h];
+    return it;
+}
+
+// Segment sizes: an LDS histogram per work item, then one global add per
+// non-empty segment.
+__global__ __launch_bounds__(SEG_CT) void k_seg_count(CollideArgs a, const int32_t *__restrict__ list,
+                                                      SegScratch ss)
+{
+    __shared__ uint32_t hist[1 << SEG_MAX_LOG2];
+    if (gated_off(a)) return;
+    const uint32_t items = a.dflags->count[CHUNK_SLOT];
+    const uint32_t step = (uint32_t)read_step(a);
+    for (uint32_t item = blockIdx.x; item < items; item += gridDim.x) {
+        const SegItem it = seg_item(a, ss, list, item);
+        const uint32_t S = 1u << it.lS;
+        for (uint32_t q = threadIdx.x; q < S; q += SEG_CT) hist[q] = 0u;
+        __syncthreads();
+        for (int i = it.b + (int)threadIdx.x; i < it.e; i += SEG_CT) {
+            const uint32_t key = draw4(a.seed, a.pid[it.lo + i], step, 0u, 0u).x;
+            atomicAdd(&hist[seg_of(key, it.lS)], 1u);
+        }
+        __syncthreads();
+        const int32_t sb = ss.hc_seg[it.h];
+        for (uint32_t q = threadIdx.x; q < S; q += SEG_CT)
+            if (hist[q]) atomicAdd(&ss.sg_cnt[sb + q], hist[q]);
+        __syncthreads();
+    }
+}
+
+// One workgroup: each segment's run in the scratch (exclusive scan of the
+// sizes in table order) and the copy cursors; a cell with a segment beyond
+// cap takes the one-workgroup path.
+__global__ __launch_bounds__(1024) void k_seg_scan(CollideArgs a, SegScratch ss, uint32_t cap)
+{
+    __shared__ uint32_t wtot[16];
+    __shared__ uint32_t s_tot;
+    if (gated_off(a)) return;
+    const uint32_t nseg = a.dflags->count[SEG_SLOT];
+    uint32_t base = 0;
+    for (uint32_t j0 = 0; j0 < nseg; j0 += 1024) {
+        const uint32_t j = j0 + threadIdx.x;
+        const uint32_t c = j < nseg ? ss.sg_cnt[j] : 0u;
+        const uint32_t off = block_excl(c, wtot);
+        if (j < nseg) {
+            ss.sg_start[j] = base + off;
+            ss.sg_cur[j] = base + off;
+            if (c > cap) ss.hc_fb[ss.sg_cell[j]] = 1;
+        }
+        if (threadIdx.x == 1023) s_tot = off + c;
+        __syncthreads();
+        base += s_tot;
+        __syncthreads();
+    }
+}
+
+// Members to their segment's run: counts per segment in LDS, one global
+// reservation per non-empty segment, then each member at its reservation
+// plus its LDS arrival rank (the order inside a run is free: the segment
+// pass sorts by key and pid).
+template <typename R>
+__global__ __launch_bounds__(SEG_CT) void k_seg_scatter(CollideArgs a, const int32_t *__restrict__ list,
+                                                        SegScratch ss)
+{
+    __shared__ uint32_t hist[1 << SEG_MAX_LOG2];
+    __shared__ uint32_t base[1 << SEG_MAX_LOG2];
+    __shared__ uint16_t sof[SEG_CHUNK];
+    if (gated_off(a)) return;
+    const uint32_t items = a.dflags->count[CHUNK_SLOT];
+    const uint32_t step = (uint32_t)read_step(a);
+    const R *v = (const R *)a.v;
+    R *mv = (R *)ss.m_v;
+    for (uint32_t item = blockIdx.x; item < items; item += gridDim.x) {
+        const SegItem it = seg_item(a, ss, list, item);
+        if (ss.hc_fb[it.h]) continue;   // the same for the whole workgroup
+        const uint32_t S = 1u << it.lS;
+        for (uint32_t q = threadIdx.x; q < S; q += SEG_CT) hist[q] = 0u;
+        __syncthreads();
+        for (int i = it.b + (int)threadIdx.x; i < it.e; i += SEG_CT) {
+            const uint32_t key = draw4(a.seed, a.pid[it.lo + i], step, 0u, 0u).x;
+            const uint32_t q = seg_of(key, it.lS);
+            sof[i - it.b] = (uint16_t)q;
+            atomicAdd(&hist[q], 1u);
+        }
+        __syncthreads();
+        const int32_t sb = ss.hc_seg[it.h];
+        for (uint32_t q = threadIdx.x; q < S; q += SEG_CT) {
+            base[q] = hist[q] ? atomicAdd(&ss.sg_cur[sb + q], hist[q]) : 0u;
+            hist[q] = 0u;
+        }
+        __syncthreads();
+        for (int i = it.b + (int)threadIdx.x; i < it.e; i += SEG_CT) {
+            const uint32_t q = sof[i - it.b];
+            const uint32_t slot = base[q] + atomicAdd(&hist[q], 1u);
+            const int64_t g = (int64_t)it.lo + i;
+            ss.m_orig[slot] = (int32_t)g;
+            ss.m_pid[slot] = a.pid[g];
+            mv[slot] = v[g];
+            mv[ss.m_stride + slot] = v[a.n + g];
+            mv[2 * ss.m_stride + slot] = v[2 * a.n + g];
+        }
+        __syncthreads();
+    }
+}
+
+// One segment: the members of run [start, start + n) sort by key (their top
+// lS bits are the segment's, so the bits below bucket them) and pid; local
+// position q is position off + q of the cell.  The cell's pairs (2i, 2i + 1)
+// inside the segment collide here as in the cell pass; a member whose
+// partner lies in a neighbouring segment is recorded for k_seg_fixup and left
+// unchanged (its null collision too).
+template <typename R, int T, int K, int F>
+__device__ void seg_pass(const CollideArgs &a, const int32_t *list, const SegScratch &ss, int seg,
+                         unsigned char *smem, uint32_t *wtot)
+{
+    constexpr bool MCC = (F & F_MCC) != 0;
+    constexpr int CAP = T * K;
+    const int h = ss.sg_cell[seg];
+    const uint32_t n = ss.sg_cnt[seg];
+    if (ss.hc_fb[h] || n == 0) {
+        __syncthreads();
+        return;
+    }
+    const int cell = list[h];
+    const int lo_c = a.cell_start[cell];
+    const uint32_t n_c = (uint32_t)(a.cell_start[cell + 1] - lo_c);
+    const uint32_t start = ss.sg_start[seg];
+    const uint32_t off = start - ss.sg_start[ss.hc_seg[h]];
+    const uint32_t lS = ss.hc_lS[h];
+    const uint32_t step = (uint32_t)read_step(a);
+    const R *mx = (const R *)ss.m_v + start;
+    const R *my = mx + ss.m_stride;
+    const R *mz = my + ss.m_stride;
+    const uint32_t *pid_s = ss.m_pid + start;
+    const int32_t *orig = ss.m_orig + start;
+    R *vx_g = (R *)a.v;
+    R *vy_g = vx_g + a.n;
+    R *vz_g = vy_g + a.n;
+    const SortLDS<T, CAP> L(smem);
+
+    R vx[K], vy[K], vz[K];
+    uint32_t w2[K], w3[K], pos[K];
+    uint32_t cand = 0;
+    const uint32_t bits = sort_bits((int)n);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int i = threadIdx.x + k * T;
+        if (i < (int)n) {
+            pos[k] = pid_s[i];
+            vx[k] = mx[i];
+            vy[k] = my[i];
+            vz[k] = mz[i];
+        }
+    }
+    L.clear();
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int i = threadIdx.x + k * T;
+        if (i < (int)n) {
+            const W4 w = draw4(a.seed, pos[k], step, 0u, 0u);
+            w2[k] = w.z;
+            w3[k] = w.w;
+            if (MCC && (uint64_t)w.y < a.mcc_thr) cand |= 1u << k;
+            pos[k] = L.count(i, w.x << lS, bits);
+        }
+    }
+    __syncthreads();
+    rank_in_lds<T, K, CAP>(pos, (int)n, bits, L, pid_s, wtot);
+
+    // local pairs cover positions [first, first + np2)
+    const uint32_t first = off & 1u;
+    const uint32_t np2 = (n - first) & ~1u;
+    uint32_t edge = 0;   // bit k: the partner is in a neighbouring segment
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int i = threadIdx.x + k * T;
+        if (i < (int)n) {
+            if (first && pos[k] == 0u) {
+                edge |= 1u << k;
+                ss.bnd_head[seg] = (int32_t)(start + i);
+            } else if (pos[k] == first + np2 && off + pos[k] + 1u < n_c) {
+                edge |= 1u << k;
+                ss.bnd_tail[seg] = (int32_t)(start + i);
+            }
+        }
+    }
+    {
+        const R C = (R)cell_C(a, cell);
+        constexpr uint32_t P = round_positions<R>(CAP);
+        Rec<R> *rec = (Rec<R> *)smem;
+        uint32_t *w3s = (uint32_t *)(rec + P);
+        for (uint32_t base = 0; base < np2; base += P) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int i = threadIdx.x + k * T;
+                const uint32_t pl = pos[k] - first;   // wraps for the lower edge member
+                const uint32_t q = pl - base;
+                if (i < (int)n && pl < np2 && q < P) {
+                    Rec<R> e;
+                    e.x = vx[k];
+                    e.y = vy[k];
+                    e.z = vz[k];
+                    e.w2 = w2[k];
+                    rec[q] = e;
+                    if (!(q & 1u)) w3s[q >> 1] = w3[k];
+                }
+            }
+            __syncthreads();
+            const uint32_t m = min(P, np2 - base) / 2;
+            for (uint32_t j = threadIdx.x; j < m; j += T) {
+                Rec<R> A = rec[2 * j], B = rec[2 * j + 1];
+                R hx, hy, hz;
+                ta_half(A.x - B.x, A.y - B.y, A.z - B.z, C, A.w2, w3s[j], B.w2, hx, hy, hz);
+                A.x += hx;
+                A.y += hy;
+                A.z += hz;
+                B.x -= hx;
+                B.y -= hy;
+                B.z -= hz;
+                rec[2 * j] = A;
+                rec[2 * j + 1] = B;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int i = threadIdx.x + k * T;
+                const uint32_t pl = pos[k] - first;
+                const uint32_t q = pl - base;
+                if (i < (int)n && pl < np2 && q < P) {
+                    const Rec<R> e = rec[q];
+                    vx[k] = e.x;
+                    vy[k] = e.y;
+                    vz[k] = e.z;
+                }
+            }
+            if (base + P < np2) __syncthreads();
+        }
+    }
+    if constexpr (MCC) {
+        uint32_t left = cand & ~edge;
+        while (__ballot(left != 0u) != 0ull) {
+            if (left) {
+                const int kk = __builtin_ctz(left);
+                left &= left - 1u;
+                R x = vx[0], y = vy[0], z = vz[0];
+#pragma unroll
+                for (int k = 1; k < K; ++k)
+                    if (kk == k) {
+                        x = vx[k];
+                        y = vy[k];
+                        z = vz[k];
+                    }
+                mcc_scatter<R>(x, y, z, pid_s[threadIdx.x + kk * T], a.seed, step, a.mass_ratio);
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+                    if (kk == k) {
+                        vx[k] = x;
+                        vy[k] = y;
+                        vz[k] = z;
+                    }
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int i = threadIdx.x + k * T;
+        if (i < (int)n && !((edge >> k) & 1u)) {
+            const int32_t g = orig[i];
+            vx_g[g] = vx[k];
+            vy_g[g] = vy[k];
+            vz_g[g] = vz[k];
+        }
+    }
+    // every thread leaves together (see cell_pass)
+    __syncthreads();
+}
+
+template <typename R, int T, int K, int F>
+__global__ __launch_bounds__(T) void k_seg_collide(CollideArgs a, const int32_t *__restrict__ list,
+                                                   SegScratch ss)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ uint32_t wtot[T / PIC_WAVE];
+    __shared__ int s_item;
+    if (gated_off(a)) return;
+    const uint32_t count = a.dflags->count[SEG_SLOT];
+    if (blockIdx.x >= count) return;   // no work for this workgroup (nor a queue atomic)
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(&a.dflags->head[SEG_SLOT], 1u);
+        __syncthreads();
+        const int item = s_item;
+        __syncthreads();
+        if (item >= (int)count) break;
+        seg_pass<R, T, K, F>(a, list, ss, item, smem, wtot);
+    }
+}
+
+// The pairs across segment edges: the lower member (even position) is the
+// last of the previous non-empty segment of the cell, the upper one the first
+// of this segment; both are still unchanged.  Rotation, the null collisions of
+// both, stores.
+template <typename R>
+__global__ __launch_bounds__(256) void k_seg_fixup(CollideArgs a, const int32_t *__restrict__ list,
+                                                   SegScratch ss)
+{
+    if (gated_off(a)) return;
+    const uint32_t nseg = a.dflags->count[SEG_SLOT];
+    const uint32_t step = (uint32_t)read_step(a);
+    R *vx_g = (R *)a.v;
+    R *vy_g = vx_g + a.n;
+    R *vz_g = vy_g + a.n;
+    const R *mx = (const R *)ss.m_v;
+    const R *my = mx + ss.m_stride;
+    const R *mz = my + ss.m_stride;
+    for (uint32_t seg = blockIdx.x * blockDim.x + threadIdx.x; seg < nseg; seg += gridDim.x * blockDim.x) {
+        const int32_t sb = ss.bnd_head[seg];
+        if (sb < 0) continue;
+        const int h = ss.sg_cell[seg];
+        if (ss.hc_fb[h]) continue;
+        int32_t sa = -1;
+        for (int p = (int)seg - 1; p >= ss.hc_seg[h]; --p)
+            if (ss.sg_cnt[p]) {
+                sa = ss.bnd_tail[p];
+                break;
+            }
+        if (sa < 0) continue;   // not reached: an odd offset follows a segment that ends on an even one
+        const R C = (R)cell_C(a, list[h]);
+        const uint32_t pa = ss.m_pid[sa], pb = ss.m_pid[sb];
+        const W4 wa = draw4(a.seed, pa, step, 0u, 0u);
+        const W4 wb = draw4(a.seed, pb, step, 0u, 0u);
+        R ax = mx[sa], ay = my[sa], az = mz[sa];
+        R bx = mx[sb], by = my[sb], bz = mz[sb];
+        R hx, hy, hz;
+        ta_half(ax - bx, ay - by, az - bz, C, wa.z, wa.w, wb.z, hx, hy, hz);
+        ax += hx;
+        ay += hy;
+        az += hz;
+        bx -= hx;
+        by -= hy;
+        bz -= hz;
+        if (a.mcc_thr && (uint64_t)wa.y < a.mcc_thr) mcc_scatter<R>(ax, ay, az, pa, a.seed, step, a.mass_ratio);
+        if (a.mcc_thr && (uint64_t)wb.y < a.mcc_thr) mcc_scatter<R>(bx, by, bz, pb, a.seed, step, a.mass_ratio);
+        const int32_t ga = ss.m_orig[sa], gb = ss.m_orig[sb];
+        vx_g[ga] = ax;
+        vy_g[ga] = ay;
+        vz_g[ga] = az;
+        vx_g[gb] = bx;
+        vy_g[gb] = by;
+        vz_g[gb] = bz;
+    }
+}
+
 // ------------------------------------------------------------ deferred cells
 // A cell the gate defers skips the Coulomb step and enters no class queue.
 // When null collisions are on it is listed here for its candidates (about 1%
@@ -699,21 +1091,55 @@ int launch_class(const CollideArgs &a, const int32_t *list, int cls, int blocks,
     return PIC_OK;
 }
 
+SegScratch g_seg;   // set from the workspace before each step's launches
+
+template <typename R, int T, int K, int F>
+int launch_seg_collide(const CollideArgs &a, const int32_t *list, const SegScratch &ss, int blocks,
+                       hipStream_t st)
+{
+    const size_t lds = lds_bytes<R>(T * K);
+    auto kern = k_seg_collide<R, T, K, F>;
+    static bool attr_done = false;
+    if (!attr_done) {
+        HIP_OK(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)lds));
+        attr_done = true;
+    }
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(T), lds, st, a, list, ss);
+    HIP_OK(hipGetLastError());
+    return PIC_OK;
+}
+
 template <typename R, int F>
 int launch_all(const CollideArgs &a, const int32_t *lists, int32_t n_cells, int num_cu,
-               const HugeScratch &hs, const ClassCaps &caps, hipStream_t st)
+               const HugeScratch &hs, const ClassCaps &caps, bool seg_path, hipStream_t st)
 {
     typedef Classes<R> C;
     constexpr bool PAIRS = (F & F_PAIRS) != 0;
+    constexpr bool SEG_OK = !PAIRS && !(F & (F_CONS | F_MOM));
     int rc;
     const int64_t M = n_cells;
+    const int *bp = caps.blocks_per_cu;
+    const int32_t *l4 = lists + 4 * M;
     // largest cells first so the small ones fill the tail
     ktime_begin(KT_HUGE, st);
-    hipLaunchKernelGGL((k_collide_huge<R, PAIRS>), dim3(num_cu * caps.blocks_per_cu[4]), dim3(1024), 0,
-                       st, a, lists + 4 * M, 4, hs);
+    if (SEG_OK && seg_path) {
+        const SegScratch &ss = g_seg;
+        hipLaunchKernelGGL(k_seg_count, dim3(num_cu * 4), dim3(SEG_CT), 0, st, a, l4, ss);
+        hipLaunchKernelGGL(k_seg_scan, dim3(1), dim3(1024), 0, st, a, ss, (uint32_t)(C::T3 * C::K3));
+        hipLaunchKernelGGL(k_seg_scatter<R>, dim3(num_cu * 4), dim3(SEG_CT), 0, st, a, l4, ss);
+        HIP_OK(hipGetLastError());
+        if ((rc = launch_seg_collide<R, C::T3, C::K3, F>(a, l4, ss, bp[3] * num_cu, st))) return rc;
+        hipLaunchKernelGGL(k_seg_fixup<R>, dim3(num_cu), dim3(256), 0, st, a, l4, ss);
+        // cells the plan could not segment
+        hipLaunchKernelGGL((k_collide_huge<R, PAIRS>), dim3(num_cu * bp[4]), dim3(1024), 0, st, a, l4, 4,
+                           hs, (const uint8_t *)ss.hc_fb);
+    } else {
+        hipLaunchKernelGGL((k_collide_huge<R, PAIRS>), dim3(num_cu * bp[4]), dim3(1024), 0, st, a, l4, 4,
+                           hs, (const uint8_t *)nullptr);
+    }
     ktime_end(KT_HUGE, st);
     HIP_OK(hipGetLastError());
-    const int *bp = caps.blocks_per_cu;
     if ((rc = launch_class<R, C::T3, C::K3, F>(a, lists + 3 * M, 3, bp[3] * num_cu, st))) return rc;
     if ((rc = launch_class<R, C::T2, C::K2, F>(a, lists + 2 * M, 2, bp[2] * num_cu, st))) return rc;
     if ((rc = launch_class<R, C::T1, C::K1, F>(a, lists + 1 * M, 1, bp[1] * num_cu, st))) return rc;
@@ -734,20 +1160,20 @@ int launch_deferred_t(const CollideArgs &a, const int32_t *lists, int32_t n_cell
 
 template <typename R>
 int launch_flags(const CollideArgs &a, const int32_t *lists, int32_t n_cells, int num_cu,
-                 const HugeScratch &hs, const ClassCaps &cc, int pairs_only, hipStream_t st)
+                 const HugeScratch &hs, const ClassCaps &cc, int pairs_only, bool sp, hipStream_t st)
 {
-    if (pairs_only) return launch_all<R, F_PAIRS>(a, lists, n_cells, num_cu, hs, cc, st);
+    if (pairs_only) return launch_all<R, F_PAIRS>(a, lists, n_cells, num_cu, hs, cc, false, st);
     const int f = (a.mcc_thr ? F_MCC : 0) | ((a.flags & PIC_CONSERVE_FIX) ? F_CONS : 0) |
                   ((a.flags & PIC_MOMENTS) ? F_MOM : 0);
     switch (f) {
-    case 0: return launch_all<R, 0>(a, lists, n_cells, num_cu, hs, cc, st);
-    case 1: return launch_all<R, 1>(a, lists, n_cells, num_cu, hs, cc, st);
-    case 2: return launch_all<R, 2>(a, lists, n_cells, num_cu, hs, cc, st);
-    case 3: return launch_all<R, 3>(a, lists, n_cells, num_cu, hs, cc, st);
-    case 4: return launch_all<R, 4>(a, lists, n_cells, num_cu, hs, cc, st);
-    case 5: return launch_all<R, 5>(a, lists, n_cells, num_cu, hs, cc, st);
-    case 6: return launch_all<R, 6>(a, lists, n_cells, num_cu, hs, cc, st);
-    default: return launch_all<R, 7>(a, lists, n_cells, num_cu, hs, cc, st);
+    case 0: return launch_all<R, 0>(a, lists, n_cells, num_cu, hs, cc, sp, st);
+    case 1: return launch_all<R, 1>(a, lists, n_cells, num_cu, hs, cc, sp, st);
+    case 2: return launch_all<R, 2>(a, lists, n_cells, num_cu, hs, cc, sp, st);
+    case 3: return launch_all<R, 3>(a, lists, n_cells, num_cu, hs, cc, sp, st);
+    case 4: return launch_all<R, 4>(a, lists, n_cells, num_cu, hs, cc, sp, st);
+    case 5: return launch_all<R, 5>(a, lists, n_cells, num_cu, hs, cc, sp, st);
+    case 6: return launch_all<R, 6>(a, lists, n_cells, num_cu, hs, cc, sp, st);
+    default: return launch_all<R, 7>(a, lists, n_cells, num_cu, hs, cc, sp, st);
     }
 }
 
@@ -811,10 +1237,70 @@ void set_huge_scratch(int dtype, int64_t n, void *base)
 }
 
 int launch_collide(int dtype, const CollideArgs &a, const int32_t *lists, int32_t n_cells,
-                   const ClassCaps &cc, int pairs_only, int num_cu, hipStream_t st)
+                   const ClassCaps &cc, int pairs_only, int num_cu, hipStream_t st, bool seg_path)
 {
-    if (dtype == PIC_F32) return launch_flags<float>(a, lists, n_cells, num_cu, g_huge, cc, pairs_only, st);
-    return launch_flags<double>(a, lists, n_cells, num_cu, g_huge, cc, pairs_only, st);
+    if (dtype == PIC_F32)
+        return launch_flags<float>(a, lists, n_cells, num_cu, g_huge, cc, pairs_only, seg_path, st);
+    return launch_flags<double>(a, lists, n_cells, num_cu, g_huge, cc, pairs_only, seg_path, st);
+}
+
+const SegScratch &seg_scratch() { return g_seg; }
+
+int seg_cap(int dtype)
+{
+    return dtype == PIC_F32 ? Classes<float>::T3 * Classes<float>::K3
+                            : Classes<double>::T3 * Classes<double>::K3;
+}
+
+int seg_target(int dtype)
+{
+    return seg_cap(dtype) * 5 / 8;
+}
+
+static int64_t seg_max_for(int dtype, int64_t n, int32_t n_cells)
+{
+    // S <= 2 ceil(n_c / target) per cell
+    return 2 * (n / seg_target(dtype) + n_cells) + 2;
+}
+
+static int64_t chunk_max_for(int64_t n, int32_t n_cells)
+{
+    return n / SEG_CHUNK + n_cells + 1;
+}
+
+size_t seg_scratch_bytes(int dtype, int64_t n, int32_t n_cells)
+{
+    const size_t S = (size_t)seg_max_for(dtype, n, n_cells), Q = (size_t)chunk_max_for(n, n_cells);
+    return (size_t)n_cells * (1 + 1 + 4 + 4) + S * 6 * 4 + Q * 4 + 11 * 256;   // 11 aligned parts
+}
+
+void set_seg_scratch(int dtype, int64_t n, int32_t n_cells, void *base, int32_t *m_orig,
+                     uint32_t *m_pid, void *m_v)
+{
+    unsigned char *p = (unsigned char *)base;
+    auto take = [&](size_t bytes) {
+        unsigned char *r = p;
+        p += (bytes + 255) & ~(size_t)255;
+        return (void *)r;
+    };
+    const int64_t S = seg_max_for(dtype, n, n_cells), Q = chunk_max_for(n, n_cells);
+    g_seg.hc_lS = (uint8_t *)take((size_t)n_cells);
+    g_seg.hc_fb = (uint8_t *)take((size_t)n_cells);
+    g_seg.hc_seg = (int32_t *)take((size_t)n_cells * 4);
+    g_seg.hc_chunk = (int32_t *)take((size_t)n_cells * 4);
+    g_seg.sg_cell = (int32_t *)take((size_t)S * 4);
+    g_seg.sg_cnt = (uint32_t *)take((size_t)S * 4);
+    g_seg.sg_start = (uint32_t *)take((size_t)S * 4);
+    g_seg.sg_cur = (uint32_t *)take((size_t)S * 4);
+    g_seg.bnd_head = (int32_t *)take((size_t)S * 4);
+    g_seg.bnd_tail = (int32_t *)take((size_t)S * 4);
+    g_seg.ch_owner = (int32_t *)take((size_t)Q * 4);
+    g_seg.m_orig = m_orig;
+    g_seg.m_pid = m_pid;
+    g_seg.m_v = m_v;
+    g_seg.m_stride = n;
+    g_seg.seg_max = S;
+    g_seg.chunk_max = Q;
 }
 
 int launch_deferred(int dtype, const CollideArgs &a, const int32_t *lists, int32_t n_cells,

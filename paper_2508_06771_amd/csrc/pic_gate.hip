@@ -483,12 +483,19 @@ __global__ __launch_bounds__(T) void k_relax_lds(RelaxArgs a, int cls)
             const uint32_t *pid_c = a.pid + lo;
             const uint32_t bits = sort_bits(n);
             uint32_t pos[K];
+            // the pids are loaded before any is used (pos holds them until
+            // the keys are counted), so the loads are in flight together
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int i = threadIdx.x + k * T;
+                if (i < n) pos[k] = pid_c[i];
+            }
             L.clear();
             __syncthreads();
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 const int i = threadIdx.x + k * T;
-                if (i < n) pos[k] = L.count(i, draw4(a.seed, pid_c[i], step, 3u, rep).x, bits);
+                if (i < n) pos[k] = L.count(i, draw4(a.seed, pos[k], step, 3u, rep).x, bits);
             }
             __syncthreads();
             rank_in_lds<T, K, CAP>(pos, n, bits, L, pid_c, wtot);

@@ -516,6 +516,47 @@ struct HugeScratch {
 };
 const HugeScratch &huge_scratch();
 
+// Multi-workgroup path for cells beyond the largest LDS class.  A cell's
+// members are split into S = 2^lS segments by the top lS bits of their sort
+// key; since the order is by key first, the cell's sorted order is the
+// segments' sorted orders one after another.  Each segment (at most
+// SEG_CAP members) is sorted and paired in LDS by its own workgroup at its
+// global offset in the cell; the pair that straddles two segments (when a
+// segment starts at an odd position) is done by a fix-up pass.  Members are
+// first copied segment-major into the scratch below.
+constexpr int SEG_CHUNK = 8192;        // members per counting / scatter work item
+constexpr int SEG_MAX_LOG2 = 12;       // at most 4096 segments per cell
+struct SegScratch {
+    // per cell of the multi-workgroup list (index h into that list)
+    uint8_t *hc_lS;       // log2 of the segment count
+    uint8_t *hc_fb;       // 1: cell takes the one-workgroup path instead
+    int32_t *hc_seg;      // first segment of the cell
+    int32_t *hc_chunk;    // first work item of the cell
+    // per segment (DevFlags count[SEG_SLOT] of them)
+    int32_t *sg_cell;     // h
+    uint32_t *sg_cnt, *sg_start, *sg_cur;
+    int32_t *bnd_head;    // scratch slot of the member paired across the lower edge, or -1
+    int32_t *bnd_tail;    // ... across the upper edge, or -1
+    // per work item (DevFlags count[CHUNK_SLOT] of them)
+    int32_t *ch_owner;    // h
+    // per member, segment-major
+    int32_t *m_orig;      // storage slot
+    uint32_t *m_pid;
+    void *m_v;            // 3 components, stride m_stride
+    int64_t m_stride;
+    int64_t seg_max, chunk_max;
+};
+constexpr int SEG_SLOT = 6, CHUNK_SLOT = 7;    // DevFlags head/count slots
+size_t seg_scratch_bytes(int dtype, int64_t n, int32_t n_cells);
+// base: seg_scratch_bytes of tables; the member arrays (n entries each, v
+// 3 n of the dtype) are lent by the caller (free during the collide pass).
+void set_seg_scratch(int dtype, int64_t n, int32_t n_cells, void *base, int32_t *m_orig,
+                     uint32_t *m_pid, void *m_v);
+const SegScratch &seg_scratch();
+// Segment target (mean members) and capacity for a dtype.
+int seg_cap(int dtype);
+int seg_target(int dtype);
+
 // Sorted positions of the members [lo, lo+n) of one cell by (keys, pid):
 // bucket b = (key * nb) >> 32 is monotone in the key, so buckets in order and
 // (key, pid) order inside a bucket give the full order.  keys[lo..) must be
@@ -632,9 +673,11 @@ struct ClassCaps {
 // it), else left out.
 constexpr int LIST_DEFERRED = 5;
 constexpr int QUEUE_LISTS = 6;
+// With seg (nullable) the cells of the multi-workgroup list are also planned
+// into segments (see SegScratch; target members per segment).
 int launch_build_queue(const int32_t *cell_start, int32_t n_cells, const ClassCaps &caps,
                        int32_t *lists, DevFlags *flags, const uint8_t *skip, int visit,
-                       hipStream_t st);
+                       const SegScratch *seg, int seg_target, hipStream_t st);
 
 struct CollideArgs {
     void *v;               // SoA base
@@ -656,8 +699,11 @@ struct CollideArgs {
     int32_t *sorted_out, *partner_out;
 };
 
+// seg_path: the cells beyond the LDS classes were planned into segments by
+// the queue builder (only for steps without PIC_CONSERVE_FIX and PIC_MOMENTS).
 int launch_collide(int dtype, const CollideArgs &a, const int32_t *lists, int32_t n_cells,
-                   const ClassCaps &caps, int pairs_only, int num_cu, hipStream_t st);
+                   const ClassCaps &caps, int pairs_only, int num_cu, hipStream_t st,
+                   bool seg_path = false);
 // Null collisions of the deferred list: see k_deferred.
 int launch_deferred(int dtype, const CollideArgs &a, const int32_t *lists, int32_t n_cells,
                     int num_cu, hipStream_t st);

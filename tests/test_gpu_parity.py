@@ -188,6 +188,46 @@ def test_ragged_cells_all_classes(ctx, dtype):
     assert rel_err(vg, vr) < tol, rel_err(vg, vr)
 
 
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_large_cells_segmented(ctx, dtype):
+    """Cells beyond the largest LDS class are split into key segments sorted
+    by separate workgroups, with the pairs across segment edges done after;
+    the step equals the oracle's (sizes give several segments, odd and even
+    counts, and a cell beside them of each small kind)."""
+    sizes = [10241, 12800, 40000, 100003, 2, 0, 30001, 6145]
+    w = ragged_workload(11, sizes, np.float32 if dtype == "f32" else np.float64)
+    dens = np.linspace(0.7, 1.6, w.n_cells)
+    for step in (5, 6):
+        vg, cg, pg = run_gpu_step(ctx, w, w.v, dtype, step, density=dens, mcc=True)
+        vr, cr, pr = run_oracle_step(w, w.v.astype(np.float64), step, density=dens, mcc=True)
+        assert np.array_equal(cg, cr) and np.array_equal(pg, pr)
+        tol = FP32_TOL if dtype == "f32" else FP64_TOL
+        assert rel_err(vg, vr) < tol, (step, rel_err(vg, vr))
+
+
+def test_segmented_equals_one_workgroup_path(ctx):
+    """The same step through the segmented path and through the one-workgroup
+    path of the largest cells (taken when the pass also writes moment sums)
+    gives bitwise equal velocities: both apply the same rotation to the same
+    pairs and the same null collisions."""
+    import torch
+    from paper_2508_06771_amd import piccoll
+    w = ragged_workload(12, [10241, 25000, 77777, 4], np.float32)
+    ctx.set_mcc(w.sigma0, w.n_neutral, w.mass_ratio)
+    out = []
+    mom = torch.zeros(w.n_cells * 14, dtype=torch.float64, device="cuda")
+    for extra in (0, piccoll.MOMENTS):
+        tv, tc, tp = dev(w.v, torch.float32), dev(w.cell_of), dev(w.pid)
+        if extra:
+            ctx.set_moments_out(mom)
+        ctx.coulomb_collide(tv, tc, tp, w.n_cells, dt=w.dt, lnL=w.lnL, seed=4, step=2,
+                            flags=piccoll.FUSE_MCC | extra)
+        ctx.sync()
+        out.append(tv)
+    ctx.set_moments_out(None)
+    assert torch.equal(out[0], out[1])
+
+
 def test_conservation_correction_fp32(ctx):
     from paper_2508_06771_amd import piccoll
     w = workloads.c2(1, n_cells=32, per_cell=10000)
