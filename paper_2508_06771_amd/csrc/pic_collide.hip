@@ -1063,7 +1063,9 @@ template <typename R> struct Classes;
 template <> struct Classes<float> {
     static constexpr int T0 = 256, K0 = 2;    // <= 512
     static constexpr int T1 = 512, K1 = 4;    // <= 2048
-    static constexpr int T2 = 1024, K2 = 4;   // <= 4096
+    // 512 x 8 rather than 1024 x 4: two workgroups (74 KB of LDS each) are
+    // resident per CU, and one hides the other's latencies
+    static constexpr int T2 = 512, K2 = 8;    // <= 4096
     static constexpr int T3 = 1024, K3 = 10;  // <= 10240
 };
 template <> struct Classes<double> {
