@@ -201,6 +201,15 @@ int pic_mlp_train_step(pic_ctx *ctx, float *params, float *adam_m, float *adam_v
                        float lr, const float *x, const float *y, int32_t batch, int bf16,
                        float *loss);
 
+/* Stand-alone gate decision for features feat[8 n_cells] (layout of
+ * pic_features): prob = the network (bf16 as in pic_mlp_forward), then
+ * skip[j] = prob > threshold and k_acc[j] < k_max; k_acc[j] (deferred-step
+ * count, device, read and updated) becomes k_acc[j] + 1 for a skipped cell and
+ * 0 otherwise.  prob_out (device float[n_cells], nullable) receives the
+ * probabilities.  No judge and no dt scale: that is the PIC_GATE step. */
+int gate_infer(pic_ctx *ctx, const float *feat, int32_t n_cells, const float *params, float threshold,
+               int32_t k_max, int bf16, uint8_t *skip, int32_t *k_acc, float *prob_out);
+
 /* Enables PIC_GATE steps: params (device, kept by pointer), skip when the
  * probability exceeds threshold and the cell has deferred fewer than k_max
  * steps; on the steps that refresh the moment sums (pic_gate_refresh) a

@@ -530,6 +530,23 @@ int pic_mlp_forward(pic_ctx *c, const float *params, const float *x, int32_t bat
     return launch_mlp_forward(params, x, batch, bf16 != 0, prob, c->stream);
 }
 
+int gate_infer(pic_ctx *c, const float *feat, int32_t n_cells, const float *params, float threshold,
+               int32_t k_max, int bf16, uint8_t *skip, int32_t *k_acc, float *prob_out)
+{
+    if (!c || n_cells < 0 || k_max < 0 || !(threshold >= 0.0f) ||
+        (n_cells > 0 && (!feat || !params || !skip || !k_acc)))
+        return PIC_ERR_ARG;
+    if (n_cells == 0) return PIC_OK;
+    CK(hipSetDevice(c->device));
+    float *prob = prob_out;
+    if (!prob) {
+        RC(ensure_ws(c, (size_t)n_cells * 4 + 256));
+        prob = (float *)c->ws;
+    }
+    RC(launch_mlp_forward(params, feat, n_cells, bf16 != 0, prob, c->stream));
+    return launch_gate_infer_decide(prob, n_cells, threshold, k_max, skip, k_acc, c->stream);
+}
+
 int pic_mlp_grad(pic_ctx *c, const float *params, const float *x, const float *y, int32_t batch,
                  int bf16, float *grad, float *loss)
 {

@@ -865,6 +865,29 @@ int launch_features(const double *moments, int32_t M, float *feat, uint8_t *vali
     return PIC_OK;
 }
 
+namespace {
+// skip = p > thr and fewer than kmax deferred steps; the count follows.
+__global__ void k_gate_infer_decide(const float *__restrict__ prob, int32_t M, float thr, int32_t kmax,
+                                    uint8_t *__restrict__ skip, int32_t *__restrict__ k_acc)
+{
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < M; j += gridDim.x * blockDim.x) {
+        const bool s = prob[j] > thr && k_acc[j] < kmax;
+        skip[j] = s;
+        k_acc[j] = s ? k_acc[j] + 1 : 0;
+    }
+}
+}  // namespace
+
+int launch_gate_infer_decide(const float *prob, int32_t M, float thr, int32_t kmax, uint8_t *skip,
+                             int32_t *k_acc, hipStream_t st)
+{
+    if (M <= 0) return PIC_OK;
+    const int g = (M + 255) / 256 < 4096 ? (M + 255) / 256 : 4096;
+    hipLaunchKernelGGL(k_gate_infer_decide, dim3(g), dim3(256), 0, st, prob, M, thr, kmax, skip, k_acc);
+    HIP_OK(hipGetLastError());
+    return PIC_OK;
+}
+
 int launch_mlp_forward(const float *params, const float *x, int32_t B, int bf16, float *prob,
                        hipStream_t st)
 {

@@ -771,6 +771,8 @@ size_t relax_part_bytes(int64_t count, int replicas);
 int launch_features(const double *moments, int32_t M, float *feat, uint8_t *valid, hipStream_t st);
 int launch_mlp_forward(const float *params, const float *x, int32_t B, int bf16, float *prob,
                        hipStream_t st);
+int launch_gate_infer_decide(const float *prob, int32_t M, float thr, int32_t kmax, uint8_t *skip,
+                             int32_t *k_acc, hipStream_t st);
 size_t mlp_grad_scratch_floats(int32_t B);
 int launch_mlp_grad(const float *params, const float *x, const float *y, int32_t B, int bf16,
                     float *scratch, float *grad, float *loss, hipStream_t st);

@@ -70,6 +70,7 @@ def _load():
         "pic_gate_state": ([vp, vp, vp, vp, vp], C.c_int),
         "pic_conserve_reset": ([vp], C.c_int),
         "pic_gate_refresh": ([vp, i32], C.c_int),
+        "gate_infer": ([vp, vp, i32, vp, C.c_float, i32, C.c_int, vp, vp, vp], C.c_int),
         "pic_autotune": ([vp, C.c_int, vp, vp, vp, i64, i32, f64, f64, u32, vp], C.c_int),
         "pic_time_kernels": ([vp, C.c_int], C.c_int),
         "pic_kernel_times": ([vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)], C.c_int),
@@ -88,7 +89,8 @@ EXPORTED = ["pic_create", "pic_destroy", "pic_strerror", "pic_sync", "pic_set_st
             "mcc_null_collide", "pic_philox", "coulomb_pairs", "pic_cell_moments", "pic_unsort",
             "pic_time_kernels", "pic_kernel_times", "pic_run_steps", "pic_features",
             "pic_relaxation", "pic_mlp_forward", "pic_mlp_grad", "pic_mlp_train_step",
-            "pic_gate_config", "pic_gate_reset", "pic_gate_stats", "pic_gate_state", "pic_autotune", "pic_conserve_reset", "pic_gate_refresh"]
+            "pic_gate_config", "pic_gate_reset", "pic_gate_stats", "pic_gate_state", "pic_autotune",
+            "pic_conserve_reset", "pic_gate_refresh", "gate_infer"]
 
 MLP_PARAMS = 4801
 GATE_STATS = ["steps", "skipped", "collided", "judged", "judged_want", "false_skip", "disabled",
@@ -231,6 +233,18 @@ class Context:
         _chk(lib.pic_mlp_forward(self._h, _p(params), _p(x), x.shape[0], int(bf16), _p(prob)),
              "pic_mlp_forward")
         return prob
+
+    def gate_infer(self, feat: torch.Tensor, params: torch.Tensor, threshold: float, k_max: int,
+                   k_acc: torch.Tensor, bf16: bool = True):
+        """(skip uint8, prob float32); k_acc (int32, device) is updated in place."""
+        self._stream()
+        assert k_acc.dtype == torch.int32 and feat.dtype == torch.float32
+        n = feat.shape[0]
+        skip = torch.empty(n, dtype=torch.uint8, device=feat.device)
+        prob = torch.empty(n, dtype=torch.float32, device=feat.device)
+        _chk(lib.gate_infer(self._h, _p(feat), n, _p(params), threshold, k_max, int(bf16), _p(skip),
+                            _p(k_acc), _p(prob)), "gate_infer")
+        return skip, prob
 
     def mlp_grad(self, params, x, y, bf16: bool = True):
         self._stream()

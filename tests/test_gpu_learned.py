@@ -112,6 +112,38 @@ def test_mlp_forward_and_grad(ctx):
     assert abs(float(host(loss16)[0]) - l16) < 1e-2 * abs(l16)
 
 
+def test_gate_infer(ctx):
+    """Stand-alone decision: probabilities are the network's (binary32 mode
+    against the oracle's FP64 forward of the same inputs), and skip / the
+    deferred counts follow the rule exactly from the kernel's own
+    probabilities over three calls (so k_max is reached)."""
+    import torch
+    rng = np.random.default_rng(5)
+    flat = rand_params(2)
+    flat[-1] = 1.5    # output bias: most cells want to skip
+    x = rng.standard_normal((777, 8))
+    tp = dev(flat.astype(np.float32))
+    tx = dev(x.astype(np.float32))
+    k = torch.zeros(777, dtype=torch.int32, device="cuda")
+    k_ref = np.zeros(777, np.int64)
+    thr, kmax = 0.6, 2
+    pr, _ = physics.mlp_forward(physics.unpack_params(flat.astype(np.float32).astype(np.float64)),
+                                x.astype(np.float32).astype(np.float64))
+    sums = []
+    for call in range(3):
+        skip, prob = ctx.gate_infer(tx, tp, thr, kmax, k, bf16=False)
+        ctx.sync()
+        skip, prob, kk = host(skip).astype(bool), host(prob), host(k)
+        assert np.allclose(prob, pr, rtol=1e-5, atol=1e-6)
+        want = (prob > thr) & (k_ref < kmax)
+        assert np.array_equal(skip, want), call
+        k_ref = np.where(want, k_ref + 1, 0)
+        assert np.array_equal(kk, k_ref), call
+        sums.append(int(want.sum()))
+    # cells that want to skip do so twice, then collide once (k_max = 2)
+    assert 0 < sums[0] < 777 and sums[1] == sums[0] and sums[2] == 0
+
+
 def test_adam_train_step(ctx):
     import torch
     rng = np.random.default_rng(3)
