@@ -1075,6 +1075,17 @@ template <> struct Classes<double> {
     static constexpr int T3 = 1024, K3 = 6;   // <= 6144
 };
 
+// Workgroup geometry of one segment of the segmented path: the largest
+// class's (segments of 2,560 members on two 512-thread workgroups per CU
+// were slower: more segments, histograms and edge pairs).
+template <typename R> struct SegGeom;
+template <> struct SegGeom<float> {
+    static constexpr int T = 1024, K = 10, PER_CU = 1;
+};
+template <> struct SegGeom<double> {
+    static constexpr int T = 1024, K = 6, PER_CU = 1;
+};
+
 template <typename R, int T, int K, int F>
 int launch_class(const CollideArgs &a, const int32_t *list, int cls, int blocks, hipStream_t st)
 {
@@ -1128,10 +1139,11 @@ int launch_all(const CollideArgs &a, const int32_t *lists, int32_t n_cells, int 
     if (SEG_OK && seg_path) {
         const SegScratch &ss = g_seg;
         hipLaunchKernelGGL(k_seg_count, dim3(num_cu * 4), dim3(SEG_CT), 0, st, a, l4, ss);
-        hipLaunchKernelGGL(k_seg_scan, dim3(1), dim3(1024), 0, st, a, ss, (uint32_t)(C::T3 * C::K3));
+        typedef SegGeom<R> G;
+        hipLaunchKernelGGL(k_seg_scan, dim3(1), dim3(1024), 0, st, a, ss, (uint32_t)(G::T * G::K));
         hipLaunchKernelGGL(k_seg_scatter<R>, dim3(num_cu * 4), dim3(SEG_CT), 0, st, a, l4, ss);
         HIP_OK(hipGetLastError());
-        if ((rc = launch_seg_collide<R, C::T3, C::K3, F>(a, l4, ss, bp[3] * num_cu, st))) return rc;
+        if ((rc = launch_seg_collide<R, G::T, G::K, F>(a, l4, ss, G::PER_CU * num_cu, st))) return rc;
         hipLaunchKernelGGL(k_seg_fixup<R>, dim3(num_cu), dim3(256), 0, st, a, l4, ss);
         // cells the plan could not segment
         hipLaunchKernelGGL((k_collide_huge<R, PAIRS>), dim3(num_cu * bp[4]), dim3(1024), 0, st, a, l4, 4,
@@ -1250,8 +1262,8 @@ const SegScratch &seg_scratch() { return g_seg; }
 
 int seg_cap(int dtype)
 {
-    return dtype == PIC_F32 ? Classes<float>::T3 * Classes<float>::K3
-                            : Classes<double>::T3 * Classes<double>::K3;
+    return dtype == PIC_F32 ? SegGeom<float>::T * SegGeom<float>::K
+                            : SegGeom<double>::T * SegGeom<double>::K;
 }
 
 int seg_target(int dtype)

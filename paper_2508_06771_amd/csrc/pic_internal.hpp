@@ -519,8 +519,8 @@ const HugeScratch &huge_scratch();
 // Multi-workgroup path for cells beyond the largest LDS class.  A cell's
 // members are split into S = 2^lS segments by the top lS bits of their sort
 // key; since the order is by key first, the cell's sorted order is the
-// segments' sorted orders one after another.  Each segment (at most
-// SEG_CAP members) is sorted and paired in LDS by its own workgroup at its
+// segments' sorted orders one after another.  Each segment (at most the
+// segment capacity, seg_cap) is sorted and paired in LDS by its own workgroup at its
 // global offset in the cell; the pair that straddles two segments (when a
 // segment starts at an odd position) is done by a fix-up pass.  Members are
 // first copied segment-major into the scratch below.
