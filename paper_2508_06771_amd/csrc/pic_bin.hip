@@ -281,25 +281,23 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(RadixPass p,
 // (seed, step, pid), so processing order never changes results.  Cells the
 // gate defers go to the deferred list when they still need a visit.
 // Segment plan of cell h of the multi-workgroup list with cnt members:
-// S = 2^lS segments of about `target` members, their table entries, and the
-// counting work items.  Segment and item ranges are reserved with atomics:
+// S = ceil(cnt / target) segments (equal key ranges), their table entries,
+// and the counting work items.  Segment and item ranges are reserved with atomics:
 // where a cell's entries sit never changes results.
 __device__ void plan_segments(const SegScratch &ss, DevFlags *f, int h, int32_t cnt, int target)
 {
     const int64_t want = ((int64_t)cnt + target - 1) / target;
-    int lS = 0;
-    while (((int64_t)1 << lS) < want) ++lS;
-    if (lS > SEG_MAX_LOG2) {
+    if (want > SEG_MAX) {
         ss.hc_fb[h] = 1;
-        ss.hc_lS[h] = 0;
+        ss.hc_S[h] = 0;
         return;
     }
-    const uint32_t S = 1u << lS;
+    const uint32_t S = want > 0 ? (uint32_t)want : 1u;
     const uint32_t nch = (uint32_t)(((int64_t)cnt + SEG_CHUNK - 1) / SEG_CHUNK);
     const uint32_t sb = atomicAdd(&f->count[SEG_SLOT], S);
     const uint32_t cb = atomicAdd(&f->count[CHUNK_SLOT], nch);
     ss.hc_fb[h] = 0;
-    ss.hc_lS[h] = (uint8_t)lS;
+    ss.hc_S[h] = S;
     ss.hc_seg[h] = (int32_t)sb;
     ss.hc_chunk[h] = (int32_t)cb;
     for (uint32_t q = 0; q < S; ++q) {

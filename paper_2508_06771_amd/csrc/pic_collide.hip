@@ -649,14 +649,20 @@ __global__ __launch_bounds__(1024) void k_collide_huge(CollideArgs a, const int3
 // sort and pair each segment in LDS, then the pairs across segment edges.
 constexpr int SEG_CT = 256;   // threads of the counting and copying kernels
 
-__device__ __forceinline__ uint32_t seg_of(uint32_t key, uint32_t lS)
+// Segment of a key among S equal key ranges, and the key's position inside
+// its range scaled to 32 bits (order-preserving within the segment).
+__device__ __forceinline__ uint32_t seg_of(uint32_t key, uint32_t S)
 {
-    return lS ? key >> (32u - lS) : 0u;
+    return (uint32_t)(((uint64_t)key * S) >> 32);
+}
+__device__ __forceinline__ uint32_t seg_key(uint32_t key, uint32_t S)
+{
+    return (uint32_t)((uint64_t)key * S);
 }
 
 struct SegItem {
     int h, lo, b, e;
-    uint32_t lS;
+    uint32_t S;
 };
 
 // Work item -> its cell h of the list, the cell's first slot and the item's
@@ -671,7 +677,7 @@ __device__ __forceinline__ SegItem seg_item(const CollideArgs &a, const SegScrat
     const int n = a.cell_start[cell + 1] - it.lo;
     it.b = (int)(item - (uint32_t)ss.hc_chunk[it.h]) * SEG_CHUNK;
     it.e = min(n, it.b + SEG_CHUNK);
-    it.lS = ss.hc_lS[it.h];
+    it.S = ss.hc_S[it.h];
     return it;
 }
 
@@ -680,18 +686,18 @@ __device__ __forceinline__ SegItem seg_item(const CollideArgs &a, const SegScrat
 __global__ __launch_bounds__(SEG_CT) void k_seg_count(CollideArgs a, const int32_t *__restrict__ list,
                                                       SegScratch ss)
 {
-    __shared__ uint32_t hist[1 << SEG_MAX_LOG2];
+    __shared__ uint32_t hist[SEG_MAX];
     if (gated_off(a)) return;
     const uint32_t items = a.dflags->count[CHUNK_SLOT];
     const uint32_t step = (uint32_t)read_step(a);
     for (uint32_t item = blockIdx.x; item < items; item += gridDim.x) {
         const SegItem it = seg_item(a, ss, list, item);
-        const uint32_t S = 1u << it.lS;
+        const uint32_t S = it.S;
         for (uint32_t q = threadIdx.x; q < S; q += SEG_CT) hist[q] = 0u;
         __syncthreads();
         for (int i = it.b + (int)threadIdx.x; i < it.e; i += SEG_CT) {
             const uint32_t key = draw4(a.seed, a.pid[it.lo + i], step, 0u, 0u).x;
-            atomicAdd(&hist[seg_of(key, it.lS)], 1u);
+            atomicAdd(&hist[seg_of(key, S)], 1u);
         }
         __syncthreads();
         const int32_t sb = ss.hc_seg[it.h];
@@ -735,8 +741,8 @@ template <typename R>
 __global__ __launch_bounds__(SEG_CT) void k_seg_scatter(CollideArgs a, const int32_t *__restrict__ list,
                                                         SegScratch ss)
 {
-    __shared__ uint32_t hist[1 << SEG_MAX_LOG2];
-    __shared__ uint32_t base[1 << SEG_MAX_LOG2];
+    __shared__ uint32_t hist[SEG_MAX];
+    __shared__ uint32_t base[SEG_MAX];
     __shared__ uint16_t sof[SEG_CHUNK];
     if (gated_off(a)) return;
     const uint32_t items = a.dflags->count[CHUNK_SLOT];
@@ -746,12 +752,12 @@ __global__ __launch_bounds__(SEG_CT) void k_seg_scatter(CollideArgs a, const int
     for (uint32_t item = blockIdx.x; item < items; item += gridDim.x) {
         const SegItem it = seg_item(a, ss, list, item);
         if (ss.hc_fb[it.h]) continue;   // the same for the whole workgroup
-        const uint32_t S = 1u << it.lS;
+        const uint32_t S = it.S;
         for (uint32_t q = threadIdx.x; q < S; q += SEG_CT) hist[q] = 0u;
         __syncthreads();
         for (int i = it.b + (int)threadIdx.x; i < it.e; i += SEG_CT) {
             const uint32_t key = draw4(a.seed, a.pid[it.lo + i], step, 0u, 0u).x;
-            const uint32_t q = seg_of(key, it.lS);
+            const uint32_t q = seg_of(key, S);
             sof[i - it.b] = (uint16_t)q;
             atomicAdd(&hist[q], 1u);
         }
@@ -776,8 +782,9 @@ __global__ __launch_bounds__(SEG_CT) void k_seg_scatter(CollideArgs a, const int
     }
 }
 
-// One segment: the members of run [start, start + n) sort by key (their top
-// lS bits are the segment's, so the bits below bucket them) and pid; local
+// One segment: the members of run [start, start + n) sort by key (by their
+// position inside the segment's key range, scaled to 32 bits, whose top bits
+// bucket them) and pid; local
 // position q is position off + q of the cell.  The cell's pairs (2i, 2i + 1)
 // inside the segment collide here as in the cell pass; a member whose
 // partner lies in a neighbouring segment is recorded for k_seg_fixup and left
@@ -799,7 +806,7 @@ __device__ void seg_pass(const CollideArgs &a, const int32_t *list, const SegScr
     const uint32_t n_c = (uint32_t)(a.cell_start[cell + 1] - lo_c);
     const uint32_t start = ss.sg_start[seg];
     const uint32_t off = start - ss.sg_start[ss.hc_seg[h]];
-    const uint32_t lS = ss.hc_lS[h];
+    const uint32_t S = ss.hc_S[h];
     const uint32_t step = (uint32_t)read_step(a);
     const R *mx = (const R *)ss.m_v + start;
     const R *my = mx + ss.m_stride;
@@ -835,7 +842,7 @@ __device__ void seg_pass(const CollideArgs &a, const int32_t *list, const SegScr
             w2[k] = w.z;
             w3[k] = w.w;
             if (MCC && (uint64_t)w.y < a.mcc_thr) cand |= 1u << k;
-            pos[k] = L.count(i, w.x << lS, bits);
+            pos[k] = L.count(i, seg_key(w.x, S), bits);
         }
     }
     __syncthreads();
@@ -1268,13 +1275,13 @@ int seg_cap(int dtype)
 
 int seg_target(int dtype)
 {
-    return seg_cap(dtype) * 5 / 8;
+    return seg_cap(dtype) * 7 / 8;
 }
 
 static int64_t seg_max_for(int dtype, int64_t n, int32_t n_cells)
 {
-    // S <= 2 ceil(n_c / target) per cell
-    return 2 * (n / seg_target(dtype) + n_cells) + 2;
+    // S = ceil(n_c / target) <= n_c / target + 1 per cell
+    return n / seg_target(dtype) + n_cells + 2;
 }
 
 static int64_t chunk_max_for(int64_t n, int32_t n_cells)
@@ -1285,7 +1292,7 @@ static int64_t chunk_max_for(int64_t n, int32_t n_cells)
 size_t seg_scratch_bytes(int dtype, int64_t n, int32_t n_cells)
 {
     const size_t S = (size_t)seg_max_for(dtype, n, n_cells), Q = (size_t)chunk_max_for(n, n_cells);
-    return (size_t)n_cells * (1 + 1 + 4 + 4) + S * 6 * 4 + Q * 4 + 11 * 256;   // 11 aligned parts
+    return (size_t)n_cells * (4 + 1 + 4 + 4) + S * 6 * 4 + Q * 4 + 11 * 256;   // 11 aligned parts
 }
 
 void set_seg_scratch(int dtype, int64_t n, int32_t n_cells, void *base, int32_t *m_orig,
@@ -1298,7 +1305,7 @@ void set_seg_scratch(int dtype, int64_t n, int32_t n_cells, void *base, int32_t 
         return (void *)r;
     };
     const int64_t S = seg_max_for(dtype, n, n_cells), Q = chunk_max_for(n, n_cells);
-    g_seg.hc_lS = (uint8_t *)take((size_t)n_cells);
+    g_seg.hc_S = (uint32_t *)take((size_t)n_cells * 4);
     g_seg.hc_fb = (uint8_t *)take((size_t)n_cells);
     g_seg.hc_seg = (int32_t *)take((size_t)n_cells * 4);
     g_seg.hc_chunk = (int32_t *)take((size_t)n_cells * 4);

@@ -517,18 +517,19 @@ struct HugeScratch {
 const HugeScratch &huge_scratch();
 
 // Multi-workgroup path for cells beyond the largest LDS class.  A cell's
-// members are split into S = 2^lS segments by the top lS bits of their sort
-// key; since the order is by key first, the cell's sorted order is the
-// segments' sorted orders one after another.  Each segment (at most the
+// members are split into S segments by their sort key: segment
+// floor(key S / 2^32), an equal split of the key range.  Since the order is
+// by key first, the cell's sorted order is the segments' sorted orders one
+// after another.  Each segment (at most the
 // segment capacity, seg_cap) is sorted and paired in LDS by its own workgroup at its
 // global offset in the cell; the pair that straddles two segments (when a
 // segment starts at an odd position) is done by a fix-up pass.  Members are
 // first copied segment-major into the scratch below.
 constexpr int SEG_CHUNK = 8192;        // members per counting / scatter work item
-constexpr int SEG_MAX_LOG2 = 12;       // at most 4096 segments per cell
+constexpr int SEG_MAX = 4096;          // at most this many segments per cell
 struct SegScratch {
     // per cell of the multi-workgroup list (index h into that list)
-    uint8_t *hc_lS;       // log2 of the segment count
+    uint32_t *hc_S;       // segment count
     uint8_t *hc_fb;       // 1: cell takes the one-workgroup path instead
     int32_t *hc_seg;      // first segment of the cell
     int32_t *hc_chunk;    // first work item of the cell
