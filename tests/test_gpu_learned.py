@@ -284,3 +284,83 @@ def test_gate_switches_off_on_false_skips(ctx):
     before = st["collided"]
     ctx.coulomb_collide(tv, tc, tp, w.n_cells, dt=w.dt, lnL=w.lnL, seed=3, step=3, flags=piccoll.GATE)
     assert ctx.gate_stats()["collided"] - before == w.n_cells
+
+
+def _tpar_over_tperp(v, cs):
+    """Per-cell T_par / T_perp (z parallel) of storage in cell order, FP64."""
+    v = v.astype(np.float64)
+    N = np.diff(cs).astype(np.float64)
+    s1 = np.add.reduceat(v, cs[:-1], axis=1) / N
+    s2 = np.add.reduceat(v * v, cs[:-1], axis=1) / N
+    T = s2 - s1 * s1
+    return T[2] / (0.5 * (T[0] + T[1]))
+
+
+def test_trained_gate_gains_over_plain(ctx, tmp_path):
+    """What the trained network gains over the plain operator.  A gate is
+    trained here on the GPU by the library's own kernels (the trainer's
+    default trajectories of the Maxwellian + beam workload), then the same 24
+    steps run from the same mixed-cell state (32,768 cells x 2,000 electrons:
+    70% near-Maxwellian, 15% Maxwellian + beam, 15% anisotropic) plainly and
+    gated, as graph replays: the gate defers a large share of the cell-steps
+    and the gated steps take less wall time, with an energy drift no worse than
+    plain's and the anisotropic cells' T_par / T_perp relaxing as in the plain
+    run to within 3% of the relaxation itself."""
+    import json
+    import torch
+    from paper_2508_06771_amd import piccoll, train_gate
+    out = tmp_path / "gate.npy"
+    train_gate.main(["--out", str(out)])
+    params = dev(np.load(out))
+    meta = json.load(open(tmp_path / "gate.json"))
+    w = workloads.c5(3, n_cells=32768)
+    K = 24
+    res = {}
+    try:
+        for mode in ("plain", "gated"):
+            v, c, p = dev(w.v, torch.float32), dev(w.cell_of), dev(w.pid)
+            fl = 0
+            if mode == "gated":
+                ctx.gate_config(params, meta["threshold"], k_max=8, judge_fraction=0.01,
+                                tolerance=meta["tolerance"], replicas=8, bf16=True)
+                ctx.gate_refresh(4)
+                ctx.gate_reset()
+                fl = piccoll.GATE
+            ctx.coulomb_collide(v, c, p, w.n_cells, dt=w.dt, lnL=w.lnL, seed=0, step=0, flags=fl)
+            ctx.sync()
+            cs = np.concatenate([[0], np.cumsum(np.bincount(host(c), minlength=w.n_cells))])
+            v0 = host(v)
+            # warm the graph, then time K replays from the same state
+            st0 = ctx.gate_stats() if mode == "gated" else None
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            ctx.run_steps(v, c, p, w.n_cells, dt=w.dt, lnL=w.lnL, seed=0, step0=1, nsteps=K,
+                          flags=fl | piccoll.ASSUME_SORTED)
+            e1.record()
+            ctx.sync()
+            torch.cuda.synchronize()
+            v1 = host(v)
+            en0 = (v0.astype(np.float64) ** 2).sum()
+            res[mode] = {
+                "ms": e0.elapsed_time(e1) / K,
+                "drift": abs((v1.astype(np.float64) ** 2).sum() - en0) / en0,
+                "r0": _tpar_over_tperp(v0, cs), "r1": _tpar_over_tperp(v1, cs),
+                "stats": ctx.gate_stats() if mode == "gated" else None,
+                "stats0": st0,
+            }
+    finally:
+        ctx.gate_refresh(1)
+    g, pl = res["gated"], res["plain"]
+    st, s0 = g["stats"], g["stats0"]
+    sk = st["skipped"] - s0["skipped"]
+    skipped = sk / (sk + st["collided"] - s0["collided"])
+    print("trained gate:", meta, "skipped", skipped, "ms/step gated", g["ms"], "plain", pl["ms"],
+          "drift", g["drift"], pl["drift"], flush=True)
+    assert st["disabled"] == 0
+    assert skipped > 0.2, skipped
+    assert g["ms"] < 0.95 * pl["ms"], (g["ms"], pl["ms"])
+    assert g["drift"] <= max(2.0 * pl["drift"], 1e-6), (g["drift"], pl["drift"])
+    aniso = w.meta["kind"] == 2
+    relax = np.abs(pl["r1"] - pl["r0"])[aniso].mean()
+    diff = np.abs(g["r1"] - pl["r1"])[aniso].mean()
+    assert diff < 0.03 * relax, (diff, relax)
