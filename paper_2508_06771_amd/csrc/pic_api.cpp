@@ -644,6 +644,9 @@ struct StepArgs {
     const double *density;
     uint64_t seed, step;
     uint32_t flags;
+    // bit c: list c (size classes 0..3, 4 = beyond them) may hold cells; a
+    // caller that knows the cell sizes clears the empty ones
+    uint32_t live = ~0u;
 };
 
 static size_t step_ws_bytes(const pic_ctx *c, const StepArgs &s)
@@ -821,7 +824,7 @@ static int step_enqueue(pic_ctx *c, const StepArgs &s, hipStream_t st, const uin
             ktime_end(KT_DEFER, st);
         }
     }
-    RC(launch_collide(dtype, a, lists, n_cells, caps, 0, c->num_cu, st, seg_path));
+    RC(launch_collide(dtype, a, lists, n_cells, caps, 0, c->num_cu, st, seg_path, s.live));
     if (gate) {
         // the sums the next decision reads: post-step state, on refresh steps
         ktime_begin(KT_MOMENTS, st);
@@ -867,6 +870,23 @@ int pic_run_steps(pic_ctx *c, int dtype, void *v, int32_t *cell_of, uint32_t *pi
     // changes cell membership): capture one such step once and replay it.
     s.flags |= PIC_ASSUME_SORTED;
     s.step = 0;
+    // the cell sizes are fixed for these steps: size classes without cells
+    // get no launches (the first step left cell_start at the workspace start)
+    {
+        std::vector<int32_t> hcs((size_t)n_cells + 1);
+        CK(hipMemcpyAsync(hcs.data(), c->ws, hcs.size() * 4, hipMemcpyDeviceToHost, c->stream));
+        CK(hipStreamSynchronize(c->stream));
+        const ClassCaps caps = c->tuned_valid[dtype] ? c->tuned[dtype] : collide_caps(dtype, c->lds_max);
+        uint32_t live = 0;
+        for (int32_t j = 0; j < n_cells; ++j) {
+            const int32_t cnt = hcs[j + 1] - hcs[j];
+            int cls = caps.ncls;
+            for (int q = caps.ncls - 1; q >= 0; --q)
+                if (cnt <= caps.cap[q]) cls = q;
+            live |= 1u << (cls < caps.ncls ? cls : 4);
+        }
+        s.live = live;
+    }
     unsigned char key[256];
     size_t kl = 0;
     auto put = [&](const void *p, size_t bytes) {

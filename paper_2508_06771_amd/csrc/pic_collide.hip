@@ -1132,7 +1132,8 @@ int launch_seg_collide(const CollideArgs &a, const int32_t *list, const SegScrat
 
 template <typename R, int F>
 int launch_all(const CollideArgs &a, const int32_t *lists, int32_t n_cells, int num_cu,
-               const HugeScratch &hs, const ClassCaps &caps, bool seg_path, hipStream_t st)
+               const HugeScratch &hs, const ClassCaps &caps, bool seg_path, uint32_t live,
+               hipStream_t st)
 {
     typedef Classes<R> C;
     constexpr bool PAIRS = (F & F_PAIRS) != 0;
@@ -1143,7 +1144,9 @@ int launch_all(const CollideArgs &a, const int32_t *lists, int32_t n_cells, int 
     const int32_t *l4 = lists + 4 * M;
     // largest cells first so the small ones fill the tail
     ktime_begin(KT_HUGE, st);
-    if (SEG_OK && seg_path) {
+    if (!(live & (1u << 4))) {
+        // no cell beyond the LDS classes
+    } else if (SEG_OK && seg_path) {
         const SegScratch &ss = g_seg;
         hipLaunchKernelGGL(k_seg_count, dim3(num_cu * 4), dim3(SEG_CT), 0, st, a, l4, ss);
         typedef SegGeom<R> G;
@@ -1161,10 +1164,18 @@ int launch_all(const CollideArgs &a, const int32_t *lists, int32_t n_cells, int 
     }
     ktime_end(KT_HUGE, st);
     HIP_OK(hipGetLastError());
-    if ((rc = launch_class<R, C::T3, C::K3, F>(a, lists + 3 * M, 3, bp[3] * num_cu, st))) return rc;
-    if ((rc = launch_class<R, C::T2, C::K2, F>(a, lists + 2 * M, 2, bp[2] * num_cu, st))) return rc;
-    if ((rc = launch_class<R, C::T1, C::K1, F>(a, lists + 1 * M, 1, bp[1] * num_cu, st))) return rc;
-    if ((rc = launch_class<R, C::T0, C::K0, F>(a, lists + 0 * M, 0, bp[0] * num_cu, st))) return rc;
+    if ((live & (1u << 3)) &&
+        (rc = launch_class<R, C::T3, C::K3, F>(a, lists + 3 * M, 3, bp[3] * num_cu, st)))
+        return rc;
+    if ((live & (1u << 2)) &&
+        (rc = launch_class<R, C::T2, C::K2, F>(a, lists + 2 * M, 2, bp[2] * num_cu, st)))
+        return rc;
+    if ((live & (1u << 1)) &&
+        (rc = launch_class<R, C::T1, C::K1, F>(a, lists + 1 * M, 1, bp[1] * num_cu, st)))
+        return rc;
+    if ((live & (1u << 0)) &&
+        (rc = launch_class<R, C::T0, C::K0, F>(a, lists + 0 * M, 0, bp[0] * num_cu, st)))
+        return rc;
     return PIC_OK;
 }
 
@@ -1181,20 +1192,21 @@ int launch_deferred_t(const CollideArgs &a, const int32_t *lists, int32_t n_cell
 
 template <typename R>
 int launch_flags(const CollideArgs &a, const int32_t *lists, int32_t n_cells, int num_cu,
-                 const HugeScratch &hs, const ClassCaps &cc, int pairs_only, bool sp, hipStream_t st)
+                 const HugeScratch &hs, const ClassCaps &cc, int pairs_only, bool sp, uint32_t lv,
+                 hipStream_t st)
 {
-    if (pairs_only) return launch_all<R, F_PAIRS>(a, lists, n_cells, num_cu, hs, cc, false, st);
+    if (pairs_only) return launch_all<R, F_PAIRS>(a, lists, n_cells, num_cu, hs, cc, false, ~0u, st);
     const int f = (a.mcc_thr ? F_MCC : 0) | ((a.flags & PIC_CONSERVE_FIX) ? F_CONS : 0) |
                   ((a.flags & PIC_MOMENTS) ? F_MOM : 0);
     switch (f) {
-    case 0: return launch_all<R, 0>(a, lists, n_cells, num_cu, hs, cc, sp, st);
-    case 1: return launch_all<R, 1>(a, lists, n_cells, num_cu, hs, cc, sp, st);
-    case 2: return launch_all<R, 2>(a, lists, n_cells, num_cu, hs, cc, sp, st);
-    case 3: return launch_all<R, 3>(a, lists, n_cells, num_cu, hs, cc, sp, st);
-    case 4: return launch_all<R, 4>(a, lists, n_cells, num_cu, hs, cc, sp, st);
-    case 5: return launch_all<R, 5>(a, lists, n_cells, num_cu, hs, cc, sp, st);
-    case 6: return launch_all<R, 6>(a, lists, n_cells, num_cu, hs, cc, sp, st);
-    default: return launch_all<R, 7>(a, lists, n_cells, num_cu, hs, cc, sp, st);
+    case 0: return launch_all<R, 0>(a, lists, n_cells, num_cu, hs, cc, sp, lv, st);
+    case 1: return launch_all<R, 1>(a, lists, n_cells, num_cu, hs, cc, sp, lv, st);
+    case 2: return launch_all<R, 2>(a, lists, n_cells, num_cu, hs, cc, sp, lv, st);
+    case 3: return launch_all<R, 3>(a, lists, n_cells, num_cu, hs, cc, sp, lv, st);
+    case 4: return launch_all<R, 4>(a, lists, n_cells, num_cu, hs, cc, sp, lv, st);
+    case 5: return launch_all<R, 5>(a, lists, n_cells, num_cu, hs, cc, sp, lv, st);
+    case 6: return launch_all<R, 6>(a, lists, n_cells, num_cu, hs, cc, sp, lv, st);
+    default: return launch_all<R, 7>(a, lists, n_cells, num_cu, hs, cc, sp, lv, st);
     }
 }
 
@@ -1258,11 +1270,12 @@ void set_huge_scratch(int dtype, int64_t n, void *base)
 }
 
 int launch_collide(int dtype, const CollideArgs &a, const int32_t *lists, int32_t n_cells,
-                   const ClassCaps &cc, int pairs_only, int num_cu, hipStream_t st, bool seg_path)
+                   const ClassCaps &cc, int pairs_only, int num_cu, hipStream_t st, bool seg_path,
+                   uint32_t live)
 {
     if (dtype == PIC_F32)
-        return launch_flags<float>(a, lists, n_cells, num_cu, g_huge, cc, pairs_only, seg_path, st);
-    return launch_flags<double>(a, lists, n_cells, num_cu, g_huge, cc, pairs_only, seg_path, st);
+        return launch_flags<float>(a, lists, n_cells, num_cu, g_huge, cc, pairs_only, seg_path, live, st);
+    return launch_flags<double>(a, lists, n_cells, num_cu, g_huge, cc, pairs_only, seg_path, live, st);
 }
 
 const SegScratch &seg_scratch() { return g_seg; }

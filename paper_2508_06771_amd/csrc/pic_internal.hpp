@@ -702,9 +702,11 @@ struct CollideArgs {
 
 // seg_path: the cells beyond the LDS classes were planned into segments by
 // the queue builder (only for steps without PIC_CONSERVE_FIX and PIC_MOMENTS).
+// live: bit c (classes 0..3, 4 = beyond the LDS classes) clear when the
+// caller knows that list is empty; its kernels are then not launched.
 int launch_collide(int dtype, const CollideArgs &a, const int32_t *lists, int32_t n_cells,
                    const ClassCaps &caps, int pairs_only, int num_cu, hipStream_t st,
-                   bool seg_path = false);
+                   bool seg_path = false, uint32_t live = ~0u);
 // Null collisions of the deferred list: see k_deferred.
 int launch_deferred(int dtype, const CollideArgs &a, const int32_t *lists, int32_t n_cells,
                     int num_cu, hipStream_t st);
