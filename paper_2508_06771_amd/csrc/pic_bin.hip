@@ -29,6 +29,7 @@ __global__ void k_reset_flags(DevFlags *f)
         f->unsorted = 0;
         f->range_err = 0;
         f->huge_total = 0;
+        f->seg_fallback = 0;
     }
     if (threadIdx.x < 8) {
         f->head[threadIdx.x] = 0;
@@ -290,6 +291,7 @@ __device__ void plan_segments(const SegScratch &ss, DevFlags *f, int h, int32_t 
     if (want > SEG_MAX) {
         ss.hc_fb[h] = 1;
         ss.hc_S[h] = 0;
+        f->seg_fallback = 1;
         return;
     }
     const uint32_t S = want > 0 ? (uint32_t)want : 1u;

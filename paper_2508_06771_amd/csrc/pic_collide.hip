@@ -503,6 +503,7 @@ __global__ __launch_bounds__(1024) void k_collide_huge(CollideArgs a, const int3
     __shared__ uint32_t wtot[16];
     __shared__ int s_item;
     if (gated_off(a)) return;
+    if (only && !a.dflags->seg_fallback) return;   // every cell went the segmented way
     const uint32_t count = a.dflags->count[cls];
     if (blockIdx.x >= count) return;   // no work for this workgroup (nor a queue atomic)
     const int T = blockDim.x;
@@ -648,6 +649,7 @@ __global__ __launch_bounds__(1024) void k_collide_huge(CollideArgs a, const int3
 // SegScratch): count members per segment, scan, copy members segment-major,
 // sort and pair each segment in LDS, then the pairs across segment edges.
 constexpr int SEG_CT = 256;   // threads of the counting and copying kernels
+constexpr int SEG_U = 8;      // members per thread whose loads are in flight together
 
 // Segment of a key among S equal key ranges, and the key's position inside
 // its range scaled to 32 bits (order-preserving within the segment).
@@ -695,9 +697,19 @@ __global__ __launch_bounds__(SEG_CT) void k_seg_count(CollideArgs a, const int32
         const uint32_t S = it.S;
         for (uint32_t q = threadIdx.x; q < S; q += SEG_CT) hist[q] = 0u;
         __syncthreads();
-        for (int i = it.b + (int)threadIdx.x; i < it.e; i += SEG_CT) {
-            const uint32_t key = draw4(a.seed, a.pid[it.lo + i], step, 0u, 0u).x;
-            atomicAdd(&hist[seg_of(key, S)], 1u);
+        // SEG_U members per thread per round, their pids loaded together
+        for (int i0 = it.b + (int)threadIdx.x; i0 < it.e; i0 += SEG_U * SEG_CT) {
+            uint32_t pv[SEG_U];
+#pragma unroll
+            for (int u = 0; u < SEG_U; ++u) {
+                const int i = i0 + u * SEG_CT;
+                if (i < it.e) pv[u] = a.pid[it.lo + i];
+            }
+#pragma unroll
+            for (int u = 0; u < SEG_U; ++u) {
+                const int i = i0 + u * SEG_CT;
+                if (i < it.e) atomicAdd(&hist[seg_of(draw4(a.seed, pv[u], step, 0u, 0u).x, S)], 1u);
+            }
         }
         __syncthreads();
         const int32_t sb = ss.hc_seg[it.h];
@@ -724,7 +736,10 @@ __global__ __launch_bounds__(1024) void k_seg_scan(CollideArgs a, SegScratch ss,
         if (j < nseg) {
             ss.sg_start[j] = base + off;
             ss.sg_cur[j] = base + off;
-            if (c > cap) ss.hc_fb[ss.sg_cell[j]] = 1;
+            if (c > cap) {
+                ss.hc_fb[ss.sg_cell[j]] = 1;
+                a.dflags->seg_fallback = 1;
+            }
         }
         if (threadIdx.x == 1023) s_tot = off + c;
         __syncthreads();
@@ -755,11 +770,22 @@ __global__ __launch_bounds__(SEG_CT) void k_seg_scatter(CollideArgs a, const int
         const uint32_t S = it.S;
         for (uint32_t q = threadIdx.x; q < S; q += SEG_CT) hist[q] = 0u;
         __syncthreads();
-        for (int i = it.b + (int)threadIdx.x; i < it.e; i += SEG_CT) {
-            const uint32_t key = draw4(a.seed, a.pid[it.lo + i], step, 0u, 0u).x;
-            const uint32_t q = seg_of(key, S);
-            sof[i - it.b] = (uint16_t)q;
-            atomicAdd(&hist[q], 1u);
+        for (int i0 = it.b + (int)threadIdx.x; i0 < it.e; i0 += SEG_U * SEG_CT) {
+            uint32_t pv[SEG_U];
+#pragma unroll
+            for (int u = 0; u < SEG_U; ++u) {
+                const int i = i0 + u * SEG_CT;
+                if (i < it.e) pv[u] = a.pid[it.lo + i];
+            }
+#pragma unroll
+            for (int u = 0; u < SEG_U; ++u) {
+                const int i = i0 + u * SEG_CT;
+                if (i < it.e) {
+                    const uint32_t q = seg_of(draw4(a.seed, pv[u], step, 0u, 0u).x, S);
+                    sof[i - it.b] = (uint16_t)q;
+                    atomicAdd(&hist[q], 1u);
+                }
+            }
         }
         __syncthreads();
         const int32_t sb = ss.hc_seg[it.h];
@@ -768,15 +794,32 @@ __global__ __launch_bounds__(SEG_CT) void k_seg_scatter(CollideArgs a, const int
             hist[q] = 0u;
         }
         __syncthreads();
-        for (int i = it.b + (int)threadIdx.x; i < it.e; i += SEG_CT) {
-            const uint32_t q = sof[i - it.b];
-            const uint32_t slot = base[q] + atomicAdd(&hist[q], 1u);
-            const int64_t g = (int64_t)it.lo + i;
-            ss.m_orig[slot] = (int32_t)g;
-            ss.m_pid[slot] = a.pid[g];
-            mv[slot] = v[g];
-            mv[ss.m_stride + slot] = v[a.n + g];
-            mv[2 * ss.m_stride + slot] = v[2 * a.n + g];
+        for (int i0 = it.b + (int)threadIdx.x; i0 < it.e; i0 += SEG_U * SEG_CT) {
+            uint32_t pv[SEG_U];
+            R x[SEG_U], y[SEG_U], z[SEG_U];
+#pragma unroll
+            for (int u = 0; u < SEG_U; ++u) {
+                const int64_t g = (int64_t)it.lo + i0 + u * SEG_CT;
+                if (i0 + u * SEG_CT < it.e) {
+                    pv[u] = a.pid[g];
+                    x[u] = v[g];
+                    y[u] = v[a.n + g];
+                    z[u] = v[2 * a.n + g];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < SEG_U; ++u) {
+                const int i = i0 + u * SEG_CT;
+                if (i < it.e) {
+                    const uint32_t q = sof[i - it.b];
+                    const uint32_t slot = base[q] + atomicAdd(&hist[q], 1u);
+                    ss.m_orig[slot] = it.lo + i;
+                    ss.m_pid[slot] = pv[u];
+                    mv[slot] = x[u];
+                    mv[ss.m_stride + slot] = y[u];
+                    mv[2 * ss.m_stride + slot] = z[u];
+                }
+            }
         }
         __syncthreads();
     }

@@ -22,7 +22,8 @@ struct DevFlags {
     unsigned int head[8];   // work-queue heads of the persistent kernels
     unsigned int count[8];  // work-queue lengths (cells per class)
     unsigned int huge_total; // members of cells in the multi-block class
-    unsigned int pad[7];
+    unsigned int seg_fallback; // some cell of that class takes the one-workgroup path
+    unsigned int pad[6];
 };
 
 // ---------------------------------------------------------------------------
