@@ -338,6 +338,68 @@ def bench_c5(args):
                  kernel_ms_per_step_gated=res["gated"]["kernel_ms"])
 
 
+def bench_dsmc(args):
+    """DSMC-Coll step (channels C1..C4, ionization appends new electrons) on
+    the 4096 x 10,000 Maxwellian + beam population, FP32, synthetic cross
+    sections, ground-state density 0.4 and metastable density 0.03 (code
+    units), dt 0.02: about 2% of the electrons collide per step."""
+    import numpy as np
+    import torch
+
+    from paper_2508_06771_amd import piccoll, workloads
+    w = workloads.c2(0)
+    n = w.n
+    ctx = piccoll.Context(0)
+    ctx.set_dsmc(workloads.dsmc_table())
+    v = torch.from_numpy(w.v).cuda()
+    cell = torch.from_numpy(w.cell_of).cuda()
+    pid = torch.from_numpy(w.pid.view(np.int32)).cuda()
+    K = args.steps
+    cap = n // 4
+    vnew = torch.zeros((3, cap), dtype=torch.float32, device="cuda")
+    pnew = torch.zeros(cap, dtype=torch.int32, device="cuda")
+    cnew = torch.zeros(cap, dtype=torch.int32, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    chan = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    kw = dict(dt=0.02, seed=0, pid_base=1 << 27, v_new=vnew, pid_new=pnew, cell_new=cnew,
+              count=cnt, n_gas0=0.4, n_meta0=0.03)
+    for s in range(args.warmup):
+        ctx.dsmc_collide(v, cell, pid, w.n_cells, step=s, channel_out=chan if s == 0 else None,
+                         **kw)
+    ctx.sync()
+    ch = np.bincount(chan.cpu().numpy(), minlength=5) / n
+    cnt.zero_()
+    ms = _timed(torch, lambda: [ctx.dsmc_collide(v, cell, pid, w.n_cells, step=args.warmup + s,
+                                                 **kw) for s in range(K)]) / K
+    ctx.sync()
+    new_per_step = int(cnt.item()) / K
+    ctx.time_kernels(True)
+    ctx.kernel_times()
+    for s in range(4):
+        ctx.dsmc_collide(v, cell, pid, w.n_cells, step=1000 + s, **kw)
+    ctx.sync()
+    kt = ctx.kernel_times()
+    ctx.time_kernels(False)
+    kern_ms = kt["dsmc"][0] / kt["dsmc"][1]
+    collided = float(ch[1:].sum())
+    # algorithmic bytes: read v 12 + pid 4 + cell 4; write v 12 of collided
+    # electrons and 20 bytes per new one
+    per_e = 20.0 + 12.0 * collided + 20.0 * new_per_step / n
+    achieved = per_e * n / (kern_ms * 1e-3) / 1e9
+    ctx.close()
+    return _line(n / (ms * 1e-3), ms, args, "f32",
+                 {"workload": f"DSMC-Coll C1..C4 on 4096 cells x 10,000 electrons ({n}), FP32, "
+                              "synthetic cross sections, n_g 0.4, n_m 0.03, dt 0.02",
+                  "n_electrons": n},
+                 channel_fractions={"none": float(ch[0]), "C1": float(ch[1]), "C2": float(ch[2]),
+                                    "C3": float(ch[3]), "C4": float(ch[4])},
+                 new_electrons_per_step=new_per_step,
+                 roofline={"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0,
+                           "unit": "GB/s", "frac": round(achieved / 8000.0, 4), "traffic": None,
+                           "kernel": "k_dsmc<float>", "kernel_avg_ms": round(kern_ms, 5),
+                           "bytes_per_electron": round(per_e, 3)})
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -346,9 +408,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-kernel-timing", action="store_true")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "dsmc"],
                     help="c2: the headline configuration; c3: log-normal cell sizes, autotuned "
-                         "routing, graph replays; c4: precision study; c5: learned gate vs plain")
+                         "routing, graph replays; c4: precision study; c5: learned gate vs plain; "
+                         "dsmc: electron-heavy collisions C1..C4 with ionization")
     ap.add_argument("--eager", action="store_true",
                     help="time one coulomb_collide call per step instead of graph replays")
     ap.add_argument("--kernel-steps", type=int, default=10,
@@ -371,7 +434,7 @@ def main():
     from paper_2508_06771_amd import piccoll, workloads
 
     if args.workload != "c2":
-        out = {"c3": bench_c3, "c4": bench_c4, "c5": bench_c5}[args.workload](args)
+        out = {"c3": bench_c3, "c4": bench_c4, "c5": bench_c5, "dsmc": bench_dsmc}[args.workload](args)
         print(json.dumps(out), flush=True)
         return
 

@@ -152,6 +152,41 @@ int mcc_null_collide(pic_ctx *ctx, int dtype, void *v, const uint32_t *pid, int6
                      double dt, double sigma0, double n_neutral, double mass_ratio,
                      uint64_t seed, uint64_t step, uint8_t *candidate_out);
 
+/* ---------------------------------------------------------------- DSMC-Coll */
+/* Electron-heavy collisions of the paper's collision table, C1 elastic, C2
+ * ionization and C3 metastable excitation on the ground-state density, C4
+ * two-step ionization on the metastable density (Table "DSMC Collision Step",
+ * CS0-CS5, and the probability pi_c = 1 - exp(-dt |v| sigma_c(E) n_k) of
+ * the section "DSMC Collision Kernel").  Cross sections (host arrays,
+ * copied): piecewise cubic in E = |v|^2 / 2 on breakpoints breaks[0] = 0 <
+ * ... < breaks[nseg] (1 <= nseg <= 64), coef[(c * nseg + p) * 4 + q] the
+ * coefficient of (E - breaks[p])^q on segment p of channel c (0..3); constant
+ * beyond breaks[nseg], clipped at 0, zero below threshold[c] (the channel's
+ * energy loss; threshold[0] is normally 0).  mass_ratio: elastic speed loss.
+ * PIC_ERR_ARG on bad input. */
+int pic_set_dsmc(pic_ctx *ctx, int32_t nseg, const double *breaks, const double *coef,
+                 const double *threshold, double mass_ratio);
+/* One DSMC-Coll step of the n particles (v SoA stride n, any storage
+ * order): per particle one domain-6 draw; U(word 0) picks the first channel
+ * whose cumulative probability exceeds it (none: no collision); the scattered
+ * direction is cos = 1 - 2 U(word 1), phi = 2 pi U(word 2); elastic keeps |v|
+ * up to the m/M loss; excitation loses threshold[2]; ionization loses its
+ * threshold and splits the rest U(word 3) : 1 - U(word 3) with a new
+ * electron whose direction uses words 1, 2 of the domain-7 draw.  The new
+ * electron is appended at slot *count (device uint64, read and advanced
+ * atomically, so the order of new electrons is arbitrary) of v_new (SoA stride
+ * cap), pid_new = pid_base + parent pid, cell_new = parent cell; beyond cap it
+ * is counted but not written and pic_sync reports PIC_ERR_STATE.  Densities:
+ * n_gas / n_meta device per-cell arrays [n_cells] indexed by cell_of, or the
+ * scalars when NULL; a particle whose cell is outside [0, n_cells) is left
+ * alone and pic_sync reports PIC_ERR_RANGE.  channel_out (nullable,
+ * uint8[n]): 0 none, 1..4 = C1..C4. */
+int dsmc_collide(pic_ctx *ctx, int dtype, void *v, const int32_t *cell_of, const uint32_t *pid,
+                 int64_t n, int32_t n_cells, const double *n_gas, const double *n_meta, double n_gas0,
+                 double n_meta0, double dt, uint64_t seed, uint64_t step, uint32_t pid_base,
+                 void *v_new, uint32_t *pid_new, int32_t *cell_new, int64_t cap, uint64_t *count,
+                 uint8_t *channel_out);
+
 /* Device buffer of n_cells * 14 doubles receiving the post-step moment sums
  * (layout of pic_cell_moments) when PIC_MOMENTS is passed; NULL clears it. */
 int pic_set_moments_out(pic_ctx *ctx, double *out);
@@ -269,7 +304,7 @@ int pic_time_kernels(pic_ctx *ctx, int on);
  * and cell starts, 6 work queue, 7 re-binning passes, 8 stand-alone
  * null-collision step, 9 learned-gate decision, 10 relaxation of the
  * judged cells, 11 null collisions of deferred cells, 12 gate's moment
- * pass (16 slots are reserved). */
+ * pass, 13 DSMC-Coll step (16 slots are reserved). */
 int pic_kernel_times(pic_ctx *ctx, double *ms, int64_t *count);
 
 /* ---------------------------------------------------------------- test exports */

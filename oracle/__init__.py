@@ -57,6 +57,13 @@ def lib():
         L.orc_pairs.restype = C.c_int
         L.orc_ta_delta.argtypes = [f64p, C.c_double, C.c_double, C.c_double, C.c_double, f64p]
         L.orc_ta_delta.restype = None
+        L.orc_dsmc_sigma.argtypes = [C.c_int32, C.c_double, C.c_int32, f64p, f64p, f64p]
+        L.orc_dsmc_sigma.restype = C.c_double
+        L.orc_dsmc.argtypes = [f64p, C.c_int64, i32p, u32p, C.c_void_p, C.c_void_p, C.c_double,
+                               C.c_double, C.c_double, C.c_int32, f64p, f64p, f64p, C.c_double,
+                               C.c_uint64, C.c_uint64, C.c_uint32, f64p, C.c_int64, u32p, i32p,
+                               C.POINTER(C.c_int64), C.c_void_p]
+        L.orc_dsmc.restype = C.c_int
         L.orc_ta_s2.argtypes = [C.c_double] * 4
         L.orc_ta_s2.restype = C.c_double
         L.orc_mcc_threshold.argtypes = [C.c_double, C.c_double, C.c_double]
@@ -217,3 +224,38 @@ def repair_u(v, cell_start, pid, seed: int, step: int, replica: int):
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+# ---------------------------------------------------------------- DSMC-Coll (C1..C4)
+def dsmc_sigma(c: int, E: float, table) -> float:
+    """Cross section of channel c (0..3) at energy E from a table dict with
+    float64 arrays 'breaks' [P+1], 'coef' [4, P, 4], 'thr' [4]."""
+    return lib().orc_dsmc_sigma(c, E, table["coef"].shape[1], table["breaks"],
+                                np.ascontiguousarray(table["coef"]).reshape(-1), table["thr"])
+
+
+def dsmc(v, cell_of, pid, *, dt: float, table, seed: int, step: int, pid_base: int,
+         n_gas=None, n_meta=None, ng0: float = 1.0, nm0: float = 0.0, mass_ratio: float = 0.0,
+         cap: int = 0):
+    """DSMC-Coll step in place on v (3, n) float64.  Returns (channel per
+    particle, 0 = none, 1..4 = C1..C4; new electrons' v (3, k), pid, cell)."""
+    n = v.shape[1]
+    cell_of = np.ascontiguousarray(cell_of, np.int32)
+    pid = np.ascontiguousarray(pid, np.uint32)
+    cap = max(int(cap), 1)
+    vn = np.zeros((3, cap), np.float64)
+    pn = np.zeros(cap, np.uint32)
+    cn = np.zeros(cap, np.int32)
+    cnt = C.c_int64(0)
+    chan = np.zeros(max(n, 1), np.uint8)
+    ng = None if n_gas is None else np.ascontiguousarray(n_gas, np.float64)
+    nm = None if n_meta is None else np.ascontiguousarray(n_meta, np.float64)
+    rc = lib().orc_dsmc(v.reshape(-1), n, cell_of, pid, _ptr(ng), _ptr(nm), ng0, nm0, dt,
+                        table["coef"].shape[1], table["breaks"],
+                        np.ascontiguousarray(table["coef"]).reshape(-1), table["thr"], mass_ratio,
+                        seed, step, pid_base, vn.reshape(-1), cap, pn, cn, C.byref(cnt),
+                        chan.ctypes.data)
+    if rc:
+        raise ValueError("orc_dsmc: more new electrons than cap")
+    k = cnt.value
+    return chan[:n], vn[:, :k], pn[:k], cn[:k]

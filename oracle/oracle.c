@@ -532,3 +532,109 @@ int orc_num_threads(void)
     return 1;
 #endif
 }
+
+/* ------------------------------------------------------------------ */
+/* DSMC-Coll step for electron-heavy collisions C1..C4 (Table          */
+/* "DSMC Collision Step", CS0-CS5, and the probability formula of the */
+/* section "DSMC Collision Kernel"):                                  */
+/*   pi_c = 1 - exp(-dt |v| sigma_c(E) n_k(c)),  E = |v|^2 / 2,        */
+/* C1 elastic and C2 ionization and C3 excitation on the ground-state */
+/* density n_g, C4 two-step ionization on the metastable density n_m. */
+/* sigma_c: piecewise cubic in E on breakpoints e_0 = 0 < ... < e_P   */
+/* (constant beyond e_P), clipped at 0, zero below the threshold.     */
+/* Selection (reading): U(w0) of the domain-6 draw picks the first    */
+/* channel whose cumulative probability exceeds it.  Post-collision   */
+/* (Vahedi & Surendra): direction cos = 1 - 2 U(w1), phi = 2 pi U(w2); */
+/* elastic keeps |v| up to the m/M loss; excitation loses eps_3;      */
+/* ionization loses eps_c and splits the rest as U(w3) : 1 - U(w3)    */
+/* between the scattered and a new electron, whose direction comes    */
+/* from words 1, 2 of the domain-7 draw.  The new electron gets pid   */
+/* pid_base + pid and the parent's cell, appended at *count.          */
+/* ------------------------------------------------------------------ */
+double orc_dsmc_sigma(int32_t c, double E, int32_t nseg, const double *breaks,
+                      const double *coef, const double *thr)
+{
+    if (E < thr[c]) return 0.0;
+    int32_t p = 0;
+    while (p + 1 < nseg && E >= breaks[p + 1]) ++p;
+    double t = E - breaks[p];
+    const double tmax = breaks[p + 1] - breaks[p];
+    if (t > tmax) t = tmax;   /* beyond the last breakpoint */
+    const double *a = coef + ((size_t)c * nseg + p) * 4;
+    double s = ((a[3] * t + a[2]) * t + a[1]) * t + a[0];
+    return s > 0.0 ? s : 0.0;
+}
+
+static void iso_dir(uint32_t wa, uint32_t wb, double s[3])
+{
+    double ct = 1.0 - 2.0 * orc_u01(wa);
+    double st = sqrt(fmax(0.0, 1.0 - ct * ct));
+    double ph = 2.0 * ORC_PI * orc_u01(wb);
+    s[0] = st * cos(ph);
+    s[1] = st * sin(ph);
+    s[2] = ct;
+}
+
+int orc_dsmc(double *v, int64_t n, const int32_t *cell, const uint32_t *pid, const double *ng,
+             const double *nm, double ng0, double nm0, double dt, int32_t nseg,
+             const double *breaks, const double *coef, const double *thr, double mass_ratio,
+             uint64_t seed, uint64_t step, uint32_t pid_base, double *v_new, int64_t cap,
+             uint32_t *pid_new, int32_t *cell_new, int64_t *count, uint8_t *chan_out)
+{
+    double *vx = v, *vy = v + n, *vz = v + 2 * n;
+    for (int64_t l = 0; l < n; ++l) {
+        const double x = vx[l], y = vy[l], z = vz[l];
+        const double sp2 = x * x + y * y + z * z;
+        const double sp = sqrt(sp2);
+        const double E = 0.5 * sp2;
+        const double dg = ng ? ng[cell[l]] : ng0;
+        const double dm = nm ? nm[cell[l]] : nm0;
+        uint32_t w[4];
+        draw(seed, pid[l], step, 6u, 0u, w);
+        const double R0 = orc_u01(w[0]);
+        double cum = 0.0;
+        int32_t ch = -1;
+        for (int32_t c = 0; c < 4 && ch < 0; ++c) {
+            const double dens = c == 3 ? dm : dg;
+            const double pc = 1.0 - exp(-dt * sp * orc_dsmc_sigma(c, E, nseg, breaks, coef, thr) * dens);
+            cum += pc;
+            if (R0 < cum) ch = c;
+        }
+        if (chan_out) chan_out[l] = (uint8_t)(ch + 1);
+        if (ch < 0) continue;
+        double s[3];
+        iso_dir(w[1], w[2], s);
+        double scale;
+        if (ch == 0) {
+            scale = sp;
+            if (sp > 0.0 && mass_ratio != 0.0) {
+                const double cosx = (x * s[0] + y * s[1] + z * s[2]) / sp;
+                scale = sp * sqrt(1.0 - 2.0 * mass_ratio * (1.0 - cosx));
+            }
+        } else if (ch == 2) {
+            scale = sqrt(2.0 * (E - thr[2]));
+        } else {
+            const double rem = E - thr[ch];
+            const double e1 = orc_u01(w[3]) * rem;
+            const double e2 = rem - e1;
+            scale = sqrt(2.0 * e1);
+            uint32_t w2[4];
+            draw(seed, pid[l], step, 7u, 0u, w2);
+            double s2[3];
+            iso_dir(w2[1], w2[2], s2);
+            const double sc2 = sqrt(2.0 * e2);
+            const int64_t k = (*count)++;
+            if (k < cap) {
+                v_new[k] = sc2 * s2[0];
+                v_new[cap + k] = sc2 * s2[1];
+                v_new[2 * cap + k] = sc2 * s2[2];
+                pid_new[k] = pid_base + pid[l];
+                cell_new[k] = cell[l];
+            }
+        }
+        vx[l] = scale * s[0];
+        vy[l] = scale * s[1];
+        vz[l] = scale * s[2];
+    }
+    return *count > cap ? 1 : 0;
+}

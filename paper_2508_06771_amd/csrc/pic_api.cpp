@@ -21,6 +21,9 @@ struct pic_ctx {
     void *ws = nullptr;
     size_t ws_cap = 0;
     double mcc_sigma0 = 0.0, mcc_nn = 0.0, mcc_mr = 0.0;
+    // DSMC-Coll cross-section table (device copy) and its host header
+    double *dsmc_buf = nullptr;
+    DsmcTable dsmc_tab = {0, nullptr, nullptr, {0, 0, 0, 0}, 0.0};
     bool mcc_set = false;
     double *moments_out = nullptr;
     // graph of one steady-state step (pic_run_steps)
@@ -332,6 +335,7 @@ void pic_destroy(pic_ctx *c)
     if (c->gate_dev) (void)hipFree(c->gate_dev);
     if (c->gate_mem) (void)hipFree(c->gate_mem);
     if (c->debt) (void)hipFree(c->debt);
+    if (c->dsmc_buf) (void)hipFree(c->dsmc_buf);
     delete c;
 }
 
@@ -367,6 +371,76 @@ int pic_set_mcc(pic_ctx *c, double sigma0, double n_neutral, double mass_ratio)
     c->mcc_mr = mass_ratio;
     c->mcc_set = true;
     return PIC_OK;
+}
+
+int pic_set_dsmc(pic_ctx *c, int32_t nseg, const double *breaks, const double *coef,
+                 const double *threshold, double mass_ratio)
+{
+    if (!c || nseg < 1 || nseg > DSMC_MAX_SEG || !breaks || !coef || !threshold ||
+        !(mass_ratio >= 0.0) || !(mass_ratio < 0.5) || breaks[0] != 0.0)
+        return PIC_ERR_ARG;
+    for (int32_t p = 0; p < nseg; ++p)
+        if (!(breaks[p + 1] > breaks[p])) return PIC_ERR_ARG;
+    for (int k = 0; k < 4; ++k)
+        if (!(threshold[k] >= 0.0)) return PIC_ERR_ARG;
+    CK(hipSetDevice(c->device));
+    const size_t nb = (size_t)(nseg + 1) + (size_t)4 * nseg * 4;
+    std::vector<double> host(nb);
+    memcpy(host.data(), breaks, (size_t)(nseg + 1) * sizeof(double));
+    memcpy(host.data() + nseg + 1, coef, (size_t)4 * nseg * 4 * sizeof(double));
+    CK(hipStreamSynchronize(c->stream));
+    if (c->dsmc_buf) CK(hipFree(c->dsmc_buf));
+    c->dsmc_buf = nullptr;
+    if (hipMalloc((void **)&c->dsmc_buf, nb * sizeof(double)) != hipSuccess) return PIC_ERR_NOMEM;
+    CK(hipMemcpy(c->dsmc_buf, host.data(), nb * sizeof(double), hipMemcpyHostToDevice));
+    c->dsmc_tab.nseg = nseg;
+    c->dsmc_tab.breaks = c->dsmc_buf;
+    c->dsmc_tab.coef = c->dsmc_buf + nseg + 1;
+    for (int k = 0; k < 4; ++k) c->dsmc_tab.thr[k] = threshold[k];
+    c->dsmc_tab.mass_ratio = mass_ratio;
+    return PIC_OK;
+}
+
+int dsmc_collide(pic_ctx *c, int dtype, void *v, const int32_t *cell_of, const uint32_t *pid,
+                 int64_t n, int32_t n_cells, const double *n_gas, const double *n_meta, double n_gas0,
+                 double n_meta0, double dt, uint64_t seed, uint64_t step, uint32_t pid_base,
+                 void *v_new, uint32_t *pid_new, int32_t *cell_new, int64_t cap, uint64_t *count,
+                 uint8_t *channel_out)
+{
+    if (!c || n < 0 || n_cells < 1 || cap < 0 || !count || !(dt > 0.0) || !(n_gas0 >= 0.0) ||
+        !(n_meta0 >= 0.0))
+        return PIC_ERR_ARG;
+    if (n > 0 && (!v || !cell_of || !pid)) return PIC_ERR_ARG;
+    if (cap > 0 && (!v_new || !pid_new || !cell_new)) return PIC_ERR_ARG;
+    RC(check_dtype(dtype));
+    if (!c->dsmc_buf) return PIC_ERR_STATE;
+    CK(hipSetDevice(c->device));
+    DsmcArgs a;
+    memset(&a, 0, sizeof(a));
+    a.v = v;
+    a.n = n;
+    a.n_cells = n_cells;
+    a.cell = cell_of;
+    a.pid = pid;
+    a.ng = n_gas;
+    a.nm = n_meta;
+    a.ng0 = n_gas0;
+    a.nm0 = n_meta0;
+    a.dt = dt;
+    a.seed = seed;
+    a.step = step;
+    a.pid_base = pid_base;
+    a.v_new = v_new;
+    a.cap = cap;
+    a.pid_new = pid_new;
+    a.cell_new = cell_new;
+    a.count = (unsigned long long *)count;
+    a.chan_out = channel_out;
+    a.dflags = c->flags;
+    ktime_begin(KT_DSMC, c->stream);
+    const int rc = launch_dsmc(dtype, a, c->dsmc_tab, c->stream);
+    ktime_end(KT_DSMC, c->stream);
+    return rc;
 }
 
 int pic_time_kernels(pic_ctx *c, int on)

@@ -638,7 +638,7 @@ struct RadixPass {
 // 7 re-binning passes, 8 stand-alone null-collision step, 9 learned gate
 // decision, 10 relaxation of the judged cells.
 enum { KT_CLASS0 = 0, KT_HUGE = 4, KT_CHECK = 5, KT_QUEUE = 6, KT_SORT = 7, KT_MCC = 8, KT_GATE = 9,
-       KT_RELAX = 10, KT_DEFER = 11, KT_MOMENTS = 12, KT_SLOTS = 16 };
+       KT_RELAX = 10, KT_DEFER = 11, KT_MOMENTS = 12, KT_DSMC = 13, KT_SLOTS = 16 };
 void ktime_begin(int slot, hipStream_t st);
 void ktime_end(int slot, hipStream_t st);
 bool ktime_pause();            // returns whether timing was on
@@ -797,6 +797,35 @@ int launch_philox(uint64_t seed, uint64_t step, uint32_t domain, uint32_t c3, co
                   int64_t n, uint32_t *out, hipStream_t st);
 // Per-cell moment sums (layout of pic_cell_moments); with run_if (nullable)
 // the pass runs only when *run_if is nonzero.
+// Electron-heavy collision channels C1..C4 (see dsmc_collide).
+constexpr int DSMC_MAX_SEG = 64;
+struct DsmcTable {
+    int32_t nseg;
+    const double *breaks;   // device [nseg + 1]
+    const double *coef;     // device [4][nseg][4]
+    double thr[4];
+    double mass_ratio;
+};
+struct DsmcArgs {
+    void *v;
+    int64_t n;
+    int32_t n_cells;
+    const int32_t *cell;
+    const uint32_t *pid;
+    const double *ng, *nm;  // per-cell densities (nullable)
+    double ng0, nm0, dt;
+    uint64_t seed, step;
+    uint32_t pid_base;
+    void *v_new;
+    int64_t cap;
+    uint32_t *pid_new;
+    int32_t *cell_new;
+    unsigned long long *count;
+    uint8_t *chan_out;
+    DevFlags *dflags;
+};
+int launch_dsmc(int dtype, const DsmcArgs &a, const DsmcTable &t, hipStream_t st);
+
 int launch_moments(int dtype, const void *v, int64_t n, const int32_t *cell_start,
                    int32_t n_cells, double *out, const int *run_if, int num_cu, hipStream_t st);
 int launch_unsort(int dtype, void *v, uint32_t *pid, int32_t *cell_of, int64_t n, void *tmp,

@@ -10,6 +10,8 @@ from __future__ import annotations
 import ctypes as C
 import os
 
+import numpy as np
+
 import torch
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
@@ -71,6 +73,9 @@ def _load():
         "pic_conserve_reset": ([vp], C.c_int),
         "pic_gate_refresh": ([vp, i32], C.c_int),
         "gate_infer": ([vp, vp, i32, vp, C.c_float, i32, C.c_int, vp, vp, vp], C.c_int),
+        "pic_set_dsmc": ([vp, i32, vp, vp, vp, f64], C.c_int),
+        "dsmc_collide": ([vp, C.c_int, vp, vp, vp, i64, i32, vp, vp, f64, f64, f64, u64, u64, u32, vp,
+                          vp, vp, i64, vp, vp], C.c_int),
         "pic_autotune": ([vp, C.c_int, vp, vp, vp, i64, i32, f64, f64, u32, vp], C.c_int),
         "pic_time_kernels": ([vp, C.c_int], C.c_int),
         "pic_kernel_times": ([vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)], C.c_int),
@@ -90,14 +95,14 @@ EXPORTED = ["pic_create", "pic_destroy", "pic_strerror", "pic_sync", "pic_set_st
             "pic_time_kernels", "pic_kernel_times", "pic_run_steps", "pic_features",
             "pic_relaxation", "pic_mlp_forward", "pic_mlp_grad", "pic_mlp_train_step",
             "pic_gate_config", "pic_gate_reset", "pic_gate_stats", "pic_gate_state", "pic_autotune",
-            "pic_conserve_reset", "pic_gate_refresh", "gate_infer"]
+            "pic_conserve_reset", "pic_gate_refresh", "gate_infer", "pic_set_dsmc", "dsmc_collide"]
 
 MLP_PARAMS = 4801
 GATE_STATS = ["steps", "skipped", "collided", "judged", "judged_want", "false_skip", "disabled",
               "have_moments"]
 
 KT_SLOTS = ["class0", "class1", "class2", "class3", "huge", "check", "queue", "sort", "mcc", "gate",
-            "relax", "deferred", "moments"]
+            "relax", "deferred", "moments", "dsmc"]
 
 
 def _dt(v: torch.Tensor) -> int:
@@ -233,6 +238,31 @@ class Context:
         _chk(lib.pic_mlp_forward(self._h, _p(params), _p(x), x.shape[0], int(bf16), _p(prob)),
              "pic_mlp_forward")
         return prob
+
+    def set_dsmc(self, table: dict, mass_ratio: float = 0.0):
+        """Cross-section table: float64 numpy arrays 'breaks' [P+1], 'coef'
+        [4, P, 4] (coefficient of (E - breaks[p])^q), 'thr' [4]."""
+        br = np.ascontiguousarray(table["breaks"], np.float64)
+        co = np.ascontiguousarray(table["coef"], np.float64)
+        th = np.ascontiguousarray(table["thr"], np.float64)
+        f64p = C.POINTER(C.c_double)
+        _chk(lib.pic_set_dsmc(self._h, co.shape[1], br.ctypes.data_as(f64p), co.ctypes.data_as(f64p),
+                              th.ctypes.data_as(f64p), mass_ratio), "pic_set_dsmc")
+
+    def dsmc_collide(self, v: torch.Tensor, cell_of: torch.Tensor, pid: torch.Tensor, n_cells: int,
+                     *, dt: float,
+                     seed: int, step: int, pid_base: int, v_new: torch.Tensor, pid_new: torch.Tensor,
+                     cell_new: torch.Tensor, count: torch.Tensor, n_gas=None, n_meta=None,
+                     n_gas0: float = 1.0, n_meta0: float = 0.0, channel_out=None):
+        """DSMC-Coll step in place; new electrons appended to v_new (3, cap)
+        at count (int64 device scalar, advanced)."""
+        self._stream()
+        assert count.dtype == torch.int64 and v_new.dtype == v.dtype
+        _chk(lib.dsmc_collide(self._h, _dt(v), _p(v), _p(cell_of), _p(pid), v.shape[1], n_cells,
+                              _p(n_gas),
+                              _p(n_meta), n_gas0, n_meta0, dt, seed, step, pid_base, _p(v_new),
+                              _p(pid_new), _p(cell_new), v_new.shape[1], _p(count), _p(channel_out)),
+             "dsmc_collide")
 
     def gate_infer(self, feat: torch.Tensor, params: torch.Tensor, threshold: float, k_max: int,
                    k_acc: torch.Tensor, bf16: bool = True):

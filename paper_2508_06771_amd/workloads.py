@@ -171,3 +171,31 @@ def c5(seed: int = 0, n_cells: int = 65536, per_cell: int = 2000, dtype=np.float
 
 
 CONFIGS = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c5": c5}
+
+
+def dsmc_table() -> dict:
+    """Synthetic cross sections for the electron-heavy channels C1..C4 (the
+    paper's argon cross sections come from LXCat, not available here), in
+    code units (E = |v|^2 / 2 with thermal speed 1): thresholds in the ratio
+    of argon's 11.55 / 15.76 / 4.21 eV (excitation / ionization / two-step
+    ionization) with the two-step threshold at E = 1; a Ramsauer-like elastic
+    minimum.  Piecewise cubic Hermite on shared breakpoints:
+    coef[c, p, q] multiplies (E - breaks[p])^q."""
+    breaks = np.array([0.0, 0.25, 0.5, 1.0, 2.0, 3.0, 4.0, 6.0, 8.0, 12.0, 16.0])
+    thr = np.array([0.0, 3.74, 2.74, 1.0])
+    y = np.array([
+        [2.0, 0.8, 0.5, 1.0, 2.0, 2.5, 2.2, 1.8, 1.5, 1.2, 1.0],      # C1 elastic
+        [0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.05, 0.3, 0.5, 0.7, 0.75],     # C2 ionization
+        [0.0, 0.0, 0.0, 0.0, 0.0, 0.02, 0.15, 0.3, 0.32, 0.28, 0.25],  # C3 excitation
+        [0.0, 0.0, 0.0, 0.0, 1.0, 1.5, 1.6, 1.5, 1.3, 1.1, 1.0],       # C4 two-step ionization
+    ])
+    P = breaks.size - 1
+    coef = np.zeros((4, P, 4))
+    for c in range(4):
+        m = np.gradient(y[c], breaks)
+        for p in range(P):
+            h = breaks[p + 1] - breaks[p]
+            d = (y[c, p + 1] - y[c, p]) / h
+            coef[c, p] = [y[c, p], m[p], (3 * d - 2 * m[p] - m[p + 1]) / h,
+                          (m[p] + m[p + 1] - 2 * d) / (h * h)]
+    return {"breaks": breaks, "coef": coef, "thr": thr}
