@@ -57,6 +57,11 @@ def lib():
         L.orc_pairs.restype = C.c_int
         L.orc_ta_delta.argtypes = [f64p, C.c_double, C.c_double, C.c_double, C.c_double, f64p]
         L.orc_ta_delta.restype = None
+        L.orc_mcc_exact_count.argtypes = [C.c_int64, C.c_double, C.c_double, C.c_double]
+        L.orc_mcc_exact_count.restype = C.c_int64
+        L.orc_mcc_exact.argtypes = [f64p, u32p, C.c_int64, C.c_double, C.c_double, C.c_double,
+                                    C.c_double, C.c_uint64, C.c_uint64, C.c_void_p]
+        L.orc_mcc_exact.restype = C.c_int
         L.orc_dsmc_sigma.argtypes = [C.c_int32, C.c_double, C.c_int32, f64p, f64p, f64p]
         L.orc_dsmc_sigma.restype = C.c_double
         L.orc_dsmc.argtypes = [f64p, C.c_int64, i32p, u32p, C.c_void_p, C.c_void_p, C.c_double,
@@ -159,6 +164,23 @@ def ta_s2(umag: float, density: float, lnL: float, dt: float) -> float:
 
 def mcc_threshold(dt: float, sigma0: float, n_neutral: float) -> int:
     return int(lib().orc_mcc_threshold(dt, sigma0, n_neutral))
+
+
+def mcc_exact_count(n: int, dt: float, sigma0: float, n_neutral: float) -> int:
+    return int(lib().orc_mcc_exact_count(n, dt, sigma0, n_neutral))
+
+
+def mcc_exact(v, pid, dt, sigma0, n_neutral, mass_ratio, seed, step):
+    """Exact-count null-collision step in place on v (3, n) float64; returns
+    the selected flags."""
+    n = v.shape[1]
+    pid = np.ascontiguousarray(pid, dtype=np.uint32)
+    flags = np.zeros(max(n, 1), np.uint8)
+    rc = lib().orc_mcc_exact(v.reshape(-1), pid, n, dt, sigma0, n_neutral, mass_ratio, seed, step,
+                             flags.ctypes.data)
+    if rc:
+        raise ValueError(f"orc_mcc_exact failed: {rc}")
+    return flags[:n]
 
 
 def mcc(v, pid, dt, sigma0, n_neutral, mass_ratio, seed, step, return_flags=False):

@@ -638,3 +638,60 @@ int orc_dsmc(double *v, int64_t n, const int32_t *cell, const uint32_t *pid, con
     }
     return *count > cap ? 1 : 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* Exact-count null-collision selection (the paper picks P_null N      */
+/* particles at random): K = round(P_null n) particles, those with the */
+/* K smallest candidate words (word 1 of the domain-0 draw, the word   */
+/* the per-particle test compares with floor(P_null 2^32)), equal     */
+/* words ordered by pid, then slot -- a uniformly random K-subset.     */
+/* Each selected particle scatters as in orc_mcc (domain 1).           */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    uint32_t key, pid;
+    int64_t slot;
+} sel_t;
+
+static int sel_cmp(const void *a, const void *b)
+{
+    const sel_t *x = a, *y = b;
+    if (x->key != y->key) return x->key < y->key ? -1 : 1;
+    if (x->pid != y->pid) return x->pid < y->pid ? -1 : 1;
+    return x->slot < y->slot ? -1 : x->slot > y->slot;
+}
+
+int64_t orc_mcc_exact_count(int64_t n, double dt, double sigma0, double n_neutral)
+{
+    const double nu_max = n_neutral * sigma0 * sqrt(2.0);
+    const double p = 1.0 - exp(-nu_max * dt);
+    return (int64_t)llround(p * (double)n);
+}
+
+int orc_mcc_exact(double *v, const uint32_t *pid, int64_t n, double dt, double sigma0,
+                  double n_neutral, double mass_ratio, uint64_t seed, uint64_t step,
+                  uint8_t *selected_out)
+{
+    if (n < 0 || !(dt > 0.0)) return 1;
+    const int64_t K = orc_mcc_exact_count(n, dt, sigma0, n_neutral);
+    sel_t *s = malloc((size_t)(n > 0 ? n : 1) * sizeof(sel_t));
+    if (!s) return 2;
+    for (int64_t l = 0; l < n; ++l) {
+        uint32_t w[4];
+        draw(seed, pid[l], step, 0u, 0u, w);
+        s[l].key = w[1];
+        s[l].pid = pid[l];
+        s[l].slot = l;
+    }
+    qsort(s, (size_t)n, sizeof(sel_t), sel_cmp);
+    double *vx = v, *vy = v + n, *vz = v + 2 * n;
+    const double nu_max = n_neutral * sigma0 * sqrt(2.0);
+    if (selected_out) memset(selected_out, 0, (size_t)n);
+    for (int64_t k = 0; k < K && k < n; ++k) {
+        const int64_t l = s[k].slot;
+        /* every selected particle is a candidate: threshold 2^32 */
+        mcc_particle(vx, vy, vz, l, pid[l], 0u, (uint64_t)1 << 32, nu_max, nu_max, mass_ratio,
+                     seed, step, selected_out);
+    }
+    free(s);
+    return 0;
+}
