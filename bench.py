@@ -400,6 +400,54 @@ def bench_dsmc(args):
                            "bytes_per_electron": round(per_e, 3)})
 
 
+def bench_mcc_exact(args):
+    """Exact-count null-collision selection (exactly round(P_null n) electrons
+    scatter) against the per-particle test, on the 4096 x 10,000 Maxwellian +
+    beam population, FP32, P_null = 1%."""
+    import numpy as np
+    import torch
+
+    from paper_2508_06771_amd import piccoll, workloads
+    w = workloads.c2(0)
+    n = w.n
+    ctx = piccoll.Context(0)
+    v = torch.from_numpy(w.v).cuda()
+    pid = torch.from_numpy(w.pid.view(np.int32)).cuda()
+    K = args.steps
+    kw = dict(dt=w.dt, sigma0=w.sigma0, n_neutral=1.0, mass_ratio=0.0, seed=0)
+    for s in range(args.warmup):
+        ctx.mcc_null_collide_exact(v, pid, step=s, **kw)
+    ctx.sync()
+    ms = _timed(torch, lambda: [ctx.mcc_null_collide_exact(v, pid, step=args.warmup + s, **kw)
+                                for s in range(K)]) / K
+    ms_plain = _timed(torch, lambda: [ctx.mcc_null_collide(v, pid, step=args.warmup + s, **kw)
+                                      for s in range(K)]) / K
+    ctx.time_kernels(True)
+    ctx.kernel_times()
+    for s in range(4):
+        ctx.mcc_null_collide_exact(v, pid, step=1000 + s, **kw)
+    ctx.sync()
+    kt = ctx.kernel_times()
+    ctx.time_kernels(False)
+    kern_ms = kt["mcc"][0] / kt["mcc"][1]
+    p = 1.0 - np.exp(-w.sigma0 * np.sqrt(2.0) * w.dt)
+    k = int(round(p * n))
+    # algorithmic bytes: read pid 4 per electron; read and write v of the k selected
+    per_e = 4.0 + 24.0 * k / n
+    achieved = per_e * n / (kern_ms * 1e-3) / 1e9
+    ctx.close()
+    return _line(n / (ms * 1e-3), ms, args, "f32",
+                 {"workload": f"exact-count null collisions on 4096 cells x 10,000 electrons ({n}), "
+                              f"FP32, P_null {p:.4f} ({k} selected per step)",
+                  "n_electrons": n},
+                 per_particle_test_ms=round(ms_plain, 5),
+                 roofline={"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0,
+                           "unit": "GB/s", "frac": round(achieved / 8000.0, 4), "traffic": None,
+                           "kernel": "k_exact_* (init, classify, select, scatter)",
+                           "kernel_avg_ms": round(kern_ms, 5),
+                           "bytes_per_electron": round(per_e, 3)})
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -408,10 +456,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-kernel-timing", action="store_true")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "dsmc"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "dsmc", "mcc_exact"],
                     help="c2: the headline configuration; c3: log-normal cell sizes, autotuned "
                          "routing, graph replays; c4: precision study; c5: learned gate vs plain; "
-                         "dsmc: electron-heavy collisions C1..C4 with ionization")
+                         "dsmc: electron-heavy collisions C1..C4 with ionization; mcc_exact: "
+                         "exact-count null-collision selection")
     ap.add_argument("--eager", action="store_true",
                     help="time one coulomb_collide call per step instead of graph replays")
     ap.add_argument("--kernel-steps", type=int, default=10,
@@ -434,7 +483,8 @@ def main():
     from paper_2508_06771_amd import piccoll, workloads
 
     if args.workload != "c2":
-        out = {"c3": bench_c3, "c4": bench_c4, "c5": bench_c5, "dsmc": bench_dsmc}[args.workload](args)
+        out = {"c3": bench_c3, "c4": bench_c4, "c5": bench_c5, "dsmc": bench_dsmc,
+               "mcc_exact": bench_mcc_exact}[args.workload](args)
         print(json.dumps(out), flush=True)
         return
 

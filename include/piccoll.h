@@ -187,6 +187,25 @@ int dsmc_collide(pic_ctx *ctx, int dtype, void *v, const int32_t *cell_of, const
                  void *v_new, uint32_t *pid_new, int32_t *cell_new, int64_t cap, uint64_t *count,
                  uint8_t *channel_out);
 
+/* Exact-count variant of the null-collision step (the paper selects P_null N
+ * particles at random, paragraph "Null Collision Method"): exactly
+ * K = round(P_null n) particles scatter, those with the K smallest candidate
+ * words (word 1 of the domain-0 draw, the word the per-particle test of
+ * mcc_null_collide compares with floor(P_null 2^32)), equal words ordered by
+ * (pid, slot) -- a uniformly random K-subset, and the particles the
+ * per-particle test picks are a subset or a superset of it.  Scattering as in
+ * mcc_null_collide.  pid holds particle ids (unique in normal use; particles
+ * sharing the threshold word are ranked pairwise, at a cost quadratic in
+ * their number).  Uses context scratch (8 bytes per particle, 8 per
+ * selected one).
+ * selected_out (nullable, n bytes) receives 1 for a selected particle.
+ * Errors: PIC_ERR_ARG (n < 0 or n > 2^31 - 1, NULL arrays with n > 0,
+ * dt <= 0, negative sigma0, n_neutral or mass ratio, mass ratio >= 1/2),
+ * PIC_ERR_DTYPE, PIC_ERR_NOMEM. */
+int mcc_null_collide_exact(pic_ctx *ctx, int dtype, void *v, const uint32_t *pid, int64_t n,
+                           double dt, double sigma0, double n_neutral, double mass_ratio,
+                           uint64_t seed, uint64_t step, uint8_t *selected_out);
+
 /* Device buffer of n_cells * 14 doubles receiving the post-step moment sums
  * (layout of pic_cell_moments) when PIC_MOMENTS is passed; NULL clears it. */
 int pic_set_moments_out(pic_ctx *ctx, double *out);

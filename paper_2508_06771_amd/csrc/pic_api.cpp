@@ -1033,6 +1033,30 @@ int mcc_null_collide(pic_ctx *c, int dtype, void *v, const uint32_t *pid, int64_
     return rc;
 }
 
+int mcc_null_collide_exact(pic_ctx *c, int dtype, void *v, const uint32_t *pid, int64_t n, double dt,
+                           double sigma0, double n_neutral, double mass_ratio, uint64_t seed,
+                           uint64_t step, uint8_t *selected_out)
+{
+    if (!c) return PIC_ERR_ARG;
+    RC(check_dtype(dtype));
+    if (n < 0 || !(dt > 0.0) || !(sigma0 >= 0.0) || !(n_neutral >= 0.0) || !(mass_ratio >= 0.0) ||
+        !(mass_ratio < 0.5))
+        return PIC_ERR_ARG;
+    if (n > 0 && (!v || !pid)) return PIC_ERR_ARG;
+    if (n > INT32_MAX) return PIC_ERR_ARG;   // slots and counts are 32-bit
+    if (n == 0) return PIC_OK;
+    CK(hipSetDevice(c->device));
+    const double nu_max = n_neutral * sigma0 * sqrt(2.0);
+    const double p = 1.0 - exp(-nu_max * dt);
+    const int64_t k = (int64_t)llround(p * (double)n);
+    RC(ensure_ws(c, mcc_exact_ws_bytes(n, k)));
+    ktime_begin(KT_MCC, c->stream);
+    const int rc = launch_mcc_exact(dtype, v, pid, n, k, mass_ratio, seed, step, selected_out, c->ws,
+                                    c->stream);
+    ktime_end(KT_MCC, c->stream);
+    return rc;
+}
+
 int pic_philox(pic_ctx *c, uint64_t seed, uint64_t step, uint32_t domain, uint32_t c3,
                const uint32_t *c0, int64_t n, uint32_t *out)
 {

@@ -791,6 +791,11 @@ int launch_gate_end(DevGate *g, hipStream_t st);
 int launch_mom_select(DevGate *g, const uint64_t *step_dev, uint64_t step, int every,
                       hipStream_t st);
 
+// Exact-count selection: the k particles with the smallest candidate words
+// ((pid, slot) breaks ties) scatter.  ws: mcc_exact_ws_bytes(n, k) of scratch.
+size_t mcc_exact_ws_bytes(int64_t n, int64_t k);
+int launch_mcc_exact(int dtype, void *v, const uint32_t *pid, int64_t n, int64_t k, double mass_ratio,
+                     uint64_t seed, uint64_t step, uint8_t *selected_out, void *ws, hipStream_t st);
 int launch_mcc(int dtype, void *v, const uint32_t *pid, int64_t n, uint64_t thr, double mass_ratio,
                uint64_t seed, uint64_t step, uint8_t *cand_out, hipStream_t st);
 int launch_philox(uint64_t seed, uint64_t step, uint32_t domain, uint32_t c3, const uint32_t *c0,

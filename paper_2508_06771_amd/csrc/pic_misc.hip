@@ -267,6 +267,307 @@ __global__ __launch_bounds__(256) void k_dsmc(DsmcArgs a, DsmcTable t)
     }
 }
 
+// ------------------------------------------------------------ exact count
+// The k smallest candidate words.  The words are uniform, so the k-th lies
+// within a few binomial standard deviations of k 2^32 / n: one pass draws
+// every word and sorts it into "below the window" (selected; slot appended to
+// the workgroup's list), "in the window" (word, pid and slot appended to the
+// workgroup's short list) or "above" (not selected).  One workgroup then
+// finds the exact threshold among the window words by radix selection; only
+// when the window missed (the count below it exceeds k, the count up to its
+// top falls short of k, or a workgroup's list overflowed) does it select over
+// every particle, re-drawing the words.  Nothing is written to v before the
+// decision, so both outcomes are exact.  The lists are per workgroup, with
+// LDS counters, because a single global counter serialises in L2.
+struct ExactState {
+    uint32_t n_x;        // tie winners (window mode)
+    uint32_t n_win;      // compacted window words
+    uint32_t fallback;   // the window missed: select over all particles
+    uint32_t t;          // threshold word
+    uint32_t krem;       // words equal to t still to select (fallback)
+    uint32_t n_ties;     // words equal to t (fallback)
+    uint32_t pad[2];
+};
+
+struct ExactBufs {
+    uint32_t *lo_slot;    // G x cap_lo slots below the window
+    uint32_t *win_key;    // G x cap_win window words
+    uint64_t *win_ps;     // G x cap_win (pid << 32) | slot
+    uint32_t *cnt_lo;     // G counts (may exceed cap_lo: overflow)
+    uint32_t *cnt_win;    // G counts
+    uint32_t *ckey;       // compacted window words
+    uint64_t *cps;        // compacted (pid << 32) | slot
+    uint32_t *x_slot;     // tie winners (k slots)
+    uint64_t *ties;       // n entries of (pid << 32) | slot
+    ExactState *st;
+    uint64_t lo, hi;      // window [lo, hi) of words, 0 <= lo <= hi <= 2^32
+    int64_t chunk;        // particles per workgroup
+    uint32_t k, cap_lo, cap_win, G;
+};
+
+constexpr int SEL_BINS = 2048;
+constexpr int SEL_T = 1024;
+constexpr int SEL_LDS = 12288;   // window words kept in LDS (48 KB)
+constexpr int EXACT_G = 2048;    // workgroups of the classify and scatter passes, at most
+
+// Index of this lane's entry when the lanes with p set append to a list
+// through one LDS counter (one atomic per wave).
+__device__ __forceinline__ uint32_t wave_append(bool p, uint32_t *ctr)
+{
+    const uint64_t m = __ballot(p);
+    if (!m) return 0u;
+    const int lane = threadIdx.x & (PIC_WAVE - 1);
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    uint32_t base = 0u;
+    if (lane == leader) base = atomicAdd(ctr, (uint32_t)__popcll(m));
+    base = __shfl(base, leader);
+    return base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+}
+
+__global__ __launch_bounds__(256) void k_exact_classify(const uint32_t *__restrict__ pid, int64_t n,
+                                                        uint64_t seed, uint32_t step, ExactBufs b,
+                                                        uint8_t *__restrict__ sel_out)
+{
+    __shared__ uint32_t s_lo, s_win;
+    if (threadIdx.x == 0) {
+        s_lo = 0u;
+        s_win = 0u;
+    }
+    __syncthreads();
+    const int64_t start = blockIdx.x * b.chunk;
+    const int64_t end = start + b.chunk < n ? start + b.chunk : n;
+    uint32_t *lo_out = b.lo_slot + (size_t)blockIdx.x * b.cap_lo;
+    uint32_t *wk = b.win_key + (size_t)blockIdx.x * b.cap_win;
+    uint64_t *wp = b.win_ps + (size_t)blockIdx.x * b.cap_win;
+    for (int64_t l = start + threadIdx.x; l < end; l += blockDim.x) {
+        const uint32_t p = pid[l];
+        const uint32_t key = draw4(seed, p, step, 0u, 0u).y;
+        const bool below = (uint64_t)key < b.lo;
+        const bool inwin = !below && (uint64_t)key < b.hi;
+        const uint32_t i = wave_append(below, &s_lo);
+        if (below && i < b.cap_lo) lo_out[i] = (uint32_t)l;
+        const uint32_t j = wave_append(inwin, &s_win);
+        if (inwin && j < b.cap_win) {
+            wk[j] = key;
+            wp[j] = ((uint64_t)p << 32) | (uint64_t)l;
+        }
+        if (sel_out) sel_out[l] = below;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        b.cnt_lo[blockIdx.x] = s_lo;
+        b.cnt_win[blockIdx.x] = s_win;
+    }
+}
+
+// One workgroup of SEL_T threads.  Window mode: the r = k - n_lo smallest
+// window words by (word, pid, slot) go to x_slot.  Fallback: the threshold
+// word t over all particles and, of the words equal to t, how many to take;
+// the scatter pass then decides every particle.
+__global__ __launch_bounds__(SEL_T) void k_exact_select(const uint32_t *__restrict__ pid, int64_t n,
+                                                        uint64_t seed, uint32_t step, ExactBufs b)
+{
+    __shared__ uint32_t h[SEL_BINS];        // list prefixes, then the histogram
+    __shared__ uint32_t s_key[SEL_LDS];
+    __shared__ uint32_t wtot[SEL_T / PIC_WAVE];
+    __shared__ uint32_t s_digit, s_before, s_nt, s_nx, s_over, s_nlo, s_nwin;
+    ExactState *st = b.st;
+    // totals over the workgroups' lists (two lists a thread)
+    const uint32_t b0 = 2 * threadIdx.x, b1 = b0 + 1;
+    const uint32_t l0 = b0 < b.G ? b.cnt_lo[b0] : 0u, l1 = b1 < b.G ? b.cnt_lo[b1] : 0u;
+    const uint32_t w0 = b0 < b.G ? b.cnt_win[b0] : 0u, w1 = b1 < b.G ? b.cnt_win[b1] : 0u;
+    if (threadIdx.x == 0) s_over = 0u;
+    __syncthreads();
+    if (l0 > b.cap_lo || l1 > b.cap_lo || w0 > b.cap_win || w1 > b.cap_win) s_over = 1u;
+    const uint32_t exl = block_excl(l0 + l1, wtot);
+    if (threadIdx.x == SEL_T - 1) s_nlo = exl + l0 + l1;
+    const uint32_t exw = block_excl(w0 + w1, wtot);
+    if (threadIdx.x == SEL_T - 1) s_nwin = exw + w0 + w1;
+    if (b0 < SEL_BINS) h[b0] = exw;
+    if (b1 < SEL_BINS) h[b1] = exw + w0;
+    __syncthreads();
+    const uint32_t n_lo = s_nlo, n_win = s_nwin;
+    const bool fb = s_over || !(n_lo <= b.k && (uint64_t)n_lo + n_win >= b.k);
+    const uint32_t r = fb ? b.k : b.k - n_lo;
+    if (r == 0) {   // nothing beyond the lists below the window
+        if (threadIdx.x == 0) {
+            st->n_x = 0u;
+            st->n_win = 0u;
+            st->fallback = 0u;
+        }
+        return;
+    }
+    const bool in_lds = n_win <= (uint32_t)SEL_LDS;
+    if (!fb) {
+        // compact the window lists (the last list whose prefix is <= i holds
+        // entry i), four entries a thread in flight
+        for (uint32_t i0 = 0; i0 < n_win; i0 += 4 * SEL_T) {
+            uint32_t kk[4];
+            uint64_t pp[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t i = i0 + u * SEL_T + threadIdx.x;
+                if (i < n_win) {
+                    uint32_t lo = 0, hi = b.G;   // h[lo] <= i < h[hi]
+                    while (hi - lo > 1) {
+                        const uint32_t mid = (lo + hi) >> 1;
+                        if (h[mid] <= i) lo = mid;
+                        else hi = mid;
+                    }
+                    const size_t src = (size_t)lo * b.cap_win + (i - h[lo]);
+                    kk[u] = b.win_key[src];
+                    pp[u] = b.win_ps[src];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t i = i0 + u * SEL_T + threadIdx.x;
+                if (i < n_win) {
+                    if (in_lds) s_key[i] = kk[u];
+                    b.ckey[i] = kk[u];
+                    b.cps[i] = pp[u];
+                }
+            }
+        }
+        __syncthreads();
+    }
+    const int64_t count = fb ? n : (int64_t)n_win;
+    auto key_at = [&](int64_t i) -> uint32_t {
+        return fb ? draw4(seed, pid[i], step, 0u, 0u).y : in_lds ? s_key[i] : b.ckey[i];
+    };
+    // digits of the word minus the window's base, over the bits its span
+    // needs (a narrow window's words share their top bits, and a histogram
+    // of those would pile into one LDS bin); 11-bit digits from the top
+    const uint32_t base = fb ? 0u : (uint32_t)b.lo;
+    const uint64_t span = fb ? (uint64_t)1 << 32 : b.hi - b.lo;
+    const int nbits = span <= 1 ? 1 : 64 - __clzll((long long)(span - 1));
+    const int npass = (nbits + 10) / 11;
+    uint32_t prefix = 0u, krem = r;
+    for (int pass = 0; pass < npass; ++pass) {
+        const int above = nbits - 11 * pass;
+        const int shift = above > 11 ? above - 11 : 0;
+        const int bits = above - shift;
+        for (int i = threadIdx.x; i < SEL_BINS; i += SEL_T) h[i] = 0u;
+        __syncthreads();
+        for (int64_t i = threadIdx.x; i < count; i += SEL_T) {
+            const uint32_t key = key_at(i) - base;
+            if (pass == 0 || (key >> above) == prefix)
+                atomicAdd(&h[(key >> shift) & ((1u << bits) - 1u)], 1u);
+        }
+        __syncthreads();
+        // the first bin whose inclusive count reaches krem (two bins a thread)
+        const uint32_t nb = 1u << bits;
+        const uint32_t c0 = b0 < nb ? h[b0] : 0u, c1 = b1 < nb ? h[b1] : 0u;
+        const uint32_t ex = block_excl(c0 + c1, wtot);
+        if (b0 < nb && ex < krem && ex + c0 >= krem) {
+            s_digit = b0;
+            s_before = ex;
+        }
+        if (b1 < nb && ex + c0 < krem && ex + c0 + c1 >= krem) {
+            s_digit = b1;
+            s_before = ex + c0;
+        }
+        __syncthreads();
+        prefix = (prefix << bits) | s_digit;
+        krem -= s_before;
+        __syncthreads();   // s_digit, s_before and h are rewritten by the next pass
+    }
+    const uint32_t t = prefix + base;
+    if (threadIdx.x == 0) {
+        s_nt = 0u;
+        s_nx = 0u;
+    }
+    __syncthreads();
+    for (int64_t i0 = 0; i0 < count; i0 += SEL_T) {   // uniform trip count: whole waves append
+        const int64_t i = i0 + threadIdx.x;
+        const bool tie = i < count && key_at(i) == t;
+        const uint32_t qt = wave_append(tie, &s_nt);
+        if (tie) b.ties[qt] = fb ? (((uint64_t)pid[i] << 32) | (uint64_t)i) : b.cps[i];
+    }
+    __syncthreads();
+    const uint32_t m = s_nt;
+    if (!fb) {
+        // of the words equal to t, the krem first by (pid, slot)
+        for (uint32_t i = threadIdx.x; i < m; i += SEL_T) {
+            const uint64_t e = b.ties[i];
+            uint32_t rank = 0u;
+            for (uint32_t j = 0; j < m; ++j) rank += b.ties[j] < e ? 1u : 0u;
+            if (rank < krem) b.x_slot[atomicAdd(&s_nx, 1u)] = (uint32_t)e;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        st->t = t;
+        st->krem = krem;
+        st->n_ties = m;
+        st->n_x = fb ? 0u : s_nx;
+        st->n_win = fb ? 0u : n_win;
+        st->fallback = fb ? 1u : 0u;
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ void exact_scatter_one(R *__restrict__ v, int64_t n, int64_t l, uint32_t p,
+                                                  double mass_ratio, uint64_t seed, uint32_t step)
+{
+    R x = v[l], y = v[n + l], z = v[2 * n + l];
+    scatter_dir(x, y, z, draw4(seed, p, step, 1u, 0u), mass_ratio);
+    v[l] = x;
+    v[n + l] = y;
+    v[2 * n + l] = z;
+}
+
+// Window mode: workgroup g scatters its own list below the window, and all
+// workgroups share the window words below t and the tie winners.  Fallback:
+// every particle, its word re-drawn; equal words ranked by (pid, slot)
+// against the collected ties.
+template <typename R>
+__global__ __launch_bounds__(256) void k_exact_scatter(R *__restrict__ v, const uint32_t *__restrict__ pid,
+                                                       int64_t n, ExactBufs b, double mass_ratio, uint64_t seed,
+                                                       uint32_t step, uint8_t *__restrict__ sel_out)
+{
+    const ExactState *st = b.st;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t g0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (!st->fallback) {
+        const uint32_t c = b.cnt_lo[blockIdx.x];   // <= cap_lo outside the fallback
+        const uint32_t *lo_in = b.lo_slot + (size_t)blockIdx.x * b.cap_lo;
+        for (uint32_t i = threadIdx.x; i < c; i += blockDim.x) {
+            const int64_t l = lo_in[i];
+            exact_scatter_one(v, n, l, pid[l], mass_ratio, seed, step);
+        }
+        const uint32_t t = st->t;
+        const int64_t n_win = st->n_win;
+        for (int64_t i = g0; i < n_win; i += stride) {
+            if (b.ckey[i] >= t) continue;
+            const int64_t l = (uint32_t)b.cps[i];
+            if (sel_out) sel_out[l] = 1;
+            exact_scatter_one(v, n, l, (uint32_t)(b.cps[i] >> 32), mass_ratio, seed, step);
+        }
+        const int64_t n_x = st->n_x;
+        for (int64_t i = g0; i < n_x; i += stride) {
+            const int64_t l = b.x_slot[i];
+            if (sel_out) sel_out[l] = 1;
+            exact_scatter_one(v, n, l, pid[l], mass_ratio, seed, step);
+        }
+        return;
+    }
+    const uint32_t t = st->t, krem = st->krem, m = st->n_ties;
+    for (int64_t l = g0; l < n; l += stride) {
+        const uint32_t p = pid[l];
+        const uint32_t key = draw4(seed, p, step, 0u, 0u).y;
+        bool sel = key < t;
+        if (key == t) {
+            const uint64_t e = ((uint64_t)p << 32) | (uint64_t)l;
+            uint32_t rank = 0u;
+            for (uint32_t j = 0; j < m; ++j) rank += b.ties[j] < e ? 1u : 0u;
+            sel = rank < krem;
+        }
+        if (sel_out) sel_out[l] = sel;
+        if (sel) exact_scatter_one(v, n, l, p, mass_ratio, seed, step);
+    }
+}
+
 int grid_for(int64_t n, int threads, int cap)
 {
     int64_t g = (n + threads - 1) / threads;
@@ -349,6 +650,97 @@ int launch_dsmc(int dtype, const DsmcArgs &a, const DsmcTable &t, hipStream_t st
         hipLaunchKernelGGL(k_dsmc<float>, dim3(g), dim3(256), 0, st, a, t);
     else
         hipLaunchKernelGGL(k_dsmc<double>, dim3(g), dim3(256), 0, st, a, t);
+    HIP_OK(hipGetLastError());
+    return PIC_OK;
+}
+
+namespace {
+struct ExactPlan {
+    uint64_t lo, hi;
+    int64_t chunk;
+    uint32_t k, cap_lo, cap_win, G;
+};
+
+// Window of words around the expected k-th: +-8 binomial standard deviations
+// of the count, plus 16; per-workgroup list capacities 10 standard
+// deviations above their expected fill, plus 32.
+ExactPlan exact_plan(int64_t n, int64_t k)
+{
+    ExactPlan p;
+    p.k = (uint32_t)(k < 0 ? 0 : (k > n ? n : k));
+    const double nn = (double)n, kk = (double)p.k;
+    const double sd = sqrt(kk * (1.0 - kk / nn));
+    const double a = (kk - 8.0 * sd - 16.0) / nn, b = (kk + 8.0 * sd + 16.0) / nn;
+    const double two32 = 4294967296.0;
+    p.lo = a <= 0.0 ? 0 : a >= 1.0 ? (uint64_t)1 << 32 : (uint64_t)floor(a * two32);
+    p.hi = b >= 1.0 ? (uint64_t)1 << 32 : (uint64_t)ceil(b * two32);
+    if (p.k == 0) p.lo = p.hi = 0;
+    int64_t G = (n + 255) / 256;
+    if (G > EXACT_G) G = EXACT_G;
+    if (G < 1) G = 1;
+    p.chunk = (n + G - 1) / G;
+    p.G = (uint32_t)((n + p.chunk - 1) / p.chunk);
+    auto cap = [&](double frac) {
+        const double mu = (double)p.chunk * frac;
+        const double c = ceil(mu + 10.0 * sqrt(mu) + 32.0);
+        return (uint32_t)(c < (double)p.chunk ? c : (double)p.chunk);
+    };
+    p.cap_lo = cap((double)p.lo / two32);
+    p.cap_win = cap((double)(p.hi - p.lo) / two32);
+    return p;
+}
+
+size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
+}  // namespace
+
+size_t mcc_exact_ws_bytes(int64_t n, int64_t k)
+{
+    const ExactPlan p = exact_plan(n, k);
+    const size_t win = (size_t)p.G * p.cap_win;
+    return round256((size_t)p.G * p.cap_lo * 4) + 2 * round256(win * 4) + 2 * round256(win * 8) +
+           2 * round256((size_t)p.G * 4) + round256((size_t)p.k * 4) + round256((size_t)n * 8) +
+           round256(sizeof(ExactState));
+}
+
+int launch_mcc_exact(int dtype, void *v, const uint32_t *pid, int64_t n, int64_t k, double mass_ratio,
+                     uint64_t seed, uint64_t step, uint8_t *selected_out, void *ws, hipStream_t st)
+{
+    if (n <= 0) return PIC_OK;
+    const ExactPlan p = exact_plan(n, k);
+    unsigned char *q = (unsigned char *)ws;
+    auto take = [&](size_t bytes) {
+        unsigned char *r = q;
+        q += round256(bytes);
+        return (void *)r;
+    };
+    const size_t win = (size_t)p.G * p.cap_win;
+    ExactBufs b;
+    b.lo_slot = (uint32_t *)take((size_t)p.G * p.cap_lo * 4);
+    b.win_key = (uint32_t *)take(win * 4);
+    b.win_ps = (uint64_t *)take(win * 8);
+    b.ckey = (uint32_t *)take(win * 4);
+    b.cps = (uint64_t *)take(win * 8);
+    b.cnt_lo = (uint32_t *)take((size_t)p.G * 4);
+    b.cnt_win = (uint32_t *)take((size_t)p.G * 4);
+    b.x_slot = (uint32_t *)take((size_t)p.k * 4);
+    b.ties = (uint64_t *)take((size_t)n * 8);
+    b.st = (ExactState *)take(sizeof(ExactState));
+    b.lo = p.lo;
+    b.hi = p.hi;
+    b.chunk = p.chunk;
+    b.k = p.k;
+    b.cap_lo = p.cap_lo;
+    b.cap_win = p.cap_win;
+    b.G = p.G;
+    hipLaunchKernelGGL(k_exact_classify, dim3(p.G), dim3(256), 0, st, pid, n, seed, (uint32_t)step, b,
+                       selected_out);
+    hipLaunchKernelGGL(k_exact_select, dim3(1), dim3(SEL_T), 0, st, pid, n, seed, (uint32_t)step, b);
+    if (dtype == PIC_F32)
+        hipLaunchKernelGGL(k_exact_scatter<float>, dim3(p.G), dim3(256), 0, st, (float *)v, pid, n, b,
+                           mass_ratio, seed, (uint32_t)step, selected_out);
+    else
+        hipLaunchKernelGGL(k_exact_scatter<double>, dim3(p.G), dim3(256), 0, st, (double *)v, pid, n, b,
+                           mass_ratio, seed, (uint32_t)step, selected_out);
     HIP_OK(hipGetLastError());
     return PIC_OK;
 }

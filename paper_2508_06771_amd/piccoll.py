@@ -55,6 +55,8 @@ def _load():
         "mcc_null_collide": ([vp, C.c_int, vp, vp, i64, f64, f64, f64, f64, u64, u64, vp],
                              C.c_int),
         "pic_philox": ([vp, u64, u64, u32, u32, vp, i64, vp], C.c_int),
+        "mcc_null_collide_exact": ([vp, C.c_int, vp, vp, i64, f64, f64, f64, f64, u64, u64, vp],
+                                   C.c_int),
         "coulomb_pairs": ([vp, vp, vp, i32, u64, u64, vp, vp], C.c_int),
         "pic_cell_moments": ([vp, C.c_int, vp, i64, vp, i32, vp], C.c_int),
         "pic_unsort": ([vp, C.c_int, vp, vp, vp, i64], C.c_int),
@@ -95,7 +97,8 @@ EXPORTED = ["pic_create", "pic_destroy", "pic_strerror", "pic_sync", "pic_set_st
             "pic_time_kernels", "pic_kernel_times", "pic_run_steps", "pic_features",
             "pic_relaxation", "pic_mlp_forward", "pic_mlp_grad", "pic_mlp_train_step",
             "pic_gate_config", "pic_gate_reset", "pic_gate_stats", "pic_gate_state", "pic_autotune",
-            "pic_conserve_reset", "pic_gate_refresh", "gate_infer", "pic_set_dsmc", "dsmc_collide"]
+            "pic_conserve_reset", "pic_gate_refresh", "gate_infer", "pic_set_dsmc", "dsmc_collide",
+            "mcc_null_collide_exact"]
 
 MLP_PARAMS = 4801
 GATE_STATS = ["steps", "skipped", "collided", "judged", "judged_want", "false_skip", "disabled",
@@ -211,6 +214,17 @@ class Context:
         _chk(lib.mcc_null_collide(self._h, _dt(v), _p(v), _p(pid), n, dt, sigma0, n_neutral,
                                   mass_ratio, seed, step, _p(cand)), "mcc_null_collide")
         return cand[:n] if candidates else None
+
+    def mcc_null_collide_exact(self, v: torch.Tensor, pid: torch.Tensor, *, dt: float,
+                               sigma0: float, n_neutral: float, mass_ratio: float, seed: int,
+                               step: int, selected: bool = False):
+        self._stream()
+        n = v.shape[1]
+        sel = torch.empty(max(n, 1), dtype=torch.uint8, device=v.device) if selected else None
+        _chk(lib.mcc_null_collide_exact(self._h, _dt(v), _p(v), _p(pid), n, dt, sigma0, n_neutral,
+                                        mass_ratio, seed, step, _p(sel)),
+             "mcc_null_collide_exact")
+        return sel[:n] if selected else None
 
     # -------------------------------------------------------------- learned gate
     def features(self, moments: torch.Tensor):
