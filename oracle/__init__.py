@@ -62,6 +62,8 @@ def lib():
         L.orc_mcc_exact.argtypes = [f64p, u32p, C.c_int64, C.c_double, C.c_double, C.c_double,
                                     C.c_double, C.c_uint64, C.c_uint64, C.c_void_p]
         L.orc_mcc_exact.restype = C.c_int
+        L.orc_p2c.argtypes = [f64p, C.c_int32, i32p, C.c_int64, C.c_int32, f64p]
+        L.orc_p2c.restype = C.c_int64
         L.orc_dsmc_sigma.argtypes = [C.c_int32, C.c_double, C.c_int32, f64p, f64p, f64p]
         L.orc_dsmc_sigma.restype = C.c_double
         L.orc_dsmc.argtypes = [f64p, C.c_int64, i32p, u32p, C.c_void_p, C.c_void_p, C.c_double,
@@ -181,6 +183,17 @@ def mcc_exact(v, pid, dt, sigma0, n_neutral, mass_ratio, seed, step):
     if rc:
         raise ValueError(f"orc_mcc_exact failed: {rc}")
     return flags[:n]
+
+
+def p2c(q, cell_of, n_cells: int):
+    """Per-cell sums (n_cells, nq) of the rows of q (nq, n); returns (sums,
+    number of skipped out-of-range ids)."""
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    nq, n = q.shape
+    cell_of = np.ascontiguousarray(cell_of, dtype=np.int32)
+    out = np.zeros((n_cells, nq), np.float64)
+    bad = lib().orc_p2c(q.reshape(-1), nq, cell_of, n, n_cells, out.reshape(-1))
+    return out, int(bad)
 
 
 def mcc(v, pid, dt, sigma0, n_neutral, mass_ratio, seed, step, return_flags=False):

@@ -695,3 +695,26 @@ int orc_mcc_exact(double *v, const uint32_t *pid, int64_t n, double dt, double s
     free(s);
     return 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* Particle-to-cell sums (section "Particle-to-Cell"): the sum of the  */
+/* per-particle vector V_l over the particles of each cell,            */
+/* out[j nq + k] = sum_{l : cell_of[l] = j} q[k n + l], in particle    */
+/* order.  Ids outside [0, M) are skipped; the return value counts     */
+/* them.                                                               */
+/* ------------------------------------------------------------------ */
+int64_t orc_p2c(const double *q, int32_t nq, const int32_t *cell_of, int64_t n, int32_t M,
+                double *out)
+{
+    int64_t bad = 0;
+    for (int64_t j = 0; j < (int64_t)M * nq; ++j) out[j] = 0.0;
+    for (int64_t l = 0; l < n; ++l) {
+        const int32_t c = cell_of[l];
+        if (c < 0 || c >= M) {
+            ++bad;
+            continue;
+        }
+        for (int32_t k = 0; k < nq; ++k) out[(int64_t)c * nq + k] += q[(int64_t)k * n + l];
+    }
+    return bad;
+}
