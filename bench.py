@@ -448,6 +448,55 @@ def bench_mcc_exact(args):
                            "bytes_per_electron": round(per_e, 3)})
 
 
+def bench_p2c(args):
+    """Particle-to-cell sums of four binary32 quantities (weight and the three
+    velocity components) over the 4096 x 10,000 population, in the
+    cell-sorted storage the collision step leaves and in random order."""
+    import numpy as np
+    import torch
+
+    from paper_2508_06771_amd import piccoll, workloads
+    w = workloads.c2(0)
+    n, M = w.n, w.n_cells
+    order = np.argsort(w.cell_of, kind="stable")
+    q = torch.from_numpy(np.ascontiguousarray(np.vstack([np.ones((1, n), np.float32), w.v[:, order]]))).cuda()
+    cell_sorted = torch.from_numpy(w.cell_of[order]).cuda()
+    perm = torch.from_numpy(np.random.default_rng(0).permutation(n)).cuda()
+    q_rand = q[:, perm].contiguous()
+    cell_rand = cell_sorted[perm].contiguous()
+    del perm
+    ctx = piccoll.Context(0)
+    out = torch.empty((M, 4), dtype=torch.float64, device="cuda")
+    K = args.steps
+    res = {}
+    for name, (qq, cc) in {"sorted": (q, cell_sorted), "random": (q_rand, cell_rand)}.items():
+        for _ in range(args.warmup):
+            ctx.p2c_sums(qq, cc, M, out)
+        ctx.sync()
+        ms = _timed(torch, lambda: [ctx.p2c_sums(qq, cc, M, out) for _ in range(K)]) / K
+        ctx.time_kernels(True)
+        ctx.kernel_times()
+        for _ in range(4):
+            ctx.p2c_sums(qq, cc, M, out)
+        ctx.sync()
+        kt = ctx.kernel_times()
+        ctx.time_kernels(False)
+        res[name] = (ms, kt["p2c"][0] / kt["p2c"][1])
+    ctx.close()
+    ms, kern_ms = res["sorted"]
+    per_e = 4 * 4 + 4.0      # four binary32 quantities and the cell id
+    achieved = per_e * n / (kern_ms * 1e-3) / 1e9
+    return _line(n / (ms * 1e-3), ms, args, "f32",
+                 {"workload": f"particle-to-cell sums of 4 binary32 quantities, 4096 cells x 10,000 "
+                              f"electrons ({n}), cell-sorted storage, binary64 accumulation",
+                  "n_electrons": n},
+                 random_order_ms=round(res["random"][0], 5),
+                 roofline={"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0,
+                           "unit": "GB/s", "frac": round(achieved / 8000.0, 4), "traffic": None,
+                           "kernel": "k_p2c_lds<float,4> + k_p2c_reduce",
+                           "kernel_avg_ms": round(kern_ms, 5), "bytes_per_electron": per_e})
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -456,11 +505,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-kernel-timing", action="store_true")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "dsmc", "mcc_exact"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "dsmc", "mcc_exact", "p2c"],
                     help="c2: the headline configuration; c3: log-normal cell sizes, autotuned "
                          "routing, graph replays; c4: precision study; c5: learned gate vs plain; "
                          "dsmc: electron-heavy collisions C1..C4 with ionization; mcc_exact: "
-                         "exact-count null-collision selection")
+                         "exact-count null-collision selection; p2c: particle-to-cell sums")
     ap.add_argument("--eager", action="store_true",
                     help="time one coulomb_collide call per step instead of graph replays")
     ap.add_argument("--kernel-steps", type=int, default=10,
@@ -484,7 +533,7 @@ def main():
 
     if args.workload != "c2":
         out = {"c3": bench_c3, "c4": bench_c4, "c5": bench_c5, "dsmc": bench_dsmc,
-               "mcc_exact": bench_mcc_exact}[args.workload](args)
+               "mcc_exact": bench_mcc_exact, "p2c": bench_p2c}[args.workload](args)
         print(json.dumps(out), flush=True)
         return
 

@@ -206,6 +206,20 @@ int mcc_null_collide_exact(pic_ctx *ctx, int dtype, void *v, const uint32_t *pid
                            double dt, double sigma0, double n_neutral, double mass_ratio,
                            uint64_t seed, uint64_t step, uint8_t *selected_out);
 
+/* Particle-to-cell sums (section "Particle-to-Cell"; steps S3a-S3b of the
+ * PIC scheme table): out[j * nq + k] = sum over the particles l with
+ * cell_of[l] == j of q[k * n + l], for cells j < n_cells and quantities
+ * k < nq.  q: nq rows of n values (SoA), binary32 or binary64 by dtype;
+ * particles in any order; sums accumulated in binary64, so the result can
+ * differ from one call to the next in the last bits (the order of the
+ * atomic additions is not fixed).  out: n_cells * nq doubles, overwritten.
+ * A cell id outside [0, n_cells) is skipped and pic_sync reports
+ * PIC_ERR_RANGE.  Errors: PIC_ERR_ARG (NULL arrays with n > 0, n < 0 or
+ * n > 2^31 - 1, n_cells < 1, nq outside 1..4, n_cells * nq > 2^28),
+ * PIC_ERR_DTYPE, PIC_ERR_NOMEM (scratch of up to 8 copies of out). */
+int p2c_sums(pic_ctx *ctx, int dtype, const void *q, int32_t nq, const int32_t *cell_of, int64_t n,
+             int32_t n_cells, double *out);
+
 /* Device buffer of n_cells * 14 doubles receiving the post-step moment sums
  * (layout of pic_cell_moments) when PIC_MOMENTS is passed; NULL clears it. */
 int pic_set_moments_out(pic_ctx *ctx, double *out);
@@ -323,7 +337,7 @@ int pic_time_kernels(pic_ctx *ctx, int on);
  * and cell starts, 6 work queue, 7 re-binning passes, 8 stand-alone
  * null-collision step, 9 learned-gate decision, 10 relaxation of the
  * judged cells, 11 null collisions of deferred cells, 12 gate's moment
- * pass, 13 DSMC-Coll step (16 slots are reserved). */
+ * pass, 13 DSMC-Coll step, 14 particle-to-cell sums (16 slots are reserved). */
 int pic_kernel_times(pic_ctx *ctx, double *ms, int64_t *count);
 
 /* ---------------------------------------------------------------- test exports */

@@ -1057,6 +1057,21 @@ int mcc_null_collide_exact(pic_ctx *c, int dtype, void *v, const uint32_t *pid, 
     return rc;
 }
 
+int p2c_sums(pic_ctx *c, int dtype, const void *q, int32_t nq, const int32_t *cell_of, int64_t n,
+             int32_t n_cells, double *out)
+{
+    if (!c || n < 0 || n_cells < 1 || nq < 1 || nq > 4 || !out || (n > 0 && (!q || !cell_of)))
+        return PIC_ERR_ARG;
+    if (n > INT32_MAX || (int64_t)n_cells * nq > (int64_t)1 << 28) return PIC_ERR_ARG;
+    RC(check_dtype(dtype));
+    CK(hipSetDevice(c->device));
+    RC(ensure_ws(c, p2c_ws_bytes(n, n_cells, nq, c->num_cu)));
+    ktime_begin(KT_P2C, c->stream);
+    const int rc = launch_p2c(dtype, nq, q, cell_of, n, n_cells, out, c->ws, c->flags, c->num_cu, c->stream);
+    ktime_end(KT_P2C, c->stream);
+    return rc;
+}
+
 int pic_philox(pic_ctx *c, uint64_t seed, uint64_t step, uint32_t domain, uint32_t c3,
                const uint32_t *c0, int64_t n, uint32_t *out)
 {

@@ -638,7 +638,7 @@ struct RadixPass {
 // 7 re-binning passes, 8 stand-alone null-collision step, 9 learned gate
 // decision, 10 relaxation of the judged cells.
 enum { KT_CLASS0 = 0, KT_HUGE = 4, KT_CHECK = 5, KT_QUEUE = 6, KT_SORT = 7, KT_MCC = 8, KT_GATE = 9,
-       KT_RELAX = 10, KT_DEFER = 11, KT_MOMENTS = 12, KT_DSMC = 13, KT_SLOTS = 16 };
+       KT_RELAX = 10, KT_DEFER = 11, KT_MOMENTS = 12, KT_DSMC = 13, KT_P2C = 14, KT_SLOTS = 16 };
 void ktime_begin(int slot, hipStream_t st);
 void ktime_end(int slot, hipStream_t st);
 bool ktime_pause();            // returns whether timing was on
@@ -830,6 +830,12 @@ struct DsmcArgs {
     DevFlags *dflags;
 };
 int launch_dsmc(int dtype, const DsmcArgs &a, const DsmcTable &t, hipStream_t st);
+
+// Particle-to-cell sums out[j * nq + k] (binary64) of nq <= 4 quantities
+// q[k * n + l] over the particles l of cell j.  ws: p2c_ws_bytes(...).
+size_t p2c_ws_bytes(int64_t n, int32_t M, int nq, int num_cu);
+int launch_p2c(int dtype, int nq, const void *q, const int32_t *cell_of, int64_t n, int32_t M, double *out,
+               void *ws, DevFlags *f, int num_cu, hipStream_t st);
 
 int launch_moments(int dtype, const void *v, int64_t n, const int32_t *cell_start,
                    int32_t n_cells, double *out, const int *run_if, int num_cu, hipStream_t st);

@@ -57,6 +57,7 @@ def _load():
         "pic_philox": ([vp, u64, u64, u32, u32, vp, i64, vp], C.c_int),
         "mcc_null_collide_exact": ([vp, C.c_int, vp, vp, i64, f64, f64, f64, f64, u64, u64, vp],
                                    C.c_int),
+        "p2c_sums": ([vp, C.c_int, vp, C.c_int32, vp, i64, C.c_int32, vp], C.c_int),
         "coulomb_pairs": ([vp, vp, vp, i32, u64, u64, vp, vp], C.c_int),
         "pic_cell_moments": ([vp, C.c_int, vp, i64, vp, i32, vp], C.c_int),
         "pic_unsort": ([vp, C.c_int, vp, vp, vp, i64], C.c_int),
@@ -98,14 +99,14 @@ EXPORTED = ["pic_create", "pic_destroy", "pic_strerror", "pic_sync", "pic_set_st
             "pic_relaxation", "pic_mlp_forward", "pic_mlp_grad", "pic_mlp_train_step",
             "pic_gate_config", "pic_gate_reset", "pic_gate_stats", "pic_gate_state", "pic_autotune",
             "pic_conserve_reset", "pic_gate_refresh", "gate_infer", "pic_set_dsmc", "dsmc_collide",
-            "mcc_null_collide_exact"]
+            "mcc_null_collide_exact", "p2c_sums"]
 
 MLP_PARAMS = 4801
 GATE_STATS = ["steps", "skipped", "collided", "judged", "judged_want", "false_skip", "disabled",
               "have_moments"]
 
 KT_SLOTS = ["class0", "class1", "class2", "class3", "huge", "check", "queue", "sort", "mcc", "gate",
-            "relax", "deferred", "moments", "dsmc"]
+            "relax", "deferred", "moments", "dsmc", "p2c"]
 
 
 def _dt(v: torch.Tensor) -> int:
@@ -225,6 +226,15 @@ class Context:
                                         mass_ratio, seed, step, _p(sel)),
              "mcc_null_collide_exact")
         return sel[:n] if selected else None
+
+    def p2c_sums(self, q: torch.Tensor, cell_of: torch.Tensor, n_cells: int, out=None):
+        """Per-cell sums of the rows of q (nq, n) over the particles of each cell."""
+        self._stream()
+        nq, n = q.shape
+        if out is None:
+            out = torch.empty((n_cells, nq), dtype=torch.float64, device=q.device)
+        _chk(lib.p2c_sums(self._h, _dt(q), _p(q), nq, _p(cell_of), n, n_cells, _p(out)), "p2c_sums")
+        return out
 
     # -------------------------------------------------------------- learned gate
     def features(self, moments: torch.Tensor):
