@@ -62,6 +62,9 @@ def lib():
         L.orc_mcc_exact.argtypes = [f64p, u32p, C.c_int64, C.c_double, C.c_double, C.c_double,
                                     C.c_double, C.c_uint64, C.c_uint64, C.c_void_p]
         L.orc_mcc_exact.restype = C.c_int
+        L.orc_recombine.argtypes = [f64p, f64p, u32p, C.c_void_p, C.c_int64, i32p, C.c_int32,
+                                    C.c_double, C.c_uint64, C.c_uint64, C.c_void_p]
+        L.orc_recombine.restype = C.c_int
         L.orc_p2c.argtypes = [f64p, C.c_int32, i32p, C.c_int64, C.c_int32, f64p]
         L.orc_p2c.restype = C.c_int64
         L.orc_dsmc_sigma.argtypes = [C.c_int32, C.c_double, C.c_int32, f64p, f64p, f64p]
@@ -183,6 +186,22 @@ def mcc_exact(v, pid, dt, sigma0, n_neutral, mass_ratio, seed, step):
     if rc:
         raise ValueError(f"orc_mcc_exact failed: {rc}")
     return flags[:n]
+
+
+def recombine(v, w, pid, primary, cell_start, eps, seed, step):
+    """Recombination C5 in place on v (3, n) and w (n,) float64, storage in
+    cell order; returns the per-cell event counts."""
+    n = v.shape[1]
+    pid = np.ascontiguousarray(pid, dtype=np.uint32)
+    primary = np.ascontiguousarray(primary, dtype=np.uint8)
+    cell_start = np.ascontiguousarray(cell_start, dtype=np.int32)
+    M = cell_start.size - 1
+    ev = np.zeros(max(M, 1), np.int32)
+    rc = lib().orc_recombine(v.reshape(-1), w, pid, primary.ctypes.data, n, cell_start, M, eps,
+                             seed, step, ev.ctypes.data)
+    if rc:
+        raise ValueError(f"orc_recombine failed: {rc}")
+    return ev[:M]
 
 
 def p2c(q, cell_of, n_cells: int):

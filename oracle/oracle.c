@@ -718,3 +718,62 @@ int64_t orc_p2c(const double *q, int32_t nq, const int32_t *cell_of, int64_t n, 
     }
     return bad;
 }
+
+/* ------------------------------------------------------------------ */
+/* Recombination C5 (section "Kernel for Recombination Collision C5"): */
+/* in each cell the primaries (flag set, weight > 0) are matched one   */
+/* to one with catalytes (flag clear, weight > 0).  Reading of the     */
+/* atomic pop: catalytes are taken in storage order from a per-cell    */
+/* offset o_j = floor(word0 C_j / 2^32) (domain 9 draw on the cell     */
+/* index), wrapping: the k-th primary in storage order gets the        */
+/* catalyte of rank (o_j + k) mod C_j, for k < min(P_j, C_j).  The     */
+/* catalyte takes the primary's kinetic energy plus the released       */
+/* energy eps (|v|^2 / 2 units) in an isotropic direction (words 1, 2  */
+/* of a domain 8 draw on its pid); the primary's weight becomes 0.     */
+/* Storage in cell order, cell_start of M + 1 entries.  events[j]      */
+/* (nullable) receives the number of recombinations in cell j.         */
+/* ------------------------------------------------------------------ */
+int orc_recombine(double *v, double *w, const uint32_t *pid, const uint8_t *primary, int64_t n,
+                  const int32_t *cell_start, int32_t M, double eps, uint64_t seed, uint64_t step,
+                  int32_t *events)
+{
+    double *vx = v, *vy = v + n, *vz = v + 2 * n;
+    int64_t *prim = malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    int64_t *cat = malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    if (!prim || !cat) {
+        free(prim);
+        free(cat);
+        return 2;
+    }
+    for (int32_t j = 0; j < M; ++j) {
+        int64_t P = 0, C = 0;
+        for (int64_t l = cell_start[j]; l < cell_start[j + 1]; ++l) {
+            if (!(w[l] > 0.0)) continue;
+            if (primary[l]) prim[P++] = l;
+            else cat[C++] = l;
+        }
+        const int64_t m = P < C ? P : C;
+        if (events) events[j] = (int32_t)m;
+        if (m == 0) continue;
+        uint32_t cw[4];
+        draw(seed, (uint32_t)j, step, 9u, 0u, cw);
+        const int64_t o = (int64_t)(((uint64_t)cw[0] * (uint64_t)C) >> 32);
+        for (int64_t k = 0; k < m; ++k) {
+            const int64_t p = prim[k], c = cat[(o + k) % C];
+            const double ep = 0.5 * (vx[p] * vx[p] + vy[p] * vy[p] + vz[p] * vz[p]);
+            const double ec = 0.5 * (vx[c] * vx[c] + vy[c] * vy[c] + vz[c] * vz[c]);
+            const double sp = sqrt(2.0 * (ec + ep + eps));
+            uint32_t dw[4];
+            double s[3];
+            draw(seed, pid[c], step, 8u, 0u, dw);
+            iso_dir(dw[1], dw[2], s);
+            vx[c] = sp * s[0];
+            vy[c] = sp * s[1];
+            vz[c] = sp * s[2];
+            w[p] = 0.0;
+        }
+    }
+    free(prim);
+    free(cat);
+    return 0;
+}
