@@ -206,6 +206,26 @@ int mcc_null_collide_exact(pic_ctx *ctx, int dtype, void *v, const uint32_t *pid
                            double dt, double sigma0, double n_neutral, double mass_ratio,
                            uint64_t seed, uint64_t step, uint8_t *selected_out);
 
+/* Recombination C5 (section "Kernel for Recombination Collision C5", table
+ * "Recombination Steps" RS1-RS5): in each cell the live primaries
+ * (primary[l] != 0, w[l] > 0; the paper's list from step CS3) are matched one
+ * to one with the live catalytes (primary[l] == 0, w[l] > 0) of the same
+ * cell.  The paper pops catalytes from per-cell lists with atomics; here the
+ * matching is fixed: the k-th primary in storage order takes the catalyte of
+ * rank (o_j + k) mod C_j in storage order, o_j = floor(word0 C_j / 2^32) of a
+ * Philox draw (domain 9, counter = cell index), for k < min(P_j, C_j).  The
+ * catalyte's speed becomes sqrt(2 (|v_c|^2/2 + |v_p|^2/2 + eps)) in an
+ * isotropic direction (words 1, 2 of a domain-8 draw on its pid); the
+ * primary's weight becomes 0 (RS5).  Storage in cell order: cell_start of
+ * n_cells + 1 entries as pic_bin_cells returns.  v (3 x n SoA) and w (n)
+ * of the velocity dtype, updated in place; events (nullable, n_cells int32)
+ * receives min(P_j, C_j).  Errors: PIC_ERR_ARG (NULL arrays with n > 0,
+ * n < 0 or n > 2^31 - 1, n_cells < 1, eps negative or not finite),
+ * PIC_ERR_DTYPE. */
+int recombine(pic_ctx *ctx, int dtype, void *v, void *w, const uint32_t *pid, const uint8_t *primary,
+              int64_t n, const int32_t *cell_start, int32_t n_cells, double eps, uint64_t seed,
+              uint64_t step, int32_t *events);
+
 /* Particle-to-cell sums (section "Particle-to-Cell"; steps S3a-S3b of the
  * PIC scheme table): out[j * nq + k] = sum over the particles l with
  * cell_of[l] == j of q[k * n + l], for cells j < n_cells and quantities
@@ -337,7 +357,8 @@ int pic_time_kernels(pic_ctx *ctx, int on);
  * and cell starts, 6 work queue, 7 re-binning passes, 8 stand-alone
  * null-collision step, 9 learned-gate decision, 10 relaxation of the
  * judged cells, 11 null collisions of deferred cells, 12 gate's moment
- * pass, 13 DSMC-Coll step, 14 particle-to-cell sums (16 slots are reserved). */
+ * pass, 13 DSMC-Coll step, 14 particle-to-cell sums, 15 recombination (16 slots
+ * are reserved). */
 int pic_kernel_times(pic_ctx *ctx, double *ms, int64_t *count);
 
 /* ---------------------------------------------------------------- test exports */

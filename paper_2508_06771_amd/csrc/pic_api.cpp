@@ -1057,6 +1057,33 @@ int mcc_null_collide_exact(pic_ctx *c, int dtype, void *v, const uint32_t *pid, 
     return rc;
 }
 
+int recombine(pic_ctx *c, int dtype, void *v, void *w, const uint32_t *pid, const uint8_t *primary,
+              int64_t n, const int32_t *cell_start, int32_t n_cells, double eps, uint64_t seed,
+              uint64_t step, int32_t *events)
+{
+    if (!c || n < 0 || n > INT32_MAX || n_cells < 1 || !cell_start || !(eps >= 0.0) ||
+        !(eps < 1e300) || (n > 0 && (!v || !w || !pid || !primary)))
+        return PIC_ERR_ARG;
+    RC(check_dtype(dtype));
+    CK(hipSetDevice(c->device));
+    RecombArgs a;
+    a.v = v;
+    a.w = w;
+    a.pid = pid;
+    a.primary = primary;
+    a.n = n;
+    a.cs = cell_start;
+    a.M = n_cells;
+    a.eps = eps;
+    a.seed = seed;
+    a.step = (uint32_t)step;
+    a.events = events;
+    ktime_begin(KT_RECOMB, c->stream);
+    const int rc = launch_recombine(dtype, a, c->num_cu, c->stream);
+    ktime_end(KT_RECOMB, c->stream);
+    return rc;
+}
+
 int p2c_sums(pic_ctx *c, int dtype, const void *q, int32_t nq, const int32_t *cell_of, int64_t n,
              int32_t n_cells, double *out)
 {

@@ -638,7 +638,7 @@ struct RadixPass {
 // 7 re-binning passes, 8 stand-alone null-collision step, 9 learned gate
 // decision, 10 relaxation of the judged cells.
 enum { KT_CLASS0 = 0, KT_HUGE = 4, KT_CHECK = 5, KT_QUEUE = 6, KT_SORT = 7, KT_MCC = 8, KT_GATE = 9,
-       KT_RELAX = 10, KT_DEFER = 11, KT_MOMENTS = 12, KT_DSMC = 13, KT_P2C = 14, KT_SLOTS = 16 };
+       KT_RELAX = 10, KT_DEFER = 11, KT_MOMENTS = 12, KT_DSMC = 13, KT_P2C = 14, KT_RECOMB = 15, KT_SLOTS = 16 };
 void ktime_begin(int slot, hipStream_t st);
 void ktime_end(int slot, hipStream_t st);
 bool ktime_pause();            // returns whether timing was on
@@ -830,6 +830,22 @@ struct DsmcArgs {
     DevFlags *dflags;
 };
 int launch_dsmc(int dtype, const DsmcArgs &a, const DsmcTable &t, hipStream_t st);
+
+// Recombination C5 on cell-sorted storage (v and w of the velocity dtype).
+struct RecombArgs {
+    void *v;
+    void *w;
+    const uint32_t *pid;
+    const uint8_t *primary;
+    int64_t n;
+    const int32_t *cs;
+    int32_t M;
+    double eps;
+    uint64_t seed;
+    uint32_t step;
+    int32_t *events;
+};
+int launch_recombine(int dtype, const RecombArgs &a, int num_cu, hipStream_t st);
 
 // Particle-to-cell sums out[j * nq + k] (binary64) of nq <= 4 quantities
 // q[k * n + l] over the particles l of cell j.  ws: p2c_ws_bytes(...).

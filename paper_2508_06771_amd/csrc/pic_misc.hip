@@ -267,6 +267,144 @@ __global__ __launch_bounds__(256) void k_dsmc(DsmcArgs a, DsmcTable t)
     }
 }
 
+// ------------------------------------------------------------ recombination
+// Recombination C5 on cell-sorted storage, one workgroup per cell.  The
+// paper pops catalytes from per-cell lists with atomics; here the matching
+// is fixed: the k-th live primary of the cell in storage order takes the
+// live catalyte of rank (o_j + k) mod C_j, o_j = floor(word0 C_j / 2^32) of
+// a domain-9 draw on the cell index, for k < min(P_j, C_j).  Each wave walks
+// a quarter of the cell with a running count (ballots, no barriers); the
+// quarters' counts give each wave its starting ranks.  Primaries of ranks
+// [k0, k0 + RC_CAP) are parked in LDS, then the catalytes matched to them
+// are updated: energy |v_c|^2/2 + |v_p|^2/2 + eps, isotropic direction from
+// words 1, 2 of a domain-8 draw on the catalyte's pid; the matched
+// primaries' weights become 0 at the end.
+constexpr int RC_T = 256;
+constexpr int RC_W = RC_T / PIC_WAVE;
+constexpr int RC_CAP = 2048;
+constexpr int RC_U = 8;   // 64-member chunks whose loads are in flight together
+
+// Walks members [qs, qe) in 64-member chunks, calling f(l, alive, primary)
+// with the whole wave for each chunk in order until f returns false (f's
+// result must be the same on every lane).  The loads of RC_U chunks are
+// issued together, past-the-end lanes reloading member qe - 1 (masked).
+template <typename R, typename F>
+__device__ __forceinline__ void rc_walk(const R *__restrict__ w, const uint8_t *__restrict__ primary, int64_t qs,
+                                        int64_t qe, F &&f)
+{
+    const int lane = threadIdx.x & (PIC_WAVE - 1);
+    for (int64_t i0 = qs; i0 < qe; i0 += RC_U * PIC_WAVE) {
+        R wv[RC_U];
+        uint8_t pv[RC_U];
+#pragma unroll
+        for (int u = 0; u < RC_U; ++u) {
+            int64_t l = i0 + u * PIC_WAVE + lane;
+            l = l < qe ? l : qe - 1;
+            wv[u] = w[l];
+            pv[u] = primary[l];
+        }
+#pragma unroll
+        for (int u = 0; u < RC_U; ++u) {
+            const int64_t l = i0 + u * PIC_WAVE + lane;
+            const bool alive = l < qe && wv[u] > (R)0;
+            if (!f(l, alive, alive && pv[u] != 0)) return;
+        }
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(RC_T) void k_recombine(RecombArgs a)
+{
+#pragma clang fp contract(off)
+    __shared__ uint32_t s_prim[RC_CAP];
+    __shared__ uint32_t s_cnt[2 * RC_W];
+    R *v = (R *)a.v;
+    R *w = (R *)a.w;
+    const int64_t n = a.n;
+    const int lane = threadIdx.x & (PIC_WAVE - 1), wid = threadIdx.x / PIC_WAVE;
+    const uint64_t below = (1ull << lane) - 1ull;
+    for (int32_t j = blockIdx.x; j < a.M; j += gridDim.x) {
+        const int64_t s = a.cs[j], e = a.cs[j + 1];
+        const int64_t q = (e - s + RC_W - 1) / RC_W;
+        const int64_t qs = s + wid * q, qe = qs + q < e ? qs + q : e;
+        uint32_t P = 0, C = 0;
+        rc_walk(w, a.primary, qs, qe, [&](int64_t, bool alive, bool pr) {
+            P += (uint32_t)__popcll(__ballot(pr));
+            C += (uint32_t)__popcll(__ballot(alive && !pr));
+            return true;
+        });
+        if (lane == 0) {
+            s_cnt[wid] = P;
+            s_cnt[RC_W + wid] = C;
+        }
+        __syncthreads();
+        uint32_t Pt = 0, Ct = 0, Pb = 0, Cb = 0;
+#pragma unroll
+        for (int x = 0; x < RC_W; ++x) {
+            Pt += s_cnt[x];
+            Ct += s_cnt[RC_W + x];
+            if (x < wid) {
+                Pb += s_cnt[x];
+                Cb += s_cnt[RC_W + x];
+            }
+        }
+        const uint32_t m = Pt < Ct ? Pt : Ct;
+        if (threadIdx.x == 0 && a.events) a.events[j] = (int32_t)m;
+        if (m > 0) {
+            const uint32_t o = (uint32_t)(((uint64_t)draw4(a.seed, (uint32_t)j, a.step, 9u, 0u).x * Ct) >> 32);
+            for (uint32_t k0 = 0; k0 < m; k0 += RC_CAP) {
+                const uint32_t k1 = m < k0 + RC_CAP ? m : k0 + RC_CAP;
+                uint32_t r0 = Pb;   // rank of this wave's next primary
+                if (r0 < k1)
+                    rc_walk(w, a.primary, qs, qe, [&](int64_t l, bool, bool pr) {
+                        const uint64_t bm = __ballot(pr);
+                        const uint32_t r = r0 + (uint32_t)__popcll(bm & below);
+                        if (pr && r >= k0 && r < k1) s_prim[r - k0] = (uint32_t)l;
+                        r0 += (uint32_t)__popcll(bm);
+                        return r0 < k1;
+                    });
+                __syncthreads();
+                uint32_t c0 = Cb;   // rank of this wave's next catalyte
+                rc_walk(w, a.primary, qs, qe, [&](int64_t l, bool alive, bool pr) {
+                    const bool ct = alive && !pr;
+                    const uint64_t bm = __ballot(ct);
+                    const uint32_t r = c0 + (uint32_t)__popcll(bm & below);
+                    c0 += (uint32_t)__popcll(bm);
+                    const uint32_t kk = ct ? (uint32_t)(((uint64_t)r + Ct - o) % Ct) : 0u;
+                    if (ct && kk >= k0 && kk < k1) {
+                        const int64_t p = s_prim[kk - k0];
+                        const double px = v[p], py = v[n + p], pz = v[2 * n + p];
+                        const double cx = v[l], cy = v[n + l], cz = v[2 * n + l];
+                        const double ep = 0.5 * (px * px + py * py + pz * pz);
+                        const double ec = 0.5 * (cx * cx + cy * cy + cz * cz);
+                        const double sp = sqrt(2.0 * (ec + ep + a.eps));
+                        const W4 dw = draw4(a.seed, a.pid[l], a.step, 8u, 0u);
+                        double sx, sy, sz;
+                        dsmc_dir(dw.y, dw.z, sx, sy, sz);
+                        v[l] = (R)(sp * sx);
+                        v[n + l] = (R)(sp * sy);
+                        v[2 * n + l] = (R)(sp * sz);
+                    }
+                    return true;
+                });
+                __syncthreads();   // s_prim is refilled by the next round
+            }
+            // the matched primaries are the first m: their weights go to 0
+            // only now, so every round above ranked the same live primaries
+            uint32_t r0 = Pb;
+            if (r0 < m)
+                rc_walk(w, a.primary, qs, qe, [&](int64_t l, bool, bool pr) {
+                    const uint64_t bm = __ballot(pr);
+                    const uint32_t r = r0 + (uint32_t)__popcll(bm & below);
+                    r0 += (uint32_t)__popcll(bm);
+                    if (pr && r < m) w[l] = (R)0;
+                    return r0 < m;
+                });
+        }
+        __syncthreads();   // s_cnt is rewritten for the next cell
+    }
+}
+
 // ------------------------------------------------------------ exact count
 // The k smallest candidate words.  The words are uniform, so the k-th lies
 // within a few binomial standard deviations of k 2^32 / n: one pass draws
@@ -741,6 +879,18 @@ int launch_mcc_exact(int dtype, void *v, const uint32_t *pid, int64_t n, int64_t
     else
         hipLaunchKernelGGL(k_exact_scatter<double>, dim3(p.G), dim3(256), 0, st, (double *)v, pid, n, b,
                            mass_ratio, seed, (uint32_t)step, selected_out);
+    HIP_OK(hipGetLastError());
+    return PIC_OK;
+}
+
+int launch_recombine(int dtype, const RecombArgs &a, int num_cu, hipStream_t st)
+{
+    if (a.M <= 0) return PIC_OK;
+    const int g = a.M < num_cu * 8 ? a.M : num_cu * 8;
+    if (dtype == PIC_F32)
+        hipLaunchKernelGGL(k_recombine<float>, dim3(g), dim3(RC_T), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_recombine<double>, dim3(g), dim3(RC_T), 0, st, a);
     HIP_OK(hipGetLastError());
     return PIC_OK;
 }

@@ -58,6 +58,7 @@ def _load():
         "mcc_null_collide_exact": ([vp, C.c_int, vp, vp, i64, f64, f64, f64, f64, u64, u64, vp],
                                    C.c_int),
         "p2c_sums": ([vp, C.c_int, vp, C.c_int32, vp, i64, C.c_int32, vp], C.c_int),
+        "recombine": ([vp, C.c_int, vp, vp, vp, vp, i64, vp, C.c_int32, f64, u64, u64, vp], C.c_int),
         "coulomb_pairs": ([vp, vp, vp, i32, u64, u64, vp, vp], C.c_int),
         "pic_cell_moments": ([vp, C.c_int, vp, i64, vp, i32, vp], C.c_int),
         "pic_unsort": ([vp, C.c_int, vp, vp, vp, i64], C.c_int),
@@ -99,14 +100,14 @@ EXPORTED = ["pic_create", "pic_destroy", "pic_strerror", "pic_sync", "pic_set_st
             "pic_relaxation", "pic_mlp_forward", "pic_mlp_grad", "pic_mlp_train_step",
             "pic_gate_config", "pic_gate_reset", "pic_gate_stats", "pic_gate_state", "pic_autotune",
             "pic_conserve_reset", "pic_gate_refresh", "gate_infer", "pic_set_dsmc", "dsmc_collide",
-            "mcc_null_collide_exact", "p2c_sums"]
+            "mcc_null_collide_exact", "p2c_sums", "recombine"]
 
 MLP_PARAMS = 4801
 GATE_STATS = ["steps", "skipped", "collided", "judged", "judged_want", "false_skip", "disabled",
               "have_moments"]
 
 KT_SLOTS = ["class0", "class1", "class2", "class3", "huge", "check", "queue", "sort", "mcc", "gate",
-            "relax", "deferred", "moments", "dsmc", "p2c"]
+            "relax", "deferred", "moments", "dsmc", "p2c", "recombine"]
 
 
 def _dt(v: torch.Tensor) -> int:
@@ -226,6 +227,19 @@ class Context:
                                         mass_ratio, seed, step, _p(sel)),
              "mcc_null_collide_exact")
         return sel[:n] if selected else None
+
+    def recombine(self, v: torch.Tensor, w: torch.Tensor, pid: torch.Tensor, primary: torch.Tensor,
+                  cell_start: torch.Tensor, *, eps: float, seed: int, step: int, events=False):
+        """Recombination C5 in place on v and w (cell-sorted storage)."""
+        self._stream()
+        n = v.shape[1]
+        M = cell_start.numel() - 1
+        if w.dtype != v.dtype:
+            raise TypeError("weights must have the velocity dtype")
+        ev = torch.empty(M, dtype=torch.int32, device=v.device) if events else None
+        _chk(lib.recombine(self._h, _dt(v), _p(v), _p(w), _p(pid), _p(primary), n, _p(cell_start), M,
+                           eps, seed, step, _p(ev)), "recombine")
+        return ev
 
     def p2c_sums(self, q: torch.Tensor, cell_of: torch.Tensor, n_cells: int, out=None):
         """Per-cell sums of the rows of q (nq, n) over the particles of each cell."""
