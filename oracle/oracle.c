@@ -777,3 +777,99 @@ int orc_recombine(double *v, double *w, const uint32_t *pid, const uint8_t *prim
     free(cat);
     return 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* Nanbu's Coulomb operator (the alternative to Takizuka & Abe the    */
+/* paper names in its related work).  Same pairs as the T&A step; the */
+/* pair (a, b), a the lower slot, turns its relative velocity by an   */
+/* angle chi whose cosine has density proportional to exp(A cos chi), */
+/* A solving coth A - 1/A = exp(-s), so that <cos chi> = exp(-s).      */
+/* Reading: s = 2 s2 with s2 the T&A variance of tan(Theta/2), so both */
+/* operators have the same small-angle diffusion (<chi^2> ~ 2 s).      */
+/* cos chi by inversion of its distribution with U = U(word 2 of a);  */
+/* azimuth 2 pi U(word 2 of b); rotation and halves as in T&A.         */
+/* ------------------------------------------------------------------ */
+/* Langevin function coth A - 1/A and its derivative (series below 0.1). */
+static void langevin(double A, double *L, double *dL)
+{
+    if (A < 0.1) {
+        double A2 = A * A;
+        *L = A * (1.0 / 3.0 - A2 * (1.0 / 45.0 - A2 * (2.0 / 945.0 - A2 / 4725.0)));
+        *dL = 1.0 / 3.0 - A2 * (1.0 / 15.0 - A2 * (2.0 / 189.0 - A2 / 675.0));
+    } else {
+        double sh = sinh(A);
+        *L = cosh(A) / sh - 1.0 / A;
+        *dL = 1.0 / (A * A) - 1.0 / (sh * sh);
+    }
+}
+
+double orc_nanbu_A(double s)
+{
+    if (s <= 0.01) return -1.0 / expm1(-s);       /* coth A = 1 to double precision */
+    double y = exp(-s);
+    if (s > 11.5) return 3.0 * y;                 /* L(A) = A/3 to 1e-10 */
+    double A = y * (3.0 - y * y) / (1.0 - y * y); /* approximate inverse, then Newton */
+    for (int it = 0; it < 8; ++it) {
+        double L, dL;
+        langevin(A, &L, &dL);
+        A -= (L - y) / dL;
+    }
+    return A;
+}
+
+/* 1 - cos chi for the uniform U. */
+double orc_nanbu_omc(double A, double U)
+{
+    if (!(A > 1e-300)) return 2.0 * (1.0 - U);    /* isotropic */
+    double omc = -log1p(-(1.0 - U) * -expm1(-2.0 * A)) / A;
+    return omc < 2.0 ? omc : 2.0;
+}
+
+int orc_nanbu(double *v, int64_t n, const int32_t *cell_start, const uint32_t *pid, int32_t M,
+              double dt, double lnL, const double *density, uint64_t seed, uint64_t step)
+{
+    if (cell_start[M] != n) return 1;
+    int32_t *sorted = malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    int32_t *partner = malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    if (!sorted || !partner) {
+        free(sorted);
+        free(partner);
+        return 2;
+    }
+    int rc = orc_pairs(cell_start, pid, M, seed, step, sorted, partner);
+    double *vx = v, *vy = v + n, *vz = v + 2 * n;
+    for (int32_t j = 0; j < M && !rc; ++j) {
+        double dens = density ? density[j] : 1.0;
+        for (int64_t a = cell_start[j]; a < cell_start[j + 1]; ++a) {
+            int64_t b = partner[a];
+            if (b <= a) continue;
+            double u[3] = {vx[a] - vx[b], vy[a] - vy[b], vz[a] - vz[b]};
+            double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+            if (uu == 0.0) continue;
+            double um = sqrt(uu), uperp = sqrt(u[0] * u[0] + u[1] * u[1]);
+            double s = 2.0 * orc_ta_s2(um, dens, lnL, dt);
+            uint32_t wa[4], wb[4];
+            draw(seed, pid[a], step, 0u, 0u, wa);
+            draw(seed, pid[b], step, 0u, 0u, wb);
+            double omc = orc_nanbu_omc(orc_nanbu_A(s), orc_u01(wa[2]));
+            double sin_t = sqrt(omc * (2.0 - omc));
+            double phi = 2.0 * ORC_PI * orc_u01(wb[2]);
+            double cphi = cos(phi), sphi = sin(phi), du[3];
+            if (uperp > 0.0) {
+                du[0] = (u[0] / uperp) * u[2] * sin_t * cphi - (u[1] / uperp) * um * sin_t * sphi - u[0] * omc;
+                du[1] = (u[1] / uperp) * u[2] * sin_t * cphi + (u[0] / uperp) * um * sin_t * sphi - u[1] * omc;
+                du[2] = -uperp * sin_t * cphi - u[2] * omc;
+            } else {
+                du[0] = um * sin_t * cphi;
+                du[1] = um * sin_t * sphi;
+                du[2] = -u[2] * omc;
+            }
+            double h0 = 0.5 * du[0], h1 = 0.5 * du[1], h2 = 0.5 * du[2];
+            vx[a] += h0; vy[a] += h1; vz[a] += h2;
+            vx[b] -= h0; vy[b] -= h1; vz[b] -= h2;
+        }
+    }
+    free(sorted);
+    free(partner);
+    return rc;
+}
