@@ -796,10 +796,10 @@ static void langevin(double A, double *L, double *dL)
         double A2 = A * A;
         *L = A * (1.0 / 3.0 - A2 * (1.0 / 45.0 - A2 * (2.0 / 945.0 - A2 / 4725.0)));
         *dL = 1.0 / 3.0 - A2 * (1.0 / 15.0 - A2 * (2.0 / 189.0 - A2 / 675.0));
-    } else {
-        double sh = sinh(A);
-        *L = cosh(A) / sh - 1.0 / A;
-        *dL = 1.0 / (A * A) - 1.0 / (sh * sh);
+    } else {   /* t = exp(-2A): coth A = (1 + t)/(1 - t), 1/sinh^2 A = 4t/(1 - t)^2 */
+        double t = exp(-2.0 * A), d = 1.0 - t;
+        *L = (1.0 + t) / d - 1.0 / A;
+        *dL = 1.0 / (A * A) - 4.0 * t / (d * d);
     }
 }
 
@@ -809,7 +809,7 @@ double orc_nanbu_A(double s)
     double y = exp(-s);
     if (s > 11.5) return 3.0 * y;                 /* L(A) = A/3 to 1e-10 */
     double A = y * (3.0 - y * y) / (1.0 - y * y); /* approximate inverse, then Newton */
-    for (int it = 0; it < 8; ++it) {
+    for (int it = 0; it < 4; ++it) {   /* from within 2%: quadratic convergence */
         double L, dL;
         langevin(A, &L, &dL);
         A -= (L - y) / dL;
@@ -817,11 +817,15 @@ double orc_nanbu_A(double s)
     return A;
 }
 
-/* 1 - cos chi for the uniform U. */
+/* 1 - cos chi for the uniform U: -log(U + (1 - U) exp(-2A)) / A, the
+ * argument written 1 - q with q = (1 - U)(1 - exp(-2A)) while q < 1/2 (log1p
+ * of -q), and as the sum itself otherwise (no cancellation when U and
+ * exp(-2A) are both small). */
 double orc_nanbu_omc(double A, double U)
 {
     if (!(A > 1e-300)) return 2.0 * (1.0 - U);    /* isotropic */
-    double omc = -log1p(-(1.0 - U) * -expm1(-2.0 * A)) / A;
+    double q = (1.0 - U) * -expm1(-2.0 * A);
+    double omc = q < 0.5 ? -log1p(-q) / A : -log(U + (1.0 - U) * exp(-2.0 * A)) / A;
     return omc < 2.0 ? omc : 2.0;
 }
 
