@@ -545,6 +545,49 @@ def bench_recombine(args):
                            "bytes_per_electron": round(per_e, 3)})
 
 
+def bench_nanbu(args):
+    """Nanbu's Coulomb operator on the 4096 x 10,000 population in cell-sorted
+    storage, FP32 velocities, binary64 arithmetic: the pairing of the
+    Takizuka-Abe step, then one thread per pair."""
+    import numpy as np
+    import torch
+
+    from paper_2508_06771_amd import piccoll, workloads
+    w = workloads.c2(0)
+    n, M = w.n, w.n_cells
+    order = np.argsort(w.cell_of, kind="stable")
+    v = torch.from_numpy(np.ascontiguousarray(w.v[:, order])).cuda()
+    pid = torch.from_numpy(np.ascontiguousarray(w.pid[order]).view(np.int32)).cuda()
+    cs = torch.from_numpy(np.searchsorted(w.cell_of[order], np.arange(M + 1)).astype(np.int32)).cuda()
+    ctx = piccoll.Context(0)
+    kw = dict(dt=w.dt, lnL=w.lnL, seed=0)
+    for s in range(args.warmup):
+        ctx.nanbu(v, pid, cs, step=s, **kw)
+    ctx.sync()
+    K = args.steps
+    ms = _timed(torch, lambda: [ctx.nanbu(v, pid, cs, step=args.warmup + s, **kw) for s in range(K)]) / K
+    ctx.time_kernels(True)
+    ctx.kernel_times()
+    for s in range(4):
+        ctx.nanbu(v, pid, cs, step=1000 + s, **kw)
+    ctx.sync()
+    kt = ctx.kernel_times()
+    ctx.time_kernels(False)
+    ctx.close()
+    kern_ms = kt["nanbu"][0] / kt["nanbu"][1]
+    # algorithmic bytes as the Takizuka-Abe step: pid 4 + v 12 read, v 12 written
+    per_e = 28.0
+    achieved = per_e * n / (kern_ms * 1e-3) / 1e9
+    return _line(n / (ms * 1e-3), ms, args, "f32",
+                 {"workload": f"Nanbu Coulomb step on 4096 cells x 10,000 electrons ({n}), FP32 storage, "
+                              "binary64 arithmetic, cell-sorted storage",
+                  "n_electrons": n},
+                 roofline={"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0,
+                           "unit": "GB/s", "frac": round(achieved / 8000.0, 4), "traffic": None,
+                           "kernel": "pairing (class kernels, pairs only) + k_nanbu<float>",
+                           "kernel_avg_ms": round(kern_ms, 5), "bytes_per_electron": per_e})
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -553,12 +596,13 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-kernel-timing", action="store_true")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "dsmc", "mcc_exact", "p2c", "recombine"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "dsmc", "mcc_exact", "p2c", "recombine",
+                                                              "nanbu"],
                     help="c2: the headline configuration; c3: log-normal cell sizes, autotuned "
                          "routing, graph replays; c4: precision study; c5: learned gate vs plain; "
                          "dsmc: electron-heavy collisions C1..C4 with ionization; mcc_exact: "
                          "exact-count null-collision selection; p2c: particle-to-cell sums; recombine: "
-                         "recombination C5")
+                         "recombination C5; nanbu: Nanbu's Coulomb operator")
     ap.add_argument("--eager", action="store_true",
                     help="time one coulomb_collide call per step instead of graph replays")
     ap.add_argument("--kernel-steps", type=int, default=10,
@@ -583,7 +627,7 @@ def main():
     if args.workload != "c2":
         out = {"c3": bench_c3, "c4": bench_c4, "c5": bench_c5, "dsmc": bench_dsmc,
                "mcc_exact": bench_mcc_exact, "p2c": bench_p2c,
-               "recombine": bench_recombine}[args.workload](args)
+               "recombine": bench_recombine, "nanbu": bench_nanbu}[args.workload](args)
         print(json.dumps(out), flush=True)
         return
 

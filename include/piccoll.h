@@ -206,6 +206,23 @@ int mcc_null_collide_exact(pic_ctx *ctx, int dtype, void *v, const uint32_t *pid
                            double dt, double sigma0, double n_neutral, double mass_ratio,
                            uint64_t seed, uint64_t step, uint8_t *selected_out);
 
+/* Nanbu's Coulomb operator (the alternative to the Takizuka & Abe method the
+ * paper names in its related work) on the pairs of coulomb_collide: same
+ * pairing (the cell's members ordered by (word 0, pid) of the step's draw,
+ * pairs (2i, 2i+1)); the pair (a, b), a the lower slot, turns its relative
+ * velocity u by chi with cos chi distributed as exp(A cos chi), A solving
+ * coth A - 1/A = exp(-s), s = 16 pi n lnLambda dt / |u|^3 (twice the Takizuka
+ * & Abe variance of tan(Theta/2), so both have the same small-angle
+ * diffusion); U = U(word 2 of a) inverts its distribution function, the
+ * azimuth is 2 pi U(word 2 of b).  Momentum and energy of each pair are kept.
+ * Storage in cell order, cell_start of n_cells + 1 entries; density per cell
+ * (nullable: 1).  Arithmetic in binary64 for either dtype.  Errors:
+ * PIC_ERR_ARG (NULL arrays with n > 0, n < 0 or n > 2^31 - 1, n_cells < 1,
+ * dt <= 0, lnLambda <= 0), PIC_ERR_DTYPE, PIC_ERR_NOMEM. */
+int coulomb_collide_nanbu(pic_ctx *ctx, int dtype, void *v, const uint32_t *pid, int64_t n,
+                          const int32_t *cell_start, int32_t n_cells, double dt, double lnLambda,
+                          const double *density, uint64_t seed, uint64_t step);
+
 /* Recombination C5 (section "Kernel for Recombination Collision C5", table
  * "Recombination Steps" RS1-RS5): in each cell the live primaries
  * (primary[l] != 0, w[l] > 0; the paper's list from step CS3) are matched one
@@ -357,8 +374,8 @@ int pic_time_kernels(pic_ctx *ctx, int on);
  * and cell starts, 6 work queue, 7 re-binning passes, 8 stand-alone
  * null-collision step, 9 learned-gate decision, 10 relaxation of the
  * judged cells, 11 null collisions of deferred cells, 12 gate's moment
- * pass, 13 DSMC-Coll step, 14 particle-to-cell sums, 15 recombination (16 slots
- * are reserved). */
+ * pass, 13 DSMC-Coll step, 14 particle-to-cell sums, 15 recombination, 16
+ * Nanbu step (pairing and rotation) (ms and count hold 20 slots). */
 int pic_kernel_times(pic_ctx *ctx, double *ms, int64_t *count);
 
 /* ---------------------------------------------------------------- test exports */

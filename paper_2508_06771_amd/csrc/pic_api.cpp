@@ -1057,6 +1057,58 @@ int mcc_null_collide_exact(pic_ctx *c, int dtype, void *v, const uint32_t *pid, 
     return rc;
 }
 
+int coulomb_collide_nanbu(pic_ctx *c, int dtype, void *v, const uint32_t *pid, int64_t n,
+                          const int32_t *cell_start, int32_t n_cells, double dt, double lnL,
+                          const double *density, uint64_t seed, uint64_t step)
+{
+    if (!c || n < 0 || n > INT32_MAX || n_cells < 1 || !cell_start || !(dt > 0.0) || !(lnL > 0.0) ||
+        (n > 0 && (!v || !pid)))
+        return PIC_ERR_ARG;
+    RC(check_dtype(dtype));
+    if (n == 0) return PIC_OK;
+    CK(hipSetDevice(c->device));
+    const size_t need = (size_t)n_cells * QUEUE_LISTS * 4 + huge_scratch_bytes(PIC_F32, n) + 2 * ((size_t)n * 4 + 256) +
+                        4096;
+    RC(ensure_ws(c, need));
+    Bump b(c->ws);
+    int32_t *lists = (int32_t *)b.take((size_t)n_cells * QUEUE_LISTS * 4);
+    set_huge_scratch(PIC_F32, n, b.take(huge_scratch_bytes(PIC_F32, n)));
+    int32_t *sorted = (int32_t *)b.take((size_t)n * 4);
+    int32_t *partner = (int32_t *)b.take((size_t)n * 4);
+    ktime_begin(KT_NANBU, c->stream);
+    RC(launch_reset_flags(c->flags, c->stream));
+    const ClassCaps caps = collide_caps(PIC_F32, c->lds_max);
+    RC(launch_build_queue(cell_start, n_cells, caps, lists, c->flags, nullptr, 0, nullptr, 0, c->stream));
+    CollideArgs a;
+    memset(&a, 0, sizeof(a));
+    a.n = n;
+    a.pid = pid;
+    a.cell_start = cell_start;
+    a.dt = 1.0;
+    a.lnL = 1.0;
+    a.seed = seed;
+    a.step = step;
+    a.dflags = c->flags;
+    a.sorted_out = sorted;
+    a.partner_out = partner;
+    RC(launch_collide(PIC_F32, a, lists, n_cells, caps, 1, c->num_cu, c->stream));
+    NanbuArgs na;
+    na.v = v;
+    na.pid = pid;
+    na.partner = partner;
+    na.cs = cell_start;
+    na.density = density;
+    na.n = n;
+    na.M = n_cells;
+    na.dt = dt;
+    na.lnL = lnL;
+    na.seed = seed;
+    na.step = (uint32_t)step;
+    const int rc = launch_nanbu(dtype, na, c->stream);
+    ktime_end(KT_NANBU, c->stream);
+    return rc;
+}
+
 int recombine(pic_ctx *c, int dtype, void *v, void *w, const uint32_t *pid, const uint8_t *primary,
               int64_t n, const int32_t *cell_start, int32_t n_cells, double eps, uint64_t seed,
               uint64_t step, int32_t *events)

@@ -405,6 +405,125 @@ __global__ __launch_bounds__(RC_T) void k_recombine(RecombArgs a)
     }
 }
 
+// ------------------------------------------------------------ Nanbu
+// Nanbu's Coulomb operator on the pairs of the Takizuka-Abe step: the pair
+// (a, b), a the lower slot, turns its relative velocity u by chi with
+// 1 - cos chi = -log1p(-(1 - U)(1 - exp(-2A))) / A, U = U(word 2 of a),
+// A solving coth A - 1/A = exp(-s), s = 2 * 8 pi n lnL dt / |u|^3; azimuth
+// 2 pi U(word 2 of b); halves as in T&A.  Binary64 storage computes in
+// binary64 (the oracle's steps exactly); binary32 storage in binary32, with
+// the Langevin series used up to A = 0.5 (five terms) where the closed form
+// would cancel, and the large-A root up to s = 0.1.
+template <typename T>
+__device__ __forceinline__ void nb_langevin(T A, T &L, T &dL)
+{
+#pragma clang fp contract(off)
+    constexpr bool F = sizeof(T) == 4;
+    if (A < (F ? (T)0.5 : (T)0.1)) {
+        const T A2 = A * A;
+        if (F) {
+            L = A * ((T)(1.0 / 3.0) -
+                     A2 * ((T)(1.0 / 45.0) - A2 * ((T)(2.0 / 945.0) - A2 * ((T)(1.0 / 4725.0) -
+                                                                            A2 * (T)(2.0 / 93555.0)))));
+            dL = (T)(1.0 / 3.0) -
+                 A2 * ((T)(1.0 / 15.0) - A2 * ((T)(2.0 / 189.0) - A2 * ((T)(1.0 / 675.0) - A2 * (T)(2.0 / 10395.0))));
+        } else {
+            L = A * (1.0 / 3.0 - A2 * (1.0 / 45.0 - A2 * (2.0 / 945.0 - A2 / 4725.0)));
+            dL = 1.0 / 3.0 - A2 * (1.0 / 15.0 - A2 * (2.0 / 189.0 - A2 / 675.0));
+        }
+    } else {   // t = exp(-2A): coth A = (1 + t)/(1 - t), 1/sinh^2 A = 4t/(1 - t)^2
+        const T t = exp((T)-2 * A), d = (T)1 - t;
+        L = ((T)1 + t) / d - (T)1 / A;
+        dL = (T)1 / (A * A) - (T)4 * t / (d * d);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ T nb_A(T s)
+{
+#pragma clang fp contract(off)
+    // coth A = 1 to working precision: A > 8.3 in binary32, A > 18.7 in binary64
+    if (s <= (sizeof(T) == 4 ? (T)0.1 : (T)0.01)) return (T)-1 / expm1(-s);
+    const T y = exp(-s);
+    if (s > (T)11.5) return (T)3 * y;             // coth A - 1/A = A/3 to 1e-10
+    T A = y * ((T)3 - y * y) / ((T)1 - y * y);
+    for (int it = 0; it < 4; ++it) {   // from within 2%: quadratic convergence
+        T L, dL;
+        nb_langevin(A, L, dL);
+        A -= (L - y) / dL;
+    }
+    return A;
+}
+
+template <typename T>
+__device__ __forceinline__ T nb_omc(T A, T U)
+{
+#pragma clang fp contract(off)
+    if (!(A > (sizeof(T) == 4 ? (T)1e-30 : (T)1e-300))) return (T)2 * ((T)1 - U);
+    // -log(U + (1 - U) exp(-2A)) / A: through log1p(-q) while q < 1/2, else
+    // the sum itself (no cancellation when U and exp(-2A) are both small)
+    const T q = ((T)1 - U) * -expm1((T)-2 * A);
+    const T omc = q < (T)0.5 ? -log1p(-q) / A : -log(U + ((T)1 - U) * exp((T)-2 * A)) / A;
+    return omc < (T)2 ? omc : (T)2;
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_nanbu(NanbuArgs a)
+{
+#pragma clang fp contract(off)
+    R *vx = (R *)a.v;
+    R *vy = vx + a.n;
+    R *vz = vy + a.n;
+    const double PI = 3.14159265358979323846;
+    for (int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; l < a.n;
+         l += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = a.partner[l];
+        if (b <= l) continue;
+        // both members' velocities held in registers: the stores below need
+        // no reloads (the compiler cannot tell that slots l and b differ)
+        const R ax = vx[l], ay = vy[l], az = vz[l], bx = vx[b], by = vy[b], bz = vz[b];
+        const R ux = ax - bx, uy = ay - by, uz = az - bz;
+        const R uu = ux * ux + uy * uy + uz * uz;
+        if (uu == (R)0) continue;
+        const R um = sqrt(uu), uperp = sqrt(ux * ux + uy * uy);
+        double dens = 1.0;
+        if (a.density) {   // the cell holding slot l: last j with cs[j] <= l
+            int32_t lo = 0, hi = a.M;
+            while (hi - lo > 1) {
+                const int32_t mid = (lo + hi) >> 1;
+                if ((int64_t)a.cs[mid] <= l) lo = mid;
+                else hi = mid;
+            }
+            dens = a.density[lo];
+        }
+        const R s = (R)2 * ((R)(8.0 * PI * dens * a.lnL * a.dt) / (um * um * um));
+        const W4 wa = draw4(a.seed, a.pid[l], a.step, 0u, 0u);
+        const W4 wb = draw4(a.seed, a.pid[b], a.step, 0u, 0u);
+        const R U = sizeof(R) == 4 ? (R)u01f(wa.z) : (R)u01d(wa.z);
+        const R omc = nb_omc(nb_A(s), U);
+        const R sin_t = sqrt(omc * ((R)2 - omc));
+        const R phi = (R)(2.0 * PI) * (sizeof(R) == 4 ? (R)u01f(wb.z) : (R)u01d(wb.z));
+        const R cphi = cos(phi), sphi = sin(phi);
+        R dx, dy, dz;
+        if (uperp > (R)0) {
+            dx = (ux / uperp) * uz * sin_t * cphi - (uy / uperp) * um * sin_t * sphi - ux * omc;
+            dy = (uy / uperp) * uz * sin_t * cphi + (ux / uperp) * um * sin_t * sphi - uy * omc;
+            dz = -uperp * sin_t * cphi - uz * omc;
+        } else {
+            dx = um * sin_t * cphi;
+            dy = um * sin_t * sphi;
+            dz = -uz * omc;
+        }
+        const R hx = (R)0.5 * dx, hy = (R)0.5 * dy, hz = (R)0.5 * dz;
+        vx[l] = ax + hx;
+        vy[l] = ay + hy;
+        vz[l] = az + hz;
+        vx[b] = bx - hx;
+        vy[b] = by - hy;
+        vz[b] = bz - hz;
+    }
+}
+
 // ------------------------------------------------------------ exact count
 // The k smallest candidate words.  The words are uniform, so the k-th lies
 // within a few binomial standard deviations of k 2^32 / n: one pass draws
@@ -891,6 +1010,18 @@ int launch_recombine(int dtype, const RecombArgs &a, int num_cu, hipStream_t st)
         hipLaunchKernelGGL(k_recombine<float>, dim3(g), dim3(RC_T), 0, st, a);
     else
         hipLaunchKernelGGL(k_recombine<double>, dim3(g), dim3(RC_T), 0, st, a);
+    HIP_OK(hipGetLastError());
+    return PIC_OK;
+}
+
+int launch_nanbu(int dtype, const NanbuArgs &a, hipStream_t st)
+{
+    if (a.n <= 0) return PIC_OK;
+    const int g = grid_for(a.n, 256, 16384);
+    if (dtype == PIC_F32)
+        hipLaunchKernelGGL(k_nanbu<float>, dim3(g), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_nanbu<double>, dim3(g), dim3(256), 0, st, a);
     HIP_OK(hipGetLastError());
     return PIC_OK;
 }

@@ -59,6 +59,8 @@ def _load():
                                    C.c_int),
         "p2c_sums": ([vp, C.c_int, vp, C.c_int32, vp, i64, C.c_int32, vp], C.c_int),
         "recombine": ([vp, C.c_int, vp, vp, vp, vp, i64, vp, C.c_int32, f64, u64, u64, vp], C.c_int),
+        "coulomb_collide_nanbu": ([vp, C.c_int, vp, vp, i64, vp, C.c_int32, f64, f64, vp, u64, u64],
+                                  C.c_int),
         "coulomb_pairs": ([vp, vp, vp, i32, u64, u64, vp, vp], C.c_int),
         "pic_cell_moments": ([vp, C.c_int, vp, i64, vp, i32, vp], C.c_int),
         "pic_unsort": ([vp, C.c_int, vp, vp, vp, i64], C.c_int),
@@ -100,14 +102,14 @@ EXPORTED = ["pic_create", "pic_destroy", "pic_strerror", "pic_sync", "pic_set_st
             "pic_relaxation", "pic_mlp_forward", "pic_mlp_grad", "pic_mlp_train_step",
             "pic_gate_config", "pic_gate_reset", "pic_gate_stats", "pic_gate_state", "pic_autotune",
             "pic_conserve_reset", "pic_gate_refresh", "gate_infer", "pic_set_dsmc", "dsmc_collide",
-            "mcc_null_collide_exact", "p2c_sums", "recombine"]
+            "mcc_null_collide_exact", "p2c_sums", "recombine", "coulomb_collide_nanbu"]
 
 MLP_PARAMS = 4801
 GATE_STATS = ["steps", "skipped", "collided", "judged", "judged_want", "false_skip", "disabled",
               "have_moments"]
 
 KT_SLOTS = ["class0", "class1", "class2", "class3", "huge", "check", "queue", "sort", "mcc", "gate",
-            "relax", "deferred", "moments", "dsmc", "p2c", "recombine"]
+            "relax", "deferred", "moments", "dsmc", "p2c", "recombine", "nanbu"]
 
 
 def _dt(v: torch.Tensor) -> int:
@@ -227,6 +229,14 @@ class Context:
                                         mass_ratio, seed, step, _p(sel)),
              "mcc_null_collide_exact")
         return sel[:n] if selected else None
+
+    def nanbu(self, v: torch.Tensor, pid: torch.Tensor, cell_start: torch.Tensor, *, dt: float,
+              lnL: float, seed: int, step: int, density=None):
+        """One Nanbu Coulomb step in place on v (cell-sorted storage)."""
+        self._stream()
+        _chk(lib.coulomb_collide_nanbu(self._h, _dt(v), _p(v), _p(pid), v.shape[1], _p(cell_start),
+                                       cell_start.numel() - 1, dt, lnL, _p(density), seed, step),
+             "coulomb_collide_nanbu")
 
     def recombine(self, v: torch.Tensor, w: torch.Tensor, pid: torch.Tensor, primary: torch.Tensor,
                   cell_start: torch.Tensor, *, eps: float, seed: int, step: int, events=False):
@@ -369,8 +379,8 @@ class Context:
 
     def kernel_times(self):
         """{slot: (total_ms, launches)} since the previous call."""
-        ms = (C.c_double * 16)()
-        cnt = (C.c_int64 * 16)()
+        ms = (C.c_double * 20)()
+        cnt = (C.c_int64 * 20)()
         _chk(lib.pic_kernel_times(self._h, ms, cnt), "pic_kernel_times")
         return {KT_SLOTS[s]: (ms[s], cnt[s]) for s in range(len(KT_SLOTS)) if cnt[s]}
 
