@@ -273,8 +273,10 @@ __global__ __launch_bounds__(256) void k_dsmc(DsmcArgs a, DsmcTable t)
 // is fixed: the k-th live primary of the cell in storage order takes the
 // live catalyte of rank (o_j + k) mod C_j, o_j = floor(word0 C_j / 2^32) of
 // a domain-9 draw on the cell index, for k < min(P_j, C_j).  Each wave walks
-// a quarter of the cell with a running count (ballots, no barriers); the
-// quarters' counts give each wave its starting ranks.  Primaries of ranks
+// a quarter of the cell with a running count (ballots, no barriers), keeping
+// each 64-member chunk's primary and catalyte ballots in LDS; the quarters'
+// counts give each wave its starting ranks, and the later passes rank from
+// the kept ballots instead of reading the cell again.  Primaries of ranks
 // [k0, k0 + RC_CAP) are parked in LDS, then the catalytes matched to them
 // are updated: energy |v_c|^2/2 + |v_p|^2/2 + eps, isotropic direction from
 // words 1, 2 of a domain-8 draw on the catalyte's pid; the matched
@@ -312,12 +314,15 @@ __device__ __forceinline__ void rc_walk(const R *__restrict__ w, const uint8_t *
     }
 }
 
+constexpr int RC_MAXC = 128;   // 64-member chunks per wave whose ballots stay in LDS (8 KB)
+
 template <typename R>
 __global__ __launch_bounds__(RC_T) void k_recombine(RecombArgs a)
 {
 #pragma clang fp contract(off)
     __shared__ uint32_t s_prim[RC_CAP];
     __shared__ uint32_t s_cnt[2 * RC_W];
+    __shared__ uint64_t s_pm[RC_W][RC_MAXC], s_cm[RC_W][RC_MAXC];   // primary / catalyte ballots
     R *v = (R *)a.v;
     R *w = (R *)a.w;
     const int64_t n = a.n;
@@ -327,12 +332,35 @@ __global__ __launch_bounds__(RC_T) void k_recombine(RecombArgs a)
         const int64_t s = a.cs[j], e = a.cs[j + 1];
         const int64_t q = (e - s + RC_W - 1) / RC_W;
         const int64_t qs = s + wid * q, qe = qs + q < e ? qs + q : e;
-        uint32_t P = 0, C = 0;
+        // count pass: the only full read of the cell; the chunks' ballots are
+        // kept (the first RC_MAXC chunks of each wave) for the later passes
+        uint32_t P = 0, C = 0, k = 0;
         rc_walk(w, a.primary, qs, qe, [&](int64_t, bool alive, bool pr) {
-            P += (uint32_t)__popcll(__ballot(pr));
-            C += (uint32_t)__popcll(__ballot(alive && !pr));
+            const uint64_t pm = __ballot(pr), cm = __ballot(alive && !pr);
+            if (k < RC_MAXC && lane == 0) {
+                s_pm[wid][k] = pm;
+                s_cm[wid][k] = cm;
+            }
+            ++k;
+            P += (uint32_t)__popcll(pm);
+            C += (uint32_t)__popcll(cm);
             return true;
         });
+        const uint32_t nk = k;
+        // chunk kk's ballots: from LDS, or re-read past the kept ones (the
+        // weights are only written by the last pass, which ranks by them first)
+        auto masks = [&](uint32_t kk, uint64_t &pm, uint64_t &cm) {
+            if (kk < RC_MAXC) {
+                pm = s_pm[wid][kk];
+                cm = s_cm[wid][kk];
+            } else {
+                const int64_t l = qs + (int64_t)kk * PIC_WAVE + lane;
+                const bool alive = l < qe && w[l] > (R)0;
+                const bool pr = alive && a.primary[l] != 0;
+                pm = __ballot(pr);
+                cm = __ballot(alive && !pr);
+            }
+        };
         if (lane == 0) {
             s_cnt[wid] = P;
             s_cnt[RC_W + wid] = C;
@@ -355,53 +383,52 @@ __global__ __launch_bounds__(RC_T) void k_recombine(RecombArgs a)
             for (uint32_t k0 = 0; k0 < m; k0 += RC_CAP) {
                 const uint32_t k1 = m < k0 + RC_CAP ? m : k0 + RC_CAP;
                 uint32_t r0 = Pb;   // rank of this wave's next primary
-                if (r0 < k1)
-                    rc_walk(w, a.primary, qs, qe, [&](int64_t l, bool, bool pr) {
-                        const uint64_t bm = __ballot(pr);
-                        const uint32_t r = r0 + (uint32_t)__popcll(bm & below);
-                        if (pr && r >= k0 && r < k1) s_prim[r - k0] = (uint32_t)l;
-                        r0 += (uint32_t)__popcll(bm);
-                        return r0 < k1;
-                    });
+                for (uint32_t kk = 0; kk < nk && r0 < k1; ++kk) {
+                    uint64_t pm, cm;
+                    masks(kk, pm, cm);
+                    const uint32_t r = r0 + (uint32_t)__popcll(pm & below);
+                    if ((pm >> lane) & 1ull && r >= k0 && r < k1)
+                        s_prim[r - k0] = (uint32_t)(qs + (int64_t)kk * PIC_WAVE + lane);
+                    r0 += (uint32_t)__popcll(pm);
+                }
                 __syncthreads();
                 uint32_t c0 = Cb;   // rank of this wave's next catalyte
-                rc_walk(w, a.primary, qs, qe, [&](int64_t l, bool alive, bool pr) {
-                    const bool ct = alive && !pr;
-                    const uint64_t bm = __ballot(ct);
-                    const uint32_t r = c0 + (uint32_t)__popcll(bm & below);
-                    c0 += (uint32_t)__popcll(bm);
-                    const uint32_t kk = ct ? (uint32_t)(((uint64_t)r + Ct - o) % Ct) : 0u;
-                    if (ct && kk >= k0 && kk < k1) {
-                        const int64_t p = s_prim[kk - k0];
-                        const double px = v[p], py = v[n + p], pz = v[2 * n + p];
-                        const double cx = v[l], cy = v[n + l], cz = v[2 * n + l];
-                        const double ep = 0.5 * (px * px + py * py + pz * pz);
-                        const double ec = 0.5 * (cx * cx + cy * cy + cz * cz);
-                        const double sp = sqrt(2.0 * (ec + ep + a.eps));
-                        const W4 dw = draw4(a.seed, a.pid[l], a.step, 8u, 0u);
-                        double sx, sy, sz;
-                        dsmc_dir(dw.y, dw.z, sx, sy, sz);
-                        v[l] = (R)(sp * sx);
-                        v[n + l] = (R)(sp * sy);
-                        v[2 * n + l] = (R)(sp * sz);
-                    }
-                    return true;
-                });
+                for (uint32_t kk = 0; kk < nk; ++kk) {
+                    uint64_t pm, cm;
+                    masks(kk, pm, cm);
+                    const uint32_t r = c0 + (uint32_t)__popcll(cm & below);
+                    c0 += (uint32_t)__popcll(cm);
+                    if (!((cm >> lane) & 1ull)) continue;
+                    const uint32_t kc = (uint32_t)(((uint64_t)r + Ct - o) % Ct);
+                    if (kc < k0 || kc >= k1) continue;
+                    const int64_t l = qs + (int64_t)kk * PIC_WAVE + lane;
+                    const int64_t p = s_prim[kc - k0];
+                    const double px = v[p], py = v[n + p], pz = v[2 * n + p];
+                    const double cx = v[l], cy = v[n + l], cz = v[2 * n + l];
+                    const double ep = 0.5 * (px * px + py * py + pz * pz);
+                    const double ec = 0.5 * (cx * cx + cy * cy + cz * cz);
+                    const double sp = sqrt(2.0 * (ec + ep + a.eps));
+                    const W4 dw = draw4(a.seed, a.pid[l], a.step, 8u, 0u);
+                    double sx, sy, sz;
+                    dsmc_dir(dw.y, dw.z, sx, sy, sz);
+                    v[l] = (R)(sp * sx);
+                    v[n + l] = (R)(sp * sy);
+                    v[2 * n + l] = (R)(sp * sz);
+                }
                 __syncthreads();   // s_prim is refilled by the next round
             }
             // the matched primaries are the first m: their weights go to 0
             // only now, so every round above ranked the same live primaries
             uint32_t r0 = Pb;
-            if (r0 < m)
-                rc_walk(w, a.primary, qs, qe, [&](int64_t l, bool, bool pr) {
-                    const uint64_t bm = __ballot(pr);
-                    const uint32_t r = r0 + (uint32_t)__popcll(bm & below);
-                    r0 += (uint32_t)__popcll(bm);
-                    if (pr && r < m) w[l] = (R)0;
-                    return r0 < m;
-                });
+            for (uint32_t kk = 0; kk < nk && r0 < m; ++kk) {
+                uint64_t pm, cm;
+                masks(kk, pm, cm);
+                const uint32_t r = r0 + (uint32_t)__popcll(pm & below);
+                r0 += (uint32_t)__popcll(pm);
+                if ((pm >> lane) & 1ull && r < m) w[qs + (int64_t)kk * PIC_WAVE + lane] = (R)0;
+            }
         }
-        __syncthreads();   // s_cnt is rewritten for the next cell
+        __syncthreads();   // s_cnt and the masks are rewritten for the next cell
     }
 }
 
