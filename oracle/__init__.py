@@ -62,6 +62,9 @@ def lib():
         L.orc_mcc_exact.argtypes = [f64p, u32p, C.c_int64, C.c_double, C.c_double, C.c_double,
                                     C.c_double, C.c_uint64, C.c_uint64, C.c_void_p]
         L.orc_mcc_exact.restype = C.c_int
+        L.orc_step_triplet.argtypes = [f64p, C.c_int64, i32p, u32p, C.c_int32, C.c_double,
+                                       C.c_double, C.c_void_p, C.c_uint64, C.c_uint64]
+        L.orc_step_triplet.restype = C.c_int
         L.orc_nanbu_A.argtypes = [C.c_double]
         L.orc_nanbu_A.restype = C.c_double
         L.orc_nanbu_omc.argtypes = [C.c_double, C.c_double]
@@ -193,6 +196,19 @@ def mcc_exact(v, pid, dt, sigma0, n_neutral, mass_ratio, seed, step):
     if rc:
         raise ValueError(f"orc_mcc_exact failed: {rc}")
     return flags[:n]
+
+
+def step_triplet(v, cell_start, pid, dt, lnL, seed, step, density=None):
+    """One Takizuka-Abe step with the triplet for odd cells, in place on v
+    (3, n) float64, storage in cell order."""
+    n = v.shape[1]
+    cell_start = np.ascontiguousarray(cell_start, dtype=np.int32)
+    pid = np.ascontiguousarray(pid, dtype=np.uint32)
+    d = None if density is None else np.ascontiguousarray(density, dtype=np.float64)
+    rc = lib().orc_step_triplet(v.reshape(-1), n, cell_start, pid, cell_start.size - 1, dt, lnL,
+                                None if d is None else d.ctypes.data, seed, step)
+    if rc:
+        raise ValueError(f"orc_step_triplet failed: {rc}")
 
 
 def nanbu_A(s: float) -> float:

@@ -877,3 +877,54 @@ int orc_nanbu(double *v, int64_t n, const int32_t *cell_start, const uint32_t *p
     free(partner);
     return rc;
 }
+
+/* ------------------------------------------------------------------ */
+/* Takizuka & Abe step with their triplet for odd cells (the paper    */
+/* leaves the last member of an odd cell idle).  Pairs as in          */
+/* orc_pairs; in a cell of odd N >= 3 the last three members in       */
+/* pairing order, p0 p1 p2, collide pairwise at dt/2 in the order     */
+/* (p0, p1), (p1, p2), (p2, p0), each on the velocities the previous   */
+/* one left.  Uniforms: (p0, p1) as a regular pair (domain 0 of p0 and */
+/* p1); (p1, p2) from domain 4 draws of p1 and p2; (p2, p0) from      */
+/* domain 5 draws of p2 and p0.  Storage in cell order.               */
+/* ------------------------------------------------------------------ */
+int orc_step_triplet(double *v, int64_t n, const int32_t *cell_start, const uint32_t *pid, int32_t M,
+                     double dt, double lnL, const double *density, uint64_t seed, uint64_t step)
+{
+    if (cell_start[M] != n) return 1;
+    int32_t *sorted = malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    int32_t *partner = malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    if (!sorted || !partner) {
+        free(sorted);
+        free(partner);
+        return 2;
+    }
+    int rc = orc_pairs(cell_start, pid, M, seed, step, sorted, partner);
+    double *vx = v, *vy = v + n, *vz = v + 2 * n;
+    for (int32_t j = 0; j < M && !rc; ++j) {
+        const double dens = density ? density[j] : 1.0;
+        const int64_t lo = cell_start[j], N = (int64_t)cell_start[j + 1] - lo;
+        const int64_t tri = (N % 2 == 1 && N >= 3) ? N - 3 : N;   /* first triplet position */
+        for (int64_t r = 0; r + 1 < tri; r += 2) {
+            const int64_t a = sorted[lo + r], b = sorted[lo + r + 1];
+            uint32_t wa[4], wb[4];
+            draw(seed, pid[a], step, 0u, 0u, wa);
+            draw(seed, pid[b], step, 0u, 0u, wb);
+            pair_collide(vx, vy, vz, a, b, wa, wb, dens, lnL, dt);
+        }
+        if (tri < N) {
+            const int64_t p[3] = {sorted[lo + tri], sorted[lo + tri + 1], sorted[lo + tri + 2]};
+            const uint32_t dom[3] = {0u, 4u, 5u};
+            for (int c = 0; c < 3; ++c) {
+                const int64_t a = p[c], b = p[(c + 1) % 3];
+                uint32_t wa[4], wb[4];
+                draw(seed, pid[a], step, dom[c], 0u, wa);
+                draw(seed, pid[b], step, dom[c], 0u, wb);
+                pair_collide(vx, vy, vz, a, b, wa, wb, dens, lnL, 0.5 * dt);
+            }
+        }
+    }
+    free(sorted);
+    free(partner);
+    return rc;
+}
