@@ -588,6 +588,54 @@ def bench_nanbu(args):
                            "kernel_avg_ms": round(kern_ms, 5), "bytes_per_electron": per_e})
 
 
+def bench_triplet(args):
+    """Takizuka-Abe step with the triplet for odd cells on 4096 cells of
+    10,000 and 10,001 electrons alternately (half the cells odd), the plain
+    workload's Maxwellian + beam velocities, FP32, cell-sorted storage: the
+    pairing of the collision step, then one thread per pairing position."""
+    import numpy as np
+    import torch
+
+    from paper_2508_06771_amd import piccoll, workloads
+    M = 4096
+    counts = np.where(np.arange(M) % 2 == 0, 10_000, 10_001)
+    n = int(counts.sum())
+    rng = np.random.default_rng(0)
+    w = workloads.c2(0)
+    vv = np.ascontiguousarray(np.concatenate([w.v, w.v[:, :n - w.n]], axis=1))
+    v = torch.from_numpy(vv).cuda()
+    pid = torch.from_numpy(rng.permutation(n).astype(np.int32)).cuda()
+    cs = torch.from_numpy(np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)).cuda()
+    ctx = piccoll.Context(0)
+    kw = dict(dt=w.dt, lnL=w.lnL, seed=0)
+    del w
+    for s in range(args.warmup):
+        ctx.triplet(v, pid, cs, step=s, **kw)
+    ctx.sync()
+    K = args.steps
+    ms = _timed(torch, lambda: [ctx.triplet(v, pid, cs, step=args.warmup + s, **kw) for s in range(K)]) / K
+    ctx.time_kernels(True)
+    ctx.kernel_times()
+    for s in range(4):
+        ctx.triplet(v, pid, cs, step=1000 + s, **kw)
+    ctx.sync()
+    kt = ctx.kernel_times()
+    ctx.time_kernels(False)
+    ctx.close()
+    kern_ms = kt["triplet"][0] / kt["triplet"][1]
+    per_e = 28.0
+    achieved = per_e * n / (kern_ms * 1e-3) / 1e9
+    return _line(n / (ms * 1e-3), ms, args, "f32",
+                 {"workload": f"Takizuka-Abe with the odd-cell triplet, 4096 cells of 10,000 and "
+                              f"10,001 electrons ({n}, {int(np.sum(counts % 2 == 1))} odd cells), FP32, "
+                              "cell-sorted storage",
+                  "n_electrons": n},
+                 roofline={"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0,
+                           "unit": "GB/s", "frac": round(achieved / 8000.0, 4), "traffic": None,
+                           "kernel": "pairing (class kernels, pairs only) + k_ta_triplet<float>",
+                           "kernel_avg_ms": round(kern_ms, 5), "bytes_per_electron": per_e})
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -597,12 +645,13 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "dsmc", "mcc_exact", "p2c", "recombine",
-                                                              "nanbu"],
+                                                              "nanbu", "triplet"],
                     help="c2: the headline configuration; c3: log-normal cell sizes, autotuned "
                          "routing, graph replays; c4: precision study; c5: learned gate vs plain; "
                          "dsmc: electron-heavy collisions C1..C4 with ionization; mcc_exact: "
                          "exact-count null-collision selection; p2c: particle-to-cell sums; recombine: "
-                         "recombination C5; nanbu: Nanbu's Coulomb operator")
+                         "recombination C5; nanbu: Nanbu's Coulomb operator; triplet: the odd-cell "
+                         "triplet")
     ap.add_argument("--eager", action="store_true",
                     help="time one coulomb_collide call per step instead of graph replays")
     ap.add_argument("--kernel-steps", type=int, default=10,
@@ -627,7 +676,8 @@ def main():
     if args.workload != "c2":
         out = {"c3": bench_c3, "c4": bench_c4, "c5": bench_c5, "dsmc": bench_dsmc,
                "mcc_exact": bench_mcc_exact, "p2c": bench_p2c,
-               "recombine": bench_recombine, "nanbu": bench_nanbu}[args.workload](args)
+               "recombine": bench_recombine, "nanbu": bench_nanbu,
+               "triplet": bench_triplet}[args.workload](args)
         print(json.dumps(out), flush=True)
         return
 

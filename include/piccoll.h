@@ -223,6 +223,20 @@ int coulomb_collide_nanbu(pic_ctx *ctx, int dtype, void *v, const uint32_t *pid,
                           const int32_t *cell_start, int32_t n_cells, double dt, double lnLambda,
                           const double *density, uint64_t seed, uint64_t step);
 
+/* The Takizuka & Abe step with their triplet for odd cells (the paper's
+ * odd-cell handling, paragraph on the Coulomb kernel, leaves the last member
+ * idle): same pairing and pair arithmetic as coulomb_collide (no null
+ * collisions, no correction); in a cell of odd N >= 3 the last three members
+ * in pairing order, p0 p1 p2, collide pairwise at dt/2 in the order
+ * (p0, p1), (p1, p2), (p2, p0), each on the velocities the previous one left,
+ * with the uniforms of Philox domains 0, 4 and 5 respectively.  Cells of
+ * even size give exactly coulomb_collide's velocities.  Storage in cell
+ * order, cell_start of n_cells + 1 entries; density per cell (nullable: 1).
+ * Errors as coulomb_collide_nanbu. */
+int coulomb_collide_triplet(pic_ctx *ctx, int dtype, void *v, const uint32_t *pid, int64_t n,
+                            const int32_t *cell_start, int32_t n_cells, double dt, double lnLambda,
+                            const double *density, uint64_t seed, uint64_t step);
+
 /* Recombination C5 (section "Kernel for Recombination Collision C5", table
  * "Recombination Steps" RS1-RS5): in each cell the live primaries
  * (primary[l] != 0, w[l] > 0; the paper's list from step CS3) are matched one
@@ -375,7 +389,8 @@ int pic_time_kernels(pic_ctx *ctx, int on);
  * null-collision step, 9 learned-gate decision, 10 relaxation of the
  * judged cells, 11 null collisions of deferred cells, 12 gate's moment
  * pass, 13 DSMC-Coll step, 14 particle-to-cell sums, 15 recombination, 16
- * Nanbu step (pairing and rotation) (ms and count hold 20 slots). */
+ * Nanbu step (pairing and rotation), 17 triplet step (pairing and collisions)
+ * (ms and count hold 20 slots). */
 int pic_kernel_times(pic_ctx *ctx, double *ms, int64_t *count);
 
 /* ---------------------------------------------------------------- test exports */

@@ -1289,6 +1289,87 @@ ClassCaps collide_caps(int dtype, size_t)
     return c;
 }
 
+namespace {
+// Takizuka & Abe on the pairing of the collision step, with their triplet for
+// odd cells: one workgroup per cell.  With t = N - 3 for odd N >= 3 (else
+// t = N), the threads take the regular pairs at positions (2i, 2i + 1),
+// 2i + 1 < t, and one thread the triplet: the members p0 p1 p2 at t, t+1,
+// t+2 collide pairwise at dt/2 in the order (p0, p1), (p1, p2), (p2, p0) on
+// the velocities the previous one left, with the uniforms of domain 0, 4
+// and 5 draws.  The pair arithmetic is ta_half, as in the collision step.
+template <typename R>
+__global__ __launch_bounds__(256) void k_ta_triplet(TripletArgs a)
+{
+    R *vx = (R *)a.v;
+    R *vy = vx + a.n;
+    R *vz = vy + a.n;
+    for (int32_t j = blockIdx.x; j < a.M; j += gridDim.x) {
+        const int64_t lo = a.cs[j], N = (int64_t)a.cs[j + 1] - lo;
+        const int64_t t = (N % 2 == 1 && N >= 3) ? N - 3 : N;
+        const double dens = a.density ? a.density[j] : 1.0;
+        const R C = (R)(8.0 * PI_D * dens * a.lnL * a.dt * 1.0);
+        for (int64_t i = threadIdx.x; 2 * i + 1 < t; i += blockDim.x) {
+            const int64_t ia = a.sorted[lo + 2 * i], ib = a.sorted[lo + 2 * i + 1];
+            const W4 wa = draw4(a.seed, a.pid[ia], a.step, 0u, 0u);
+            const W4 wb = draw4(a.seed, a.pid[ib], a.step, 0u, 0u);
+            R ax = vx[ia], ay = vy[ia], az = vz[ia], bx = vx[ib], by = vy[ib], bz = vz[ib];
+            R hx, hy, hz;
+            ta_half(ax - bx, ay - by, az - bz, C, wa.z, wa.w, wb.z, hx, hy, hz);
+            vx[ia] = ax + hx;
+            vy[ia] = ay + hy;
+            vz[ia] = az + hz;
+            vx[ib] = bx - hx;
+            vy[ib] = by - hy;
+            vz[ib] = bz - hz;
+        }
+        if (t < N && threadIdx.x == blockDim.x - 1) {
+            const int64_t s0[3] = {a.sorted[lo + t], a.sorted[lo + t + 1], a.sorted[lo + t + 2]};
+            R x[3], y[3], z[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                x[c] = vx[s0[c]];
+                y[c] = vy[s0[c]];
+                z[c] = vz[s0[c]];
+            }
+            const R Ch = (R)(8.0 * PI_D * dens * a.lnL * (0.5 * a.dt));
+            const uint32_t dom[3] = {0u, 4u, 5u};
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const int i = c, k = (c + 1) % 3;
+                const W4 wa = draw4(a.seed, a.pid[s0[i]], a.step, dom[c], 0u);
+                const W4 wb = draw4(a.seed, a.pid[s0[k]], a.step, dom[c], 0u);
+                R hx, hy, hz;
+                ta_half(x[i] - x[k], y[i] - y[k], z[i] - z[k], Ch, wa.z, wa.w, wb.z, hx, hy, hz);
+                x[i] += hx;
+                y[i] += hy;
+                z[i] += hz;
+                x[k] -= hx;
+                y[k] -= hy;
+                z[k] -= hz;
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                vx[s0[c]] = x[c];
+                vy[s0[c]] = y[c];
+                vz[s0[c]] = z[c];
+            }
+        }
+    }
+}
+}  // namespace
+
+int launch_ta_triplet(int dtype, const TripletArgs &a, hipStream_t st)
+{
+    if (a.n <= 0) return PIC_OK;
+    const int g = a.M < 4096 ? a.M : 4096;
+    if (dtype == PIC_F32)
+        hipLaunchKernelGGL(k_ta_triplet<float>, dim3(g), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_ta_triplet<double>, dim3(g), dim3(256), 0, st, a);
+    HIP_OK(hipGetLastError());
+    return PIC_OK;
+}
+
 size_t huge_scratch_bytes(int dtype, int64_t n)
 {
     const size_t rec = dtype == PIC_F32 ? 16 : 32;

@@ -638,7 +638,7 @@ struct RadixPass {
 // 7 re-binning passes, 8 stand-alone null-collision step, 9 learned gate
 // decision, 10 relaxation of the judged cells.
 enum { KT_CLASS0 = 0, KT_HUGE = 4, KT_CHECK = 5, KT_QUEUE = 6, KT_SORT = 7, KT_MCC = 8, KT_GATE = 9,
-       KT_RELAX = 10, KT_DEFER = 11, KT_MOMENTS = 12, KT_DSMC = 13, KT_P2C = 14, KT_RECOMB = 15, KT_NANBU = 16, KT_SLOTS = 20 };
+       KT_RELAX = 10, KT_DEFER = 11, KT_MOMENTS = 12, KT_DSMC = 13, KT_P2C = 14, KT_RECOMB = 15, KT_NANBU = 16, KT_TRIPLET = 17, KT_SLOTS = 20 };
 void ktime_begin(int slot, hipStream_t st);
 void ktime_end(int slot, hipStream_t st);
 bool ktime_pause();            // returns whether timing was on
@@ -830,6 +830,21 @@ struct DsmcArgs {
     DevFlags *dflags;
 };
 int launch_dsmc(int dtype, const DsmcArgs &a, const DsmcTable &t, hipStream_t st);
+
+// Takizuka & Abe on the pairing order sorted[] with the triplet for odd cells.
+struct TripletArgs {
+    void *v;
+    const uint32_t *pid;
+    const int32_t *sorted;
+    const int32_t *cs;
+    const double *density;
+    int64_t n;
+    int32_t M;
+    double dt, lnL;
+    uint64_t seed;
+    uint32_t step;
+};
+int launch_ta_triplet(int dtype, const TripletArgs &a, hipStream_t st);
 
 // Nanbu's operator on the pairs partner[] of the T&A step (storage in cell order).
 struct NanbuArgs {

@@ -61,6 +61,8 @@ def _load():
         "recombine": ([vp, C.c_int, vp, vp, vp, vp, i64, vp, C.c_int32, f64, u64, u64, vp], C.c_int),
         "coulomb_collide_nanbu": ([vp, C.c_int, vp, vp, i64, vp, C.c_int32, f64, f64, vp, u64, u64],
                                   C.c_int),
+        "coulomb_collide_triplet": ([vp, C.c_int, vp, vp, i64, vp, C.c_int32, f64, f64, vp, u64, u64],
+                                    C.c_int),
         "coulomb_pairs": ([vp, vp, vp, i32, u64, u64, vp, vp], C.c_int),
         "pic_cell_moments": ([vp, C.c_int, vp, i64, vp, i32, vp], C.c_int),
         "pic_unsort": ([vp, C.c_int, vp, vp, vp, i64], C.c_int),
@@ -102,14 +104,15 @@ EXPORTED = ["pic_create", "pic_destroy", "pic_strerror", "pic_sync", "pic_set_st
             "pic_relaxation", "pic_mlp_forward", "pic_mlp_grad", "pic_mlp_train_step",
             "pic_gate_config", "pic_gate_reset", "pic_gate_stats", "pic_gate_state", "pic_autotune",
             "pic_conserve_reset", "pic_gate_refresh", "gate_infer", "pic_set_dsmc", "dsmc_collide",
-            "mcc_null_collide_exact", "p2c_sums", "recombine", "coulomb_collide_nanbu"]
+            "mcc_null_collide_exact", "p2c_sums", "recombine", "coulomb_collide_nanbu",
+            "coulomb_collide_triplet"]
 
 MLP_PARAMS = 4801
 GATE_STATS = ["steps", "skipped", "collided", "judged", "judged_want", "false_skip", "disabled",
               "have_moments"]
 
 KT_SLOTS = ["class0", "class1", "class2", "class3", "huge", "check", "queue", "sort", "mcc", "gate",
-            "relax", "deferred", "moments", "dsmc", "p2c", "recombine", "nanbu"]
+            "relax", "deferred", "moments", "dsmc", "p2c", "recombine", "nanbu", "triplet"]
 
 
 def _dt(v: torch.Tensor) -> int:
@@ -237,6 +240,15 @@ class Context:
         _chk(lib.coulomb_collide_nanbu(self._h, _dt(v), _p(v), _p(pid), v.shape[1], _p(cell_start),
                                        cell_start.numel() - 1, dt, lnL, _p(density), seed, step),
              "coulomb_collide_nanbu")
+
+    def triplet(self, v: torch.Tensor, pid: torch.Tensor, cell_start: torch.Tensor, *, dt: float,
+                lnL: float, seed: int, step: int, density=None):
+        """One Takizuka-Abe step with the triplet for odd cells, in place on v
+        (cell-sorted storage)."""
+        self._stream()
+        _chk(lib.coulomb_collide_triplet(self._h, _dt(v), _p(v), _p(pid), v.shape[1], _p(cell_start),
+                                         cell_start.numel() - 1, dt, lnL, _p(density), seed, step),
+             "coulomb_collide_triplet")
 
     def recombine(self, v: torch.Tensor, w: torch.Tensor, pid: torch.Tensor, primary: torch.Tensor,
                   cell_start: torch.Tensor, *, eps: float, seed: int, step: int, events=False):
