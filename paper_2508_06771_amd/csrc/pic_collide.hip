@@ -1297,8 +1297,10 @@ namespace {
 // t+2 collide pairwise at dt/2 in the order (p0, p1), (p1, p2), (p2, p0) on
 // the velocities the previous one left, with the uniforms of domain 0, 4
 // and 5 draws.  The pair arithmetic is ta_half, as in the collision step.
+// 1024-thread workgroups: two cells per CU in flight keep the cells' members
+// (reached in pairing order, so scattered) within the last-level cache.
 template <typename R>
-__global__ __launch_bounds__(256) void k_ta_triplet(TripletArgs a)
+__global__ __launch_bounds__(1024) void k_ta_triplet(TripletArgs a)
 {
     R *vx = (R *)a.v;
     R *vy = vx + a.n;
@@ -1363,9 +1365,9 @@ int launch_ta_triplet(int dtype, const TripletArgs &a, hipStream_t st)
     if (a.n <= 0) return PIC_OK;
     const int g = a.M < 4096 ? a.M : 4096;
     if (dtype == PIC_F32)
-        hipLaunchKernelGGL(k_ta_triplet<float>, dim3(g), dim3(256), 0, st, a);
+        hipLaunchKernelGGL(k_ta_triplet<float>, dim3(g), dim3(1024), 0, st, a);
     else
-        hipLaunchKernelGGL(k_ta_triplet<double>, dim3(g), dim3(256), 0, st, a);
+        hipLaunchKernelGGL(k_ta_triplet<double>, dim3(g), dim3(1024), 0, st, a);
     HIP_OK(hipGetLastError());
     return PIC_OK;
 }
