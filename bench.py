@@ -5,14 +5,19 @@ Workload (default): 4096 cells x 10,000 electrons (40.96M), binary32 SoA
 velocities, 95% Maxwellian + 5% cold beam at 3 v_th, one step = Coulomb
 (Takizuka & Abe pairing within each cell) + null-collision MCC (sigma0 E^-1/2,
 P_null = 0.01) fused into the same pass, lnLambda = 10, dt = 0.01 tau_e.
-Storage starts unsorted; the first warm-up step re-bins it (timed separately
-as rebin_step_ms), the timed steps run on storage already in cell order, as a
-step of a collision-only loop does.
+Storage starts unsorted; the first step re-bins it (first_step_ms), then
+W warm-up steps capture and replay a HIP graph of the steady-state step
+(storage already in cell order, as in a collision-only loop), and K timed
+steps are graph replays, each between two HIP events on the library's
+stream (the median is reported).  Replays then continue to the
+configuration's 1000 steps for the energy drift.
 
 Prints one JSON line: whole-job throughput (electron updates per second with
 inputs resident in HBM), the dominant kernel's roofline figures from HIP
-events on the library's stream, the energy drift over the timed steps, and
-the FP64 CPU oracle timed on a bounded sample of the same workload.
+events on the library's stream (eager steps of the same kernels), the energy
+drift over 1000 steps, the same figures for the workload in binary64 (the
+"fp64" object), and the FP64 CPU oracle timed on a bounded sample of the
+same workload.
 """
 import argparse
 import json
@@ -644,6 +649,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the binary64 leg of the c2 workload")
+    ap.add_argument("--drift-steps", type=int, default=None,
+                    help="c2: steps over which the energy drift is taken (default: the "
+                         "configuration's 1000; at least the steps already run)")
     ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "dsmc", "mcc_exact", "p2c", "recombine",
                                                               "nanbu", "triplet"],
                     help="c2: the headline configuration; c3: log-normal cell sizes, autotuned "
@@ -652,8 +661,6 @@ def main():
                          "exact-count null-collision selection; p2c: particle-to-cell sums; recombine: "
                          "recombination C5; nanbu: Nanbu's Coulomb operator; triplet: the odd-cell "
                          "triplet")
-    ap.add_argument("--eager", action="store_true",
-                    help="time one coulomb_collide call per step instead of graph replays")
     ap.add_argument("--kernel-steps", type=int, default=10,
                     help="extra eager steps after the timed region whose kernels are timed")
     ap.add_argument("--gate-params", default=None, help="trained gate parameters (.npy) for c5")
@@ -668,10 +675,7 @@ def main():
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
-
-    from paper_2508_06771_amd import piccoll, workloads
 
     if args.workload != "c2":
         out = {"c3": bench_c3, "c4": bench_c4, "c5": bench_c5, "dsmc": bench_dsmc,
@@ -681,114 +685,146 @@ def main():
         print(json.dumps(out), flush=True)
         return
 
-    w = workloads.c2(0)
+    leg32 = c2_leg(args, "f32")
+    leg64 = None if args.no_fp64 else c2_leg(args, "f64")
+    copy_gbs, _ = copy_probe(torch)
+    cpu = None if args.no_cpu else cpu_baseline(args.cpu_seconds)
+    config = {"workload": "4096 cells x 10,000 electrons (40.96M), FP32 SoA, Maxwellian + "
+                          "5% cold beam, Coulomb (Takizuka-Abe) + fused null-collision MCC",
+              "n_electrons": leg32["n"], "n_cells": 4096, "dt_over_tau_e": 0.01,
+              "lnLambda": 10.0, "p_null": 0.01}
+    out = _line(leg32["value"], leg32["ms_per_step"], args, "f32", config)
+    out.update({k: leg32[k] for k in leg32 if k not in ("value", "ms_per_step", "n")})
+    out["copy_probe_gbs"] = round(copy_gbs, 1)
+    out["cpu_baseline"] = cpu
+    if leg64 is not None:
+        fp64 = {k: leg64[k] for k in leg64 if k != "n"}
+        fp64["dtype"] = "f64"
+        fp64["unit"] = "electron-updates/s"
+        fp64["config"] = dict(config, workload=config["workload"].replace("FP32", "FP64"))
+        # the oracle computes in binary64: the same CPU figure is this leg's baseline
+        fp64["cpu_baseline"] = cpu
+        out["fp64"] = fp64
+    print(json.dumps(out), flush=True)
+
+
+def c2_leg(args, dtype_name):
+    """One precision of the headline workload: the re-binning step, W warm-up
+    graph replays, K timed replays (each between two HIP events on the
+    library's stream; median reported), replays up to the configuration's
+    1000 steps for the energy drift, then eager steps with the library's
+    per-launch events for the roofline of the dominant kernel."""
+    import numpy as np
+    import torch
+
+    from paper_2508_06771_amd import piccoll, workloads
+    f32 = dtype_name == "f32"
+    w = workloads.c2(0, dtype=np.float32 if f32 else np.float64)
     v = torch.from_numpy(w.v).cuda()
     cell = torch.from_numpy(w.cell_of).cuda()
     pid = torch.from_numpy(w.pid.view(np.int32)).cuda()
     n = w.n
     del w.v
+    es = 4 if f32 else 8
+    bytes_collide = 4 + 6 * es          # read pid + v, write v
+    bytes_step = BYTES_CHECK + bytes_collide
     ctx = piccoll.Context(0)
     ctx.set_mcc(w.sigma0, w.n_neutral, 0.0)
-    flags = piccoll.FUSE_MCC
+    fl = piccoll.FUSE_MCC
+    kw = dict(dt=w.dt, lnL=w.lnL, seed=0)
 
-    def step(k):
-        ctx.coulomb_collide(v, cell, pid, w.n_cells, dt=w.dt, lnL=w.lnL, seed=0, step=k,
-                            flags=flags)
-
+    E0 = energy(v)
     torch.cuda.synchronize()
     s0, e0 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     s0.record()
-    step(0)                              # re-binning step (storage starts unsorted)
+    ctx.coulomb_collide(v, cell, pid, w.n_cells, step=0, flags=fl, **kw)   # storage starts unsorted
     e0.record()
     ctx.sync()
-    rebin_ms = s0.elapsed_time(e0)
-    for k in range(1, max(args.warmup, 1)):
-        step(k)
+    first_ms = s0.elapsed_time(e0)
+    # warm-up: captures the steady-state step once, then replays it
+    W = max(args.warmup, 1)
+    ctx.run_steps(v, cell, pid, w.n_cells, step0=1, nsteps=W, flags=fl | piccoll.ASSUME_SORTED, **kw)
     ctx.sync()
-    E0 = energy(v)
-    k0 = max(args.warmup, 1)
-
+    k = 1 + W
+    K = args.steps
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(K)]
     torch.cuda.synchronize()
-    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    s.record()
-    if args.eager:
-        for k in range(args.steps):
-            step(k0 + k)
-    else:
-        ctx.run_steps(v, cell, pid, w.n_cells, dt=w.dt, lnL=w.lnL, seed=0, step0=k0,
-                      nsteps=args.steps, flags=flags | piccoll.ASSUME_SORTED)
-    e.record()
+    t0 = time.perf_counter()
+    for i in range(K):
+        evs[i][0].record()
+        ctx.run_steps(v, cell, pid, w.n_cells, step0=k + i, nsteps=1,
+                      flags=fl | piccoll.ASSUME_SORTED, **kw)
+        evs[i][1].record()
     torch.cuda.synchronize()
-    ms_total = s.elapsed_time(e)
+    wall_ms = (time.perf_counter() - t0) * 1e3
+    per = sorted(a.elapsed_time(b) for a, b in evs)
+    ms_med = per[len(per) // 2] if len(per) % 2 else 0.5 * (per[len(per) // 2 - 1] + per[len(per) // 2])
+    k += K
+    ctx.sync()
+    # the configuration's 1000 steps for the energy drift (graph replays)
+    total = max(w.steps if args.drift_steps is None else args.drift_steps, k)
+    if total > k:
+        ctx.run_steps(v, cell, pid, w.n_cells, step0=k, nsteps=total - k,
+                      flags=fl | piccoll.ASSUME_SORTED, **kw)
     ctx.sync()
     E1 = energy(v)
+    k = total
 
-    # kernel durations: HIP events recorded by the library around each launch
-    # on its stream, over a few more steps of the same kind (outside the
-    # timed region; graph replays cannot carry per-kernel events)
     kt = {}
     if not args.no_kernel_timing and args.kernel_steps > 0:
         ctx.time_kernels(True)
         ctx.kernel_times()
-        k1 = k0 + args.steps
-        for k in range(args.kernel_steps):
-            ctx.coulomb_collide(v, cell, pid, w.n_cells, dt=w.dt, lnL=w.lnL, seed=0, step=k1 + k,
-                                flags=flags | piccoll.ASSUME_SORTED)
+        for i in range(args.kernel_steps):
+            ctx.coulomb_collide(v, cell, pid, w.n_cells, step=k + i,
+                                flags=fl | piccoll.ASSUME_SORTED, **kw)
         ctx.sync()
         kt = ctx.kernel_times()
         ctx.time_kernels(False)
-
-    ms_step = ms_total / args.steps
-    value = n / (ms_step * 1e-3)
-    step_gbs = n * (BYTES_CHECK + BYTES_COLLIDE) / (ms_step * 1e-3) / 1e9
+    kms = {name: t / c for name, (t, c) in kt.items()}
+    nsteps_k = max(args.kernel_steps, 1)
+    kernel_sum = sum(t for t, c in kt.values()) / nsteps_k if kt else None
 
     roof = None
-    if "class3" in kt:
-        kms, kcnt = kt["class3"]
-        kavg = kms / kcnt
-        achieved = n * BYTES_COLLIDE / (kavg * 1e-3) / 1e9
-        tb = measured_traffic()
+    dom = None
+    if f32 and "class3" in kms:
+        dom = ("class3", "k_collide<float,1024,10> (cells of 4097..10240 members)")
+    elif not f32 and "huge" in kms:
+        dom = ("huge", "segmented path of cells beyond 6144 members (k_seg_count, k_seg_scan, "
+                       "k_seg_scatter, k_seg_collide, k_seg_fixup)")
+    if dom is not None:
+        kavg = kms[dom[0]]
+        achieved = n * bytes_collide / (kavg * 1e-3) / 1e9
+        tb = measured_traffic() if f32 else None
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if tb is None else round(tb / (kavg * 1e-3) / 1e9, 1),
-                "traffic_bytes_per_launch": tb,
-                "kernel": "k_collide<float,1024,10> (cells of 4097..10240 members)",
-                "kernel_avg_ms": round(kavg, 5),
-                "bytes_per_launch": n * BYTES_COLLIDE}
-
-    copy_gbs, _ = copy_probe(torch)
-    cpu = None if args.no_cpu else cpu_baseline(args.cpu_seconds)
-
-    out = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "electron-updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": "4096 cells x 10,000 electrons (40.96M), FP32 SoA, Maxwellian + "
-                               "5% cold beam, Coulomb (Takizuka-Abe) + fused null-collision MCC",
-                   "n_electrons": n, "n_cells": w.n_cells, "dt_over_tau_e": 0.01,
-                   "lnLambda": w.lnL, "p_null": 0.01},
+                "traffic_bytes_per_launch": tb, "kernel": dom[1], "kernel_avg_ms": round(kavg, 5),
+                "bytes_per_launch": n * bytes_collide}
+    step_gbs = n * bytes_step / (ms_med * 1e-3) / 1e9
+    ctx.close()
+    del v, cell, pid
+    torch.cuda.empty_cache()
+    return {
+        "n": n,
+        "value": n / (ms_med * 1e-3),
+        "ms_per_step": ms_med,
+        "ms_per_step_mean": wall_ms / K,
+        "ms_per_step_min": per[0],
+        "ms_per_step_max": per[-1],
+        "timing": f"median of {K} graph replays, each between two HIP events on the library's "
+                  f"stream, after {W} warm-up replays",
         "hbm_frac_step": round(step_gbs / HBM_PEAK_GBS, 4),
         "step_algorithmic_gbs": round(step_gbs, 1),
-        "algorithmic_bytes_per_electron": BYTES_CHECK + BYTES_COLLIDE,
-        "copy_probe_gbs": round(copy_gbs, 1),
-        "launch": "eager" if args.eager else "graph",
-        "rebin_step_ms": round(rebin_ms, 4),
+        "algorithmic_bytes_per_electron": bytes_step,
+        "launch": "graph",
+        "first_step_ms": round(first_ms, 4),
         "energy_drift": abs(E1 - E0) / E0,
-        "kernel_ms_per_step": {k: round(t / c, 5) for k, (t, c) in kt.items()},
+        "energy_drift_steps": total,
+        "kernel_ms_per_step": {name: round(t / nsteps_k, 5) for name, (t, c) in kt.items()},
+        "kernel_sum_ms_per_step": None if kernel_sum is None else round(kernel_sum, 5),
         "roofline": roof,
-        "cpu_baseline": cpu,
     }
-    ctx.close()
-    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

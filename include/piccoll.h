@@ -117,14 +117,16 @@ int coulomb_collide(pic_ctx *ctx, int dtype, void *v, int32_t *cell_of, uint32_t
 
 /* nsteps consecutive steps step0, step0+1, ... with the arguments of
  * coulomb_collide (the operator split of the PIC scheme runs several collision
- * steps between field solves, paragraph "Operator Splitting Algorithms").  The
- * first step re-bins unsorted storage; the collision step never changes cell
- * membership, so the following steps run as one captured HIP graph of a
- * steady-state step (order check, work queue, collide pass, step counter
- * increment in device memory) replayed nsteps - 1 times.  The graph is kept in
- * the context and captured again when any argument, the MCC parameters, the
- * moments buffer or the scratch memory changes.  A violated order (cell ids
- * changed between replays) latches PIC_ERR_STATE and leaves v unchanged. */
+ * steps between field solves, paragraph "Operator Splitting Algorithms").
+ * Without PIC_ASSUME_SORTED the first step runs eagerly and re-bins unsorted
+ * storage; the collision step never changes cell membership, so the other
+ * steps (all nsteps with PIC_ASSUME_SORTED) are replays of one captured HIP
+ * graph of a steady-state step (order check, work queue, collide pass, step
+ * counter increment in device memory).  No call waits for the device: the
+ * graph is captured without executing anything, kept in the context and
+ * captured again when any argument, the MCC parameters, the moments buffer or
+ * the scratch memory changes.  A violated order (cell ids changed between
+ * replays) latches PIC_ERR_STATE and leaves v unchanged. */
 int pic_run_steps(pic_ctx *ctx, int dtype, void *v, int32_t *cell_of, uint32_t *pid, int64_t n,
                   int32_t n_cells, double dt, double lnLambda, const double *density,
                   uint64_t seed, uint64_t step0, int64_t nsteps, uint32_t flags);

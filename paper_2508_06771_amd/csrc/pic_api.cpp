@@ -938,29 +938,25 @@ int pic_run_steps(pic_ctx *c, int dtype, void *v, int32_t *cell_of, uint32_t *pi
     if (!c || nsteps < 0) return PIC_ERR_ARG;
     if (nsteps == 0) return PIC_OK;
     StepArgs s = {dtype, v, cell_of, pid, n, n_cells, dt, lnLambda, density, seed, step0, flags};
-    RC(collide_common(c, s));          // first step: re-bins unsorted storage
-    if (nsteps == 1) return PIC_OK;
+    int64_t done = 0;
+    if (!(flags & PIC_ASSUME_SORTED)) {
+        RC(collide_common(c, s));          // first step: re-bins unsorted storage
+        done = 1;
+        if (nsteps == 1) return PIC_OK;
+    } else {
+        // every step is a replay: the same checks and scratch as an eager step
+        RC(step_check(c, s));
+        CK(hipSetDevice(c->device));
+        RC(ensure_ws(c, step_ws_bytes(c, s)));
+        if (s.flags & PIC_GATE) RC(ensure_gate(c, s.n_cells));
+        if (s.flags & PIC_CONSERVE_FIX) RC(ensure_debt(c, s.n_cells));
+    }
     // Later steps find the storage in cell order (the collision step never
     // changes cell membership): capture one such step once and replay it.
+    // Nothing here waits for the device: size classes without cells are
+    // launched and leave at once (their counts are read on the device).
     s.flags |= PIC_ASSUME_SORTED;
     s.step = 0;
-    // the cell sizes are fixed for these steps: size classes without cells
-    // get no launches (the first step left cell_start at the workspace start)
-    {
-        std::vector<int32_t> hcs((size_t)n_cells + 1);
-        CK(hipMemcpyAsync(hcs.data(), c->ws, hcs.size() * 4, hipMemcpyDeviceToHost, c->stream));
-        CK(hipStreamSynchronize(c->stream));
-        const ClassCaps caps = c->tuned_valid[dtype] ? c->tuned[dtype] : collide_caps(dtype, c->lds_max);
-        uint32_t live = 0;
-        for (int32_t j = 0; j < n_cells; ++j) {
-            const int32_t cnt = hcs[j + 1] - hcs[j];
-            int cls = caps.ncls;
-            for (int q = caps.ncls - 1; q >= 0; --q)
-                if (cnt <= caps.cap[q]) cls = q;
-            live |= 1u << (cls < caps.ncls ? cls : 4);
-        }
-        s.live = live;
-    }
     unsigned char key[256];
     size_t kl = 0;
     auto put = [&](const void *p, size_t bytes) {
@@ -991,7 +987,6 @@ int pic_run_steps(pic_ctx *c, int dtype, void *v, int32_t *cell_of, uint32_t *pi
             c->exec = nullptr;
         }
         if (!c->cap_stream) CK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
-        CK(hipStreamSynchronize(c->stream));
         const bool timing = ktime_pause();
         hipGraph_t g = nullptr;
         CK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
@@ -1010,8 +1005,8 @@ int pic_run_steps(pic_ctx *c, int dtype, void *v, int32_t *cell_of, uint32_t *pi
         memcpy(c->graph_key, key, kl);
         c->graph_key_len = kl;
     }
-    RC(launch_set_step(c->step_dev, step0 + 1, c->stream));
-    for (int64_t k = 1; k < nsteps; ++k) CK(hipGraphLaunch(c->exec, c->stream));
+    RC(launch_set_step(c->step_dev, step0 + (uint64_t)done, c->stream));
+    for (int64_t k = done; k < nsteps; ++k) CK(hipGraphLaunch(c->exec, c->stream));
     return PIC_OK;
 }
 
