@@ -25,6 +25,8 @@
 // algorithm with its per-cell arrays in global scratch indexed by slot.
 #include <float.h>
 
+#include <type_traits>
+
 #include "pic_internal.hpp"
 
 #define HIP_OK(x) do { if ((x) != hipSuccess) return PIC_ERR_HIP; } while (0)
@@ -37,9 +39,18 @@ constexpr double PI_D = 3.14159265358979323846;
 // relative velocity u = v_a - v_b.  C = 8 pi n lnL dt (so s^2 = C / |u|^3);
 // U1, U2 (words 2, 3 of a) give z by Box-Muller, U3 (word 2 of b) the
 // azimuth.  The rotation keeps |u|: u' = u cos T + |u| sin T (cos P e1 + sin P e2).
-__device__ __forceinline__ void ta_half(float ux, float uy, float uz, float C, uint32_t wa2,
-                                        uint32_t wa3, uint32_t wb2, float &hx, float &hy,
-                                        float &hz)
+// The standard normal deviate of the pair from words 2, 3 of its first member
+// (Box-Muller, cosine branch; the hardware log is base 2 and the cosine takes
+// revolutions).
+__device__ __forceinline__ float ta_z(uint32_t wa2, uint32_t wa3)
+{
+    return __builtin_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u01f(wa2))) *
+           __builtin_amdgcn_cosf(u01f(wa3));
+}
+
+// The same from the deviate z already drawn.
+__device__ __forceinline__ void ta_half_z(float ux, float uy, float uz, float C, float z,
+                                          uint32_t wb2, float &hx, float &hy, float &hz)
 {
     const float uu = ux * ux + uy * uy + uz * uz;
     hx = hy = hz = 0.0f;
@@ -47,7 +58,6 @@ __device__ __forceinline__ void ta_half(float ux, float uy, float uz, float C, u
     const float rinv = __builtin_amdgcn_rsqf(uu);     // 1 / |u|
     const float um = uu * rinv;                        // |u|
     const float s = __builtin_sqrtf(C * rinv * rinv * rinv);
-    const float z = __builtin_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u01f(wa2))) * __builtin_amdgcn_cosf(u01f(wa3));
     const float d = s * z;
     // sin T = 2d / (1 + d^2), 1 - cos T = 2 d^2 / (1 + d^2); for |d| > 1 the
     // same ratios in t = 1/d avoid overflow of d^2.
@@ -82,6 +92,13 @@ __device__ __forceinline__ void ta_half(float ux, float uy, float uz, float C, u
     hx = 0.5f * dx;
     hy = 0.5f * dy;
     hz = 0.5f * dz;
+}
+
+__device__ __forceinline__ void ta_half(float ux, float uy, float uz, float C, uint32_t wa2,
+                                        uint32_t wa3, uint32_t wb2, float &hx, float &hy,
+                                        float &hz)
+{
+    ta_half_z(ux, uy, uz, C, ta_z(wa2, wa3), wb2, hx, hy, hz);
 }
 
 __device__ __forceinline__ void ta_half(double ux, double uy, double uz, double C, uint32_t wa2,
@@ -488,6 +505,373 @@ __global__ __launch_bounds__(T) void k_collide(CollideArgs a, const int32_t *__r
         __syncthreads();
         if (item >= (int)count) break;
         cell_pass<R, T, K, F>(a, list[item], smem, red, wtot, s_before);
+    }
+}
+
+// ------------------------------------------------------------ lean pass
+// The binary32 pass of the plain step (optionally with the fused null
+// collisions) for cells of up to T*K members, written for few VALU
+// instructions and few LDS operations per member:
+//   * bucket counters are whole words (no 16-bit packing), nb = 2^bits >= n
+//     buckets, so a bucket holds 0.5..1 members on average;
+//   * after the scan only members that share their bucket write their key
+//     and index to LDS, and only they compare keys to rank themselves
+//     (about half the members are alone in their bucket);
+//   * the first member of each pair draws its Box-Muller deviate before the
+//     exchange, so a record is 16 bytes (velocity and one word) and a cell of
+//     up to lean_positions(T*K) members exchanges in one round;
+//   * pair threads write both new velocities back in place; members read
+//     their record.
+// The pairs, the rotation (ta_half_z) and the null collisions are those of
+// cell_pass, so the two give identical velocities.
+// Workgroup barrier for LDS traffic only: waits for this wave's LDS
+// operations, not for its global loads and stores (a __syncthreads would make
+// every barrier wait for the velocity loads in flight and the stores of the
+// previous cell).  The memory clobber keeps the compiler from moving memory
+// accesses across it.
+__device__ __forceinline__ void lds_barrier()
+{
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// Inclusive scan of one word per lane over the wave with DPP: shifts by 1, 2,
+// 4, 8 inside each 16-lane row, then the last lane of row 0 (2) added to row
+// 1 (3) and the last lane of row 1 added to rows 2 and 3.
+__device__ __forceinline__ uint32_t wave_incl_scan_dpp(uint32_t x)
+{
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false);   // row_shr:1
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false);   // row_shr:2
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false);   // row_shr:4
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false);   // row_shr:8
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);   // row_bcast:15
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);   // row_bcast:31
+    return x;
+}
+
+// Exclusive scan in place of the nb (a power of two) bucket counters, with
+// cnt[nb] = total.  With nb >= T each wave takes a contiguous run of nb / NW
+// counters in rows of 64 (lane l reads word l of the row: no bank conflicts)
+// and scans row by row with a running carry; the waves' totals are then
+// added in order.  Contains the barriers.
+template <int T, int ROWMAX>
+__device__ __forceinline__ void lds_excl_scan(uint32_t *cnt, uint32_t nb, uint32_t *wtot)
+{
+    constexpr int NW = T / PIC_WAVE;
+    const uint32_t lane = threadIdx.x & (PIC_WAVE - 1), wid = threadIdx.x / PIC_WAVE;
+    if (nb >= (uint32_t)T) {
+        const uint32_t seg = nb / NW, rows = seg / PIC_WAVE;
+        uint32_t *base = cnt + wid * seg + lane;
+        uint32_t x[ROWMAX];
+        uint32_t carry = 0;
+#pragma unroll
+        for (int r = 0; r < ROWMAX; ++r) {
+            if ((uint32_t)r < rows) {
+                const uint32_t v = base[r * PIC_WAVE];
+                const uint32_t inc = wave_incl_scan_dpp(v);
+                x[r] = carry + inc - v;
+                carry += (uint32_t)__builtin_amdgcn_readlane((int)inc, PIC_WAVE - 1);
+            }
+        }
+        if (lane == 0) wtot[wid] = carry;
+        lds_barrier();
+        uint32_t off = 0, tot = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            const uint32_t t = wtot[w];
+            off += (uint32_t)w < wid ? t : 0u;
+            tot += t;
+        }
+#pragma unroll
+        for (int r = 0; r < ROWMAX; ++r)
+            if ((uint32_t)r < rows) base[r * PIC_WAVE] = off + x[r];
+        if (threadIdx.x == 0) cnt[nb] = tot;
+    } else {
+        const uint32_t v = threadIdx.x < nb ? cnt[threadIdx.x] : 0u;
+        const uint32_t inc = wave_incl_scan_dpp(v);
+        if (lane == PIC_WAVE - 1) wtot[wid] = inc;
+        lds_barrier();
+        uint32_t off = 0, tot = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            const uint32_t t = wtot[w];
+            off += (uint32_t)w < wid ? t : 0u;
+            tot += t;
+        }
+        if (threadIdx.x < nb) cnt[threadIdx.x] = off + inc - v;
+        if (threadIdx.x == 0) cnt[nb] = tot;
+    }
+    lds_barrier();
+}
+
+template <int T, int K>
+struct LeanGeom {
+    static constexpr int CAP = T * K;
+    static constexpr int NBMAX = (int)next_pow2((uint32_t)CAP);
+    static constexpr int PERMAX = NBMAX >= T ? NBMAX / T : 1;   // counters per thread
+    static constexpr int ROWMAX = NBMAX >= T ? NBMAX / T : 1;   // scan rows per wave
+    static constexpr size_t CNT_WORDS = (size_t)NBMAX + 4;      // counters, starts, end
+    static constexpr size_t SORT_BYTES = CNT_WORDS * 4 + (size_t)CAP * 4 + (size_t)CAP * 2;
+};
+
+// Dynamic LDS the lean pass may use (its static part is below 512 bytes).
+constexpr size_t LEAN_LDS_LIMIT = 160 * 1024 - 512;
+
+// Positions exchanged per round: the whole cell when its records fit.
+__host__ __device__ constexpr uint32_t lean_positions(int cap)
+{
+    const size_t want = ((size_t)cap + 1) & ~(size_t)1;
+    const size_t lim = (LEAN_LDS_LIMIT / sizeof(Rec<float>)) & ~(size_t)63;
+    return (uint32_t)(want < lim ? want : lim);
+}
+
+template <int T, int K>
+__host__ __device__ constexpr size_t lean_lds_bytes()
+{
+    const size_t ex = (size_t)lean_positions(T * K) * sizeof(Rec<float>);
+    const size_t s = LeanGeom<T, K>::SORT_BYTES;
+    return s > ex ? s : ex;
+}
+
+// One exchange round over the sorted positions [base, base + P): members post
+// (velocity, word) at their position, one thread per pair rotates, members
+// read their record back.  Contains the barriers.
+template <int T, int K>
+__device__ __forceinline__ void lean_round(uint32_t base, uint32_t P, uint32_t np2, int n, float C,
+                                           Rec<float> *rec, float (&vx)[K], float (&vy)[K],
+                                           float (&vz)[K], const uint32_t (&w2)[K],
+                                           const uint32_t (&w3)[K], const uint32_t (&pos)[K])
+{
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int i = threadIdx.x + k * T;
+        const uint32_t q = pos[k] - base;
+        if (i < n && q < P && pos[k] < np2) {
+            // first members carry their deviate, second ones word 2
+            const float z = ta_z(w2[k], w3[k]);
+            Rec<float> e;
+            e.x = vx[k];
+            e.y = vy[k];
+            e.z = vz[k];
+            e.w2 = (pos[k] & 1u) ? w2[k] : __float_as_uint(z);
+            rec[q] = e;
+        }
+    }
+    lds_barrier();
+    const uint32_t m = min(P, np2 - base) / 2;
+    for (uint32_t j = threadIdx.x; j < m; j += T) {
+        Rec<float> A = rec[2 * j], B = rec[2 * j + 1];
+        float hx, hy, hz;
+        ta_half_z(A.x - B.x, A.y - B.y, A.z - B.z, C, __uint_as_float(A.w2), B.w2, hx, hy, hz);
+        A.x += hx;
+        A.y += hy;
+        A.z += hz;
+        B.x -= hx;
+        B.y -= hy;
+        B.z -= hz;
+        rec[2 * j] = A;
+        rec[2 * j + 1] = B;
+    }
+    lds_barrier();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int i = threadIdx.x + k * T;
+        const uint32_t q = pos[k] - base;
+        if (i < n && q < P && pos[k] < np2) {
+            const Rec<float> e = rec[q];
+            vx[k] = e.x;
+            vy[k] = e.y;
+            vz[k] = e.z;
+        }
+    }
+}
+
+template <int T, int K, bool MCC>
+__device__ void lean_pass(const CollideArgs &a, int cell, unsigned char *smem, uint32_t *wtot)
+{
+    typedef LeanGeom<T, K> G;
+    constexpr uint32_t P = lean_positions(G::CAP);
+    const int lo = a.cell_start[cell];
+    const int n = a.cell_start[cell + 1] - lo;
+    const uint32_t step = (uint32_t)read_step(a);
+    float *vx_g = (float *)a.v + lo;
+    float *vy_g = (float *)a.v + a.n + lo;
+    float *vz_g = (float *)a.v + 2 * a.n + lo;
+    const uint32_t *pid_c = a.pid + lo;
+
+    float vx[K], vy[K], vz[K];
+    uint32_t w2[K], w3[K], key[K], pos[K];
+    uint32_t cand = 0, multi = 0;
+
+    if (n == 0) {
+        lds_barrier();   // leave together (see the end of the pass)
+        return;
+    }
+    // every load of the thread is in flight before the first is used, the
+    // ids first (the Philox calls wait for them only).  Members past the end
+    // load the last one instead (ignored): with no branch around the loads the
+    // compiler waits for each load by count instead of for all of them.
+    {
+        int ic[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) ic[k] = min((int)threadIdx.x + k * T, n - 1);
+#pragma unroll
+        for (int k = 0; k < K; ++k) pos[k] = pid_c[ic[k]];
+        asm volatile("" ::: "memory");   // keep the id loads ahead of the velocity loads
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            vx[k] = vx_g[ic[k]];
+            vy[k] = vy_g[ic[k]];
+            vz[k] = vz_g[ic[k]];
+        }
+    }
+    if (n >= 2) {
+        const uint32_t bits = sort_bits(n);
+        const uint32_t nb = 1u << bits;
+        const uint32_t per = nb >= (uint32_t)T ? nb / (uint32_t)T : 1u;
+        uint32_t *cnt = (uint32_t *)smem;
+        uint32_t *sk = cnt + G::CNT_WORDS;              // keys of members sharing a bucket
+        uint16_t *lst = (uint16_t *)(sk + G::CAP);      // ... and their index in the cell
+#pragma unroll
+        for (int q = 0; q < G::PERMAX; ++q)
+            if ((uint32_t)q < per && threadIdx.x + q * T < nb) cnt[threadIdx.x + q * T] = 0u;
+        lds_barrier();
+        // one Philox call per particle; count its key's bucket
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int i = threadIdx.x + k * T;
+            if (i < n) {
+                const W4 w = draw4(a.seed, pos[k], step, 0u, 0u);
+                key[k] = w.x;
+                w2[k] = w.z;
+                w3[k] = w.w;
+                if (MCC && (uint64_t)w.y < a.mcc_thr) cand |= 1u << k;
+                const uint32_t b = w.x >> (32u - bits);
+                pos[k] = atomicAdd(&cnt[b], 1u);   // arrival rank in the bucket
+            }
+        }
+        lds_barrier();
+        // bucket starts (cnt[nb] = n)
+        lds_excl_scan<T, G::ROWMAX>(cnt, nb, wtot);
+        // slot = bucket start + arrival; members sharing their bucket post
+        // their key and index there
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int i = threadIdx.x + k * T;
+            if (i < n) {
+                const uint32_t b = key[k] >> (32u - bits);
+                const uint32_t st = cnt[b], en = cnt[b + 1];
+                const uint32_t slot = st + pos[k];
+                pos[k] = slot;
+                if (en - st > 1u) {
+                    multi |= 1u << k;
+                    sk[slot] = key[k];
+                    lst[slot] = (uint16_t)i;
+                }
+            }
+        }
+        lds_barrier();
+        // rank inside a shared bucket by (key, pid)
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if ((multi >> k) & 1u) {
+                const int i = threadIdx.x + k * T;
+                const uint32_t b = key[k] >> (32u - bits);
+                const uint32_t st = cnt[b], en = cnt[b + 1];
+                const uint32_t size = en - st;
+                uint32_t r = 0, tie = 0;
+                // the first four slots without a loop (reads past the bucket
+                // stay inside the sort's memory and are ignored)
+#pragma unroll
+                for (uint32_t j = 0; j < 4; ++j) {
+                    const uint32_t kj = sk[st + j];
+                    const bool in = j < size;
+                    r += (in && kj < key[k]) ? 1u : 0u;
+                    tie |= (in && kj == key[k] && st + j != pos[k]) ? 1u : 0u;
+                }
+                for (uint32_t j = st + 4; j < en; ++j) {
+                    const uint32_t kj = sk[j];
+                    r += kj < key[k] ? 1u : 0u;
+                    tie |= (kj == key[k] && j != pos[k]) ? 1u : 0u;
+                }
+                if (tie) {
+                    // equal keys (rare): the smaller pid comes first
+                    const uint32_t pi = pid_c[i];
+                    for (uint32_t j = st; j < en; ++j)
+                        if (j != pos[k] && sk[j] == key[k] && pid_c[lst[j]] < pi) ++r;
+                }
+                pos[k] = st + r;
+            }
+        }
+        lds_barrier();   // the sort's memory becomes the exchange records
+
+        const float C = (float)cell_C(a, cell);
+        const uint32_t np2 = (uint32_t)n & ~1u;     // positions with a partner
+        Rec<float> *rec = (Rec<float> *)smem;
+        for (uint32_t base = 0; base < np2; base += P) {
+            if (base) lds_barrier();
+            lean_round<T, K>(base, P, np2, n, C, rec, vx, vy, vz, w2, w3, pos);
+        }
+    } else if (MCC) {
+        const W4 w = draw4(a.seed, pos[0], step, 0u, 0u);
+        if (threadIdx.x == 0 && (uint64_t)w.y < a.mcc_thr) cand = 1u;
+    }
+
+    // null collisions, one candidate at a time per lane (as in cell_pass)
+    if constexpr (MCC) {
+        uint32_t left = cand;
+        while (__ballot(left != 0u) != 0ull) {
+            if (left) {
+                const int kk = __builtin_ctz(left);
+                left &= left - 1u;
+                float x = vx[0], y = vy[0], z = vz[0];
+#pragma unroll
+                for (int k = 1; k < K; ++k)
+                    if (kk == k) {
+                        x = vx[k];
+                        y = vy[k];
+                        z = vz[k];
+                    }
+                mcc_scatter<float>(x, y, z, pid_c[threadIdx.x + kk * T], a.seed, step, a.mass_ratio);
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+                    if (kk == k) {
+                        vx[k] = x;
+                        vy[k] = y;
+                        vz[k] = z;
+                    }
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int i = threadIdx.x + k * T;
+        if (i < n) {
+            vx_g[i] = vx[k];
+            vy_g[i] = vy[k];
+            vz_g[i] = vz[k];
+        }
+    }
+    // the next cell reuses the LDS; the stores stay in flight into it
+    lds_barrier();
+}
+
+template <int T, int K, bool MCC>
+__global__ __launch_bounds__(T) void k_collide_lean(CollideArgs a, const int32_t *__restrict__ list,
+                                                    int cls)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ uint32_t wtot[T / PIC_WAVE];
+    __shared__ int s_item;
+    if (gated_off(a)) return;
+    const uint32_t count = a.dflags->count[cls];
+    if (blockIdx.x >= count) return;   // no work for this workgroup (nor a queue atomic)
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(&a.dflags->head[cls], 1u);
+        lds_barrier();
+        const int item = s_item;
+        lds_barrier();
+        if (item >= (int)count) break;
+        lean_pass<T, K, MCC>(a, list[item], smem, wtot);
     }
 }
 
@@ -1154,6 +1538,31 @@ int launch_class(const CollideArgs &a, const int32_t *list, int cls, int blocks,
     return PIC_OK;
 }
 
+// The lean pass for binary32 steps without conservation sums, moment sums or
+// the pairing export; cell_pass otherwise.
+template <typename R, int T, int K, int F>
+int launch_class_best(const CollideArgs &a, const int32_t *list, int cls, int blocks, hipStream_t st)
+{
+    if constexpr (std::is_same<R, float>::value && (F & ~F_MCC) == 0) {
+        constexpr bool MCC = (F & F_MCC) != 0;
+        const size_t lds = lean_lds_bytes<T, K>();
+        auto kern = k_collide_lean<T, K, MCC>;
+        static bool attr_done = false;
+        if (!attr_done) {
+            HIP_OK(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds));
+            attr_done = true;
+        }
+        ktime_begin(KT_CLASS0 + cls, st);
+        hipLaunchKernelGGL(kern, dim3(blocks), dim3(T), lds, st, a, list, cls);
+        ktime_end(KT_CLASS0 + cls, st);
+        HIP_OK(hipGetLastError());
+        return PIC_OK;
+    } else {
+        return launch_class<R, T, K, F>(a, list, cls, blocks, st);
+    }
+}
+
 SegScratch g_seg;   // set from the workspace before each step's launches
 
 template <typename R, int T, int K, int F>
@@ -1208,7 +1617,7 @@ int launch_all(const CollideArgs &a, const int32_t *lists, int32_t n_cells, int 
     ktime_end(KT_HUGE, st);
     HIP_OK(hipGetLastError());
     if ((live & (1u << 3)) &&
-        (rc = launch_class<R, C::T3, C::K3, F>(a, lists + 3 * M, 3, bp[3] * num_cu, st)))
+        (rc = launch_class_best<R, C::T3, C::K3, F>(a, lists + 3 * M, 3, bp[3] * num_cu, st)))
         return rc;
     if ((live & (1u << 2)) &&
         (rc = launch_class<R, C::T2, C::K2, F>(a, lists + 2 * M, 2, bp[2] * num_cu, st)))
