@@ -115,6 +115,32 @@ int coulomb_collide(pic_ctx *ctx, int dtype, void *v, int32_t *cell_of, uint32_t
                     int64_t n, int32_t n_cells, double dt, double lnLambda,
                     const double *density, uint64_t seed, uint64_t step, uint32_t flags);
 
+/* Allocation-free form of coulomb_collide, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, pairs and arithmetic as
+ * coulomb_collide (its kernels and results, bit for bit), restricted to
+ *  - storage already in cell order (PIC_ASSUME_SORTED is implied; a violated
+ *    order latches PIC_ERR_STATE at pic_sync and leaves v unchanged);
+ *  - n_cells <= PIC_NOALLOC_MAX_CELLS (else PIC_ERR_RANGE, nothing runs);
+ *  - cells of at most PIC_NOALLOC_MAX_CELL_F32 (binary32) or
+ *    PIC_NOALLOC_MAX_CELL_F64 (binary64) members: larger cells are left
+ *    unchanged and pic_sync reports PIC_ERR_STATE;
+ *  - flags among PIC_FUSE_MCC, PIC_ASSUME_SORTED and PIC_MOMENTS (the buffer of
+ *    pic_set_moments_out); PIC_GATE or PIC_CONSERVE_FIX give PIC_ERR_ARG.
+ * Its scratch (cell starts and work lists) is a fixed device array of
+ * PIC_NOALLOC_SCRATCH_BYTES per GPU, in the library's code object, whose
+ * address pic_create takes once per device: the call allocates nothing.
+ * Every call on a GPU shares that GPU's array, so calls that overlap on one
+ * GPU (several streams or host threads) race; calls in one stream do not.
+ * Other errors as coulomb_collide. */
+#define PIC_NOALLOC_MAX_CELLS 65536
+#define PIC_NOALLOC_MAX_CELL_F32 10240
+#define PIC_NOALLOC_MAX_CELL_F64 6144
+#define PIC_NOALLOC_SCRATCH_BYTES (2u << 20)
+int coulomb_collide_noalloc(pic_ctx *ctx, int dtype, void *v, int32_t *cell_of, uint32_t *pid,
+                            int64_t n, int32_t n_cells, double dt, double lnLambda,
+                            const double *density, uint64_t seed, uint64_t step, uint32_t flags);
+
 /* nsteps consecutive steps step0, step0+1, ... with the arguments of
  * coulomb_collide (the operator split of the PIC scheme runs several collision
  * steps between field solves, paragraph "Operator Splitting Algorithms").

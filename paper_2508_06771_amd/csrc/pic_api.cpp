@@ -6,14 +6,41 @@
 #include <stdio.h>
 #include <stdlib.h>
 
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
 
 #include "pic_internal.hpp"
 
+// Scratch of coulomb_collide_noalloc: a fixed array in the code object, one
+// copy per GPU.  Host code uses only the per-device address that
+// hipGetSymbolAddress returns (the array's name is a host-side stand-in).
+static __device__ __align__(256) unsigned char scratch[PIC_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// The address of this GPU's copy of `scratch`, taken once per device with the
+// device current (the caller has set it).
+void *noalloc_scratch(int device)
+{
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+        g_scratch_ptr[device] = p;
+    }
+    return g_scratch_ptr[device];
+}
+}  // namespace
+
 struct pic_ctx {
     int device = 0;
+    void *noalloc = nullptr;   // this device's copy of `scratch`
     hipStream_t stream = nullptr;
     int num_cu = 256;
     size_t lds_max = 65536;
@@ -292,6 +319,7 @@ int pic_create(pic_ctx **out, int device, void *hip_stream)
         delete c;
         return PIC_ERR_HIP;
     }
+    c->noalloc = noalloc_scratch(device);   // null: coulomb_collide_noalloc reports PIC_ERR_STATE
     int v = 0;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && v > 0)
         c->num_cu = v;
@@ -929,6 +957,54 @@ int coulomb_collide(pic_ctx *c, int dtype, void *v, int32_t *cell_of, uint32_t *
     if (!c) return PIC_ERR_ARG;
     const StepArgs s = {dtype, v, cell_of, pid, n, n_cells, dt, lnLambda, density, seed, step, flags};
     return collide_common(c, s);
+}
+
+int coulomb_collide_noalloc(pic_ctx *c, int dtype, void *v, int32_t *cell_of, uint32_t *pid,
+                            int64_t n, int32_t n_cells, double dt, double lnLambda,
+                            const double *density, uint64_t seed, uint64_t step, uint32_t flags)
+{
+    if (!c) return PIC_ERR_ARG;
+    const StepArgs s = {dtype, v, cell_of, pid, n, n_cells, dt, lnLambda, density, seed, step,
+                        flags | PIC_ASSUME_SORTED};
+    if (flags & ~(uint32_t)(PIC_FUSE_MCC | PIC_ASSUME_SORTED | PIC_MOMENTS)) return PIC_ERR_ARG;
+    RC(step_check(c, s));
+    if (n_cells > PIC_NOALLOC_MAX_CELLS) return PIC_ERR_RANGE;
+    const size_t cs_bytes = ((size_t)(n_cells + 1) * 4 + 255) & ~(size_t)255;
+    static_assert(((size_t)(PIC_NOALLOC_MAX_CELLS + 1) * 4 + 255) / 256 * 256 +
+                          (size_t)PIC_NOALLOC_MAX_CELLS * QUEUE_LISTS * 4 <=
+                      PIC_NOALLOC_SCRATCH_BYTES,
+                  "scratch holds the cell starts and work lists of the largest grid");
+    if (!c->noalloc) return PIC_ERR_STATE;
+    CK(hipSetDevice(c->device));
+    hipStream_t st = c->stream;
+    unsigned char *base = (unsigned char *)c->noalloc;
+    int32_t *cs = (int32_t *)base;
+    int32_t *lists = (int32_t *)(base + cs_bytes);
+    // the default routing: every cell of the LDS classes, none beyond them
+    const ClassCaps caps = collide_caps(dtype, c->lds_max);
+    const uint64_t mcc_thr = (flags & PIC_FUSE_MCC) ? mcc_threshold(dt, c->mcc_sigma0, c->mcc_nn) : 0;
+    RC(launch_reset_flags(c->flags, st));
+    RC(launch_bin_check(cell_of, n, n_cells, cs, c->flags, 2, nullptr, st));
+    RC(launch_build_queue(cs, n_cells, caps, lists, c->flags, nullptr, 0, nullptr, 0, st));
+    RC(launch_reject_list(c->flags, caps.ncls, st));   // cells beyond the LDS classes
+    CollideArgs a;
+    memset(&a, 0, sizeof(a));
+    a.v = v;
+    a.n = n;
+    a.pid = pid;
+    a.cell_start = cs;
+    a.density = density;
+    a.dt = dt;
+    a.lnL = lnLambda;
+    a.seed = seed;
+    a.step = step;
+    a.flags = s.flags;
+    a.mcc_thr = mcc_thr;
+    a.mass_ratio = c->mcc_mr;
+    a.moments = c->moments_out;
+    a.dflags = c->flags;
+    const uint32_t lds_classes = (1u << caps.ncls) - 1u;
+    return launch_collide(dtype, a, lists, n_cells, caps, 0, c->num_cu, st, false, lds_classes);
 }
 
 int pic_run_steps(pic_ctx *c, int dtype, void *v, int32_t *cell_of, uint32_t *pid, int64_t n,

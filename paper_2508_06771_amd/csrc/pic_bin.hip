@@ -37,6 +37,12 @@ __global__ void k_reset_flags(DevFlags *f)
     }
 }
 
+// Latches PIC_ERR_STATE when work list `list` holds any cell.
+__global__ void k_reject_list(DevFlags *f, int list)
+{
+    if (threadIdx.x == 0 && f->count[list] != 0u) f->sticky_state = 1;
+}
+
 __global__ void k_set_step(uint64_t *s, uint64_t v)
 {
     if (threadIdx.x == 0) *s = v;
@@ -363,6 +369,13 @@ int grid_for(int64_t n, int threads, int cap)
 int launch_reset_flags(DevFlags *flags, hipStream_t st)
 {
     hipLaunchKernelGGL(k_reset_flags, dim3(1), dim3(64), 0, st, flags);
+    HIP_OK(hipGetLastError());
+    return PIC_OK;
+}
+
+int launch_reject_list(DevFlags *flags, int list, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_reject_list, dim3(1), dim3(64), 0, st, flags, list);
     HIP_OK(hipGetLastError());
     return PIC_OK;
 }

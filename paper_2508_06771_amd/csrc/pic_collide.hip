@@ -1508,6 +1508,9 @@ template <> struct Classes<double> {
     static constexpr int T2 = 1024, K2 = 4;
     static constexpr int T3 = 1024, K3 = 6;   // <= 6144
 };
+static_assert(Classes<float>::T3 * Classes<float>::K3 == PIC_NOALLOC_MAX_CELL_F32 &&
+                  Classes<double>::T3 * Classes<double>::K3 == PIC_NOALLOC_MAX_CELL_F64,
+              "the allocation-free step takes the cells of the LDS classes");
 
 // Workgroup geometry of one segment of the segmented path: the largest
 // class's (segments of 2,560 members on two 512-thread workgroups per CU

@@ -658,6 +658,8 @@ int radix_pass(const RadixPass &p, const BinScratch &s, hipStream_t st);
 int launch_bin_check(const int32_t *cell_of, int64_t n, int32_t n_cells, int32_t *cell_start,
                      DevFlags *flags, int set_unsorted, const int *gate, hipStream_t st);
 int launch_reset_flags(DevFlags *flags, hipStream_t st);
+// Latches sticky_state when work list `list` is not empty.
+int launch_reject_list(DevFlags *flags, int list, hipStream_t st);
 int launch_set_step(uint64_t *step_dev, uint64_t value, hipStream_t st);
 int launch_step_inc(uint64_t *step_dev, hipStream_t st);
 int launch_copy32(uint32_t *dst, const uint32_t *src, int64_t n, const int *gate, hipStream_t st);

@@ -23,6 +23,11 @@ FUSE_MCC = 1 << 1
 GATE = 1 << 2
 ASSUME_SORTED = 1 << 3
 MOMENTS = 1 << 4
+PIC_ERR_ARG, PIC_ERR_RANGE, PIC_ERR_STATE = 1, 2, 6
+# limits of coulomb_collide_noalloc (its fixed scratch and the LDS classes)
+NOALLOC_MAX_CELLS = 65536
+NOALLOC_MAX_CELL_F32 = 10240
+NOALLOC_MAX_CELL_F64 = 6144
 
 _STATUS = {0: "PIC_OK", 1: "PIC_ERR_ARG", 2: "PIC_ERR_RANGE", 3: "PIC_ERR_HIP",
            4: "PIC_ERR_NOMEM", 5: "PIC_ERR_DTYPE", 6: "PIC_ERR_STATE"}
@@ -48,6 +53,8 @@ def _load():
         "pic_sync": ([vp], C.c_int),
         "pic_set_stream": ([vp, vp], C.c_int),
         "pic_bin_cells": ([vp, vp, i64, i32, vp, vp], C.c_int),
+        "coulomb_collide_noalloc": ([vp, C.c_int, vp, vp, vp, i64, i32, f64, f64, vp, u64, u64,
+                                     u32], C.c_int),
         "coulomb_collide": ([vp, C.c_int, vp, vp, vp, i64, i32, f64, f64, vp, u64, u64, u32],
                             C.c_int),
         "pic_set_mcc": ([vp, f64, f64, f64], C.c_int),
@@ -105,7 +112,7 @@ EXPORTED = ["pic_create", "pic_destroy", "pic_strerror", "pic_sync", "pic_set_st
             "pic_gate_config", "pic_gate_reset", "pic_gate_stats", "pic_gate_state", "pic_autotune",
             "pic_conserve_reset", "pic_gate_refresh", "gate_infer", "pic_set_dsmc", "dsmc_collide",
             "mcc_null_collide_exact", "p2c_sums", "recombine", "coulomb_collide_nanbu",
-            "coulomb_collide_triplet"]
+            "coulomb_collide_triplet", "coulomb_collide_noalloc"]
 
 MLP_PARAMS = 4801
 GATE_STATS = ["steps", "skipped", "collided", "judged", "judged_want", "false_skip", "disabled",
@@ -201,6 +208,20 @@ class Context:
         _chk(lib.coulomb_collide(self._h, _dt(v), _p(v), _p(cell_of), _p(pid), v.shape[1],
                                  n_cells, dt, lnL, _p(density), seed, step, flags),
              "coulomb_collide")
+
+    def coulomb_collide_noalloc(self, v: torch.Tensor, cell_of: torch.Tensor, pid: torch.Tensor,
+                                n_cells: int, *, dt: float, lnL: float, seed: int, step: int,
+                                density=None, flags: int = 0):
+        """coulomb_collide on storage already in cell order, with the library's
+        fixed per-GPU scratch (no device allocation)."""
+        assert v.dim() == 2 and v.shape[0] == 3
+        assert cell_of.dtype == torch.int32 and pid.dtype in (torch.int32, torch.uint32)
+        if density is not None:
+            assert density.dtype == torch.float64 and density.numel() == n_cells
+        self._stream()
+        _chk(lib.coulomb_collide_noalloc(self._h, _dt(v), _p(v), _p(cell_of), _p(pid), v.shape[1],
+                                         n_cells, dt, lnL, _p(density), seed, step, flags),
+             "coulomb_collide_noalloc")
 
     def run_steps(self, v: torch.Tensor, cell_of: torch.Tensor, pid: torch.Tensor, n_cells: int,
                   *, dt: float, lnL: float, seed: int, step0: int, nsteps: int, density=None,

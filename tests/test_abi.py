@@ -63,3 +63,12 @@ def test_null_context_is_rejected(lib):
     assert lib.pic_bin_cells(None, None, 0, 1, None, None) == 1
     lib.pic_create.argtypes = [vp, C.c_int, vp]
     assert lib.pic_create(None, 0, None) == 1
+
+
+def test_noalloc_limits_match_header():
+    """The binding's limits of coulomb_collide_noalloc are the header's."""
+    from paper_2508_06771_amd import piccoll
+    text = open(HEADER).read()
+    for name in ("NOALLOC_MAX_CELLS", "NOALLOC_MAX_CELL_F32", "NOALLOC_MAX_CELL_F64"):
+        m = re.search(r"#define PIC_%s (\d+)" % name, text)
+        assert m and int(m.group(1)) == getattr(piccoll, name), name
