@@ -650,6 +650,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the binary64 leg of the c2 workload")
+    ap.add_argument("--fp64-only", action="store_true",
+                    help="c2: run only the binary64 leg (its figures become the line's)")
     ap.add_argument("--drift-steps", type=int, default=None,
                     help="c2: steps over which the energy drift is taken (default: the "
                          "configuration's 1000; at least the steps already run)")
@@ -685,6 +687,18 @@ def main():
         print(json.dumps(out), flush=True)
         return
 
+    if args.fp64_only:
+        leg = c2_leg(args, "f64")
+        cpu = None if args.no_cpu else cpu_baseline(args.cpu_seconds)
+        config = {"workload": "4096 cells x 10,000 electrons (40.96M), FP64 SoA, Maxwellian + "
+                              "5% cold beam, Coulomb (Takizuka-Abe) + fused null-collision MCC",
+                  "n_electrons": leg["n"], "n_cells": 4096, "dt_over_tau_e": 0.01,
+                  "lnLambda": 10.0, "p_null": 0.01}
+        out = _line(leg["value"], leg["ms_per_step"], args, "f64", config)
+        out.update({k: leg[k] for k in leg if k not in ("value", "ms_per_step", "n")})
+        out["cpu_baseline"] = cpu
+        print(json.dumps(out), flush=True)
+        return
     leg32 = c2_leg(args, "f32")
     leg64 = None if args.no_fp64 else c2_leg(args, "f64")
     copy_gbs, _ = copy_probe(torch)
@@ -788,7 +802,7 @@ def c2_leg(args, dtype_name):
     roof = None
     dom = None
     if f32 and "class3" in kms:
-        dom = ("class3", "k_collide<float,1024,10> (cells of 4097..10240 members)")
+        dom = ("class3", "k_collide_lean<1024,10,MCC> (cells of 4097..10240 members)")
     elif not f32 and "huge" in kms:
         dom = ("huge", "segmented path of cells beyond 6144 members (k_seg_count, k_seg_scan, "
                        "k_seg_scatter, k_seg_collide, k_seg_fixup)")
