@@ -65,6 +65,10 @@ def lib():
         L.orc_step_triplet.argtypes = [f64p, C.c_int64, i32p, u32p, C.c_int32, C.c_double,
                                        C.c_double, C.c_void_p, C.c_uint64, C.c_uint64]
         L.orc_step_triplet.restype = C.c_int
+        L.orc_step_weighted.argtypes = [f64p, C.c_void_p, C.c_int64, i32p, u32p, C.c_int32,
+                                        C.c_double, C.c_double, C.c_void_p, C.c_uint64,
+                                        C.c_uint64, C.c_int32, C.c_double, C.c_double, C.c_double]
+        L.orc_step_weighted.restype = C.c_int
         L.orc_nanbu_A.argtypes = [C.c_double]
         L.orc_nanbu_A.restype = C.c_double
         L.orc_nanbu_omc.argtypes = [C.c_double, C.c_double]
@@ -209,6 +213,22 @@ def step_triplet(v, cell_start, pid, dt, lnL, seed, step, density=None):
                                 None if d is None else d.ctypes.data, seed, step)
     if rc:
         raise ValueError(f"orc_step_triplet failed: {rc}")
+
+
+def step_weighted(v, w, cell_start, pid, dt, lnL, seed, step, density=None, mcc=False,
+                  sigma0=0.0, n_neutral=0.0, mass_ratio=0.0):
+    """One Takizuka-Abe step of variable-weight particles (weights w, (n,)
+    float64), in place on v (3, n) float64, storage in cell order."""
+    n = v.shape[1]
+    cell_start = np.ascontiguousarray(cell_start, dtype=np.int32)
+    pid = np.ascontiguousarray(pid, dtype=np.uint32)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    d = None if density is None else np.ascontiguousarray(density, dtype=np.float64)
+    rc = lib().orc_step_weighted(v.reshape(-1), w.ctypes.data, n, cell_start, pid,
+                                 cell_start.size - 1, dt, lnL, None if d is None else d.ctypes.data,
+                                 seed, step, int(bool(mcc)), sigma0, n_neutral, mass_ratio)
+    if rc:
+        raise ValueError(f"orc_step_weighted failed: {rc}")
 
 
 def nanbu_A(s: float) -> float:

@@ -928,3 +928,75 @@ int orc_step_triplet(double *v, int64_t n, const int32_t *cell_start, const uint
     free(partner);
     return rc;
 }
+
+/* ------------------------------------------------------------------ */
+/* Variable-weight particles (the paper names weights that differ     */
+/* between particles as the next step beyond its uniform weights,      */
+/* Sec. "Conclusion").  Reading W1, after Nanbu & Yonemura's rule for  */
+/* binary collisions of weighted particles: the pairs, deflection and  */
+/* half change h = du/2 are the uniform step's (s^2 from the cell      */
+/* density); then the member of smaller weight w_l takes its half       */
+/* change always and the one of larger weight w_h with probability     */
+/* w_l / w_h: accepted iff U4 * w_h < w_l in binary64, with U4 the      */
+/* uniform of word 3 of the second member's domain-0 draw (the one word */
+/* of the pair's two draws the uniform step leaves unused).  Equal      */
+/* weights: both take it (the uniform step).  For w_a >= w_b the        */
+/* expected weighted change of momentum, w_a (w_b/w_a) h - w_b h, is   */
+/* zero, and so is that of w |v|^2 since u.h = -|h|^2: both are         */
+/* conserved on average, not in each collision.  Null collisions as in */
+/* the uniform step.  Storage in cell order.                            */
+/* ------------------------------------------------------------------ */
+int orc_step_weighted(double *v, const double *w, int64_t n, const int32_t *cell_start,
+                      const uint32_t *pid, int32_t M, double dt, double lnL, const double *density,
+                      uint64_t seed, uint64_t step, int32_t mcc, double sigma0, double n_neutral,
+                      double mass_ratio)
+{
+    if (cell_start[M] != n) return 1;
+    int32_t *sorted = malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    int32_t *partner = malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    if (!sorted || !partner) {
+        free(sorted);
+        free(partner);
+        return 2;
+    }
+    int rc = orc_pairs(cell_start, pid, M, seed, step, sorted, partner);
+    double *vx = v, *vy = v + n, *vz = v + 2 * n;
+    const uint64_t thr = orc_mcc_threshold(dt, sigma0, n_neutral);
+    const double nu_max = n_neutral * sigma0 * sqrt(2.0);
+    for (int32_t j = 0; j < M && !rc; ++j) {
+        const double dens = density ? density[j] : 1.0;
+        const int64_t lo = cell_start[j], N = (int64_t)cell_start[j + 1] - lo;
+        for (int64_t r = 0; r + 1 < N; r += 2) {
+            const int64_t a = sorted[lo + r], b = sorted[lo + r + 1];
+            uint32_t wa[4], wb[4];
+            draw(seed, pid[a], step, 0u, 0u, wa);
+            draw(seed, pid[b], step, 0u, 0u, wb);
+            double u[3] = {vx[a] - vx[b], vy[a] - vy[b], vz[a] - vz[b]};
+            double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+            if (uu == 0.0) continue;
+            double du[3];
+            orc_ta_delta(u, orc_ta_s2(sqrt(uu), dens, lnL, dt), orc_u01(wa[2]), orc_u01(wa[3]),
+                         orc_u01(wb[2]), du);
+            double h0 = 0.5 * du[0], h1 = 0.5 * du[1], h2 = 0.5 * du[2];
+            int take_a = 1, take_b = 1;
+            if (w[a] != w[b]) {
+                const double U4 = orc_u01(wb[3]);
+                if (w[a] > w[b]) take_a = U4 * w[a] < w[b];
+                else take_b = U4 * w[b] < w[a];
+            }
+            if (take_a) { vx[a] += h0; vy[a] += h1; vz[a] += h2; }
+            if (take_b) { vx[b] -= h0; vy[b] -= h1; vz[b] -= h2; }
+        }
+        if (mcc) {
+            for (int64_t m = lo; m < lo + N; ++m) {
+                uint32_t d0[4];
+                draw(seed, pid[m], step, 0u, 0u, d0);
+                mcc_particle(vx, vy, vz, m, pid[m], d0[1], thr, nu_max, nu_max, mass_ratio, seed,
+                             step, NULL);
+            }
+        }
+    }
+    free(sorted);
+    free(partner);
+    return rc;
+}
