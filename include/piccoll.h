@@ -265,6 +265,24 @@ int coulomb_collide_triplet(pic_ctx *ctx, int dtype, void *v, const uint32_t *pi
                             const int32_t *cell_start, int32_t n_cells, double dt, double lnLambda,
                             const double *density, uint64_t seed, uint64_t step);
 
+/* The Takizuka & Abe step for particles of unequal weight (the paper uses
+ * uniform weights and names weights that differ between particles as the
+ * next step, Sec. "Conclusion").  Rule (Nanbu & Yonemura's for weighted
+ * binary collisions): the pairs and each pair's half change h are
+ * coulomb_collide's; the member of smaller weight w_l always takes its half
+ * change, the other one iff U4 * w_h < w_l in binary64, with U4 the uniform
+ * of word 3 of the second member's domain-0 draw.  Equal weights give
+ * coulomb_collide's velocities; weighted momentum and energy are conserved
+ * on average.  w: n weights (>= 0) of `dtype`, not modified.  Storage in cell
+ * order (v, w and pid), cell_start of n_cells + 1 entries; density per cell
+ * (nullable: 1).  flags: 0 or PIC_FUSE_MCC (null collisions as
+ * coulomb_collide's, PIC_ERR_STATE before pic_set_mcc).  Errors as
+ * coulomb_collide_nanbu, PIC_ERR_ARG for a NULL w or other flags. */
+int coulomb_collide_weighted(pic_ctx *ctx, int dtype, void *v, const void *w, const uint32_t *pid,
+                             int64_t n, const int32_t *cell_start, int32_t n_cells, double dt,
+                             double lnLambda, const double *density, uint64_t seed, uint64_t step,
+                             uint32_t flags);
+
 /* Recombination C5 (section "Kernel for Recombination Collision C5", table
  * "Recombination Steps" RS1-RS5): in each cell the live primaries
  * (primary[l] != 0, w[l] > 0; the paper's list from step CS3) are matched one

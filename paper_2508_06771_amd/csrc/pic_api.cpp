@@ -1193,6 +1193,48 @@ int coulomb_collide_nanbu(pic_ctx *c, int dtype, void *v, const uint32_t *pid, i
     return rc;
 }
 
+int coulomb_collide_weighted(pic_ctx *c, int dtype, void *v, const void *w, const uint32_t *pid,
+                             int64_t n, const int32_t *cell_start, int32_t n_cells, double dt,
+                             double lnL, const double *density, uint64_t seed, uint64_t step,
+                             uint32_t flags)
+{
+    if (!c || n < 0 || n > INT32_MAX || n_cells < 1 || !cell_start || !(dt > 0.0) || !(lnL > 0.0) ||
+        (n > 0 && (!v || !w || !pid)))
+        return PIC_ERR_ARG;
+    RC(check_dtype(dtype));
+    if (flags & ~(uint32_t)PIC_FUSE_MCC) return PIC_ERR_ARG;
+    if ((flags & PIC_FUSE_MCC) && !c->mcc_set) return PIC_ERR_STATE;
+    if (n == 0) return PIC_OK;
+    CK(hipSetDevice(c->device));
+    hipStream_t st = c->stream;
+    RC(ensure_ws(c, (size_t)n_cells * QUEUE_LISTS * 4 + huge_scratch_bytes(dtype, n) + 4096));
+    Bump b(c->ws);
+    int32_t *lists = (int32_t *)b.take((size_t)n_cells * QUEUE_LISTS * 4);
+    set_huge_scratch(dtype, n, b.take(huge_scratch_bytes(dtype, n)));
+    const ClassCaps caps = collide_caps(dtype, c->lds_max);
+    ktime_begin(KT_WEIGHTED, st);
+    RC(launch_reset_flags(c->flags, st));
+    RC(launch_build_queue(cell_start, n_cells, caps, lists, c->flags, nullptr, 0, nullptr, 0, st));
+    CollideArgs a;
+    memset(&a, 0, sizeof(a));
+    a.v = v;
+    a.w = w;
+    a.n = n;
+    a.pid = pid;
+    a.cell_start = cell_start;
+    a.density = density;
+    a.dt = dt;
+    a.lnL = lnL;
+    a.seed = seed;
+    a.step = step;
+    a.mcc_thr = (flags & PIC_FUSE_MCC) ? mcc_threshold(dt, c->mcc_sigma0, c->mcc_nn) : 0;
+    a.mass_ratio = c->mcc_mr;
+    a.dflags = c->flags;
+    const int rc = launch_collide(dtype, a, lists, n_cells, caps, 0, c->num_cu, st, false, ~0u);
+    ktime_end(KT_WEIGHTED, st);
+    return rc;
+}
+
 int coulomb_collide_triplet(pic_ctx *c, int dtype, void *v, const uint32_t *pid, int64_t n,
                             const int32_t *cell_start, int32_t n_cells, double dt, double lnL,
                             const double *density, uint64_t seed, uint64_t step)

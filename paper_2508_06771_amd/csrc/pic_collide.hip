@@ -166,7 +166,22 @@ __device__ __forceinline__ bool gated_off(const CollideArgs &a)
 }
 
 // Variants compiled per kernel: which optional parts of the pass exist.
-enum { F_MCC = 1, F_CONS = 2, F_MOM = 4, F_PAIRS = 8 };
+enum { F_MCC = 1, F_CONS = 2, F_MOM = 4, F_PAIRS = 8, F_WT = 16 };
+
+// Variable-weight rule for the pair (a, b) with half change h (a += h,
+// b -= h in the uniform step): the member of smaller weight always takes its
+// half, the other one iff U4 * w_heavy < w_light in binary64, U4 = U(word 3 of
+// b's domain-0 draw).  Equal weights: both take it.
+template <typename R>
+__device__ __forceinline__ void weight_rule(R wa, R wb, uint32_t w3b, bool &take_a, bool &take_b)
+{
+    take_a = take_b = true;
+    if (wa != wb) {
+        const double U4 = u01d(w3b);
+        if (wa > wb) take_a = U4 * (double)wa < (double)wb;
+        else take_b = U4 * (double)wb < (double)wa;
+    }
+}
 
 // Pair-major exchange records.  In each round the members whose sorted
 // position falls in the round post their velocity and word 2 at that
@@ -180,20 +195,22 @@ template <> struct __align__(16) Rec<double> { double x, y, z; uint32_t w2, pad;
 // Dynamic LDS a cell pass may use (the static part is below 4 KB).
 constexpr size_t LDS_DYN_LIMIT = 152 * 1024;
 
-// Positions per exchange round: the whole cell when its records fit.
-template <typename R>
+// Positions per exchange round: the whole cell when its records fit.  With
+// weights a pair also holds the second member's word 3 and both weights.
+template <typename R, bool WT = false>
 __host__ __device__ constexpr uint32_t round_positions(int cap)
 {
-    const size_t per_pair = 2 * sizeof(Rec<R>) + 4;
+    const size_t per_pair = 2 * sizeof(Rec<R>) + 4 + (WT ? 4 + 2 * sizeof(R) : 0);
     const size_t want = ((size_t)cap + 1) / 2;
     const size_t lim = (LDS_DYN_LIMIT / per_pair) & ~(size_t)63;
     return (uint32_t)(2 * (want < lim ? want : lim));
 }
 
-template <typename R>
+template <typename R, bool WT = false>
 __host__ __device__ constexpr size_t lds_bytes(int cap)
 {
-    const size_t ex = (size_t)round_positions<R>(cap) / 2 * (2 * sizeof(Rec<R>) + 4);
+    const size_t ex = (size_t)round_positions<R, WT>(cap) / 2 *
+                      (2 * sizeof(Rec<R>) + 4 + (WT ? 4 + 2 * sizeof(R) : 0));
     const size_t s = sort_bytes(cap);
     return s > ex ? s : ex;
 }
@@ -264,6 +281,7 @@ __device__ void cell_pass(const CollideArgs &a, int cell, unsigned char *smem, d
     constexpr bool MCC = (F & F_MCC) != 0;
     constexpr bool CONS = (F & F_CONS) != 0;
     constexpr bool MOM = (F & F_MOM) != 0;
+    constexpr bool WT = (F & F_WT) != 0;
     constexpr int CAP = T * K;
     const int lo = a.cell_start[cell];
     const int n = a.cell_start[cell + 1] - lo;
@@ -355,9 +373,13 @@ __device__ void cell_pass(const CollideArgs &a, int cell, unsigned char *smem, d
     if (coul) {
         const R C = (R)cell_C(a, cell);
         const uint32_t np2 = (uint32_t)n & ~1u;     // positions with a partner
-        constexpr uint32_t P = round_positions<R>(CAP);
+        constexpr uint32_t P = round_positions<R, WT>(CAP);
         Rec<R> *rec = (Rec<R> *)smem;
         uint32_t *w3s = (uint32_t *)(rec + P);
+        // with weights: the second member's word 3 per pair, the weight per position
+        uint32_t *w3b = w3s + P / 2;
+        R *wts = (R *)(w3b + P / 2);
+        const R *w_c = (const R *)a.w + lo;
         for (uint32_t base = 0; base < np2; base += P) {
 #pragma unroll
             for (int k = 0; k < K; ++k) {
@@ -371,6 +393,10 @@ __device__ void cell_pass(const CollideArgs &a, int cell, unsigned char *smem, d
                     e.w2 = w2[k];
                     rec[q] = e;
                     if (!(q & 1u)) w3s[q >> 1] = w3[k];
+                    if constexpr (WT) {
+                        if (q & 1u) w3b[q >> 1] = w3[k];
+                        wts[q] = w_c[i];
+                    }
                 }
             }
             __syncthreads();
@@ -379,12 +405,18 @@ __device__ void cell_pass(const CollideArgs &a, int cell, unsigned char *smem, d
                 Rec<R> A = rec[2 * j], B = rec[2 * j + 1];
                 R hx, hy, hz;
                 ta_half(A.x - B.x, A.y - B.y, A.z - B.z, C, A.w2, w3s[j], B.w2, hx, hy, hz);
-                A.x += hx;
-                A.y += hy;
-                A.z += hz;
-                B.x -= hx;
-                B.y -= hy;
-                B.z -= hz;
+                bool ta = true, tb = true;
+                if constexpr (WT) weight_rule<R>(wts[2 * j], wts[2 * j + 1], w3b[j], ta, tb);
+                if (ta) {
+                    A.x += hx;
+                    A.y += hy;
+                    A.z += hz;
+                }
+                if (tb) {
+                    B.x -= hx;
+                    B.y -= hy;
+                    B.z -= hz;
+                }
                 rec[2 * j] = A;
                 rec[2 * j + 1] = B;
             }
@@ -955,12 +987,22 @@ __global__ __launch_bounds__(1024) void k_collide_huge(CollideArgs a, const int3
                     R hx, hy, hz;
                     ta_half(x - e.x, y - e.y, z - e.z, C, hs.w23[2 * (int64_t)(lo + i)],
                             hs.w23[2 * (int64_t)(lo + i) + 1], e.w2, hx, hy, hz);
-                    vx_g[lo + i] = x + hx;
-                    vy_g[lo + i] = y + hy;
-                    vz_g[lo + i] = z + hz;
-                    e.x = hx;
-                    e.y = hy;
-                    e.z = hz;
+                    bool ta = true, tb = true;
+                    if (a.w) {
+                        // the partner: the member at the next position
+                        const R *wg = (const R *)a.w + lo;
+                        const uint32_t j = hs.lst[lo + p + 1];
+                        weight_rule<R>(wg[i], wg[j], hs.w23[2 * (int64_t)(lo + j) + 1], ta, tb);
+                    }
+                    if (ta) {
+                        vx_g[lo + i] = x + hx;
+                        vy_g[lo + i] = y + hy;
+                        vz_g[lo + i] = z + hz;
+                    }
+                    // the second member subtracts what is left here
+                    e.x = tb ? hx : (R)0;
+                    e.y = tb ? hy : (R)0;
+                    e.z = tb ? hz : (R)0;
                 }
             }
             __syncthreads();
@@ -1526,7 +1568,7 @@ template <> struct SegGeom<double> {
 template <typename R, int T, int K, int F>
 int launch_class(const CollideArgs &a, const int32_t *list, int cls, int blocks, hipStream_t st)
 {
-    const size_t lds = lds_bytes<R>(T * K);
+    const size_t lds = lds_bytes<R, (F & F_WT) != 0>(T * K);
     auto kern = k_collide<R, T, K, F>;
     static bool attr_done = false;
     if (!attr_done) {
@@ -1592,16 +1634,17 @@ int launch_all(const CollideArgs &a, const int32_t *lists, int32_t n_cells, int 
 {
     typedef Classes<R> C;
     constexpr bool PAIRS = (F & F_PAIRS) != 0;
-    constexpr bool SEG_OK = !PAIRS && !(F & (F_CONS | F_MOM));
+    constexpr bool SEG_OK = !PAIRS && !(F & (F_CONS | F_MOM | F_WT));
     int rc;
     const int64_t M = n_cells;
     const int *bp = caps.blocks_per_cu;
     const int32_t *l4 = lists + 4 * M;
     // largest cells first so the small ones fill the tail
     ktime_begin(KT_HUGE, st);
-    if (!(live & (1u << 4))) {
-        // no cell beyond the LDS classes
-    } else if (SEG_OK && seg_path) {
+    bool seg_done = !(live & (1u << 4));   // no cell beyond the LDS classes
+    if constexpr (SEG_OK) {
+      if (!seg_done && seg_path) {
+        seg_done = true;
         const SegScratch &ss = g_seg;
         hipLaunchKernelGGL(k_seg_count, dim3(num_cu * 4), dim3(SEG_CT), 0, st, a, l4, ss);
         typedef SegGeom<R> G;
@@ -1613,10 +1656,11 @@ int launch_all(const CollideArgs &a, const int32_t *lists, int32_t n_cells, int 
         // cells the plan could not segment
         hipLaunchKernelGGL((k_collide_huge<R, PAIRS>), dim3(num_cu * bp[4]), dim3(1024), 0, st, a, l4, 4,
                            hs, (const uint8_t *)ss.hc_fb);
-    } else {
+      }
+    }
+    if (!seg_done)
         hipLaunchKernelGGL((k_collide_huge<R, PAIRS>), dim3(num_cu * bp[4]), dim3(1024), 0, st, a, l4, 4,
                            hs, (const uint8_t *)nullptr);
-    }
     ktime_end(KT_HUGE, st);
     HIP_OK(hipGetLastError());
     if ((live & (1u << 3)) &&
@@ -1651,6 +1695,12 @@ int launch_flags(const CollideArgs &a, const int32_t *lists, int32_t n_cells, in
                  hipStream_t st)
 {
     if (pairs_only) return launch_all<R, F_PAIRS>(a, lists, n_cells, num_cu, hs, cc, false, ~0u, st);
+    if (a.w) {
+        // variable weights: the plain step (optionally with null collisions),
+        // cells beyond the LDS classes on one workgroup each
+        if (a.mcc_thr) return launch_all<R, F_WT | F_MCC>(a, lists, n_cells, num_cu, hs, cc, false, lv, st);
+        return launch_all<R, F_WT>(a, lists, n_cells, num_cu, hs, cc, false, lv, st);
+    }
     const int f = (a.mcc_thr ? F_MCC : 0) | ((a.flags & PIC_CONSERVE_FIX) ? F_CONS : 0) |
                   ((a.flags & PIC_MOMENTS) ? F_MOM : 0);
     switch (f) {

@@ -638,7 +638,7 @@ struct RadixPass {
 // 7 re-binning passes, 8 stand-alone null-collision step, 9 learned gate
 // decision, 10 relaxation of the judged cells.
 enum { KT_CLASS0 = 0, KT_HUGE = 4, KT_CHECK = 5, KT_QUEUE = 6, KT_SORT = 7, KT_MCC = 8, KT_GATE = 9,
-       KT_RELAX = 10, KT_DEFER = 11, KT_MOMENTS = 12, KT_DSMC = 13, KT_P2C = 14, KT_RECOMB = 15, KT_NANBU = 16, KT_TRIPLET = 17, KT_SLOTS = 20 };
+       KT_RELAX = 10, KT_DEFER = 11, KT_MOMENTS = 12, KT_DSMC = 13, KT_P2C = 14, KT_RECOMB = 15, KT_NANBU = 16, KT_TRIPLET = 17, KT_WEIGHTED = 18, KT_SLOTS = 20 };
 void ktime_begin(int slot, hipStream_t st);
 void ktime_end(int slot, hipStream_t st);
 bool ktime_pause();            // returns whether timing was on
@@ -685,6 +685,7 @@ int launch_build_queue(const int32_t *cell_start, int32_t n_cells, const ClassCa
 
 struct CollideArgs {
     void *v;               // SoA base
+    const void *w;         // per-particle weights of the velocity dtype (variable-weight step), or null
     int64_t n;             // stride between components
     const uint32_t *pid;
     const int32_t *cell_start;

@@ -70,6 +70,8 @@ def _load():
                                   C.c_int),
         "coulomb_collide_triplet": ([vp, C.c_int, vp, vp, i64, vp, C.c_int32, f64, f64, vp, u64, u64],
                                     C.c_int),
+        "coulomb_collide_weighted": ([vp, C.c_int, vp, vp, vp, i64, vp, C.c_int32, f64, f64, vp, u64,
+                                      u64, u32], C.c_int),
         "coulomb_pairs": ([vp, vp, vp, i32, u64, u64, vp, vp], C.c_int),
         "pic_cell_moments": ([vp, C.c_int, vp, i64, vp, i32, vp], C.c_int),
         "pic_unsort": ([vp, C.c_int, vp, vp, vp, i64], C.c_int),
@@ -112,14 +114,14 @@ EXPORTED = ["pic_create", "pic_destroy", "pic_strerror", "pic_sync", "pic_set_st
             "pic_gate_config", "pic_gate_reset", "pic_gate_stats", "pic_gate_state", "pic_autotune",
             "pic_conserve_reset", "pic_gate_refresh", "gate_infer", "pic_set_dsmc", "dsmc_collide",
             "mcc_null_collide_exact", "p2c_sums", "recombine", "coulomb_collide_nanbu",
-            "coulomb_collide_triplet", "coulomb_collide_noalloc"]
+            "coulomb_collide_triplet", "coulomb_collide_noalloc", "coulomb_collide_weighted"]
 
 MLP_PARAMS = 4801
 GATE_STATS = ["steps", "skipped", "collided", "judged", "judged_want", "false_skip", "disabled",
               "have_moments"]
 
 KT_SLOTS = ["class0", "class1", "class2", "class3", "huge", "check", "queue", "sort", "mcc", "gate",
-            "relax", "deferred", "moments", "dsmc", "p2c", "recombine", "nanbu", "triplet"]
+            "relax", "deferred", "moments", "dsmc", "p2c", "recombine", "nanbu", "triplet", "weighted"]
 
 
 def _dt(v: torch.Tensor) -> int:
@@ -270,6 +272,18 @@ class Context:
         _chk(lib.coulomb_collide_triplet(self._h, _dt(v), _p(v), _p(pid), v.shape[1], _p(cell_start),
                                          cell_start.numel() - 1, dt, lnL, _p(density), seed, step),
              "coulomb_collide_triplet")
+
+    def weighted(self, v: torch.Tensor, w: torch.Tensor, pid: torch.Tensor,
+                 cell_start: torch.Tensor, *, dt: float, lnL: float, seed: int, step: int,
+                 density=None, flags: int = 0):
+        """One Takizuka-Abe step of variable-weight particles in place on v
+        (cell-sorted storage; w of v's dtype, not modified)."""
+        assert w.dtype == v.dtype and w.numel() == v.shape[1]
+        self._stream()
+        _chk(lib.coulomb_collide_weighted(self._h, _dt(v), _p(v), _p(w), _p(pid), v.shape[1],
+                                          _p(cell_start), cell_start.numel() - 1, dt, lnL,
+                                          _p(density), seed, step, flags),
+             "coulomb_collide_weighted")
 
     def recombine(self, v: torch.Tensor, w: torch.Tensor, pid: torch.Tensor, primary: torch.Tensor,
                   cell_start: torch.Tensor, *, eps: float, seed: int, step: int, events=False):
