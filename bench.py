@@ -550,6 +550,61 @@ def bench_recombine(args):
                            "bytes_per_electron": round(per_e, 3)})
 
 
+def bench_rebin(args):
+    """The data-moving re-binning alone (stable counting sort of v, pid and
+    cell_of by cell, two 6-bit passes for 4,096 cells, then the order check)
+    on the 4096 x 10,000 workload, storage shuffled before every call; times
+    from the library's events around the sort passes."""
+    import numpy as np
+    import torch
+
+    from paper_2508_06771_amd import piccoll, workloads
+    w = workloads.c2(0)
+    n = w.n
+    v = torch.from_numpy(w.v).cuda()
+    cell = torch.from_numpy(w.cell_of).cuda()
+    pid = torch.from_numpy(w.pid.view(np.int32)).cuda()
+    ctx = piccoll.Context(0)
+    ctx.set_mcc(w.sigma0, w.n_neutral, 0.0)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0)
+
+    def shuffled_step(k):
+        perm = torch.randperm(n, device="cuda", generator=g)
+        vv, cc, pp = v[:, perm].contiguous(), cell[perm].contiguous(), pid[perm].contiguous()
+        ctx.coulomb_collide(vv, cc, pp, w.n_cells, dt=w.dt, lnL=w.lnL, seed=0, step=k,
+                            flags=piccoll.FUSE_MCC)
+        return vv, cc
+
+    for k in range(max(args.warmup, 1)):
+        shuffled_step(k)
+    ctx.sync()
+    ctx.time_kernels(True)
+    ctx.kernel_times()
+    reps = max(args.steps // 4, 3)
+    for k in range(reps):
+        vv, cc = shuffled_step(100 + k)
+    ctx.sync()
+    kt = ctx.kernel_times()
+    ctx.time_kernels(False)
+    assert bool((cc[1:] >= cc[:-1]).all())          # the storage is in cell order
+    sort_ms = kt["sort"][0] / kt["sort"][1]
+    bytes_sort = 2 * 2 * 20 + 4                      # two passes: read and write key + pid + v; the check
+    achieved = n * bytes_sort / (sort_ms * 1e-3) / 1e9
+    ctx.close()
+    return _line(n / (sort_ms * 1e-3), sort_ms, args, "f32",
+                 {"workload": "re-binning of 4096 cells x 10,000 electrons (40.96M), FP32 SoA, "
+                              "storage shuffled before each call", "n_electrons": n},
+                 metric_note="electron re-bins per second (the sort passes and the order check "
+                             "of an unsorted step)",
+                 kernel_ms_per_step={k2: round(t / c, 5) for k2, (t, c) in kt.items()},
+                 roofline={"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                           "traffic": None, "kernel": "k_radix_hist + scans + k_radix_scatter_lds "
+                           "(two passes) + k_bin_check", "kernel_avg_ms": round(sort_ms, 5),
+                           "bytes_per_launch": n * bytes_sort})
+
+
 def bench_nanbu(args):
     """Nanbu's Coulomb operator on the 4096 x 10,000 population in cell-sorted
     storage, FP32 velocities, binary64 arithmetic: the pairing of the
@@ -656,7 +711,7 @@ def main():
                     help="c2: steps over which the energy drift is taken (default: the "
                          "configuration's 1000; at least the steps already run)")
     ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "dsmc", "mcc_exact", "p2c", "recombine",
-                                                              "nanbu", "triplet"],
+                                                              "nanbu", "triplet", "rebin"],
                     help="c2: the headline configuration; c3: log-normal cell sizes, autotuned "
                          "routing, graph replays; c4: precision study; c5: learned gate vs plain; "
                          "dsmc: electron-heavy collisions C1..C4 with ionization; mcc_exact: "
@@ -683,7 +738,7 @@ def main():
         out = {"c3": bench_c3, "c4": bench_c4, "c5": bench_c5, "dsmc": bench_dsmc,
                "mcc_exact": bench_mcc_exact, "p2c": bench_p2c,
                "recombine": bench_recombine, "nanbu": bench_nanbu,
-               "triplet": bench_triplet}[args.workload](args)
+               "triplet": bench_triplet, "rebin": bench_rebin}[args.workload](args)
         print(json.dumps(out), flush=True)
         return
 

@@ -281,6 +281,132 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(RadixPass p,
     }
 }
 
+// Stable scatter with the tile staged in LDS (tiles of RS_TILE elements, so
+// the per-tile digit counts of k_radix_hist apply).  Wave w takes elements
+// [w * 256, w * 256 + 256) of the tile in four rounds of 64; an element's rank
+// among equal digits of its wave comes from ballots over the digit bits and a
+// per-wave running count in LDS (no block barrier while ranking).  The waves'
+// counts then give each (wave, digit) its start inside the tile, every element
+// goes to its place in a digit-sorted copy of the tile in LDS, and the copy is
+// written out in slot order: consecutive slots of one digit go to consecutive
+// addresses, so the stores are coalesced runs instead of one scattered word
+// per element and array.
+constexpr int RS2_THREADS = 1024;
+constexpr int RS2_WAVES = RS2_THREADS / PIC_WAVE;
+constexpr int RS2_PER_WAVE = RS_TILE / RS2_WAVES;          // 256 elements
+constexpr int RS2_ROUNDS = RS2_PER_WAVE / PIC_WAVE;         // 4
+static_assert(RS2_ROUNDS * PIC_WAVE * RS2_WAVES == RS_TILE, "tile split");
+
+// Dynamic LDS of the staged scatter (its static part is about 21 KB).
+constexpr size_t RS2_LDS_MAX = 136 * 1024;
+
+size_t rs2_stage_bytes(int n32, int n64)
+{
+    return (size_t)RS_TILE * (4 + 4 * (size_t)n32 + 8 * (size_t)n64);
+}
+
+__global__ __launch_bounds__(RS2_THREADS) void k_radix_scatter_lds(RadixPass p,
+                                                                   const uint32_t *__restrict__ offs)
+{
+    if (p.gate && *p.gate == 0) return;
+    extern __shared__ __align__(16) unsigned char stage[];
+    __shared__ uint32_t run[RS2_WAVES * 256];   // per-wave running digit counts, then wave starts
+    __shared__ uint32_t tstart[257];            // digit starts inside the tile
+    __shared__ uint32_t goff[256];              // global start of this tile's run of each digit
+    const int R = 1 << p.bits;
+    const int lane = threadIdx.x & (PIC_WAVE - 1), wid = threadIdx.x / PIC_WAVE;
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (PIC_WAVE - lane));
+    const int64_t tile = (int64_t)blockIdx.x * RS_TILE;
+    const int64_t tn = p.n - tile < RS_TILE ? p.n - tile : RS_TILE;   // elements in this tile
+    uint32_t *skey = (uint32_t *)stage;
+    uint32_t *s32 = skey + RS_TILE;
+    uint64_t *s64 = (uint64_t *)(s32 + (size_t)p.n32 * RS_TILE);
+    for (int q = threadIdx.x; q < RS2_WAVES * 256; q += RS2_THREADS) run[q] = 0;
+    if (threadIdx.x < R) goff[threadIdx.x] = offs[(int64_t)threadIdx.x * gridDim.x + blockIdx.x];
+    // digit starts inside the tile from this tile's counts (one wave scans):
+    // the offsets are an exclusive scan over (digit, tile), so a tile's count
+    // of a digit is the next offset minus its own (the total after the last)
+    if (wid == 0) {
+        const int64_t L = (int64_t)R * gridDim.x;
+        uint32_t carry = 0;
+        for (int d0 = 0; d0 < R; d0 += PIC_WAVE) {
+            const int d = d0 + lane;
+            uint32_t c = 0;
+            if (d < R) {
+                const int64_t idx = (int64_t)d * gridDim.x + blockIdx.x;
+                c = (idx + 1 < L ? offs[idx + 1] : (uint32_t)p.n) - offs[idx];
+            }
+            const uint32_t inc = wave_incl_scan(c);
+            if (d < R) tstart[d] = carry + inc - c;
+            carry += __shfl(inc, PIC_WAVE - 1, PIC_WAVE);
+        }
+        if (lane == 0) tstart[R] = carry;
+    }
+    // this thread's elements: round r is element wid * 256 + r * 64 + lane
+    int32_t key[RS2_ROUNDS];
+    uint32_t rank[RS2_ROUNDS];
+#pragma unroll
+    for (int r = 0; r < RS2_ROUNDS; ++r) {
+        const int64_t le = (int64_t)wid * RS2_PER_WAVE + r * PIC_WAVE + lane;
+        key[r] = le < tn ? p.key_in[tile + le] : 0;
+    }
+    __syncthreads();
+    uint32_t *wrun = run + wid * 256;
+#pragma unroll
+    for (int r = 0; r < RS2_ROUNDS; ++r) {
+        const int64_t le = (int64_t)wid * RS2_PER_WAVE + r * PIC_WAVE + lane;
+        const bool valid = le < tn;
+        const uint32_t d = digit_of(key[r], p.shift, p.bits);
+        uint64_t peers = __ballot(valid);
+        for (int b = 0; b < p.bits; ++b) {
+            const uint64_t m = __ballot((d >> b) & 1u);
+            peers &= ((d >> b) & 1u) ? m : ~m;
+        }
+        const uint32_t before = valid ? wrun[d] : 0u;
+        rank[r] = before + __popcll(peers & lt);
+        // the group's first lane advances the wave's count (same wave: LDS
+        // operations stay in order)
+        if (valid && (peers & lt) == 0ull) wrun[d] = before + __popcll(peers);
+        __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): the count is in LDS
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    // wave starts per digit: tile start + the earlier waves' counts
+    for (int d = threadIdx.x; d < R; d += RS2_THREADS) {
+        uint32_t acc = tstart[d];
+        for (int w = 0; w < RS2_WAVES; ++w) {
+            const uint32_t c = run[w * 256 + d];
+            run[w * 256 + d] = acc;
+            acc += c;
+        }
+    }
+    __syncthreads();
+    // stage every element at its place in the digit-sorted tile
+#pragma unroll
+    for (int r = 0; r < RS2_ROUNDS; ++r) {
+        const int64_t le = (int64_t)wid * RS2_PER_WAVE + r * PIC_WAVE + lane;
+        if (le < tn) {
+            const int64_t e = tile + le;
+            const uint32_t d = digit_of(key[r], p.shift, p.bits);
+            const uint32_t q = wrun[d] + rank[r];
+            skey[q] = (uint32_t)key[r];
+            for (int s = 0; s < p.n32; ++s)
+                s32[(size_t)s * RS_TILE + q] = (s == p.iota_slot) ? (uint32_t)e : p.p32_in[s][e];
+            for (int s = 0; s < p.n64; ++s) s64[(size_t)s * RS_TILE + q] = p.p64_in[s][e];
+        }
+    }
+    __syncthreads();
+    // write out in slot order
+    for (int q = threadIdx.x; q < tn; q += RS2_THREADS) {
+        const uint32_t k = skey[q];
+        const uint32_t d = digit_of((int32_t)k, p.shift, p.bits);
+        const int64_t o = (int64_t)goff[d] + (q - (int64_t)tstart[d]);
+        p.key_out[o] = (int32_t)k;
+        for (int s = 0; s < p.n32; ++s) p.p32_out[s][o] = s32[(size_t)s * RS_TILE + q];
+        for (int s = 0; s < p.n64; ++s) p.p64_out[s][o] = s64[(size_t)s * RS_TILE + q];
+    }
+}
+
 // Cells by size class.  lists[c * n_cells + k] = k-th cell of class c; the
 // class lengths go to flags->count[c]; flags->huge_total sums the members of
 // cells beyond the largest LDS class.  Within a class the order is
@@ -431,8 +557,21 @@ int radix_pass(const RadixPass &p, const BinScratch &s, hipStream_t st)
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_THREADS), 0, st, s.bsum, ns, p.gate);
     hipLaunchKernelGGL(k_scan_down, dim3((unsigned)ns), dim3(SCAN_THREADS), 0, st, s.hist, L, s.bsum,
                        p.gate);
-    hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(RS_THREADS), 0, st, p,
-                       (const uint32_t *)s.hist);
+    const size_t lds = rs2_stage_bytes(p.n32, p.n64);
+    if (lds <= RS2_LDS_MAX) {
+        static size_t attr_set = 0;
+        if (lds > attr_set) {
+            HIP_OK(hipFuncSetAttribute((const void *)k_radix_scatter_lds,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+            attr_set = lds;
+        }
+        hipLaunchKernelGGL(k_radix_scatter_lds, dim3((unsigned)nb), dim3(RS2_THREADS), lds, st, p,
+                           (const uint32_t *)s.hist);
+    } else {
+        // a tile of this many payload words does not fit: one word per element and array
+        hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(RS_THREADS), 0, st, p,
+                           (const uint32_t *)s.hist);
+    }
     HIP_OK(hipGetLastError());
     return PIC_OK;
 }
