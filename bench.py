@@ -169,6 +169,16 @@ def bench_c3(args):
     ms_default = _timed(torch, lambda: eager(args.steps)) / args.steps
     kt = ctx.kernel_times()
     ctx.time_kernels(False)
+    # the single persistent launch (smallest class one wave per cell, or every
+    # cell on whole workgroups), graph replays
+    one_launch = {}
+    for sched, name in ((1, "wave"), (2, "block")):
+        ctx.set_schedule(torch.float32, sched)
+        graph(2)
+        one_launch[name] = _timed(torch, lambda: graph(args.steps)) / args.steps
+    ctx.set_schedule(torch.float32, 0)
+    graph(2)
+    ms_class_graph = _timed(torch, lambda: graph(args.steps)) / args.steps
     choice = ctx.autotune(v, cell, pid, w.n_cells, dt=w.dt, lnL=w.lnL, flags=fl)
     eager(2)
     ms_tuned = _timed(torch, lambda: eager(args.steps)) / args.steps
@@ -186,6 +196,9 @@ def bench_c3(args):
                   "share_in_cells_over_10240": float(counts[counts > 10240].sum() / n)},
                  ms_default_routing_eager=ms_default, ms_autotuned_eager=ms_tuned,
                  ms_autotuned_graph=ms_graph, autotune_choice=choice, rebin_step_ms=rebin_ms,
+                 ms_class_launches_graph=ms_class_graph,
+                 ms_one_launch_wave_graph=one_launch["wave"],
+                 ms_one_launch_block_graph=one_launch["block"],
                  hbm_frac_step=round(hbm / HBM_PEAK_GBS, 4),
                  kernel_ms_per_step_default={kk: round(t / c, 5) for kk, (t, c) in kt.items()})
 
@@ -856,7 +869,10 @@ def c2_leg(args, dtype_name):
 
     roof = None
     dom = None
-    if f32 and "class3" in kms:
+    if "all" in kms:
+        dom = ("all", f"k_collide_all<{'float' if f32 else 'double'},MCC> (the step's collide pass "
+                      f"as one persistent launch)")
+    elif f32 and "class3" in kms:
         dom = ("class3", "k_collide_lean<1024,10,MCC> (cells of 4097..10240 members)")
     elif not f32 and "huge" in kms:
         dom = ("huge", "segmented path of cells beyond 6144 members (k_seg_count, k_seg_scan, "

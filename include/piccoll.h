@@ -407,8 +407,19 @@ int pic_gate_state(pic_ctx *ctx, uint8_t *skip, int32_t *k_acc, float *prob, dou
 
 /* Batching.  Cells go to size classes (workgroup-per-cell kernels of 256,
  * 512 and 1024 threads holding up to 512 / 2048 / 4096 / 10240 members in
- * binary32, 512 / 2048 / 4096 / 6144 in binary64, and a multi-block class
- * beyond), each a persistent kernel draining its work list.  pic_autotune
+ * binary32, 256 / 2048 / 4096 / 6144 in binary64, and a multi-block class
+ * beyond), each a persistent kernel draining its work list.  The plain step
+ * (with or without PIC_FUSE_MCC) can instead run its whole collide pass as
+ * one persistent launch (the paper runs several steps per kernel call to
+ * avoid relaunch costs, paragraph "Operator Splitting Algorithms"): the
+ * segments of the largest cells first, then the other cells largest first on
+ * whole workgroups, and when that queue is empty every wave takes cells of
+ * the smallest class one at a time (or every cell on whole workgroups).
+ * pic_set_schedule picks the form for a dtype: 0 one launch per class (the
+ * default), 1 one launch with the wave schedule for the smallest class, 2 one
+ * launch with every cell on whole workgroups; it keeps the class thresholds
+ * and replaces an earlier pic_autotune choice.  Results do not depend on the
+ * form, bit for bit.  PIC_ERR_ARG for another schedule.  pic_autotune
  * times candidate routing thresholds and resident-workgroup counts for the
  * given state on a scratch copy (the caller's arrays are not modified; it
  * synchronises and allocates) and keeps the fastest for later steps of this
@@ -417,6 +428,7 @@ int pic_gate_state(pic_ctx *ctx, uint8_t *skip, int32_t *k_acc, float *prob, dou
  * by (device architecture, dtype, n, n_cells, flags, histogram of log2 cell
  * sizes).  *choice_out (nullable) receives the chosen candidate index.
  * Flags PIC_GATE, PIC_MOMENTS and PIC_ASSUME_SORTED are ignored here. */
+int pic_set_schedule(pic_ctx *ctx, int dtype, int schedule);
 int pic_autotune(pic_ctx *ctx, int dtype, const void *v, const int32_t *cell_of,
                  const uint32_t *pid, int64_t n, int32_t n_cells, double dt, double lnLambda,
                  uint32_t flags, int32_t *choice_out);

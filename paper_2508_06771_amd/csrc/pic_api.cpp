@@ -755,7 +755,7 @@ static size_t step_ws_bytes(const pic_ctx *c, const StepArgs &s)
 {
     const size_t es = s.dtype == PIC_F32 ? 4 : 8;
     const size_t part = (s.flags & PIC_GATE) ? relax_part_bytes(s.n_cells, c->gate_replicas) : 0;
-    return (size_t)(s.n_cells + 1) * 4 + (size_t)s.n_cells * QUEUE_LISTS * 4 + (size_t)s.n * (8 + 3 * es) +
+    return (size_t)(s.n_cells + 1) * 4 + (size_t)s.n_cells * (QUEUE_LISTS + 1) * 4 + (size_t)s.n * (8 + 3 * es) +
            radix_scratch_bytes(s.n) + huge_scratch_bytes(s.dtype, s.n) +
            seg_scratch_bytes(s.dtype, s.n, s.n_cells) + part + 8192;
 }
@@ -784,6 +784,7 @@ static int step_enqueue(pic_ctx *c, const StepArgs &s, hipStream_t st, const uin
     Bump b(c->ws);
     int32_t *cs = (int32_t *)b.take((size_t)(n_cells + 1) * 4);
     int32_t *lists = (int32_t *)b.take((size_t)n_cells * QUEUE_LISTS * 4);
+    int32_t *order = (int32_t *)b.take((size_t)n_cells * 4);
     int32_t *tkey = (int32_t *)b.take((size_t)n * 4);
     uint32_t *tpid = (uint32_t *)b.take((size_t)n * 4);
     void *tv = b.take((size_t)n * 3 * es);
@@ -915,6 +916,7 @@ static int step_enqueue(pic_ctx *c, const StepArgs &s, hipStream_t st, const uin
     a.moments = c->moments_out;
     a.debt = (s.flags & PIC_CONSERVE_FIX) ? c->debt : nullptr;
     a.dflags = c->flags;
+    a.order = order;
     if (gate) {
         // deferred cells are in no class queue: their null collisions run
         // here, and moment sums come from the pass after the collisions
@@ -1371,7 +1373,7 @@ static std::vector<ClassCaps> tune_candidates(const ClassCaps &b)
 {
     std::vector<ClassCaps> v;
     auto add = [&](ClassCaps c) { v.push_back(c); };
-    add(b);
+    add(b);                                   // one launch per size class
     ClassCaps c = b;
     c.cap[0] = b.cap[0] / 2;                  // fewer cells on the 256-thread class
     add(c);
@@ -1391,7 +1393,30 @@ static std::vector<ClassCaps> tune_candidates(const ClassCaps &b)
     c = b;
     c.blocks_per_cu[4] = 2;
     add(c);
+    ClassCaps u = b;
+    u.unified = 1;                            // one persistent launch, small cells one wave each
+    u.wave = 1;
+    add(u);
+    c = u;
+    c.wave = 0;                               // ... every cell on a whole workgroup
+    add(c);
+    c = u;
+    c.cap[0] = b.cap[0] / 2;                  // ... fewer cells on the wave schedule
+    add(c);
     return v;
+}
+
+int pic_set_schedule(pic_ctx *c, int dtype, int schedule)
+{
+    if (!c || schedule < 0 || schedule > 2) return PIC_ERR_ARG;
+    RC(check_dtype(dtype));
+    const int di = dtype == PIC_F64;
+    ClassCaps caps = c->tuned_valid[di] ? c->tuned[di] : collide_caps(dtype, c->lds_max);
+    caps.unified = schedule != 0;
+    caps.wave = schedule == 1;
+    c->tuned[di] = caps;
+    c->tuned_valid[di] = true;
+    return PIC_OK;
 }
 
 int pic_autotune(pic_ctx *c, int dtype, const void *v, const int32_t *cell_of, const uint32_t *pid,

@@ -274,7 +274,7 @@ __device__ __forceinline__ void cell_moments_out(double *out, const R (&vx)[K], 
 }
 
 template <typename R, int T, int K, int F>
-__device__ void cell_pass(const CollideArgs &a, int cell, unsigned char *smem, double *red,
+__device__ __forceinline__ void cell_pass(const CollideArgs &a, int cell, unsigned char *smem, double *red,
                           uint32_t *wtot, double *s_before)
 {
     constexpr bool PAIRS = (F & F_PAIRS) != 0;
@@ -718,7 +718,7 @@ __device__ __forceinline__ void lean_round(uint32_t base, uint32_t P, uint32_t n
 }
 
 template <int T, int K, bool MCC>
-__device__ void lean_pass(const CollideArgs &a, int cell, unsigned char *smem, uint32_t *wtot)
+__device__ __forceinline__ void lean_pass(const CollideArgs &a, int cell, unsigned char *smem, uint32_t *wtot)
 {
     typedef LeanGeom<T, K> G;
     constexpr uint32_t P = lean_positions(G::CAP);
@@ -1259,7 +1259,7 @@ __global__ __launch_bounds__(SEG_CT) void k_seg_scatter(CollideArgs a, const int
 // partner lies in a neighbouring segment is recorded for k_seg_fixup and left
 // unchanged (its null collision too).
 template <typename R, int T, int K, int F>
-__device__ void seg_pass(const CollideArgs &a, const int32_t *list, const SegScratch &ss, int seg,
+__device__ __forceinline__ void seg_pass(const CollideArgs &a, const int32_t *list, const SegScratch &ss, int seg,
                          unsigned char *smem, uint32_t *wtot)
 {
     constexpr bool MCC = (F & F_MCC) != 0;
@@ -1565,6 +1565,345 @@ template <> struct SegGeom<double> {
     static constexpr int T = 1024, K = 6, PER_CU = 1;
 };
 
+// ------------------------------------------------------------ one wave per cell
+// Small cells on a single wave with its own slice of LDS: the same pairing,
+// rotation and null collisions as the block passes, with wave-level
+// synchronisation only (LDS operations of one wave complete in order), so the
+// 16 waves of a workgroup work on 16 cells at once.
+template <typename R> struct WaveGeom;
+template <> struct WaveGeom<float> {
+    static constexpr int KW = 8;       // cells of up to 512 members
+};
+template <> struct WaveGeom<double> {
+    static constexpr int KW = 4;       // up to 256 (records of 32 bytes)
+};
+constexpr size_t WAVE_SLICE = 8 * 1024 + 512;   // LDS bytes per wave
+
+__device__ __forceinline__ void wave_sync()
+{
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+}
+
+template <typename R, bool MCC>
+__device__ __forceinline__ void wave_pass(const CollideArgs &a, int cell, unsigned char *slice)
+{
+    constexpr int KW = WaveGeom<R>::KW;
+    constexpr int CAP = PIC_WAVE * KW;
+    const int lane = threadIdx.x & (PIC_WAVE - 1);
+    const int lo = a.cell_start[cell];
+    const int n = a.cell_start[cell + 1] - lo;
+    if (n == 0) return;
+    const uint32_t step = (uint32_t)read_step(a);
+    R *vx_g = (R *)a.v + lo;
+    R *vy_g = (R *)a.v + a.n + lo;
+    R *vz_g = (R *)a.v + 2 * a.n + lo;
+    const uint32_t *pid_c = a.pid + lo;
+    R vx[KW], vy[KW], vz[KW];
+    uint32_t w2[KW], w3[KW], key[KW], pos[KW];
+    uint32_t cand = 0, multi = 0;
+    {
+        int ic[KW];
+#pragma unroll
+        for (int k = 0; k < KW; ++k) ic[k] = min(lane + k * PIC_WAVE, n - 1);
+#pragma unroll
+        for (int k = 0; k < KW; ++k) pos[k] = pid_c[ic[k]];
+        asm volatile("" ::: "memory");   // keep the id loads ahead of the velocity loads
+#pragma unroll
+        for (int k = 0; k < KW; ++k) {
+            vx[k] = vx_g[ic[k]];
+            vy[k] = vy_g[ic[k]];
+            vz[k] = vz_g[ic[k]];
+        }
+    }
+    if (n >= 2) {
+        const uint32_t bits = sort_bits(n);
+        const uint32_t nb = 1u << bits;
+        uint32_t *cnt = (uint32_t *)slice;
+        uint32_t *sk = cnt + CAP + 4;
+        uint16_t *lst = (uint16_t *)(sk + CAP);
+        for (uint32_t q = lane; q < nb; q += PIC_WAVE) cnt[q] = 0u;
+        wave_sync();
+#pragma unroll
+        for (int k = 0; k < KW; ++k) {
+            const int i = lane + k * PIC_WAVE;
+            if (i < n) {
+                const W4 w = draw4(a.seed, pos[k], step, 0u, 0u);
+                key[k] = w.x;
+                w2[k] = w.z;
+                w3[k] = w.w;
+                if (MCC && (uint64_t)w.y < a.mcc_thr) cand |= 1u << k;
+                pos[k] = atomicAdd(&cnt[w.x >> (32u - bits)], 1u);
+            }
+        }
+        wave_sync();
+        {
+            // bucket starts: rows of 64 counters with a running carry
+            uint32_t carry = 0;
+            for (uint32_t r0 = 0; r0 < nb; r0 += PIC_WAVE) {
+                const uint32_t q = r0 + lane;
+                const uint32_t v = q < nb ? cnt[q] : 0u;
+                const uint32_t inc = wave_incl_scan_dpp(v);
+                if (q < nb) cnt[q] = carry + inc - v;
+                carry += (uint32_t)__builtin_amdgcn_readlane((int)inc, PIC_WAVE - 1);
+            }
+            if (lane == 0) cnt[nb] = carry;
+        }
+        wave_sync();
+#pragma unroll
+        for (int k = 0; k < KW; ++k) {
+            const int i = lane + k * PIC_WAVE;
+            if (i < n) {
+                const uint32_t b = key[k] >> (32u - bits);
+                const uint32_t st = cnt[b], en = cnt[b + 1];
+                const uint32_t slot = st + pos[k];
+                pos[k] = slot;
+                if (en - st > 1u) {
+                    multi |= 1u << k;
+                    sk[slot] = key[k];
+                    lst[slot] = (uint16_t)i;
+                }
+            }
+        }
+        wave_sync();
+#pragma unroll
+        for (int k = 0; k < KW; ++k) {
+            if ((multi >> k) & 1u) {
+                const int i = lane + k * PIC_WAVE;
+                const uint32_t b = key[k] >> (32u - bits);
+                const uint32_t st = cnt[b], en = cnt[b + 1];
+                uint32_t r = 0, tie = 0;
+                for (uint32_t j = st; j < en; ++j) {
+                    const uint32_t kj = sk[j];
+                    r += kj < key[k] ? 1u : 0u;
+                    tie |= (kj == key[k] && j != pos[k]) ? 1u : 0u;
+                }
+                if (tie) {
+                    const uint32_t pi = pid_c[i];
+                    for (uint32_t j = st; j < en; ++j)
+                        if (j != pos[k] && sk[j] == key[k] && pid_c[lst[j]] < pi) ++r;
+                }
+                pos[k] = st + r;
+            }
+        }
+        wave_sync();   // the sort's slice becomes the exchange records
+        const R C = (R)cell_C(a, cell);
+        const uint32_t np2 = (uint32_t)n & ~1u;
+        Rec<R> *rec = (Rec<R> *)slice;
+#pragma unroll
+        for (int k = 0; k < KW; ++k) {
+            const int i = lane + k * PIC_WAVE;
+            if (i < n && pos[k] < np2) {
+                Rec<R> e;
+                e.x = vx[k];
+                e.y = vy[k];
+                e.z = vz[k];
+                if constexpr (std::is_same<R, float>::value) {
+                    // first members carry their deviate, second ones word 2
+                    e.w2 = (pos[k] & 1u) ? w2[k] : __float_as_uint(ta_z(w2[k], w3[k]));
+                } else {
+                    e.w2 = w2[k];
+                    e.pad = w3[k];
+                }
+                rec[pos[k]] = e;
+            }
+        }
+        wave_sync();
+        for (uint32_t j = lane; j < np2 / 2; j += PIC_WAVE) {
+            Rec<R> A = rec[2 * j], B = rec[2 * j + 1];
+            R hx, hy, hz;
+            if constexpr (std::is_same<R, float>::value)
+                ta_half_z(A.x - B.x, A.y - B.y, A.z - B.z, C, __uint_as_float(A.w2), B.w2, hx, hy, hz);
+            else
+                ta_half(A.x - B.x, A.y - B.y, A.z - B.z, C, A.w2, A.pad, B.w2, hx, hy, hz);
+            A.x += hx;
+            A.y += hy;
+            A.z += hz;
+            B.x -= hx;
+            B.y -= hy;
+            B.z -= hz;
+            rec[2 * j] = A;
+            rec[2 * j + 1] = B;
+        }
+        wave_sync();
+#pragma unroll
+        for (int k = 0; k < KW; ++k) {
+            const int i = lane + k * PIC_WAVE;
+            if (i < n && pos[k] < np2) {
+                const Rec<R> e = rec[pos[k]];
+                vx[k] = e.x;
+                vy[k] = e.y;
+                vz[k] = e.z;
+            }
+        }
+    } else if (MCC) {
+        const W4 w = draw4(a.seed, pos[0], step, 0u, 0u);
+        if (lane == 0 && (uint64_t)w.y < a.mcc_thr) cand = 1u;
+    }
+    if constexpr (MCC) {
+        uint32_t left = cand;
+        while (__ballot(left != 0u) != 0ull) {
+            if (left) {
+                const int kk = __builtin_ctz(left);
+                left &= left - 1u;
+                R x = vx[0], y = vy[0], z = vz[0];
+#pragma unroll
+                for (int k = 1; k < KW; ++k)
+                    if (kk == k) {
+                        x = vx[k];
+                        y = vy[k];
+                        z = vz[k];
+                    }
+                mcc_scatter<R>(x, y, z, pid_c[lane + kk * PIC_WAVE], a.seed, step, a.mass_ratio);
+#pragma unroll
+                for (int k = 0; k < KW; ++k)
+                    if (kk == k) {
+                        vx[k] = x;
+                        vy[k] = y;
+                        vz[k] = z;
+                    }
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < KW; ++k) {
+        const int i = lane + k * PIC_WAVE;
+        if (i < n) {
+            vx_g[i] = vx[k];
+            vy_g[i] = vy[k];
+            vz_g[i] = vz[k];
+        }
+    }
+    wave_sync();   // the slice is free for the wave's next cell
+}
+
+// ------------------------------------------------------------ one launch per step
+// The block cells of the step (every class that a whole workgroup takes, and
+// with the wave schedule off also the smallest class) in one list ordered
+// largest first: a counting sort of the cells by a size bucket that halves
+// every four steps (sizes within a bucket differ by at most 19%).  One
+// workgroup; order[] gets the cells, flags->pad[ORDER_TOTAL] their number.
+constexpr int ORDER_BUCKETS = 72;
+constexpr int ORDER_TOTAL = 0;   // index into DevFlags::pad
+
+__device__ __forceinline__ int order_bucket(int32_t n)
+{
+    // 4 log2 n rounded down, from the leading bit and the two bits after it
+    const uint32_t u = n > 1 ? (uint32_t)n : 1u;
+    const int msb = 31 - __clz(u);
+    const int frac = msb >= 2 ? (int)((u >> (msb - 2)) & 3u) : (int)((u << (2 - msb)) & 3u);
+    const int key = 4 * msb + frac;                 // grows with n
+    const int b = ORDER_BUCKETS - 1 - key;          // largest first
+    return b < 0 ? 0 : b;
+}
+
+__global__ __launch_bounds__(1024) void k_order_queue(const int32_t *__restrict__ cs,
+                                                      const int32_t *__restrict__ lists, int32_t M,
+                                                      int first_cls, int last_cls, DevFlags *f,
+                                                      int32_t *__restrict__ order)
+{
+    __shared__ uint32_t hist[ORDER_BUCKETS];
+    __shared__ uint32_t cls_off[5];
+    if (threadIdx.x < ORDER_BUCKETS) hist[threadIdx.x] = 0u;
+    if (threadIdx.x == 0) {
+        uint32_t acc = 0;
+        for (int c = first_cls; c <= last_cls; ++c) {
+            cls_off[c] = acc;
+            acc += f->count[c];
+        }
+        cls_off[4] = acc;
+        f->pad[ORDER_TOTAL] = acc;
+    }
+    __syncthreads();
+    const uint32_t total = cls_off[4];
+    // the cells of classes first..last, walked as one run
+    auto cell_at = [&](uint32_t q) {
+        int c = first_cls;
+        while (c < last_cls && q >= cls_off[c + 1]) ++c;
+        return lists[(int64_t)c * M + (q - cls_off[c])];
+    };
+    for (uint32_t q = threadIdx.x; q < total; q += 1024) {
+        const int32_t cell = cell_at(q);
+        atomicAdd(&hist[order_bucket(cs[cell + 1] - cs[cell])], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < PIC_WAVE) {
+        uint32_t carry = 0;
+        for (int b0 = 0; b0 < ORDER_BUCKETS; b0 += PIC_WAVE) {
+            const int b = b0 + (int)threadIdx.x;
+            const uint32_t v = b < ORDER_BUCKETS ? hist[b] : 0u;
+            const uint32_t inc = wave_incl_scan(v);
+            if (b < ORDER_BUCKETS) hist[b] = carry + inc - v;
+            carry += __shfl(inc, PIC_WAVE - 1, PIC_WAVE);
+        }
+    }
+    __syncthreads();
+    for (uint32_t q = threadIdx.x; q < total; q += 1024) {
+        const int32_t cell = cell_at(q);
+        order[atomicAdd(&hist[order_bucket(cs[cell + 1] - cs[cell])], 1u)] = cell;
+    }
+}
+
+// The whole collide pass of a step in one persistent launch: each workgroup
+// takes items from one queue, the segments of the largest cells first, then
+// the block cells largest first (their size picks the pass: 1024 threads with
+// K members each), and when that queue is empty each of its waves takes cells
+// of the smallest class one at a time.  Small cells thus fill the tail that
+// the large ones leave, inside the same launch.
+template <typename R, int F>
+__global__ __launch_bounds__(1024) void k_collide_all(CollideArgs a, const int32_t *__restrict__ lists,
+                                                      int32_t M, const int32_t *__restrict__ order,
+                                                      SegScratch ss, ClassCaps caps, int use_seg,
+                                                      int wave_cls)
+{
+    constexpr bool MCC = (F & F_MCC) != 0;
+    typedef Classes<R> CL;
+    typedef SegGeom<R> SG;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ uint32_t wtot[16];
+    __shared__ int s_item;
+    if (gated_off(a)) return;
+    const uint32_t nseg = use_seg ? a.dflags->count[SEG_SLOT] : 0u;
+    const uint32_t nblk = nseg + a.dflags->pad[ORDER_TOTAL];
+    const int32_t *l4 = lists + (int64_t)4 * M;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(&a.dflags->head[0], 1u);
+        lds_barrier();   // the previous cell's stores stay in flight
+        const uint32_t item = (uint32_t)s_item;
+        lds_barrier();
+        if (item >= nblk) break;
+        if (item < nseg) {
+            seg_pass<R, SG::T, SG::K, F>(a, l4, ss, (int)item, smem, wtot);
+            continue;
+        }
+        const int cell = order[item - nseg];
+        const int n = a.cell_start[cell + 1] - a.cell_start[cell];
+        if constexpr (std::is_same<R, float>::value && (F & ~F_MCC) == 0) {
+            // one geometry for every block cell (a second one in the same
+            // kernel pushes the largest past the register file)
+            (void)n;
+            lean_pass<1024, CL::K3, MCC>(a, cell, smem, wtot);
+        } else {
+            __shared__ double red[16 * 16];
+            __shared__ double s_before[4];
+            if (n <= 2048) cell_pass<R, 1024, 2, F>(a, cell, smem, red, wtot, s_before);
+            else if (n <= 4096) cell_pass<R, 1024, 4, F>(a, cell, smem, red, wtot, s_before);
+            else cell_pass<R, 1024, CL::K3, F>(a, cell, smem, red, wtot, s_before);
+        }
+    }
+    if (wave_cls < 0) return;
+    // wave phase: one cell per wave, no workgroup barriers from here on
+    const uint32_t nw = a.dflags->count[wave_cls];
+    const int32_t *wl = lists + (int64_t)wave_cls * M;
+    unsigned char *slice = smem + (threadIdx.x / PIC_WAVE) * WAVE_SLICE;
+    for (;;) {
+        uint32_t item = 0;
+        if ((threadIdx.x & (PIC_WAVE - 1)) == 0) item = atomicAdd(&a.dflags->head[1], 1u);
+        item = (uint32_t)__builtin_amdgcn_readfirstlane((int)__shfl(item, 0, PIC_WAVE));
+        if (item >= nw) break;
+        wave_pass<R, MCC>(a, wl[item], slice);
+    }
+}
+
 template <typename R, int T, int K, int F>
 int launch_class(const CollideArgs &a, const int32_t *list, int cls, int blocks, hipStream_t st)
 {
@@ -1678,6 +2017,75 @@ int launch_all(const CollideArgs &a, const int32_t *lists, int32_t n_cells, int 
     return PIC_OK;
 }
 
+// Dynamic LDS of the one-launch pass: the largest of its block passes and the
+// waves' slices.
+template <typename R, int F>
+constexpr size_t all_lds_bytes()
+{
+    typedef Classes<R> CL;
+    size_t b = 16 * WAVE_SLICE;
+    const size_t seg = lds_bytes<R>(SegGeom<R>::T * SegGeom<R>::K);
+    b = seg > b ? seg : b;
+    if constexpr (std::is_same<R, float>::value && (F & ~F_MCC) == 0) {
+        const size_t l = lean_lds_bytes<1024, CL::K3>();
+        b = l > b ? l : b;
+    } else {
+        const size_t l = lds_bytes<R>(1024 * CL::K3);
+        b = l > b ? l : b;
+    }
+    return b;
+}
+
+// The step's collide pass as one persistent launch (see k_collide_all): the
+// segment pre-passes of the cells beyond the LDS classes, the largest-first
+// order of the block cells, the launch, then the pairs across segment edges
+// and the cells no segment plan could take.
+template <typename R, int F>
+int launch_unified(const CollideArgs &a, const int32_t *lists, int32_t n_cells, int num_cu,
+                   const HugeScratch &hs, const ClassCaps &caps, bool seg_path, hipStream_t st)
+{
+    const int32_t *l4 = lists + 4 * (int64_t)n_cells;
+    const SegScratch &ss = g_seg;
+    if (seg_path) {
+        ktime_begin(KT_HUGE, st);
+        hipLaunchKernelGGL(k_seg_count, dim3(num_cu * 4), dim3(SEG_CT), 0, st, a, l4, ss);
+        typedef SegGeom<R> G;
+        hipLaunchKernelGGL(k_seg_scan, dim3(1), dim3(1024), 0, st, a, ss, (uint32_t)(G::T * G::K));
+        hipLaunchKernelGGL(k_seg_scatter<R>, dim3(num_cu * 4), dim3(SEG_CT), 0, st, a, l4, ss);
+        ktime_end(KT_HUGE, st);
+    }
+    const int wave_cls = caps.wave ? 0 : -1;
+    ktime_begin(KT_QUEUE, st);
+    hipLaunchKernelGGL(k_order_queue, dim3(1), dim3(1024), 0, st, a.cell_start, lists, n_cells,
+                       caps.wave ? 1 : 0, caps.ncls - 1, a.dflags, a.order);
+    ktime_end(KT_QUEUE, st);
+    constexpr size_t lds = all_lds_bytes<R, F>();
+    auto kern = k_collide_all<R, F>;
+    static bool attr_done = false;
+    if (!attr_done) {
+        HIP_OK(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)lds));
+        attr_done = true;
+    }
+    ktime_begin(KT_ALL, st);
+    hipLaunchKernelGGL(kern, dim3(num_cu), dim3(1024), lds, st, a, lists, n_cells,
+                       (const int32_t *)a.order, ss, caps, seg_path ? 1 : 0, wave_cls);
+    ktime_end(KT_ALL, st);
+    HIP_OK(hipGetLastError());
+    ktime_begin(KT_HUGE, st);
+    if (seg_path) {
+        hipLaunchKernelGGL(k_seg_fixup<R>, dim3(num_cu), dim3(256), 0, st, a, l4, ss);
+        hipLaunchKernelGGL((k_collide_huge<R, false>), dim3(num_cu), dim3(1024), 0, st, a, l4, 4, hs,
+                           (const uint8_t *)ss.hc_fb);
+    } else {
+        hipLaunchKernelGGL((k_collide_huge<R, false>), dim3(num_cu), dim3(1024), 0, st, a, l4, 4, hs,
+                           (const uint8_t *)nullptr);
+    }
+    ktime_end(KT_HUGE, st);
+    HIP_OK(hipGetLastError());
+    return PIC_OK;
+}
+
 template <typename R>
 int launch_deferred_t(const CollideArgs &a, const int32_t *lists, int32_t n_cells, int num_cu,
                       hipStream_t st)
@@ -1703,6 +2111,10 @@ int launch_flags(const CollideArgs &a, const int32_t *lists, int32_t n_cells, in
     }
     const int f = (a.mcc_thr ? F_MCC : 0) | ((a.flags & PIC_CONSERVE_FIX) ? F_CONS : 0) |
                   ((a.flags & PIC_MOMENTS) ? F_MOM : 0);
+    // the plain step (with or without null collisions) as one launch
+    if (cc.unified && a.order && (f & ~F_MCC) == 0)
+        return f ? launch_unified<R, F_MCC>(a, lists, n_cells, num_cu, hs, cc, sp, st)
+                 : launch_unified<R, 0>(a, lists, n_cells, num_cu, hs, cc, sp, st);
     switch (f) {
     case 0: return launch_all<R, 0>(a, lists, n_cells, num_cu, hs, cc, sp, lv, st);
     case 1: return launch_all<R, 1>(a, lists, n_cells, num_cu, hs, cc, sp, lv, st);
@@ -1730,6 +2142,11 @@ ClassCaps collide_caps(int dtype, size_t)
 {
     ClassCaps c;
     c.ncls = 4;
+    // one launch per size class by default: measured faster than the single
+    // persistent launch on the uniform and the log-normal workloads (the
+    // autotuner tries both)
+    c.unified = 0;
+    c.wave = 1;
     c.blocks_per_cu[0] = 8;
     c.blocks_per_cu[1] = 4;
     c.blocks_per_cu[2] = 2;
@@ -1743,7 +2160,8 @@ ClassCaps collide_caps(int dtype, size_t)
         c.cap[3] = C::T3 * C::K3;
     } else {
         typedef Classes<double> C;
-        c.cap[0] = C::T0 * C::K0;
+        // the wave schedule takes cells of up to 256 members in binary64
+        c.cap[0] = PIC_WAVE * WaveGeom<double>::KW;
         c.cap[1] = C::T1 * C::K1;
         c.cap[2] = C::T2 * C::K2;
         c.cap[3] = C::T3 * C::K3;

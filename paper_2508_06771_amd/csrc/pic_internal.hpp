@@ -638,7 +638,7 @@ struct RadixPass {
 // 7 re-binning passes, 8 stand-alone null-collision step, 9 learned gate
 // decision, 10 relaxation of the judged cells.
 enum { KT_CLASS0 = 0, KT_HUGE = 4, KT_CHECK = 5, KT_QUEUE = 6, KT_SORT = 7, KT_MCC = 8, KT_GATE = 9,
-       KT_RELAX = 10, KT_DEFER = 11, KT_MOMENTS = 12, KT_DSMC = 13, KT_P2C = 14, KT_RECOMB = 15, KT_NANBU = 16, KT_TRIPLET = 17, KT_WEIGHTED = 18, KT_SLOTS = 20 };
+       KT_RELAX = 10, KT_DEFER = 11, KT_MOMENTS = 12, KT_DSMC = 13, KT_P2C = 14, KT_RECOMB = 15, KT_NANBU = 16, KT_TRIPLET = 17, KT_WEIGHTED = 18, KT_ALL = 19, KT_SLOTS = 20 };
 void ktime_begin(int slot, hipStream_t st);
 void ktime_end(int slot, hipStream_t st);
 bool ktime_pause();            // returns whether timing was on
@@ -669,6 +669,8 @@ struct ClassCaps {
     int ncls;            // number of LDS classes (<= 4), class ncls = multi-block
     int cap[4];          // max members per cell routed to each class (<= its capacity)
     int blocks_per_cu[5];  // persistent workgroups per CU of classes 0-3 and the multi-block class
+    int unified;         // plain steps: the collide pass as one persistent launch
+    int wave;            // ... with class 0 on one wave per cell (else on whole workgroups)
 };
 // lists holds QUEUE_LISTS runs of n_cells entries: the classes, the
 // multi-block class at index ncls, and the cells the gate defers at
@@ -702,6 +704,7 @@ struct CollideArgs {
     DevFlags *dflags;
     // pairing export
     int32_t *sorted_out, *partner_out;
+    int32_t *order;        // n_cells entries of scratch for the one-launch pass (nullable: class launches)
 };
 
 // seg_path: the cells beyond the LDS classes were planned into segments by

@@ -94,6 +94,7 @@ def _load():
         "dsmc_collide": ([vp, C.c_int, vp, vp, vp, i64, i32, vp, vp, f64, f64, f64, u64, u64, u32, vp,
                           vp, vp, i64, vp, vp], C.c_int),
         "pic_autotune": ([vp, C.c_int, vp, vp, vp, i64, i32, f64, f64, u32, vp], C.c_int),
+        "pic_set_schedule": ([vp, C.c_int, C.c_int], C.c_int),
         "pic_time_kernels": ([vp, C.c_int], C.c_int),
         "pic_kernel_times": ([vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)], C.c_int),
     }
@@ -114,14 +115,15 @@ EXPORTED = ["pic_create", "pic_destroy", "pic_strerror", "pic_sync", "pic_set_st
             "pic_gate_config", "pic_gate_reset", "pic_gate_stats", "pic_gate_state", "pic_autotune",
             "pic_conserve_reset", "pic_gate_refresh", "gate_infer", "pic_set_dsmc", "dsmc_collide",
             "mcc_null_collide_exact", "p2c_sums", "recombine", "coulomb_collide_nanbu",
-            "coulomb_collide_triplet", "coulomb_collide_noalloc", "coulomb_collide_weighted"]
+            "coulomb_collide_triplet", "coulomb_collide_noalloc", "coulomb_collide_weighted", "pic_set_schedule"]
 
 MLP_PARAMS = 4801
 GATE_STATS = ["steps", "skipped", "collided", "judged", "judged_want", "false_skip", "disabled",
               "have_moments"]
 
 KT_SLOTS = ["class0", "class1", "class2", "class3", "huge", "check", "queue", "sort", "mcc", "gate",
-            "relax", "deferred", "moments", "dsmc", "p2c", "recombine", "nanbu", "triplet", "weighted"]
+            "relax", "deferred", "moments", "dsmc", "p2c", "recombine", "nanbu", "triplet", "weighted",
+            "all"]
 
 
 def _dt(v: torch.Tensor) -> int:
@@ -224,6 +226,12 @@ class Context:
         _chk(lib.coulomb_collide_noalloc(self._h, _dt(v), _p(v), _p(cell_of), _p(pid), v.shape[1],
                                          n_cells, dt, lnL, _p(density), seed, step, flags),
              "coulomb_collide_noalloc")
+
+    def set_schedule(self, dtype, schedule: int):
+        """0: one launch per size class; 1: one persistent launch, smallest
+        class one wave per cell; 2: one persistent launch, whole workgroups."""
+        d = PIC_F32 if dtype in (torch.float32, "f32") else PIC_F64
+        _chk(lib.pic_set_schedule(self._h, d, schedule), "pic_set_schedule")
 
     def run_steps(self, v: torch.Tensor, cell_of: torch.Tensor, pid: torch.Tensor, n_cells: int,
                   *, dt: float, lnL: float, seed: int, step0: int, nsteps: int, density=None,
