@@ -620,8 +620,8 @@ def bench_rebin(args):
 
 def bench_nanbu(args):
     """Nanbu's Coulomb operator on the 4096 x 10,000 population in cell-sorted
-    storage, FP32 velocities, binary64 arithmetic: the pairing of the
-    Takizuka-Abe step, then one thread per pair."""
+    storage, FP32 velocities: the class kernels of the Takizuka-Abe step with
+    Nanbu's deflection as their pair operator."""
     import numpy as np
     import torch
 
@@ -657,7 +657,7 @@ def bench_nanbu(args):
                   "n_electrons": n},
                  roofline={"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0,
                            "unit": "GB/s", "frac": round(achieved / 8000.0, 4), "traffic": None,
-                           "kernel": "pairing (class kernels, pairs only) + k_nanbu<float>",
+                           "kernel": "class kernels with Nanbu's pair operator (k_collide<float, T, K, F_NANBU>)",
                            "kernel_avg_ms": round(kern_ms, 5), "bytes_per_electron": per_e})
 
 
@@ -665,7 +665,8 @@ def bench_triplet(args):
     """Takizuka-Abe step with the triplet for odd cells on 4096 cells of
     10,000 and 10,001 electrons alternately (half the cells odd), the plain
     workload's Maxwellian + beam velocities, FP32, cell-sorted storage: the
-    pairing of the collision step, then one thread per pairing position."""
+    class kernels of the collision step with the triplet done by one thread of
+    each odd cell's workgroup."""
     import numpy as np
     import torch
 
@@ -705,7 +706,7 @@ def bench_triplet(args):
                   "n_electrons": n},
                  roofline={"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0,
                            "unit": "GB/s", "frac": round(achieved / 8000.0, 4), "traffic": None,
-                           "kernel": "pairing (class kernels, pairs only) + k_ta_triplet<float>",
+                           "kernel": "class kernels with the odd-cell triplet (k_collide<float, T, K, F_TRIP>)",
                            "kernel_avg_ms": round(kern_ms, 5), "bytes_per_electron": per_e})
 
 

@@ -1130,44 +1130,13 @@ int mcc_null_collide_exact(pic_ctx *c, int dtype, void *v, const uint32_t *pid, 
     return rc;
 }
 
-// The pairing of the collision step (pairs-only form of its kernels) into
-// context scratch: sorted[] (pairing order) and partner[].
-static int pairs_into_ws(pic_ctx *c, const uint32_t *pid, int64_t n, const int32_t *cell_start,
-                         int32_t n_cells, uint64_t seed, uint64_t step, int32_t **sorted_out,
-                         int32_t **partner_out)
-{
-    const size_t need = (size_t)n_cells * QUEUE_LISTS * 4 + huge_scratch_bytes(PIC_F32, n) + 2 * ((size_t)n * 4 + 256) +
-                        4096;
-    RC(ensure_ws(c, need));
-    Bump b(c->ws);
-    int32_t *lists = (int32_t *)b.take((size_t)n_cells * QUEUE_LISTS * 4);
-    set_huge_scratch(PIC_F32, n, b.take(huge_scratch_bytes(PIC_F32, n)));
-    int32_t *sorted = (int32_t *)b.take((size_t)n * 4);
-    int32_t *partner = (int32_t *)b.take((size_t)n * 4);
-    RC(launch_reset_flags(c->flags, c->stream));
-    const ClassCaps caps = collide_caps(PIC_F32, c->lds_max);
-    RC(launch_build_queue(cell_start, n_cells, caps, lists, c->flags, nullptr, 0, nullptr, 0, c->stream));
-    CollideArgs a;
-    memset(&a, 0, sizeof(a));
-    a.n = n;
-    a.pid = pid;
-    a.cell_start = cell_start;
-    a.dt = 1.0;
-    a.lnL = 1.0;
-    a.seed = seed;
-    a.step = step;
-    a.dflags = c->flags;
-    a.sorted_out = sorted;
-    a.partner_out = partner;
-    RC(launch_collide(PIC_F32, a, lists, n_cells, caps, 1, c->num_cu, c->stream));
-    *sorted_out = sorted;
-    *partner_out = partner;
-    return PIC_OK;
-}
 
-int coulomb_collide_nanbu(pic_ctx *c, int dtype, void *v, const uint32_t *pid, int64_t n,
-                          const int32_t *cell_start, int32_t n_cells, double dt, double lnL,
-                          const double *density, uint64_t seed, uint64_t step)
+// Nanbu's operator or the triplet variant on cell-ordered storage: the class
+// kernels with that pair operator (cells beyond the LDS classes on one
+// workgroup each).
+static int variant_step(pic_ctx *c, int dtype, void *v, const uint32_t *pid, int64_t n,
+                        const int32_t *cell_start, int32_t n_cells, double dt, double lnL,
+                        const double *density, uint64_t seed, uint64_t step, int variant, int slot)
 {
     if (!c || n < 0 || n > INT32_MAX || n_cells < 1 || !cell_start || !(dt > 0.0) || !(lnL > 0.0) ||
         (n > 0 && (!v || !pid)))
@@ -1175,24 +1144,39 @@ int coulomb_collide_nanbu(pic_ctx *c, int dtype, void *v, const uint32_t *pid, i
     RC(check_dtype(dtype));
     if (n == 0) return PIC_OK;
     CK(hipSetDevice(c->device));
-    int32_t *sorted = nullptr, *partner = nullptr;
-    ktime_begin(KT_NANBU, c->stream);
-    RC(pairs_into_ws(c, pid, n, cell_start, n_cells, seed, step, &sorted, &partner));
-    NanbuArgs na;
-    na.v = v;
-    na.pid = pid;
-    na.partner = partner;
-    na.cs = cell_start;
-    na.density = density;
-    na.n = n;
-    na.M = n_cells;
-    na.dt = dt;
-    na.lnL = lnL;
-    na.seed = seed;
-    na.step = (uint32_t)step;
-    const int rc = launch_nanbu(dtype, na, c->stream);
-    ktime_end(KT_NANBU, c->stream);
+    hipStream_t st = c->stream;
+    RC(ensure_ws(c, (size_t)n_cells * QUEUE_LISTS * 4 + huge_scratch_bytes(dtype, n) + 4096));
+    Bump b(c->ws);
+    int32_t *lists = (int32_t *)b.take((size_t)n_cells * QUEUE_LISTS * 4);
+    set_huge_scratch(dtype, n, b.take(huge_scratch_bytes(dtype, n)));
+    const ClassCaps caps = collide_caps(dtype, c->lds_max);
+    ktime_begin(slot, st);
+    RC(launch_reset_flags(c->flags, st));
+    RC(launch_build_queue(cell_start, n_cells, caps, lists, c->flags, nullptr, 0, nullptr, 0, st));
+    CollideArgs a;
+    memset(&a, 0, sizeof(a));
+    a.v = v;
+    a.n = n;
+    a.pid = pid;
+    a.cell_start = cell_start;
+    a.density = density;
+    a.dt = dt;
+    a.lnL = lnL;
+    a.seed = seed;
+    a.step = step;
+    a.dflags = c->flags;
+    a.variant = variant;
+    const int rc = launch_collide(dtype, a, lists, n_cells, caps, 0, c->num_cu, st, false, ~0u);
+    ktime_end(slot, st);
     return rc;
+}
+
+int coulomb_collide_nanbu(pic_ctx *c, int dtype, void *v, const uint32_t *pid, int64_t n,
+                          const int32_t *cell_start, int32_t n_cells, double dt, double lnL,
+                          const double *density, uint64_t seed, uint64_t step)
+{
+    return variant_step(c, dtype, v, pid, n, cell_start, n_cells, dt, lnL, density, seed, step,
+                        VAR_NANBU, KT_NANBU);
 }
 
 int coulomb_collide_weighted(pic_ctx *c, int dtype, void *v, const void *w, const uint32_t *pid,
@@ -1241,30 +1225,8 @@ int coulomb_collide_triplet(pic_ctx *c, int dtype, void *v, const uint32_t *pid,
                             const int32_t *cell_start, int32_t n_cells, double dt, double lnL,
                             const double *density, uint64_t seed, uint64_t step)
 {
-    if (!c || n < 0 || n > INT32_MAX || n_cells < 1 || !cell_start || !(dt > 0.0) || !(lnL > 0.0) ||
-        (n > 0 && (!v || !pid)))
-        return PIC_ERR_ARG;
-    RC(check_dtype(dtype));
-    if (n == 0) return PIC_OK;
-    CK(hipSetDevice(c->device));
-    int32_t *sorted = nullptr, *partner = nullptr;
-    ktime_begin(KT_TRIPLET, c->stream);
-    RC(pairs_into_ws(c, pid, n, cell_start, n_cells, seed, step, &sorted, &partner));
-    TripletArgs ta;
-    ta.v = v;
-    ta.pid = pid;
-    ta.sorted = sorted;
-    ta.cs = cell_start;
-    ta.density = density;
-    ta.n = n;
-    ta.M = n_cells;
-    ta.dt = dt;
-    ta.lnL = lnL;
-    ta.seed = seed;
-    ta.step = (uint32_t)step;
-    const int rc = launch_ta_triplet(dtype, ta, c->stream);
-    ktime_end(KT_TRIPLET, c->stream);
-    return rc;
+    return variant_step(c, dtype, v, pid, n, cell_start, n_cells, dt, lnL, density, seed, step,
+                        VAR_TRIPLET, KT_TRIPLET);
 }
 
 int recombine(pic_ctx *c, int dtype, void *v, void *w, const uint32_t *pid, const uint8_t *primary,

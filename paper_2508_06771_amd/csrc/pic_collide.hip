@@ -166,7 +166,7 @@ __device__ __forceinline__ bool gated_off(const CollideArgs &a)
 }
 
 // Variants compiled per kernel: which optional parts of the pass exist.
-enum { F_MCC = 1, F_CONS = 2, F_MOM = 4, F_PAIRS = 8, F_WT = 16 };
+enum { F_MCC = 1, F_CONS = 2, F_MOM = 4, F_PAIRS = 8, F_WT = 16, F_NANBU = 32, F_TRIP = 64 };
 
 // Variable-weight rule for the pair (a, b) with half change h (a += h,
 // b -= h in the uniform step): the member of smaller weight always takes its
@@ -195,24 +195,102 @@ template <> struct __align__(16) Rec<double> { double x, y, z; uint32_t w2, pad;
 // Dynamic LDS a cell pass may use (the static part is below 4 KB).
 constexpr size_t LDS_DYN_LIMIT = 152 * 1024;
 
-// Positions per exchange round: the whole cell when its records fit.  With
-// weights a pair also holds the second member's word 3 and both weights.
-template <typename R, bool WT = false>
+// Layout of one exchange round of P positions: P + 2 records (two beyond P
+// for an odd cell's triplet that straddles the end of the round), the first
+// members' word 3 per pair, and with weights the second members' word 3 and
+// the weight per position, with Nanbu's operator or the triplet the member
+// index per position.
+template <typename R, int F>
+struct ExchLayout {
+    static constexpr bool WT = (F & F_WT) != 0;
+    static constexpr bool SLOT = (F & (F_NANBU | F_TRIP)) != 0;
+    __host__ __device__ static constexpr size_t bytes(uint32_t P)
+    {
+        size_t b = ((size_t)P + 2) * sizeof(Rec<R>) + ((size_t)P / 2 + 1) * 4;
+        if (WT) b += ((size_t)P / 2 + 1) * 4 + ((size_t)P + 2) * sizeof(R);
+        if (SLOT) b += ((size_t)P + 2) * 2;
+        return (b + 15) & ~(size_t)15;
+    }
+};
+
+// Positions per exchange round: the whole cell when its records fit.
+template <typename R, int F = 0>
 __host__ __device__ constexpr uint32_t round_positions(int cap)
 {
-    const size_t per_pair = 2 * sizeof(Rec<R>) + 4 + (WT ? 4 + 2 * sizeof(R) : 0);
-    const size_t want = ((size_t)cap + 1) / 2;
-    const size_t lim = (LDS_DYN_LIMIT / per_pair) & ~(size_t)63;
-    return (uint32_t)(2 * (want < lim ? want : lim));
+    const uint32_t want = (uint32_t)(((size_t)cap + 1) & ~(size_t)1);
+    uint32_t P = want;
+    while (P > 64 && ExchLayout<R, F>::bytes(P) > LDS_DYN_LIMIT) P -= 64;
+    return P;
 }
 
-template <typename R, bool WT = false>
+template <typename R, int F = 0>
 __host__ __device__ constexpr size_t lds_bytes(int cap)
 {
-    const size_t ex = (size_t)round_positions<R, WT>(cap) / 2 *
-                      (2 * sizeof(Rec<R>) + 4 + (WT ? 4 + 2 * sizeof(R) : 0));
+    const size_t ex = ExchLayout<R, F>::bytes(round_positions<R, F>(cap));
     const size_t s = sort_bytes(cap);
     return s > ex ? s : ex;
+}
+
+// Nanbu's deflection of the pair (a, b), a the member in the lower storage
+// slot: 1 - cos chi from Nanbu's distribution with U = U(word 2 of a) and
+// A(s), s twice the Takizuka & Abe variance (C / |u|^3, C = 8 pi n lnL dt);
+// azimuth 2 pi U(word 2 of b); rotation and halves as in Takizuka & Abe.
+// Binary64 computes the oracle's steps; binary32 its own (see nb_A).
+template <typename R>
+__device__ __forceinline__ void nanbu_half(R ux, R uy, R uz, R C, uint32_t wa2, uint32_t wb2, R &hx,
+                                           R &hy, R &hz)
+{
+#pragma clang fp contract(off)
+    const double PI = 3.14159265358979323846;
+    hx = hy = hz = (R)0;
+    const R uu = ux * ux + uy * uy + uz * uz;
+    if (uu == (R)0) return;
+    const R um = sqrt(uu), uperp = sqrt(ux * ux + uy * uy);
+    const R s = (R)2 * nb_div(C, um * um * um);
+    const R U = sizeof(R) == 4 ? (R)u01f(wa2) : (R)u01d(wa2);
+    const R omc = nb_omc(nb_A(s), U);
+    const R sin_t = sqrt(omc * ((R)2 - omc));
+    const R phi = (R)(2.0 * PI) * (sizeof(R) == 4 ? (R)u01f(wb2) : (R)u01d(wb2));
+    const R cphi = cos(phi), sphi = sin(phi);
+    R dx, dy, dz;
+    if (uperp > (R)0) {
+        const R ex = nb_div(ux, uperp), ey = nb_div(uy, uperp);
+        dx = ex * uz * sin_t * cphi - ey * um * sin_t * sphi - ux * omc;
+        dy = ey * uz * sin_t * cphi + ex * um * sin_t * sphi - uy * omc;
+        dz = -uperp * sin_t * cphi - uz * omc;
+    } else {
+        dx = um * sin_t * cphi;
+        dy = um * sin_t * sphi;
+        dz = -uz * omc;
+    }
+    hx = (R)0.5 * dx;
+    hy = (R)0.5 * dy;
+    hz = (R)0.5 * dz;
+}
+
+// Takizuka & Abe's triplet for an odd cell: the members p0 p1 p2 (the last
+// three in pairing order) collide pairwise at dt/2 in the order (p0, p1),
+// (p1, p2), (p2, p0), each on the velocities the previous one left, with the
+// uniforms of Philox domains 0, 4 and 5.  In place on x, y, z.
+template <typename R>
+__device__ __forceinline__ void triplet_collide(R (&x)[3], R (&y)[3], R (&z)[3], const uint32_t (&pd)[3],
+                                                R Ch, uint64_t seed, uint32_t step)
+{
+    const uint32_t dom[3] = {0u, 4u, 5u};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const int i = c, k = (c + 1) % 3;
+        const W4 wa = draw4(seed, pd[i], step, dom[c], 0u);
+        const W4 wb = draw4(seed, pd[k], step, dom[c], 0u);
+        R hx, hy, hz;
+        ta_half(x[i] - x[k], y[i] - y[k], z[i] - z[k], Ch, wa.z, wa.w, wb.z, hx, hy, hz);
+        x[i] += hx;
+        y[i] += hy;
+        z[i] += hz;
+        x[k] -= hx;
+        y[k] -= hy;
+        z[k] -= hz;
+    }
 }
 
 // ------------------------------------------------------------ LDS-class pass
@@ -282,6 +360,8 @@ __device__ __forceinline__ void cell_pass(const CollideArgs &a, int cell, unsign
     constexpr bool CONS = (F & F_CONS) != 0;
     constexpr bool MOM = (F & F_MOM) != 0;
     constexpr bool WT = (F & F_WT) != 0;
+    constexpr bool NANBU = (F & F_NANBU) != 0;
+    constexpr bool TRIP = (F & F_TRIP) != 0;
     constexpr int CAP = T * K;
     const int lo = a.cell_start[cell];
     const int n = a.cell_start[cell + 1] - lo;
@@ -373,19 +453,28 @@ __device__ __forceinline__ void cell_pass(const CollideArgs &a, int cell, unsign
     if (coul) {
         const R C = (R)cell_C(a, cell);
         const uint32_t np2 = (uint32_t)n & ~1u;     // positions with a partner
-        constexpr uint32_t P = round_positions<R, WT>(CAP);
+        // with the triplet, an odd cell's last three positions form it
+        const uint32_t tstart = (TRIP && (n & 1) && n >= 3) ? (uint32_t)n - 3u : np2;
+        const uint32_t npost = tstart < np2 ? (uint32_t)n : np2;   // positions with records
+        constexpr uint32_t P = round_positions<R, F>(CAP);
         Rec<R> *rec = (Rec<R> *)smem;
-        uint32_t *w3s = (uint32_t *)(rec + P);
+        uint32_t *w3s = (uint32_t *)(rec + P + 2);
         // with weights: the second member's word 3 per pair, the weight per position
-        uint32_t *w3b = w3s + P / 2;
-        R *wts = (R *)(w3b + P / 2);
+        uint32_t *w3b = w3s + P / 2 + 1;
+        R *wts = (R *)(w3b + (WT ? P / 2 + 1 : 0));
+        // with Nanbu's operator or the triplet: the member index per position
+        uint16_t *slt = (uint16_t *)(wts + (WT ? P + 2 : 0));
         const R *w_c = (const R *)a.w + lo;
-        for (uint32_t base = 0; base < np2; base += P) {
+        for (uint32_t base = 0; base < npost; base += P) {
+            // a member posts in the round of its position; the triplet's three
+            // in the round holding its start
+            const bool tri_here = tstart < npost && tstart >= base && tstart - base < P;
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 const int i = threadIdx.x + k * T;
                 const uint32_t q = pos[k] - base;
-                if (i < n && q < P && pos[k] < np2) {
+                const bool mine = pos[k] < tstart ? q < P : (pos[k] < npost && tri_here);
+                if (i < n && mine) {
                     Rec<R> e;
                     e.x = vx[k];
                     e.y = vy[k];
@@ -397,16 +486,30 @@ __device__ __forceinline__ void cell_pass(const CollideArgs &a, int cell, unsign
                         if (q & 1u) w3b[q >> 1] = w3[k];
                         wts[q] = w_c[i];
                     }
+                    if constexpr (NANBU || TRIP) slt[q] = (uint16_t)i;
                 }
             }
             __syncthreads();
-            const uint32_t m = min(P, np2 - base) / 2;
+            const uint32_t lim = min(base + P, tstart);
+            const uint32_t m = lim > base ? (lim - base) / 2 : 0u;
             for (uint32_t j = threadIdx.x; j < m; j += T) {
                 Rec<R> A = rec[2 * j], B = rec[2 * j + 1];
                 R hx, hy, hz;
-                ta_half(A.x - B.x, A.y - B.y, A.z - B.z, C, A.w2, w3s[j], B.w2, hx, hy, hz);
                 bool ta = true, tb = true;
-                if constexpr (WT) weight_rule<R>(wts[2 * j], wts[2 * j + 1], w3b[j], ta, tb);
+                if constexpr (NANBU) {
+                    // the member in the lower storage slot is the operator's first
+                    if (slt[2 * j] < slt[2 * j + 1]) {
+                        nanbu_half<R>(A.x - B.x, A.y - B.y, A.z - B.z, C, A.w2, B.w2, hx, hy, hz);
+                    } else {
+                        nanbu_half<R>(B.x - A.x, B.y - A.y, B.z - A.z, C, B.w2, A.w2, hx, hy, hz);
+                        hx = -hx;
+                        hy = -hy;
+                        hz = -hz;
+                    }
+                } else {
+                    ta_half(A.x - B.x, A.y - B.y, A.z - B.z, C, A.w2, w3s[j], B.w2, hx, hy, hz);
+                    if constexpr (WT) weight_rule<R>(wts[2 * j], wts[2 * j + 1], w3b[j], ta, tb);
+                }
                 if (ta) {
                     A.x += hx;
                     A.y += hy;
@@ -420,19 +523,46 @@ __device__ __forceinline__ void cell_pass(const CollideArgs &a, int cell, unsign
                 rec[2 * j] = A;
                 rec[2 * j + 1] = B;
             }
+            if constexpr (TRIP) {
+                if (tri_here && threadIdx.x == 0) {
+                    const uint32_t q0 = tstart - base;
+                    R x[3], y[3], z[3];
+                    uint32_t pd[3];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const Rec<R> e = rec[q0 + c];
+                        x[c] = e.x;
+                        y[c] = e.y;
+                        z[c] = e.z;
+                        pd[c] = pid_c[slt[q0 + c]];
+                    }
+                    const double dens = a.density ? a.density[cell] : 1.0;
+                    triplet_collide<R>(x, y, z, pd, (R)(8.0 * PI_D * dens * a.lnL * (0.5 * a.dt)),
+                                       a.seed, step);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        Rec<R> e = rec[q0 + c];
+                        e.x = x[c];
+                        e.y = y[c];
+                        e.z = z[c];
+                        rec[q0 + c] = e;
+                    }
+                }
+            }
             __syncthreads();
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 const int i = threadIdx.x + k * T;
                 const uint32_t q = pos[k] - base;
-                if (i < n && q < P && pos[k] < np2) {
+                const bool mine = pos[k] < tstart ? q < P : (pos[k] < npost && tri_here);
+                if (i < n && mine) {
                     const Rec<R> e = rec[q];
                     vx[k] = e.x;
                     vy[k] = e.y;
                     vz[k] = e.z;
                 }
             }
-            if (base + P < np2) __syncthreads();
+            if (base + P < npost) __syncthreads();
         }
 
         if constexpr (CONS) {
@@ -979,14 +1109,31 @@ __global__ __launch_bounds__(1024) void k_collide_huge(CollideArgs a, const int3
                 }
             }
             __syncthreads();
+            // with the triplet, an odd cell's last three positions form it
+            const uint32_t tstart = (a.variant == VAR_TRIPLET && (n & 1) && n >= 3) ? (uint32_t)n - 3u
+                                                                                 : (uint32_t)n & ~1u;
             for (int i = threadIdx.x; i < n; i += T) {
                 const uint32_t p = hs.pos[lo + i];
-                if (!(p & 1u) && p + 1 < (uint32_t)n) {
+                if (!(p & 1u) && p + 1 < tstart) {
                     Rec<R> &e = pc[p >> 1];
                     R x = vx_g[lo + i], y = vy_g[lo + i], z = vz_g[lo + i];
                     R hx, hy, hz;
-                    ta_half(x - e.x, y - e.y, z - e.z, C, hs.w23[2 * (int64_t)(lo + i)],
-                            hs.w23[2 * (int64_t)(lo + i) + 1], e.w2, hx, hy, hz);
+                    if (a.variant == VAR_NANBU) {
+                        // the member in the lower storage slot is the operator's first
+                        const uint32_t j = hs.lst[lo + p + 1];
+                        const uint32_t own = hs.w23[2 * (int64_t)(lo + i)];
+                        if ((uint32_t)i < j) {
+                            nanbu_half<R>(x - e.x, y - e.y, z - e.z, C, own, e.w2, hx, hy, hz);
+                        } else {
+                            nanbu_half<R>(e.x - x, e.y - y, e.z - z, C, e.w2, own, hx, hy, hz);
+                            hx = -hx;
+                            hy = -hy;
+                            hz = -hz;
+                        }
+                    } else {
+                        ta_half(x - e.x, y - e.y, z - e.z, C, hs.w23[2 * (int64_t)(lo + i)],
+                                hs.w23[2 * (int64_t)(lo + i) + 1], e.w2, hx, hy, hz);
+                    }
                     bool ta = true, tb = true;
                     if (a.w) {
                         // the partner: the member at the next position
@@ -1008,11 +1155,35 @@ __global__ __launch_bounds__(1024) void k_collide_huge(CollideArgs a, const int3
             __syncthreads();
             for (int i = threadIdx.x; i < n; i += T) {
                 const uint32_t p = hs.pos[lo + i];
-                if (p & 1u) {
+                if ((p & 1u) && p < tstart) {
                     const Rec<R> &e = pc[p >> 1];
                     vx_g[lo + i] -= e.x;
                     vy_g[lo + i] -= e.y;
                     vz_g[lo + i] -= e.z;
+                }
+            }
+            __syncthreads();
+            if (tstart + 3 == (uint32_t)n && (n & 1) && threadIdx.x == 0) {
+                // the triplet: one thread, members read through the sorted list
+                int64_t sl[3];
+                R x[3], y[3], z[3];
+                uint32_t pd[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    sl[c] = lo + (int64_t)hs.lst[lo + tstart + c];
+                    x[c] = vx_g[sl[c]];
+                    y[c] = vy_g[sl[c]];
+                    z[c] = vz_g[sl[c]];
+                    pd[c] = a.pid[sl[c]];
+                }
+                const double dens = a.density ? a.density[cell] : 1.0;
+                triplet_collide<R>(x, y, z, pd, (R)(8.0 * PI_D * dens * a.lnL * (0.5 * a.dt)), a.seed,
+                                   step);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    vx_g[sl[c]] = x[c];
+                    vy_g[sl[c]] = y[c];
+                    vz_g[sl[c]] = z[c];
                 }
             }
             __syncthreads();
@@ -1907,7 +2078,7 @@ __global__ __launch_bounds__(1024) void k_collide_all(CollideArgs a, const int32
 template <typename R, int T, int K, int F>
 int launch_class(const CollideArgs &a, const int32_t *list, int cls, int blocks, hipStream_t st)
 {
-    const size_t lds = lds_bytes<R, (F & F_WT) != 0>(T * K);
+    const size_t lds = lds_bytes<R, F>(T * K);
     auto kern = k_collide<R, T, K, F>;
     static bool attr_done = false;
     if (!attr_done) {
@@ -1973,7 +2144,7 @@ int launch_all(const CollideArgs &a, const int32_t *lists, int32_t n_cells, int 
 {
     typedef Classes<R> C;
     constexpr bool PAIRS = (F & F_PAIRS) != 0;
-    constexpr bool SEG_OK = !PAIRS && !(F & (F_CONS | F_MOM | F_WT));
+    constexpr bool SEG_OK = !PAIRS && !(F & (F_CONS | F_MOM | F_WT | F_NANBU | F_TRIP));
     int rc;
     const int64_t M = n_cells;
     const int *bp = caps.blocks_per_cu;
@@ -2103,6 +2274,8 @@ int launch_flags(const CollideArgs &a, const int32_t *lists, int32_t n_cells, in
                  hipStream_t st)
 {
     if (pairs_only) return launch_all<R, F_PAIRS>(a, lists, n_cells, num_cu, hs, cc, false, ~0u, st);
+    if (a.variant == VAR_NANBU) return launch_all<R, F_NANBU>(a, lists, n_cells, num_cu, hs, cc, false, lv, st);
+    if (a.variant == VAR_TRIPLET) return launch_all<R, F_TRIP>(a, lists, n_cells, num_cu, hs, cc, false, lv, st);
     if (a.w) {
         // variable weights: the plain step (optionally with null collisions),
         // cells beyond the LDS classes on one workgroup each
@@ -2169,88 +2342,7 @@ ClassCaps collide_caps(int dtype, size_t)
     return c;
 }
 
-namespace {
-// Takizuka & Abe on the pairing of the collision step, with their triplet for
-// odd cells: one workgroup per cell.  With t = N - 3 for odd N >= 3 (else
-// t = N), the threads take the regular pairs at positions (2i, 2i + 1),
-// 2i + 1 < t, and one thread the triplet: the members p0 p1 p2 at t, t+1,
-// t+2 collide pairwise at dt/2 in the order (p0, p1), (p1, p2), (p2, p0) on
-// the velocities the previous one left, with the uniforms of domain 0, 4
-// and 5 draws.  The pair arithmetic is ta_half, as in the collision step.
-// 1024-thread workgroups: two cells per CU in flight keep the cells' members
-// (reached in pairing order, so scattered) within the last-level cache.
-template <typename R>
-__global__ __launch_bounds__(1024) void k_ta_triplet(TripletArgs a)
-{
-    R *vx = (R *)a.v;
-    R *vy = vx + a.n;
-    R *vz = vy + a.n;
-    for (int32_t j = blockIdx.x; j < a.M; j += gridDim.x) {
-        const int64_t lo = a.cs[j], N = (int64_t)a.cs[j + 1] - lo;
-        const int64_t t = (N % 2 == 1 && N >= 3) ? N - 3 : N;
-        const double dens = a.density ? a.density[j] : 1.0;
-        const R C = (R)(8.0 * PI_D * dens * a.lnL * a.dt * 1.0);
-        for (int64_t i = threadIdx.x; 2 * i + 1 < t; i += blockDim.x) {
-            const int64_t ia = a.sorted[lo + 2 * i], ib = a.sorted[lo + 2 * i + 1];
-            const W4 wa = draw4(a.seed, a.pid[ia], a.step, 0u, 0u);
-            const W4 wb = draw4(a.seed, a.pid[ib], a.step, 0u, 0u);
-            R ax = vx[ia], ay = vy[ia], az = vz[ia], bx = vx[ib], by = vy[ib], bz = vz[ib];
-            R hx, hy, hz;
-            ta_half(ax - bx, ay - by, az - bz, C, wa.z, wa.w, wb.z, hx, hy, hz);
-            vx[ia] = ax + hx;
-            vy[ia] = ay + hy;
-            vz[ia] = az + hz;
-            vx[ib] = bx - hx;
-            vy[ib] = by - hy;
-            vz[ib] = bz - hz;
-        }
-        if (t < N && threadIdx.x == blockDim.x - 1) {
-            const int64_t s0[3] = {a.sorted[lo + t], a.sorted[lo + t + 1], a.sorted[lo + t + 2]};
-            R x[3], y[3], z[3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                x[c] = vx[s0[c]];
-                y[c] = vy[s0[c]];
-                z[c] = vz[s0[c]];
-            }
-            const R Ch = (R)(8.0 * PI_D * dens * a.lnL * (0.5 * a.dt));
-            const uint32_t dom[3] = {0u, 4u, 5u};
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const int i = c, k = (c + 1) % 3;
-                const W4 wa = draw4(a.seed, a.pid[s0[i]], a.step, dom[c], 0u);
-                const W4 wb = draw4(a.seed, a.pid[s0[k]], a.step, dom[c], 0u);
-                R hx, hy, hz;
-                ta_half(x[i] - x[k], y[i] - y[k], z[i] - z[k], Ch, wa.z, wa.w, wb.z, hx, hy, hz);
-                x[i] += hx;
-                y[i] += hy;
-                z[i] += hz;
-                x[k] -= hx;
-                y[k] -= hy;
-                z[k] -= hz;
-            }
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                vx[s0[c]] = x[c];
-                vy[s0[c]] = y[c];
-                vz[s0[c]] = z[c];
-            }
-        }
-    }
-}
-}  // namespace
 
-int launch_ta_triplet(int dtype, const TripletArgs &a, hipStream_t st)
-{
-    if (a.n <= 0) return PIC_OK;
-    const int g = a.M < 4096 ? a.M : 4096;
-    if (dtype == PIC_F32)
-        hipLaunchKernelGGL(k_ta_triplet<float>, dim3(g), dim3(1024), 0, st, a);
-    else
-        hipLaunchKernelGGL(k_ta_triplet<double>, dim3(g), dim3(1024), 0, st, a);
-    HIP_OK(hipGetLastError());
-    return PIC_OK;
-}
 
 size_t huge_scratch_bytes(int dtype, int64_t n)
 {

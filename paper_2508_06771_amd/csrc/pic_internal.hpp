@@ -77,6 +77,77 @@ __device__ __forceinline__ double u01d(uint32_t x)
     return ((double)(x >> 9) + 0.5) * 0x1p-23;
 }
 
+// Nanbu's Coulomb operator on the pairs of the Takizuka-Abe step: the pair
+// (a, b), a the lower slot, turns its relative velocity u by chi with
+// 1 - cos chi = -log1p(-(1 - U)(1 - exp(-2A))) / A, U = U(word 2 of a),
+// A solving coth A - 1/A = exp(-s), s = 2 * 8 pi n lnL dt / |u|^3; azimuth
+// 2 pi U(word 2 of b); halves as in T&A.  Binary64 storage computes in
+// binary64 (the oracle's steps exactly); binary32 storage in binary32, with
+// the Langevin series used up to A = 0.5 (five terms) where the closed form
+// would cancel, and the large-A root up to s = 0.1.
+// a / b, correctly rounded in both precisions (the hardware reciprocal's
+// extra rounding was enough to miss the binary32 bar where a collision
+// leaves a member almost at rest)
+template <typename T>
+__device__ __forceinline__ T nb_div(T a, T b)
+{
+    return a / b;
+}
+
+template <typename T>
+__device__ __forceinline__ void nb_langevin(T A, T &L, T &dL)
+{
+#pragma clang fp contract(off)
+    constexpr bool F = sizeof(T) == 4;
+    if (A < (F ? (T)0.5 : (T)0.1)) {
+        const T A2 = A * A;
+        if (F) {
+            L = A * ((T)(1.0 / 3.0) -
+                     A2 * ((T)(1.0 / 45.0) - A2 * ((T)(2.0 / 945.0) - A2 * ((T)(1.0 / 4725.0) -
+                                                                            A2 * (T)(2.0 / 93555.0)))));
+            dL = (T)(1.0 / 3.0) -
+                 A2 * ((T)(1.0 / 15.0) - A2 * ((T)(2.0 / 189.0) - A2 * ((T)(1.0 / 675.0) - A2 * (T)(2.0 / 10395.0))));
+        } else {
+            L = A * (1.0 / 3.0 - A2 * (1.0 / 45.0 - A2 * (2.0 / 945.0 - A2 / 4725.0)));
+            dL = 1.0 / 3.0 - A2 * (1.0 / 15.0 - A2 * (2.0 / 189.0 - A2 / 675.0));
+        }
+    } else {   // t = exp(-2A): coth A = (1 + t)/(1 - t), 1/sinh^2 A = 4t/(1 - t)^2
+        const T t = exp((T)-2 * A), d = (T)1 - t;
+        L = nb_div((T)1 + t, d) - nb_div((T)1, A);
+        dL = nb_div((T)1, A * A) - nb_div((T)4 * t, d * d);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ T nb_A(T s)
+{
+#pragma clang fp contract(off)
+    // coth A = 1 to working precision: A > 8.3 in binary32, A > 18.7 in binary64
+    if (s <= (sizeof(T) == 4 ? (T)0.1 : (T)0.01)) return nb_div((T)-1, expm1(-s));
+    const T y = exp(-s);
+    if (s > (T)11.5) return (T)3 * y;             // coth A - 1/A = A/3 to 1e-10
+    T A = nb_div(y * ((T)3 - y * y), (T)1 - y * y);
+    for (int it = 0; it < 4; ++it) {   // from within 2%: quadratic convergence
+        T L, dL;
+        nb_langevin(A, L, dL);
+        A -= nb_div(L - y, dL);
+    }
+    return A;
+}
+
+template <typename T>
+__device__ __forceinline__ T nb_omc(T A, T U)
+{
+#pragma clang fp contract(off)
+    if (!(A > (sizeof(T) == 4 ? (T)1e-30 : (T)1e-300))) return (T)2 * ((T)1 - U);
+    // -log(U + (1 - U) exp(-2A)) / A: through log1p(-q) while q < 1/2, else
+    // the sum itself (no cancellation when U and exp(-2A) are both small)
+    const T q = ((T)1 - U) * -expm1((T)-2 * A);
+    const T omc = nb_div(q < (T)0.5 ? -log1p(-q) : -log(U + ((T)1 - U) * exp((T)-2 * A)), A);
+    return omc < (T)2 ? omc : (T)2;
+}
+
+
 // ---------------------------------------------------------------------------
 // Elastic isotropic scattering of a null-collision candidate from its domain-1
 // draw w: cos(theta) = 1 - 2 U(w.y), phi = 2 pi U(w.z) (binary32: the hardware
@@ -705,7 +776,9 @@ struct CollideArgs {
     // pairing export
     int32_t *sorted_out, *partner_out;
     int32_t *order;        // n_cells entries of scratch for the one-launch pass (nullable: class launches)
+    int variant;           // pair operator: VAR_TA (the step), VAR_NANBU, VAR_TRIPLET
 };
+enum { VAR_TA = 0, VAR_NANBU = 1, VAR_TRIPLET = 2 };
 
 // seg_path: the cells beyond the LDS classes were planned into segments by
 // the queue builder (only for steps without PIC_CONSERVE_FIX and PIC_MOMENTS).
@@ -836,36 +909,6 @@ struct DsmcArgs {
     DevFlags *dflags;
 };
 int launch_dsmc(int dtype, const DsmcArgs &a, const DsmcTable &t, hipStream_t st);
-
-// Takizuka & Abe on the pairing order sorted[] with the triplet for odd cells.
-struct TripletArgs {
-    void *v;
-    const uint32_t *pid;
-    const int32_t *sorted;
-    const int32_t *cs;
-    const double *density;
-    int64_t n;
-    int32_t M;
-    double dt, lnL;
-    uint64_t seed;
-    uint32_t step;
-};
-int launch_ta_triplet(int dtype, const TripletArgs &a, hipStream_t st);
-
-// Nanbu's operator on the pairs partner[] of the T&A step (storage in cell order).
-struct NanbuArgs {
-    void *v;
-    const uint32_t *pid;
-    const int32_t *partner;
-    const int32_t *cs;
-    const double *density;
-    int64_t n;
-    int32_t M;
-    double dt, lnL;
-    uint64_t seed;
-    uint32_t step;
-};
-int launch_nanbu(int dtype, const NanbuArgs &a, hipStream_t st);
 
 // Recombination C5 on cell-sorted storage (v and w of the velocity dtype).
 struct RecombArgs {

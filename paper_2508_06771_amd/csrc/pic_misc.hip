@@ -433,169 +433,6 @@ __global__ __launch_bounds__(RC_T) void k_recombine(RecombArgs a)
 }
 
 // ------------------------------------------------------------ Nanbu
-// Nanbu's Coulomb operator on the pairs of the Takizuka-Abe step: the pair
-// (a, b), a the lower slot, turns its relative velocity u by chi with
-// 1 - cos chi = -log1p(-(1 - U)(1 - exp(-2A))) / A, U = U(word 2 of a),
-// A solving coth A - 1/A = exp(-s), s = 2 * 8 pi n lnL dt / |u|^3; azimuth
-// 2 pi U(word 2 of b); halves as in T&A.  Binary64 storage computes in
-// binary64 (the oracle's steps exactly); binary32 storage in binary32, with
-// the Langevin series used up to A = 0.5 (five terms) where the closed form
-// would cancel, and the large-A root up to s = 0.1.
-// a / b, correctly rounded in both precisions (the hardware reciprocal's
-// extra rounding was enough to miss the binary32 bar where a collision
-// leaves a member almost at rest)
-template <typename T>
-__device__ __forceinline__ T nb_div(T a, T b)
-{
-    return a / b;
-}
-
-template <typename T>
-__device__ __forceinline__ void nb_langevin(T A, T &L, T &dL)
-{
-#pragma clang fp contract(off)
-    constexpr bool F = sizeof(T) == 4;
-    if (A < (F ? (T)0.5 : (T)0.1)) {
-        const T A2 = A * A;
-        if (F) {
-            L = A * ((T)(1.0 / 3.0) -
-                     A2 * ((T)(1.0 / 45.0) - A2 * ((T)(2.0 / 945.0) - A2 * ((T)(1.0 / 4725.0) -
-                                                                            A2 * (T)(2.0 / 93555.0)))));
-            dL = (T)(1.0 / 3.0) -
-                 A2 * ((T)(1.0 / 15.0) - A2 * ((T)(2.0 / 189.0) - A2 * ((T)(1.0 / 675.0) - A2 * (T)(2.0 / 10395.0))));
-        } else {
-            L = A * (1.0 / 3.0 - A2 * (1.0 / 45.0 - A2 * (2.0 / 945.0 - A2 / 4725.0)));
-            dL = 1.0 / 3.0 - A2 * (1.0 / 15.0 - A2 * (2.0 / 189.0 - A2 / 675.0));
-        }
-    } else {   // t = exp(-2A): coth A = (1 + t)/(1 - t), 1/sinh^2 A = 4t/(1 - t)^2
-        const T t = exp((T)-2 * A), d = (T)1 - t;
-        L = nb_div((T)1 + t, d) - nb_div((T)1, A);
-        dL = nb_div((T)1, A * A) - nb_div((T)4 * t, d * d);
-    }
-}
-
-template <typename T>
-__device__ __forceinline__ T nb_A(T s)
-{
-#pragma clang fp contract(off)
-    // coth A = 1 to working precision: A > 8.3 in binary32, A > 18.7 in binary64
-    if (s <= (sizeof(T) == 4 ? (T)0.1 : (T)0.01)) return nb_div((T)-1, expm1(-s));
-    const T y = exp(-s);
-    if (s > (T)11.5) return (T)3 * y;             // coth A - 1/A = A/3 to 1e-10
-    T A = nb_div(y * ((T)3 - y * y), (T)1 - y * y);
-    for (int it = 0; it < 4; ++it) {   // from within 2%: quadratic convergence
-        T L, dL;
-        nb_langevin(A, L, dL);
-        A -= nb_div(L - y, dL);
-    }
-    return A;
-}
-
-template <typename T>
-__device__ __forceinline__ T nb_omc(T A, T U)
-{
-#pragma clang fp contract(off)
-    if (!(A > (sizeof(T) == 4 ? (T)1e-30 : (T)1e-300))) return (T)2 * ((T)1 - U);
-    // -log(U + (1 - U) exp(-2A)) / A: through log1p(-q) while q < 1/2, else
-    // the sum itself (no cancellation when U and exp(-2A) are both small)
-    const T q = ((T)1 - U) * -expm1((T)-2 * A);
-    const T omc = nb_div(q < (T)0.5 ? -log1p(-q) : -log(U + ((T)1 - U) * exp((T)-2 * A)), A);
-    return omc < (T)2 ? omc : (T)2;
-}
-
-constexpr int NB_T = 256;
-constexpr int NB_CHUNK = 8 * NB_T;   // slots whose pairs are gathered before any is processed
-
-// One workgroup gathers the lower slots of the pairs in a chunk of NB_CHUNK
-// slots into LDS (one LDS atomic per wave and load), then every thread takes
-// pairs from that list, so no lane idles on an upper slot.
-template <typename R>
-__global__ __launch_bounds__(NB_T) void k_nanbu(NanbuArgs a)
-{
-#pragma clang fp contract(off)
-    __shared__ uint32_t s_a[NB_CHUNK], s_b[NB_CHUNK];
-    __shared__ uint32_t s_cnt;
-    R *vx = (R *)a.v;
-    R *vy = vx + a.n;
-    R *vz = vy + a.n;
-    const double PI = 3.14159265358979323846;
-    const int lane = threadIdx.x & (PIC_WAVE - 1);
-    for (int64_t base = blockIdx.x * (int64_t)NB_CHUNK; base < a.n; base += (int64_t)gridDim.x * NB_CHUNK) {
-        if (threadIdx.x == 0) s_cnt = 0u;
-        __syncthreads();
-        int32_t pb[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int64_t l = base + u * NB_T + threadIdx.x;
-            pb[u] = l < a.n ? a.partner[l] : -1;
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int64_t l = base + u * NB_T + threadIdx.x;
-            const bool lower = pb[u] > l;
-            const uint64_t m = __ballot(lower);
-            if (!m) continue;
-            const int leader = __ffsll((unsigned long long)m) - 1;
-            uint32_t at = 0u;
-            if (lane == leader) at = atomicAdd(&s_cnt, (uint32_t)__popcll(m));
-            at = __shfl(at, leader, PIC_WAVE) + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-            if (lower) {
-                s_a[at] = (uint32_t)l;
-                s_b[at] = (uint32_t)pb[u];
-            }
-        }
-        __syncthreads();
-        const uint32_t cnt = s_cnt;
-        for (uint32_t i = threadIdx.x; i < cnt; i += NB_T) {
-            const int64_t l = s_a[i], b = s_b[i];
-            // both members' velocities held in registers: the stores below need
-            // no reloads (the compiler cannot tell that slots l and b differ)
-            const R ax = vx[l], ay = vy[l], az = vz[l], bx = vx[b], by = vy[b], bz = vz[b];
-            const R ux = ax - bx, uy = ay - by, uz = az - bz;
-            const R uu = ux * ux + uy * uy + uz * uz;
-            if (uu == (R)0) continue;
-            const R um = sqrt(uu), uperp = sqrt(ux * ux + uy * uy);
-            double dens = 1.0;
-            if (a.density) {   // the cell holding slot l: last j with cs[j] <= l
-                int32_t lo = 0, hi = a.M;
-                while (hi - lo > 1) {
-                    const int32_t mid = (lo + hi) >> 1;
-                    if ((int64_t)a.cs[mid] <= l) lo = mid;
-                    else hi = mid;
-                }
-                dens = a.density[lo];
-            }
-            const R s = (R)2 * nb_div((R)(8.0 * PI * dens * a.lnL * a.dt), um * um * um);
-            const W4 wa = draw4(a.seed, a.pid[l], a.step, 0u, 0u);
-            const W4 wb = draw4(a.seed, a.pid[b], a.step, 0u, 0u);
-            const R U = sizeof(R) == 4 ? (R)u01f(wa.z) : (R)u01d(wa.z);
-            const R omc = nb_omc(nb_A(s), U);
-            const R sin_t = sqrt(omc * ((R)2 - omc));
-            const R phi = (R)(2.0 * PI) * (sizeof(R) == 4 ? (R)u01f(wb.z) : (R)u01d(wb.z));
-            const R cphi = cos(phi), sphi = sin(phi);
-            R dx, dy, dz;
-            if (uperp > (R)0) {
-                const R ex = nb_div(ux, uperp), ey = nb_div(uy, uperp);
-                dx = ex * uz * sin_t * cphi - ey * um * sin_t * sphi - ux * omc;
-                dy = ey * uz * sin_t * cphi + ex * um * sin_t * sphi - uy * omc;
-                dz = -uperp * sin_t * cphi - uz * omc;
-            } else {
-                dx = um * sin_t * cphi;
-                dy = um * sin_t * sphi;
-                dz = -uz * omc;
-            }
-            const R hx = (R)0.5 * dx, hy = (R)0.5 * dy, hz = (R)0.5 * dz;
-            vx[l] = ax + hx;
-            vy[l] = ay + hy;
-            vz[l] = az + hz;
-            vx[b] = bx - hx;
-            vy[b] = by - hy;
-            vz[b] = bz - hz;
-        }
-        __syncthreads();   // s_cnt and the lists are reused by the next chunk
-    }
-}
-
 // ------------------------------------------------------------ exact count
 // The k smallest candidate words.  The words are uniform, so the k-th lies
 // within a few binomial standard deviations of k 2^32 / n: one pass draws
@@ -1086,14 +923,3 @@ int launch_recombine(int dtype, const RecombArgs &a, int num_cu, hipStream_t st)
     return PIC_OK;
 }
 
-int launch_nanbu(int dtype, const NanbuArgs &a, hipStream_t st)
-{
-    if (a.n <= 0) return PIC_OK;
-    const int g = grid_for(a.n, NB_CHUNK, 4096);
-    if (dtype == PIC_F32)
-        hipLaunchKernelGGL(k_nanbu<float>, dim3(g), dim3(NB_T), 0, st, a);
-    else
-        hipLaunchKernelGGL(k_nanbu<double>, dim3(g), dim3(NB_T), 0, st, a);
-    HIP_OK(hipGetLastError());
-    return PIC_OK;
-}
