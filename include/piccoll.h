@@ -50,7 +50,8 @@ typedef enum {
     PIC_ERR_HIP = 3,    /* a HIP runtime call failed */
     PIC_ERR_NOMEM = 4,  /* scratch memory could not be allocated */
     PIC_ERR_DTYPE = 5,  /* unknown pic_dtype */
-    PIC_ERR_STATE = 6   /* call not valid in the context's current state */
+    PIC_ERR_STATE = 6,  /* call not valid in the context's current state */
+    PIC_ERR_NONFINITE = 7 /* a velocity was not finite after a step with PIC_CHECK_FINITE */
 } pic_status;
 
 typedef enum { PIC_F32 = 0, PIC_F64 = 1 } pic_dtype;
@@ -68,8 +69,11 @@ enum {
                                     order: the re-binning kernels are not
                                     launched; the check still runs and a
                                     violation is reported as PIC_ERR_STATE */
-    PIC_MOMENTS = 1u << 4        /* write the 14 per-cell FP64 moment sums of the
+    PIC_MOMENTS = 1u << 4,       /* write the 14 per-cell FP64 moment sums of the
                                     post-step state to the pic_set_moments_out buffer */
+    PIC_CHECK_FINITE = 1u << 5   /* debug: after the step, one read of the velocities;
+                                    any NaN or infinity is reported by pic_sync as
+                                    PIC_ERR_NONFINITE */
 };
 
 /* Create a context on HIP device `device`, issuing work on `hip_stream`
@@ -80,10 +84,14 @@ void pic_destroy(pic_ctx *ctx);
 /* Static string describing a pic_status. */
 const char *pic_strerror(int status);
 /* Waits for the context's stream, then returns (and clears) any latched
- * device error: PIC_ERR_RANGE, PIC_ERR_STATE, or PIC_OK. */
+ * device error: PIC_ERR_RANGE, PIC_ERR_STATE, PIC_ERR_NONFINITE, or PIC_OK. */
 int pic_sync(pic_ctx *ctx);
 /* Changes the stream subsequent calls are issued on. */
 int pic_set_stream(pic_ctx *ctx, void *hip_stream);
+/* Caps the scratch memory the context may hold at `bytes` (0: no cap, the
+ * default).  A call whose scratch would exceed it returns PIC_ERR_NOMEM before
+ * anything runs and leaves its arrays unchanged. */
+int pic_set_workspace_limit(pic_ctx *ctx, size_t bytes);
 
 /* Binning, CCS1-CCS3 of the Coulombic collision steps.
  * cell_of[n] in [0, n_cells).  Writes cell_start[n_cells+1] (exclusive prefix

@@ -47,6 +47,7 @@ struct pic_ctx {
     DevFlags *flags = nullptr;
     void *ws = nullptr;
     size_t ws_cap = 0;
+    size_t ws_limit = 0;   // most scratch bytes the context may hold (0: no limit)
     double mcc_sigma0 = 0.0, mcc_nn = 0.0, mcc_mr = 0.0;
     // DSMC-Coll cross-section table (device copy) and its host header
     double *dsmc_buf = nullptr;
@@ -154,6 +155,7 @@ struct Bump {
 int ensure_ws(pic_ctx *c, size_t bytes)
 {
     if (bytes <= c->ws_cap) return PIC_OK;
+    if (c->ws_limit && bytes > c->ws_limit) return PIC_ERR_NOMEM;   // beyond the caller's budget
     CK(hipSetDevice(c->device));
     CK(hipStreamSynchronize(c->stream));
     if (c->ws) {
@@ -161,7 +163,8 @@ int ensure_ws(pic_ctx *c, size_t bytes)
         c->ws = nullptr;
         c->ws_cap = 0;
     }
-    const size_t want = bytes + bytes / 8;
+    size_t want = bytes + bytes / 8;
+    if (c->ws_limit && want > c->ws_limit) want = c->ws_limit;
     if (hipMalloc(&c->ws, want) != hipSuccess) {
         (void)hipGetLastError();
         c->ws = nullptr;
@@ -297,6 +300,7 @@ const char *pic_strerror(int s)
     case PIC_OK: return "ok";
     case PIC_ERR_ARG: return "invalid argument";
     case PIC_ERR_RANGE: return "cell id out of range";
+    case PIC_ERR_NONFINITE: return "non-finite velocity after the step";
     case PIC_ERR_HIP: return "HIP runtime error";
     case PIC_ERR_NOMEM: return "out of device memory";
     case PIC_ERR_DTYPE: return "unknown dtype";
@@ -379,14 +383,15 @@ int pic_sync(pic_ctx *c)
     if (!c) return PIC_ERR_ARG;
     CK(hipSetDevice(c->device));
     CK(hipStreamSynchronize(c->stream));
-    int host[4] = {0, 0, 0, 0};
+    int host[5] = {0, 0, 0, 0, 0};
     CK(hipMemcpy(host, c->flags, sizeof(host), hipMemcpyDeviceToHost));
-    if (host[2] || host[3]) {
-        const int zero[2] = {0, 0};
+    if (host[2] || host[3] || host[4]) {
+        const int zero[3] = {0, 0, 0};
         CK(hipMemcpy(&c->flags->sticky_range, zero, sizeof(zero), hipMemcpyHostToDevice));
     }
     if (host[2]) return PIC_ERR_RANGE;
     if (host[3]) return PIC_ERR_STATE;
+    if (host[4]) return PIC_ERR_NONFINITE;
     return PIC_OK;
 }
 
@@ -929,6 +934,7 @@ static int step_enqueue(pic_ctx *c, const StepArgs &s, hipStream_t st, const uin
         }
     }
     RC(launch_collide(dtype, a, lists, n_cells, caps, 0, c->num_cu, st, seg_path, s.live));
+    if (s.flags & PIC_CHECK_FINITE) RC(launch_check_finite(dtype, s.v, n, c->flags, st));
     if (gate) {
         // the sums the next decision reads: post-step state, on refresh steps
         ktime_begin(KT_MOMENTS, st);
@@ -1366,6 +1372,13 @@ static std::vector<ClassCaps> tune_candidates(const ClassCaps &b)
     c.cap[0] = b.cap[0] / 2;                  // ... fewer cells on the wave schedule
     add(c);
     return v;
+}
+
+int pic_set_workspace_limit(pic_ctx *c, size_t bytes)
+{
+    if (!c) return PIC_ERR_ARG;
+    c->ws_limit = bytes;
+    return PIC_OK;
 }
 
 int pic_set_schedule(pic_ctx *c, int dtype, int schedule)

@@ -37,6 +37,18 @@ __global__ void k_reset_flags(DevFlags *f)
     }
 }
 
+// Any non-finite component of v latches PIC_ERR_NONFINITE (a debug check:
+// one streaming read of the velocities).
+template <typename R>
+__global__ void k_check_finite(const R *__restrict__ v, int64_t m, DevFlags *f)
+{
+    bool bad = false;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
+         i += (int64_t)gridDim.x * blockDim.x)
+        bad |= !isfinite(v[i]);
+    if (__ballot(bad) && (threadIdx.x & (PIC_WAVE - 1)) == 0) atomicOr(&f->sticky_nonfinite, 1);
+}
+
 // Latches PIC_ERR_STATE when work list `list` holds any cell.
 __global__ void k_reject_list(DevFlags *f, int list)
 {
@@ -495,6 +507,18 @@ int grid_for(int64_t n, int threads, int cap)
 int launch_reset_flags(DevFlags *flags, hipStream_t st)
 {
     hipLaunchKernelGGL(k_reset_flags, dim3(1), dim3(64), 0, st, flags);
+    HIP_OK(hipGetLastError());
+    return PIC_OK;
+}
+
+int launch_check_finite(int dtype, const void *v, int64_t n, DevFlags *flags, hipStream_t st)
+{
+    if (n <= 0) return PIC_OK;
+    const int g = grid_for(3 * n, 256, 4096);
+    if (dtype == PIC_F32)
+        hipLaunchKernelGGL(k_check_finite<float>, dim3(g), dim3(256), 0, st, (const float *)v, 3 * n, flags);
+    else
+        hipLaunchKernelGGL(k_check_finite<double>, dim3(g), dim3(256), 0, st, (const double *)v, 3 * n, flags);
     HIP_OK(hipGetLastError());
     return PIC_OK;
 }

@@ -19,11 +19,12 @@ struct DevFlags {
     int range_err;       // a cell id outside [0, n_cells) in this call
     int sticky_range;    // latched PIC_ERR_RANGE
     int sticky_state;    // latched PIC_ERR_STATE
+    int sticky_nonfinite;  // latched PIC_ERR_NONFINITE
     unsigned int head[8];   // work-queue heads of the persistent kernels
     unsigned int count[8];  // work-queue lengths (cells per class)
     unsigned int huge_total; // members of cells in the multi-block class
     unsigned int seg_fallback; // some cell of that class takes the one-workgroup path
-    unsigned int pad[6];
+    unsigned int pad[5];
 };
 
 // ---------------------------------------------------------------------------
@@ -729,6 +730,8 @@ int radix_pass(const RadixPass &p, const BinScratch &s, hipStream_t st);
 int launch_bin_check(const int32_t *cell_of, int64_t n, int32_t n_cells, int32_t *cell_start,
                      DevFlags *flags, int set_unsorted, const int *gate, hipStream_t st);
 int launch_reset_flags(DevFlags *flags, hipStream_t st);
+// Latches sticky_nonfinite when any of the 3 n velocities is not finite.
+int launch_check_finite(int dtype, const void *v, int64_t n, DevFlags *flags, hipStream_t st);
 // Latches sticky_state when work list `list` is not empty.
 int launch_reject_list(DevFlags *flags, int list, hipStream_t st);
 int launch_set_step(uint64_t *step_dev, uint64_t value, hipStream_t st);

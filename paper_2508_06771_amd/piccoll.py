@@ -23,14 +23,15 @@ FUSE_MCC = 1 << 1
 GATE = 1 << 2
 ASSUME_SORTED = 1 << 3
 MOMENTS = 1 << 4
-PIC_ERR_ARG, PIC_ERR_RANGE, PIC_ERR_STATE = 1, 2, 6
+CHECK_FINITE = 1 << 5
+PIC_ERR_ARG, PIC_ERR_RANGE, PIC_ERR_NOMEM, PIC_ERR_STATE, PIC_ERR_NONFINITE = 1, 2, 4, 6, 7
 # limits of coulomb_collide_noalloc (its fixed scratch and the LDS classes)
 NOALLOC_MAX_CELLS = 65536
 NOALLOC_MAX_CELL_F32 = 10240
 NOALLOC_MAX_CELL_F64 = 6144
 
 _STATUS = {0: "PIC_OK", 1: "PIC_ERR_ARG", 2: "PIC_ERR_RANGE", 3: "PIC_ERR_HIP",
-           4: "PIC_ERR_NOMEM", 5: "PIC_ERR_DTYPE", 6: "PIC_ERR_STATE"}
+           4: "PIC_ERR_NOMEM", 5: "PIC_ERR_DTYPE", 6: "PIC_ERR_STATE", 7: "PIC_ERR_NONFINITE"}
 
 
 class PicError(RuntimeError):
@@ -95,6 +96,7 @@ def _load():
                           vp, vp, i64, vp, vp], C.c_int),
         "pic_autotune": ([vp, C.c_int, vp, vp, vp, i64, i32, f64, f64, u32, vp], C.c_int),
         "pic_set_schedule": ([vp, C.c_int, C.c_int], C.c_int),
+        "pic_set_workspace_limit": ([vp, C.c_size_t], C.c_int),
         "pic_time_kernels": ([vp, C.c_int], C.c_int),
         "pic_kernel_times": ([vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)], C.c_int),
     }
@@ -115,7 +117,8 @@ EXPORTED = ["pic_create", "pic_destroy", "pic_strerror", "pic_sync", "pic_set_st
             "pic_gate_config", "pic_gate_reset", "pic_gate_stats", "pic_gate_state", "pic_autotune",
             "pic_conserve_reset", "pic_gate_refresh", "gate_infer", "pic_set_dsmc", "dsmc_collide",
             "mcc_null_collide_exact", "p2c_sums", "recombine", "coulomb_collide_nanbu",
-            "coulomb_collide_triplet", "coulomb_collide_noalloc", "coulomb_collide_weighted", "pic_set_schedule"]
+            "coulomb_collide_triplet", "coulomb_collide_noalloc", "coulomb_collide_weighted", "pic_set_schedule",
+            "pic_set_workspace_limit"]
 
 MLP_PARAMS = 4801
 GATE_STATS = ["steps", "skipped", "collided", "judged", "judged_want", "false_skip", "disabled",
@@ -226,6 +229,10 @@ class Context:
         _chk(lib.coulomb_collide_noalloc(self._h, _dt(v), _p(v), _p(cell_of), _p(pid), v.shape[1],
                                          n_cells, dt, lnL, _p(density), seed, step, flags),
              "coulomb_collide_noalloc")
+
+    def set_workspace_limit(self, nbytes: int):
+        """Cap on the context's scratch memory (0: none)."""
+        _chk(lib.pic_set_workspace_limit(self._h, nbytes), "pic_set_workspace_limit")
 
     def set_schedule(self, dtype, schedule: int):
         """0: one launch per size class; 1: one persistent launch, smallest

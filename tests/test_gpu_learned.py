@@ -81,6 +81,20 @@ def rand_params(seed, scale=0.4):
     return physics.pack_params([rng.standard_normal(s) * scale for s in physics.mlp_init_shapes()])
 
 
+GRAD_TENSORS = ("W1", "b1", "W2", "b2", "W3", "b3")
+
+
+def assert_grad_elementwise(g, gr, rtol, atol_frac):
+    """Every entry of every parameter tensor: |g - g_ref| <= rtol |g_ref| +
+    atol_frac max |g_ref| over that tensor (so a small tensor such as the
+    output bias is held to its own scale, not the whole vector's)."""
+    for name, a, b in zip(GRAD_TENSORS, physics.unpack_params(np.asarray(g, np.float64)),
+                          physics.unpack_params(np.asarray(gr, np.float64))):
+        bound = rtol * np.abs(b) + atol_frac * np.max(np.abs(b))
+        worst = np.max(np.abs(a - b) / np.maximum(bound, 1e-300))
+        assert worst <= 1.0, (name, worst)
+
+
 def test_mlp_forward_and_grad(ctx):
     import torch
     rng = np.random.default_rng(0)
@@ -101,6 +115,7 @@ def test_mlp_forward_and_grad(ctx):
     lr, gr = physics.mlp_bce_grad(physics.unpack_params(p32), x32, y)
     gr = physics.pack_params(gr)
     assert np.linalg.norm(host(g) - gr) / np.linalg.norm(gr) < 1e-5
+    assert_grad_elementwise(host(g), gr, rtol=1e-4, atol_frac=1e-5)
     assert abs(float(host(loss)[0]) - lr) < 1e-5 * abs(lr)
     # bfloat16 mode vs the oracle's bfloat16-rounded FP64 backprop
     prob16 = host(ctx.mlp_forward(tp, tx, bf16=True))
@@ -109,6 +124,7 @@ def test_mlp_forward_and_grad(ctx):
     l16, gr16, pr16 = physics.mlp_bce_grad_bf16(p32, x32, y)
     assert np.max(np.abs(prob16 - pr16)) < 1e-2
     assert np.linalg.norm(host(g16) - gr16) / np.linalg.norm(gr16) < 1e-2
+    assert_grad_elementwise(host(g16), gr16, rtol=3e-2, atol_frac=1e-2)
     assert abs(float(host(loss16)[0]) - l16) < 1e-2 * abs(l16)
 
 

@@ -104,6 +104,54 @@ def test_initial_relaxation_default_dt_matches_exact_expectation(orc):
     assert 0.92 < exact / ode < 0.98
 
 
+def exact_change_from_state(v, cell_start, dt, lnL=10.0, n=1.0):
+    """Exact expectation of the one-step change of T_par from the given state:
+    a pair (a, b) of a cell is drawn with probability floor(N/2) / C(N, 2) and
+    changes sum v_z^2 by 1/4 h(s2) (|u|^2 - 3 u_z^2) on average, so the sum over
+    all pairs of every cell (h by quadrature) divided by the particle count."""
+    grid = np.logspace(-10, 12, 500)
+    lg = np.log(grid)
+    lhg = np.log(np.array([physics.h_angle(float(x)) for x in grid]))
+    tot = 0.0
+    for j in range(cell_start.size - 1):
+        vv = v[:, cell_start[j]:cell_start[j + 1]]
+        m = vv.shape[1]
+        if m < 2:
+            continue
+        iu = np.triu_indices(m, 1)
+        u = [(vv[c][:, None] - vv[c][None, :])[iu] for c in range(3)]
+        uu = u[0] ** 2 + u[1] ** 2 + u[2] ** 2
+        h = np.exp(np.interp(np.log(8 * math.pi * n * lnL * dt / uu ** 1.5), lg, lhg))
+        tot += (m // 2) / (m * (m - 1) / 2) * np.sum(h / 4 * (uu - 3 * u[2] ** 2))
+    return tot / v.shape[1]
+
+
+def test_relaxation_at_step_100_matches_exact_expectation_from_state(orc):
+    """After 100 steps of the bi-Maxwellian (dt = 0.01 tau_e, 256k electrons)
+    the mean one-step change of T_par over 128 independent re-pairings of that
+    state equals the exact expectation computed from the state itself (all
+    pairs of every cell) within 4 standard errors; the expectation a
+    bi-Maxwellian of the same temperatures would have is 5-20% larger, which
+    is the closure effect that keeps the late anisotropy above the rate ODE."""
+    w = workloads.c1(0, n_cells=1000)
+    v, cell, pid = w.v.copy(), w.cell_of.copy(), w.pid.copy()
+    for k in range(100):
+        orc.step(v, cell, pid, w.n_cells, dt=w.dt, lnL=w.lnL, seed=0, step=k)
+    tpa, tpe = measured_temperatures(v)
+    cs = np.searchsorted(cell, np.arange(w.n_cells + 1))
+    exact = exact_change_from_state(v, cs, w.dt, w.lnL)
+    meas = []
+    for r in range(128):
+        a, c, p = v.copy(), cell.copy(), pid.copy()
+        orc.step(a, c, p, w.n_cells, dt=w.dt, lnL=w.lnL, seed=1000 + r, step=100)
+        meas.append(measured_temperatures(a)[0] - tpa)
+    meas = np.array(meas)
+    se = meas.std() / np.sqrt(meas.size)
+    assert abs(meas.mean() - exact) < 4 * se, (meas.mean(), exact, se)
+    bimax = one_step_change_exact(tpa, tpe, w.dt)
+    assert 0.80 < exact / bimax < 0.95, (exact, bimax)
+
+
 @pytest.mark.slow
 def test_c1_isotropisation_trajectory(orc):
     """c1 (64 x 256, 100 steps, 8 seeds): T_par / T_perp relaxes like the rate
