@@ -205,15 +205,25 @@ def bench_c3(args):
 
 def bench_c4(args):
     """Precision study: 32,768 cells x 3,052 electrons (100M), c1's
-    bi-Maxwellian; binary32, binary32 + FP64 conservation correction, binary64.
-    Energy drift and the isotropisation T_par/T_perp after the timed steps;
-    64 sampled cells re-run by the FP64 oracle from the same initial state."""
+    bi-Maxwellian, --c4-steps steps (10,000) in binary32, binary32 + FP64
+    conservation correction and binary64.  Every --c4-every steps (100): the
+    energy drift |E(m) - E(0)| / E(0), T_par / T_perp over all electrons
+    against the bi-Maxwellian relaxation ODE, and the largest relative error
+    of 64 sampled cells against the FP64 oracle, which runs the same steps on
+    those cells alone (the operator is cell-local and the draws are keyed by
+    particle id and step, so a subset reproduces exactly) in a host thread
+    beside the GPU runs."""
+    import threading
+
     import numpy as np
     import torch
 
     import oracle
     from oracle import physics
     from paper_2508_06771_amd import piccoll, workloads
+    S, E = args.c4_steps, args.c4_every
+    if S < E or S % E:
+        raise SystemExit("--c4-steps must be a positive multiple of --c4-every")
     w = workloads.c4(0, dtype=np.float64)
     n = w.n
     rng = np.random.default_rng(0)
@@ -223,43 +233,102 @@ def bench_c4(args):
     remap[sample] = np.arange(64, dtype=np.int32)
     ov = np.ascontiguousarray(w.v[:, sel])
     oc, op = remap[w.cell_of[sel]].copy(), w.pid[sel].copy()
-    S = args.steps
-    for k in range(S + 1):
-        oracle.step(ov, oc, op, 64, dt=w.dt, lnL=w.lnL, seed=0, step=k)
+    ockpt = {}
+    t_oracle = [0.0]
+
+    def run_oracle():
+        t0 = time.perf_counter()
+        for k in range(S):
+            oracle.step(ov, oc, op, 64, dt=w.dt, lnL=w.lnL, seed=0, step=k)
+            if (k + 1) % E == 0:
+                o = np.argsort(op)
+                ockpt[k + 1] = ov[:, o].copy()
+        t_oracle[0] = time.perf_counter() - t0
+
+    th = threading.Thread(target=run_oracle, daemon=True)
+    th.start()
+    c0 = w.v - w.v.mean(axis=1, keepdims=True)
+    tpa0, tpe0 = float((c0[2] ** 2).mean()), float(0.5 * ((c0[0] ** 2).mean() + (c0[1] ** 2).mean()))
+    ode_pa, ode_pe = physics.isotropisation_rk4(tpa0, tpe0, w.dt, S, lnL=w.lnL)
     ctx = piccoll.Context(0)
-    results = {}
+    sample_t = torch.from_numpy(sample.astype(np.int32)).cuda()
+    results, samples = {}, {}
     for name, dt_, fl in (("f32", torch.float32, 0), ("f32_fix", torch.float32, piccoll.CONSERVE_FIX),
                           ("f64", torch.float64, 0)):
         v = torch.from_numpy(w.v).to(dt_).cuda()
         cell = torch.from_numpy(w.cell_of).cuda()
         pid = torch.from_numpy(w.pid.view(np.int32)).cuda()
         ctx.conserve_reset()
-        ctx.coulomb_collide(v, cell, pid, w.n_cells, dt=w.dt, lnL=w.lnL, seed=0, step=0, flags=fl)
-        ctx.sync()
         E0 = energy(v)
-        t0 = temperatures(torch, v)
-        ms = _timed(torch, lambda: ctx.run_steps(v, cell, pid, w.n_cells, dt=w.dt, lnL=w.lnL, seed=0,
-                                                 step0=1, nsteps=S,
-                                                 flags=fl | piccoll.ASSUME_SORTED)) / S
-        ctx.sync()
-        E1 = energy(v)
-        t1 = temperatures(torch, v)
-        opa, ope = physics.isotropisation_rk4(t0[0], t0[1], w.dt, S)
-        gsel = torch.from_numpy(np.isin(cell.cpu().numpy(), sample)).cuda()
-        gv = v[:, gsel].double().cpu().numpy()
-        err = float(np.max(np.max(np.abs(gv - ov), axis=0) /
-                           np.maximum(np.linalg.norm(ov, axis=0), 1e-3)))
+        drift, ratio, snaps = [], [], {}
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        timed_ms, timed_steps = 0.0, 0
+        for c in range(S // E):
+            ev0.record()
+            ctx.run_steps(v, cell, pid, w.n_cells, dt=w.dt, lnL=w.lnL, seed=0, step0=c * E,
+                          nsteps=E, flags=fl | (piccoll.ASSUME_SORTED if c else 0))
+            ev1.record()
+            ctx.sync()
+            if c:
+                timed_ms += ev0.elapsed_time(ev1)
+                timed_steps += E
+            drift.append(abs(energy(v) - E0) / E0)
+            tz, tp = temperatures(torch, v)
+            ratio.append(tz / tp)
+            gmask = torch.isin(cell, sample_t)      # storage order changes at the first re-bin
+            gp = pid[gmask].cpu().numpy().view(np.uint32)
+            o = np.argsort(gp)
+            snaps[(c + 1) * E] = v[:, gmask].double().cpu().numpy()[:, o]
+            if ((c + 1) * E) % max(E, S // 10) == 0:
+                print(f"c4 {name}: {(c + 1) * E} of {S} steps, drift {drift[-1]:.3e}, "
+                      f"T_par/T_perp {ratio[-1]:.4f}", file=sys.stderr, flush=True)
+        ms = timed_ms / max(1, timed_steps)
         results[name] = {"ms_per_step": ms, "updates_per_s": n / (ms * 1e-3),
-                         "energy_drift": abs(E1 - E0) / E0,
-                         "tpar_over_tperp": t1[0] / t1[1], "ode_tpar_over_tperp": opa[-1] / ope[-1],
-                         "sampled_cells_max_rel_err_vs_oracle": err}
+                         "energy_drift_every": drift, "tpar_over_tperp_every": ratio,
+                         "energy_drift_final": drift[-1], "energy_drift_max": max(drift)}
+        samples[name] = snaps
         del v, cell, pid
         torch.cuda.empty_cache()
     ctx.close()
+    print("c4: waiting for the oracle on the sampled cells", file=sys.stderr, flush=True)
+    th.join()
+    ode_ratio = [float(ode_pa[m] / ode_pe[m]) for m in range(E, S + 1, E)]
+    # per sampled cell (pid order; the initial storage index is the pid)
+    cl = remap[w.cell_of[np.sort(w.pid[sel])]]
+
+    def cell_sums(x):
+        e = np.bincount(cl, weights=(x * x).sum(axis=0), minlength=64)
+        p = np.stack([np.bincount(cl, weights=x[d], minlength=64) for d in range(3)])
+        return e, p
+
+    def ratio(x):
+        c = x - x.mean(axis=1, keepdims=True)
+        return float((c[2] ** 2).mean() / (0.5 * ((c[0] ** 2).mean() + (c[1] ** 2).mean())))
+
+    for name, snaps in samples.items():
+        errs, de, dp, rg, ro = [], [], [], [], []
+        for m in range(E, S + 1, E):
+            ref = ockpt[m]
+            errs.append(float(np.max(np.max(np.abs(snaps[m] - ref), axis=0) /
+                                     np.maximum(np.linalg.norm(ref, axis=0), 1e-3))))
+            eg, pg = cell_sums(snaps[m])
+            eo, po = cell_sums(ref)
+            de.append(float(np.max(np.abs(eg - eo) / eo)))
+            dp.append(float(np.max(np.abs(pg - po) / np.sqrt(eo))))
+            rg.append(ratio(snaps[m]))
+            ro.append(ratio(ref))
+        results[name]["sampled_cells_max_rel_err_every"] = errs
+        results[name]["sampled_cells_max_rel_err_final"] = errs[-1]
+        results[name]["sampled_cells_energy_rel_diff_every"] = de
+        results[name]["sampled_cells_momentum_diff_every"] = dp
+        results[name]["sampled_tpar_over_tperp_every"] = rg
+        results[name]["oracle_sampled_tpar_over_tperp_every"] = ro
     r = results["f32_fix"]
     return _line(r["updates_per_s"], r["ms_per_step"], args, "f32",
                  {"workload": f"32768 cells x 3052 electrons ({n}), bi-Maxwellian T_par = 2 T_perp, "
-                              f"{S} steps per variant, graph replays", "n_electrons": n},
+                              f"{S} steps per precision, graph replays of {E} steps", "n_electrons": n},
+                 every=E, steps_per_variant=S, ode_tpar_over_tperp_every=ode_ratio,
+                 oracle_sampled_cells=64, oracle_seconds=round(t_oracle[0], 1),
                  precision=results)
 
 
@@ -273,13 +342,63 @@ def _cell_ratio(ctx, torch, v, cell, n_cells):
     return T[:, 2] / (0.5 * (T[:, 0] + T[:, 1]))
 
 
+def _c5_calibrate(args, ctx, params, tol):
+    """Thresholds of the learned and the analytic gate on a held-out workload
+    of the same recipe (seed 1; the measured run uses seed 0): a plain run of
+    --c5-cal-steps steps, and every --c5-cal-every steps each cell's label
+    (pic_relaxation with the judge's re-pairings), network probability and
+    analytic estimate.  Each threshold is the loosest whose skipped cells hold
+    at most --c5-max-false cells with a label at or above the tolerance."""
+    import numpy as np
+    import torch
+
+    from paper_2508_06771_amd import gate, piccoll, workloads
+    w = workloads.c5(1)
+    K = args.gate_replicas
+    v = torch.from_numpy(w.v).cuda()
+    cell = torch.from_numpy(w.cell_of).cuda()
+    pid = torch.from_numpy(w.pid.view(np.int32)).cuda()
+    mom = torch.zeros((w.n_cells, 14), dtype=torch.float64, device="cuda")
+    ctx.set_moments_out(mom)
+    ps, qs, rs = [], [], []
+    for k in range(args.c5_cal_steps):
+        ctx.coulomb_collide(v, cell, pid, w.n_cells, dt=w.dt, lnL=w.lnL, seed=1, step=k,
+                            flags=piccoll.MOMENTS | (piccoll.ASSUME_SORTED if k else 0))
+        if (k + 1) % args.c5_cal_every == 0:
+            cs, _ = ctx.bin_cells(cell, w.n_cells)
+            feat, valid = ctx.features(mom)
+            keep = valid.bool()
+            ps.append(ctx.mlp_forward(params, feat, bf16=True)[keep].clone())
+            qs.append((ctx.analytic_relaxation(mom, dt=w.dt, lnL=w.lnL, replicas=K) / tol)[keep].clone())
+            rs.append(ctx.relaxation(v, cs, pid, dt=w.dt, lnL=w.lnL, seed=1, step=k + 1,
+                                     replicas=K)[keep].clone())
+    ctx.set_moments_out(None)
+    ctx.sync()
+    p, q, r = torch.cat(ps), torch.cat(qs), torch.cat(rs)
+    thr = gate.tune_threshold(p, r, tol, args.c5_max_false)
+    thr_a = -gate.tune_threshold(-q, r, tol, args.c5_max_false)
+    bad = (r >= tol).cpu().numpy()
+    pn, qn = p.cpu().numpy(), q.cpu().numpy()
+    out = {"samples": int(r.numel()), "label_at_or_above_tol": float(bad.mean()),
+           "learned": {"threshold": thr, "skip_fraction": float((pn > thr).mean()),
+                       "false_skip_fraction": float(bad[pn > thr].mean()) if (pn > thr).any() else 0.0},
+           "analytic": {"threshold": thr_a, "skip_fraction": float((qn < thr_a).mean()),
+                        "false_skip_fraction": float(bad[qn < thr_a].mean()) if (qn < thr_a).any() else 0.0}}
+    del v, cell, pid, mom
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_c5(args):
     """Learned sub-cycling on 65,536 cells x 2,000 electrons (131M, FP32): 70%
     near-Maxwellian cells, 15% Maxwellian + beam, 15% bi-Maxwellian with
-    anisotropy 1..4.  The same K steps from the same state with the plain
-    operator and with the gate (1% judged cells, at most 8 deferred steps);
-    speedup, judged false skips, energy drift and the per-cell T_par/T_perp
-    difference to the plain run."""
+    anisotropy 1..4.  Both gates' thresholds are first tuned on a held-out
+    workload of the same recipe (seed 1) to --c5-max-false judged-style false
+    skips; then the same K steps from the same state (seed 0) with the plain
+    operator, the learned gate and the analytic moment gate (1% judged cells
+    with --gate-replicas re-pairings, at most 8 deferred steps): speedup,
+    judged false skips, energy drift and the per-cell T_par/T_perp difference
+    to the plain run."""
     import numpy as np
     import torch
 
@@ -287,19 +406,26 @@ def bench_c5(args):
     path = args.gate_params or os.path.join(ROOT, "paper_2508_06771_amd", "gate_params.npy")
     params = torch.from_numpy(np.load(path)).cuda()
     meta = json.load(open(os.path.splitext(path)[0] + ".json"))
+    tol = meta["tolerance"]
+    ctx = piccoll.Context(0)
+    cal = _c5_calibrate(args, ctx, params, tol)
+    print(f"c5 calibration: {json.dumps(cal)}", file=sys.stderr, flush=True)
     w = workloads.c5(0)
     n = w.n
-    ctx = piccoll.Context(0)
     K = args.steps
     res = {}
-    for mode in ("plain", "gated"):
+    for mode in ("plain", "learned", "analytic"):
         v = torch.from_numpy(w.v).cuda()
         cell = torch.from_numpy(w.cell_of).cuda()
         pid = torch.from_numpy(w.pid.view(np.int32)).cuda()
         fl = 0
-        if mode == "gated":
-            ctx.gate_config(params, meta["threshold"], k_max=8, judge_fraction=0.01,
-                            tolerance=meta["tolerance"], replicas=args.gate_replicas, bf16=True)
+        if mode == "learned":
+            ctx.gate_config(params, cal["learned"]["threshold"], k_max=8, judge_fraction=0.01,
+                            tolerance=tol, replicas=args.gate_replicas, bf16=True)
+        elif mode == "analytic":
+            ctx.gate_config_analytic(cal["analytic"]["threshold"], k_max=8, judge_fraction=0.01,
+                                     tolerance=tol, replicas=args.gate_replicas)
+        if mode != "plain":
             ctx.gate_refresh(args.gate_refresh)
             ctx.gate_reset()
             fl = piccoll.GATE
@@ -315,6 +441,8 @@ def bench_c5(args):
         ctx.sync()
         res[mode] = {"ms_per_step": ms, "energy_drift": abs(energy(v) - E0) / E0,
                      "ratio_start": r0, "ratio_end": _cell_ratio(ctx, torch, v, cell, w.n_cells)}
+        if mode != "plain":
+            res[mode]["gate"] = ctx.gate_stats()
         # per-kernel times of a few more eager steps (after the measured state)
         ctx.time_kernels(True)
         ctx.kernel_times()
@@ -324,36 +452,42 @@ def bench_c5(args):
         ctx.sync()
         res[mode]["kernel_ms"] = {k: round(t / 5, 5) for k, (t, c) in ctx.kernel_times().items()}
         ctx.time_kernels(False)
-        if mode == "gated":
-            res[mode]["gate"] = ctx.gate_stats()
+        print(f"c5 {mode}: {ms:.4f} ms per step", file=sys.stderr, flush=True)
         del v, cell, pid
         torch.cuda.empty_cache()
     ctx.close()
     kind = w.meta["kind"]
-    dr = np.abs(res["gated"]["ratio_end"] - res["plain"]["ratio_end"])
     relax = np.abs(res["plain"]["ratio_start"] - res["plain"]["ratio_end"])
-    g = res["gated"]["gate"]
-    out_kind = {}
-    for k, name in enumerate(("near_maxwellian", "maxwellian_beam", "bi_maxwellian")):
-        sel = kind == k
-        out_kind[name] = {"mean_abs_ratio_diff_vs_plain": float(dr[sel].mean()),
-                          "mean_plain_relaxation_of_ratio": float(relax[sel].mean())}
-    speed = res["plain"]["ms_per_step"] / res["gated"]["ms_per_step"]
-    return _line(n / (res["gated"]["ms_per_step"] * 1e-3), res["gated"]["ms_per_step"], args,
+    gates = {}
+    for mode in ("learned", "analytic"):
+        g = res[mode]["gate"]
+        dr = np.abs(res[mode]["ratio_end"] - res["plain"]["ratio_end"])
+        by_kind = {}
+        for k, name in enumerate(("near_maxwellian", "maxwellian_beam", "bi_maxwellian")):
+            sel = kind == k
+            by_kind[name] = {"mean_abs_ratio_diff_vs_plain": float(dr[sel].mean()),
+                             "mean_plain_relaxation_of_ratio": float(relax[sel].mean())}
+        gates[mode] = {"threshold": cal[mode]["threshold"],
+                       "ms_per_step": res[mode]["ms_per_step"],
+                       "speedup_over_plain": res["plain"]["ms_per_step"] / res[mode]["ms_per_step"],
+                       "skipped_fraction": g["skipped"] / max(1, g["skipped"] + g["collided"]),
+                       "judged": g["judged"], "judged_want_skip": g["judged_want"],
+                       "judged_false_skips": g["false_skip"],
+                       "judged_false_skip_fraction": g["false_skip"] / max(1, g["judged_want"]),
+                       "switched_off": g["disabled"],
+                       "energy_drift": res[mode]["energy_drift"], "by_cell_kind": by_kind,
+                       "kernel_ms_per_step": res[mode]["kernel_ms"]}
+    L = gates["learned"]
+    return _line(n / (L["ms_per_step"] * 1e-3), L["ms_per_step"], args,
                  "f32", {"workload": f"65536 cells x 2000 electrons ({n}), mixed cells, FP32, "
-                                     f"Coulomb only, learned gate (threshold {meta['threshold']:.4f}, "
-                                     f"tolerance {meta['tolerance']}, 1% judged with "
-                                     f"{args.gate_replicas} re-pairings, k_max 8, moments every "
-                                     f"{args.gate_refresh} steps)",
+                                     f"Coulomb only, learned gate (threshold tuned on a held-out "
+                                     f"seed to {args.c5_max_false:.0%} false skips, tolerance {tol}, "
+                                     f"1% judged with {args.gate_replicas} re-pairings, k_max 8, "
+                                     f"moments every {args.gate_refresh} steps)",
                          "n_electrons": n},
-                 speedup_over_plain=speed, ms_plain=res["plain"]["ms_per_step"],
-                 skipped_fraction=g["skipped"] / max(1, g["skipped"] + g["collided"]),
-                 judged=g["judged"], judged_false_skips=g["false_skip"],
-                 judged_want_skip=g["judged_want"], gate_switched_off=g["disabled"],
-                 energy_drift_plain=res["plain"]["energy_drift"],
-                 energy_drift_gated=res["gated"]["energy_drift"], by_cell_kind=out_kind,
-                 kernel_ms_per_step_plain=res["plain"]["kernel_ms"],
-                 kernel_ms_per_step_gated=res["gated"]["kernel_ms"])
+                 speedup_over_plain=L["speedup_over_plain"], ms_plain=res["plain"]["ms_per_step"],
+                 energy_drift_plain=res["plain"]["energy_drift"], calibration=cal,
+                 gates=gates, kernel_ms_per_step_plain=res["plain"]["kernel_ms"])
 
 
 def bench_dsmc(args):
@@ -732,6 +866,13 @@ def main():
                          "exact-count null-collision selection; p2c: particle-to-cell sums; recombine: "
                          "recombination C5; nanbu: Nanbu's Coulomb operator; triplet: the odd-cell "
                          "triplet")
+    ap.add_argument("--c4-steps", type=int, default=10000, help="steps per precision (c4)")
+    ap.add_argument("--c4-every", type=int, default=100,
+                    help="steps between drift / relaxation / oracle checkpoints (c4)")
+    ap.add_argument("--c5-max-false", type=float, default=0.015,
+                    help="false-skip fraction the c5 gate thresholds are tuned to")
+    ap.add_argument("--c5-cal-steps", type=int, default=100, help="steps of the c5 calibration run")
+    ap.add_argument("--c5-cal-every", type=int, default=20, help="c5 calibration sampling interval")
     ap.add_argument("--kernel-steps", type=int, default=10,
                     help="extra eager steps after the timed region whose kernels are timed")
     ap.add_argument("--gate-params", default=None, help="trained gate parameters (.npy) for c5")

@@ -344,7 +344,7 @@ int pic_set_moments_out(pic_ctx *ctx, double *out);
  * with binary32 accumulation. */
 
 /* Features from per-cell raw sums (layout of pic_cell_moments), feat[8*j..]:
- * ln N, ln T, T_xx/T, T_yy/T, T_zz/T, ||offdiag T||_F/T, |q|/(N T^1.5),
+ * ln N, ln T, T_xx/T - 1, T_yy/T - 1, T_zz/T - 1, ||offdiag T||_F/T, |q|/(N T^1.5),
  * <|c|^4>/(15 T^2) - 1 with c = v - V, T_ab = <c_a c_b>, T = tr/3,
  * q = 1/2 sum |c|^2 c.  Cells with N < 2 or T <= 0: zeros, valid[j] = 0
  * (valid nullable). */
@@ -359,6 +359,21 @@ int pic_relaxation(pic_ctx *ctx, int dtype, const void *v, int64_t n, const int3
                    const uint32_t *pid, int32_t n_cells, double dt, double lnLambda,
                    const double *density, const double *dt_scale, uint64_t seed, uint64_t step,
                    int32_t replicas, double *r_out);
+
+/* Estimate of pic_relaxation's r_j from the moment sums alone (layout of
+ * pic_cell_moments; no pairing), the baseline gate the network is compared
+ * with: r^2 = r_aniso^2 + r_floor^2, r_aniso = 3 nu_0 dt ||A||_F for the
+ * traceless part A of the temperature tensor in units of T (linearised
+ * isotropisation, nu_0 = (8 sqrt(pi) / 15) n lnL / T^1.5), and
+ * r_floor^2 = (8 pi n lnL dt / T^1.5)^2 / N (a - b + (3/2 - a) / K), the
+ * small-angle spread of the pair sum of an isotropic Maxwellian cell over
+ * random pairings, a = 6 E[psi^2] = 0.1521598 (psi from the Maxwellian's
+ * Rosenbluth potential), b = 10 / (25 pi), K = replicas.  density per cell
+ * (device, nullable: 1).  r_out: device double[n_cells]; NaN for cells of
+ * fewer than 2 members or no temperature.  PIC_ERR_ARG for NULL arrays,
+ * n_cells < 1, dt <= 0, lnLambda <= 0 or replicas < 1. */
+int pic_analytic_relaxation(pic_ctx *ctx, const double *moments, int32_t n_cells, double dt,
+                            double lnLambda, const double *density, int32_t replicas, double *r_out);
 
 /* prob[b] = network output for x[8*b .. 8*b+7]. */
 int pic_mlp_forward(pic_ctx *ctx, const float *params, const float *x, int32_t batch, int bf16,
@@ -396,6 +411,14 @@ int gate_infer(pic_ctx *ctx, const float *feat, int32_t n_cells, const float *pa
  * PIC_MOMENTS the moment sums of every cell are written after the step. */
 int pic_gate_config(pic_ctx *ctx, const float *params, float threshold, int32_t k_max,
                     double judge_fraction, double tolerance, int32_t replicas, int bf16);
+/* The same gate with the analytic estimate of pic_analytic_relaxation in
+ * place of the network: a cell may skip when its estimate over the
+ * tolerance is below threshold (from the gate's refreshed moments, with the
+ * step's dt, lnLambda and densities and K = replicas).  Judge, switch-off,
+ * refresh and deferral as pic_gate_config, which it replaces (as that
+ * replaces it).  pic_gate_state's prob receives estimate / tolerance. */
+int pic_gate_config_analytic(pic_ctx *ctx, float threshold, int32_t k_max, double judge_fraction,
+                             double tolerance, int32_t replicas);
 /* Moment refresh interval of the gate: the 14 moment sums its features come
  * from are recomputed (a streaming pass over the post-step velocities) on
  * the first gated step and then on steps that are multiples of `every`

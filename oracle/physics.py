@@ -11,7 +11,8 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
 * Per-cell features (eight Galilean-invariant moments) computed directly
   from velocities with a two-pass central-moment definition.
 * The learned-gate label: the expected one-step change of a cell's
-  temperature tensor, averaged over independent re-pairings.
+  temperature tensor, averaged over independent re-pairings; and its
+  estimate from the moments alone (the analytic gate).
 * A dense FP64 reference of the 8-64-64-1 gate network: forward, binary
   cross-entropy, backward by the chain rule, and Adam.
 
@@ -112,7 +113,7 @@ def h_angle(s2: float) -> float:
 
 def cell_features(v: np.ndarray, cell_start: np.ndarray) -> np.ndarray:
     """Eight features per cell, from the cell's velocities (two passes):
-    ln N, ln T, T_xx/T, T_yy/T, T_zz/T, ||offdiag T||_F / T,
+    ln N, ln T, T_xx/T - 1, T_yy/T - 1, T_zz/T - 1, ||offdiag T||_F / T,
     |q| / (N T^1.5) with q = 1/2 sum |c|^2 c, <|c|^4> / (15 T^2) - 1,
     where c = v - mean(v), T_ab = <c_a c_b>, T = tr(T) / 3.
     Cells with fewer than 2 members or T <= 0 get NaN rows."""
@@ -131,7 +132,8 @@ def cell_features(v: np.ndarray, cell_start: np.ndarray) -> np.ndarray:
         off = math.sqrt(2.0 * (Tt[0, 1] ** 2 + Tt[0, 2] ** 2 + Tt[1, 2] ** 2))
         c2 = (c * c).sum(axis=0)
         q = 0.5 * (c2[None, :] * c).sum(axis=1)
-        out[j] = [math.log(N), math.log(T), Tt[0, 0] / T, Tt[1, 1] / T, Tt[2, 2] / T, off / T,
+        out[j] = [math.log(N), math.log(T), Tt[0, 0] / T - 1.0, Tt[1, 1] / T - 1.0, Tt[2, 2] / T - 1.0,
+                  off / T,
                   np.linalg.norm(q) / (N * T ** 1.5), (c2 * c2).mean() / (15.0 * T * T) - 1.0]
     return out
 
@@ -177,6 +179,71 @@ def relaxation(v, cell_start, pid, *, dt, lnL, seed, step, replicas, density=Non
         T = float((c * c).sum()) / (3 * N)
         r[j] = np.linalg.norm(acc[j] / replicas) / (N * T)
     return r
+
+
+# ---------------------------------------------------------------- analytic gate
+
+
+def _psi(v: float) -> float:
+    """psi(v) = G'(v)/v - G''(v) for the Rosenbluth potential G(v) = E|v - w|
+    of a unit Maxwellian, G = (v + 1/v) erf(v/sqrt2) + sqrt(2/pi) exp(-v^2/2):
+    psi = (1/v - 3/v^3) erf(v/sqrt2) + 3 sqrt(2/pi) exp(-v^2/2) / v^2.
+    E_w[(I - 3 u^ u^T) / |u|] over u = v - w equals -psi(|v|) (I - 3 v^ v^T)."""
+    from scipy.special import erf
+    if v < 1e-2:   # series: the closed form cancels near 0
+        return math.sqrt(2.0 / math.pi) * v * v * (2.0 / 15.0 - v * v / 35.0)
+    return (1.0 / v - 3.0 / v ** 3) * erf(v / math.sqrt(2.0)) + \
+        3.0 * math.sqrt(2.0 / math.pi) * math.exp(-0.5 * v * v) / (v * v)
+
+
+def pairing_noise_constants():
+    """(6 E[psi^2], 6 E[psi v^2]^2 / E[v^4]) over a unit Maxwellian, by quadrature.
+    The second is 10 / (25 pi): the part of the pair sum's pairing-independent
+    fluctuation that the sample's second-moment anisotropy explains."""
+    dens = lambda v: 4.0 * math.pi * v * v * (2.0 * math.pi) ** -1.5 * math.exp(-0.5 * v * v)
+    e2, _ = integrate.quad(lambda v: _psi(v) ** 2 * dens(v), 0.0, 40.0, limit=400, epsrel=1e-12)
+    e1, _ = integrate.quad(lambda v: _psi(v) * v * v * dens(v), 0.0, 40.0, limit=400, epsrel=1e-12)
+    return 6.0 * e2, 6.0 * e1 * e1 / 15.0
+
+
+def analytic_relaxation(v, cell_start, *, dt, lnL, replicas, density=None):
+    """Estimate of the label r_j from the cell's moments alone (no pairing),
+    the baseline the learned gate is compared with:
+        r_pred^2 = r_aniso^2 + r_floor^2,
+        r_aniso = 3 nu_0 dt ||A||_F,
+        r_floor^2 = (c / T^1.5)^2 / N * (a - b + (3/2 - a) / K),
+    with c = 8 pi n lnL dt, (a, b) = pairing_noise_constants().
+    A = T_ab / T - I is the traceless part of the temperature tensor in units
+    of T = tr(T_ab) / 3 (its diagonal and off-diagonal norm are features 2-5
+    of cell_features).  Linearised about isotropy the
+    traceless part decays at 3 nu_0 (for a bi-Maxwellian, T_par - T_perp
+    decays at 3 nu_T), nu_0 = (8 sqrt(pi) / 15) n lnL / T^1.5 the
+    small-anisotropy limit of nu_isotropisation.  The floor is the spread of
+    the pair sum of an isotropic Maxwellian cell in the small-angle limit
+    h = 4 s^2, where a pair adds c (I - 3 u^ u^T) / |u|: split into the
+    pairing-independent part sum_a g(v_a) (variance a N (c/T^1.5)^2 T^2, of
+    which the fraction b/a is the second-moment anisotropy already in r_aniso)
+    and the pairing part (variance (3/2 - a) N (...)^2, E|u|^-2 = 1/(2T),
+    divided by K by the average over re-pairings).  Slow pairs, whose angle
+    is not small, make the floor an overestimate at larger dt.  NaN for cells
+    without features."""
+    a, b = pairing_noise_constants()
+    f = cell_features(v, cell_start)
+    M = cell_start.size - 1
+    out = np.full(M, np.nan)
+    for j in range(M):
+        if np.isnan(f[j, 0]):
+            continue
+        N = math.exp(f[j, 0])
+        T = math.exp(f[j, 1])
+        n = 1.0 if density is None else float(density[j])
+        a2 = f[j, 2] ** 2 + f[j, 3] ** 2 + f[j, 4] ** 2 + f[j, 5] ** 2
+        nu0 = 8.0 * math.sqrt(math.pi) / 15.0 * n * lnL / T ** 1.5
+        r_aniso = 3.0 * nu0 * dt * math.sqrt(a2)
+        c = 8.0 * math.pi * n * lnL * dt / T ** 1.5
+        r_floor2 = c * c / N * (a - b + (1.5 - a) / replicas)
+        out[j] = math.sqrt(r_aniso ** 2 + r_floor2)
+    return out
 
 
 # ---------------------------------------------------------------- gate MLP (FP64)

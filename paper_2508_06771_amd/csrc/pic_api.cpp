@@ -58,7 +58,7 @@ struct pic_ctx {
     uint64_t *step_dev = nullptr;
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t exec = nullptr;
-    unsigned char graph_key[256];
+    unsigned char graph_key[512];
     size_t graph_key_len = 0;
     // learned gate
     const float *gate_params = nullptr;
@@ -66,7 +66,7 @@ struct pic_ctx {
     int gate_kmax = 8;
     double gate_judge_frac = 0.01, gate_tol = 1e-3, gate_max_false = 0.1;
     int gate_mom_every = 1;
-    int gate_replicas = 8, gate_bf16 = 1;
+    int gate_replicas = 8, gate_bf16 = 1, gate_analytic = 0;
     uint32_t gate_min_judged = 20;
     DevGate *gate_dev = nullptr;
     int32_t gate_M = 0;
@@ -530,6 +530,7 @@ int pic_gate_config(pic_ctx *c, const float *params, float threshold, int32_t k_
         !(judge_fraction <= 1.0) || !(tolerance > 0.0) || replicas < 1)
         return PIC_ERR_ARG;
     c->gate_params = params;
+    c->gate_analytic = 0;
     c->gate_thr = threshold;
     c->gate_kmax = k_max;
     c->gate_judge_frac = judge_fraction;
@@ -537,6 +538,31 @@ int pic_gate_config(pic_ctx *c, const float *params, float threshold, int32_t k_
     c->gate_replicas = replicas;
     c->gate_bf16 = bf16 != 0;
     return PIC_OK;
+}
+
+int pic_gate_config_analytic(pic_ctx *c, float threshold, int32_t k_max, double judge_fraction,
+                             double tolerance, int32_t replicas)
+{
+    if (!c || !(threshold >= 0.0f) || k_max < 0 || !(judge_fraction >= 0.0) || !(judge_fraction <= 1.0) ||
+        !(tolerance > 0.0) || replicas < 1)
+        return PIC_ERR_ARG;
+    c->gate_params = nullptr;
+    c->gate_analytic = 1;
+    c->gate_thr = threshold;
+    c->gate_kmax = k_max;
+    c->gate_judge_frac = judge_fraction;
+    c->gate_tol = tolerance;
+    c->gate_replicas = replicas;
+    return PIC_OK;
+}
+
+int pic_analytic_relaxation(pic_ctx *c, const double *moments, int32_t n_cells, double dt, double lnLambda,
+                            const double *density, int32_t replicas, double *r_out)
+{
+    if (!c || !moments || !r_out || n_cells < 1 || !(dt > 0.0) || !(lnLambda > 0.0) || replicas < 1)
+        return PIC_ERR_ARG;
+    CK(hipSetDevice(c->device));
+    return launch_analytic_relax(moments, n_cells, dt, lnLambda, density, replicas, r_out, c->stream);
 }
 
 int pic_gate_refresh(pic_ctx *c, int32_t every)
@@ -774,7 +800,7 @@ static int step_check(pic_ctx *c, const StepArgs &s)
     if (s.n > 0 && (!s.v || !s.cell_of || !s.pid)) return PIC_ERR_ARG;
     if ((s.flags & PIC_FUSE_MCC) && !c->mcc_set) return PIC_ERR_STATE;
     if ((s.flags & PIC_MOMENTS) && !(s.flags & PIC_GATE) && !c->moments_out) return PIC_ERR_STATE;
-    if ((s.flags & PIC_GATE) && !c->gate_params) return PIC_ERR_STATE;
+    if ((s.flags & PIC_GATE) && !c->gate_params && !c->gate_analytic) return PIC_ERR_STATE;
     return PIC_OK;
 }
 
@@ -866,6 +892,12 @@ static int step_enqueue(pic_ctx *c, const StepArgs &s, hipStream_t st, const uin
         g.prob = c->gate_prob;
         g.judge_list = c->gate_judge;
         g.g = c->gate_dev;
+        g.analytic = c->gate_analytic;
+        g.replicas = c->gate_replicas;
+        g.dt = s.dt;
+        g.lnL = s.lnL;
+        g.tol = c->gate_tol;
+        g.density = s.density;
         ktime_begin(KT_GATE, st);
         RC(launch_gate(g, st));
         ktime_end(KT_GATE, st);
@@ -1041,9 +1073,14 @@ int pic_run_steps(pic_ctx *c, int dtype, void *v, int32_t *cell_of, uint32_t *pi
     // launched and leave at once (their counts are read on the device).
     s.flags |= PIC_ASSUME_SORTED;
     s.step = 0;
-    unsigned char key[256];
+    unsigned char key[sizeof(c->graph_key)];
     size_t kl = 0;
+    bool key_full = false;
     auto put = [&](const void *p, size_t bytes) {
+        if (kl + bytes > sizeof(key)) {
+            key_full = true;
+            return;
+        }
         memcpy(key + kl, p, bytes);
         kl += bytes;
     };
@@ -1061,10 +1098,12 @@ int pic_run_steps(pic_ctx *c, int dtype, void *v, int32_t *cell_of, uint32_t *pi
     put(&c->gate_tol, sizeof(double));
     put(&c->gate_replicas, sizeof(int));
     put(&c->gate_bf16, sizeof(int));
+    put(&c->gate_analytic, sizeof(int));
     put(&c->gate_mem, sizeof(void *));
     put(&c->debt, sizeof(void *));
     put(&c->tuned_valid[dtype == PIC_F64], sizeof(bool));
     put(&c->tuned[dtype == PIC_F64], sizeof(ClassCaps));
+    if (key_full) return PIC_ERR_STATE;   // the key outgrew its buffer: a build error, not a caller's
     if (!c->exec || kl != c->graph_key_len || memcmp(key, c->graph_key, kl) != 0) {
         if (c->exec) {
             CK(hipGraphExecDestroy(c->exec));

@@ -78,9 +78,11 @@ __device__ bool features_from_sums(const double *m, float f[8])
                       2.0 * VV * Q - 3.0 * N * VV * VV;
     f[0] = (float)log(N);
     f[1] = (float)log(T);
-    f[2] = (float)(Txx / T);
-    f[3] = (float)(Tyy / T);
-    f[4] = (float)(Tzz / T);
+    // diagonal anisotropy centred on isotropy (computed before rounding, so
+    // bfloat16 inputs keep the resolution of small anisotropies)
+    f[2] = (float)((Txx - T) / T);
+    f[3] = (float)((Tyy - T) / T);
+    f[4] = (float)((Tzz - T) / T);
     f[5] = (float)(sqrt(2.0 * (Txy * Txy + Txz * Txz + Tyz * Tyz)) / T);
     f[6] = (float)(sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]) / (N * T * sqrt(T)));
     f[7] = (float)(c4 / N / (15.0 * T * T) - 1.0);
@@ -279,13 +281,64 @@ __global__ __launch_bounds__(256) void k_mlp_forward_mfma(const float *__restric
     }
 }
 
+// ------------------------------------------------------------ analytic gate
+// Estimate of the judged relaxation r (expected one-step change of the
+// temperature tensor, averaged over K re-pairings, over N T) from the raw
+// moment sums alone, for the gate that needs no network:
+//   r^2 = r_aniso^2 + r_floor^2,
+//   r_aniso = 3 nu_0 dt ||A||_F: the traceless part A of the temperature
+//     tensor (in units of T = tr / 3) decays at 3 nu_0 near isotropy (the
+//     bi-Maxwellian T_par - T_perp decays at 3 nu_T), with
+//     nu_0 = (8 sqrt(pi) / 15) n lnL / T^1.5, the small-anisotropy limit of
+//     the isotropisation rate;
+//   r_floor^2 = (c / T^1.5)^2 / N (a - b + (3/2 - a) / K), c = 8 pi n lnL dt:
+//     the spread of the pair sum for an isotropic Maxwellian cell with small
+//     angles (a pair adds c (I - 3 u^ u^T) / |u|, E|u|^-2 = 1 / (2T)).  Its
+//     part that does not depend on the pairing is sum_a g(v_a),
+//     g(v) = -psi(|v|) (I - 3 v^ v^T), psi = G'/v - G'' for the Rosenbluth
+//     potential G of the Maxwellian, of variance a = 6 E[psi^2] per member
+//     (numerical integral over the unit Maxwellian); b = 10 / (25 pi) of it
+//     is the sample's second-moment anisotropy already counted in r_aniso.
+//     The pairing part (3/2 - a) is divided by K.
+// NaN for cells of fewer than two members or no temperature.
+constexpr double ANALYTIC_A = 0.15215976481548635;   // 6 E[psi^2]
+constexpr double ANALYTIC_B = 10.0 / (25.0 * PI_D);
+
+__device__ double analytic_relax(const double *m, double dt, double lnL, double n, int K)
+{
+    const double N = m[0];
+    if (!(N >= 2.0)) return __longlong_as_double(0x7ff8000000000000ll);
+    const double Vx = m[1] / N, Vy = m[2] / N, Vz = m[3] / N;
+    const double Txx = m[4] / N - Vx * Vx, Tyy = m[5] / N - Vy * Vy, Tzz = m[6] / N - Vz * Vz;
+    const double Txy = m[7] / N - Vx * Vy, Txz = m[8] / N - Vx * Vz, Tyz = m[9] / N - Vy * Vz;
+    const double T = (Txx + Tyy + Tzz) / 3.0;
+    if (!(T > 0.0)) return __longlong_as_double(0x7ff8000000000000ll);
+    const double a2 = ((Txx - T) * (Txx - T) + (Tyy - T) * (Tyy - T) + (Tzz - T) * (Tzz - T) +
+                       2.0 * (Txy * Txy + Txz * Txz + Tyz * Tyz)) / (T * T);
+    const double t15 = T * sqrt(T);
+    const double r_aniso = 8.0 * sqrt(PI_D) / 5.0 * n * lnL * dt * sqrt(a2) / t15;
+    const double c = 8.0 * PI_D * n * lnL * dt / t15;
+    const double floor2 = c * c / N * (ANALYTIC_A - ANALYTIC_B + (1.5 - ANALYTIC_A) / (double)K);
+    return sqrt(r_aniso * r_aniso + floor2);
+}
+
+__global__ __launch_bounds__(256) void k_analytic_relax(const double *__restrict__ mom, int32_t M, double dt,
+                                                        double lnL, const double *__restrict__ density,
+                                                        int K, double *__restrict__ r)
+{
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < M; j += gridDim.x * blockDim.x)
+        r[j] = analytic_relax(mom + (int64_t)j * 14, dt, lnL, density ? density[j] : 1.0, K);
+}
+
 // ------------------------------------------------------------ gate per step
-// Decision for cell j from the network's probability p (valid: the cell
-// has features and the gate is on).
+// Decision for cell j from the network's probability p, or in the analytic
+// gate from p = estimated relaxation / tolerance (valid: the cell has
+// features and the gate is on).
 __device__ __forceinline__ void gate_decide(const GateArgs &a, int j, bool valid, float p, uint64_t step,
                                             bool on, bool judge_now)
 {
-    const bool want = valid && p > a.thr && a.k_acc[j] < a.kmax;
+    const bool pass = a.analytic ? p < a.thr : p > a.thr;
+    const bool want = valid && pass && a.k_acc[j] < a.kmax;
     const W4 w = draw4(a.seed, (uint32_t)j, (uint32_t)step, 2u, 0u);
     const bool judge = on && judge_now && (uint64_t)w.x < a.judge_thr;
     const bool skip = want && !judge;
@@ -371,6 +424,25 @@ __global__ __launch_bounds__(256) void k_gate(GateArgs a)
             if (valid) p = 1.0f / (1.0f + __expf(-mlp_logit(P, f, false)));
         }
         gate_decide(a, j, valid, p, step, on, judge_now);
+    }
+}
+
+// The analytic gate: one thread per cell, the estimate in binary64.
+__global__ __launch_bounds__(256) void k_gate_analytic(GateArgs a)
+{
+    const uint64_t step = a.step_dev ? *a.step_dev : a.step;
+    const bool on = a.g->have_moments && !a.g->disabled;
+    const bool judge_now = a.g->mom_now != 0;
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < a.M; j += gridDim.x * blockDim.x) {
+        float q = 0.0f;
+        bool valid = false;
+        if (on) {
+            const double r = analytic_relax(a.moments + (int64_t)j * 14, a.dt, a.lnL,
+                                            a.density ? a.density[j] : 1.0, a.replicas);
+            valid = r == r;
+            if (valid) q = (float)(r / a.tol);
+        }
+        gate_decide(a, j, valid, q, step, on, judge_now);
     }
 }
 
@@ -932,9 +1004,22 @@ int launch_adam(float *params, float *m, float *v, const float *grad, int32_t t,
     return PIC_OK;
 }
 
+int launch_analytic_relax(const double *moments, int32_t M, double dt, double lnL, const double *density,
+                          int replicas, double *r, hipStream_t st)
+{
+    const int g = (M + 255) / 256 < 2048 ? (M + 255) / 256 : 2048;
+    hipLaunchKernelGGL(k_analytic_relax, dim3(g > 0 ? g : 1), dim3(256), 0, st, moments, M, dt, lnL,
+                       density, replicas, r);
+    HIP_OK(hipGetLastError());
+    return PIC_OK;
+}
+
 int launch_gate(const GateArgs &a, hipStream_t st)
 {
-    if (a.bf16) {
+    if (a.analytic) {
+        const int g = (a.M + 255) / 256 < 2048 ? (a.M + 255) / 256 : 2048;
+        hipLaunchKernelGGL(k_gate_analytic, dim3(g > 0 ? g : 1), dim3(256), 0, st, a);
+    } else if (a.bf16) {
         const int tiles = (a.M + 31) / 32;
         const int g = (tiles + 3) / 4 < 1024 ? (tiles + 3) / 4 : 1024;
         hipLaunchKernelGGL(k_gate_mfma, dim3(g > 0 ? g : 1), dim3(256), 0, st, a);

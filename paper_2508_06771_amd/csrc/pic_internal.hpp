@@ -824,6 +824,11 @@ struct GateArgs {
     float *prob;
     int32_t *judge_list;
     DevGate *g;
+    // analytic moment gate (instead of the network): skip when the estimated
+    // relaxation over the tolerance is below thr
+    int analytic, replicas;
+    double dt, lnL, tol;
+    const double *density;   // per cell, nullable (1)
 };
 
 struct RelaxArgs {
@@ -865,6 +870,8 @@ int launch_mlp_grad(const float *params, const float *x, const float *y, int32_t
 int launch_adam(float *params, float *m, float *v, const float *grad, int32_t t, float lr,
                 hipStream_t st);
 int launch_gate(const GateArgs &a, hipStream_t st);
+int launch_analytic_relax(const double *moments, int32_t M, double dt, double lnL, const double *density,
+                          int replicas, double *r, hipStream_t st);
 int launch_gate_score(DevGate *g, const int32_t *judge_list, const uint8_t *want, const double *r,
                       double tol, double max_false, uint32_t min_judged, hipStream_t st);
 int launch_relax(int dtype, const RelaxArgs &a, int num_cu, hipStream_t st);

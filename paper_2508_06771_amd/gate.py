@@ -64,11 +64,19 @@ def collect(ctx: "piccoll.Context", v, cell_of, pid, n_cells: int, *, dt: float,
 
 def train(ctx: "piccoll.Context", data: Dataset, tol: float, *, epochs: int = 20,
           batch: int = 4096, lr: float = 3e-3, bf16: bool = True, seed: int = 0,
-          params: torch.Tensor | None = None):
+          params: torch.Tensor | None = None, scale_inputs: bool = False):
     """Binary cross-entropy training of P(relaxation < tol) with Adam.
+    scale_inputs: train on each feature divided by its standard deviation
+    over the training set (better conditioned: the anisotropy features span
+    a few hundredths), then fold the scales into the first layer's weights,
+    so the returned network takes the plain features.
     Returns (params, per-epoch mean losses)."""
     y = (data.r < tol).to(torch.float32)
     S = data.x.shape[0]
+    x = data.x
+    if scale_inputs:
+        sd = data.x.double().std(dim=0).clamp_min(1e-3).to(torch.float32)
+        x = (data.x / sd).contiguous()
     params = init_params(seed, data.x.device) if params is None else params
     m = torch.zeros_like(params)
     vv = torch.zeros_like(params)
@@ -79,11 +87,14 @@ def train(ctx: "piccoll.Context", data: Dataset, tol: float, *, epochs: int = 20
         losses = []
         for b0 in range(0, S - batch + 1, batch):
             idx = perm[b0:b0 + batch]
-            xb = data.x[idx].contiguous()
+            xb = x[idx].contiguous()
             yb = y[idx].contiguous()
             t += 1
             losses.append(ctx.mlp_train_step(params, m, vv, t, lr, xb, yb, bf16=bf16))
         hist.append(float(torch.stack(losses).mean().item()))
+    if scale_inputs:
+        # W1 is row-major [8][64]: row i multiplies feature i
+        params[:512].view(8, 64).div_(sd.view(8, 1))
     return params, hist
 
 

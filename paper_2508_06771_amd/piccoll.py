@@ -85,6 +85,8 @@ def _load():
         "pic_mlp_grad": ([vp, vp, vp, vp, i32, C.c_int, vp, vp], C.c_int),
         "pic_mlp_train_step": ([vp, vp, vp, vp, i32, C.c_float, vp, vp, i32, C.c_int, vp], C.c_int),
         "pic_gate_config": ([vp, vp, C.c_float, i32, f64, f64, i32, C.c_int], C.c_int),
+        "pic_gate_config_analytic": ([vp, C.c_float, i32, f64, f64, i32], C.c_int),
+        "pic_analytic_relaxation": ([vp, vp, i32, f64, f64, vp, i32, vp], C.c_int),
         "pic_gate_reset": ([vp], C.c_int),
         "pic_gate_stats": ([vp, C.POINTER(C.c_int64)], C.c_int),
         "pic_gate_state": ([vp, vp, vp, vp, vp], C.c_int),
@@ -114,7 +116,7 @@ EXPORTED = ["pic_create", "pic_destroy", "pic_strerror", "pic_sync", "pic_set_st
             "mcc_null_collide", "pic_philox", "coulomb_pairs", "pic_cell_moments", "pic_unsort",
             "pic_time_kernels", "pic_kernel_times", "pic_run_steps", "pic_features",
             "pic_relaxation", "pic_mlp_forward", "pic_mlp_grad", "pic_mlp_train_step",
-            "pic_gate_config", "pic_gate_reset", "pic_gate_stats", "pic_gate_state", "pic_autotune",
+            "pic_gate_config", "pic_gate_config_analytic", "pic_analytic_relaxation", "pic_gate_reset", "pic_gate_stats", "pic_gate_state", "pic_autotune",
             "pic_conserve_reset", "pic_gate_refresh", "gate_infer", "pic_set_dsmc", "dsmc_collide",
             "mcc_null_collide_exact", "p2c_sums", "recombine", "coulomb_collide_nanbu",
             "coulomb_collide_triplet", "coulomb_collide_noalloc", "coulomb_collide_weighted", "pic_set_schedule",
@@ -342,6 +344,15 @@ class Context:
              "pic_relaxation")
         return r
 
+    def analytic_relaxation(self, moments: torch.Tensor, *, dt: float, lnL: float, replicas: int = 8,
+                            density=None):
+        self._stream()
+        M = moments.shape[0]
+        r = torch.empty(M, dtype=torch.float64, device=moments.device)
+        _chk(lib.pic_analytic_relaxation(self._h, _p(moments), M, dt, lnL, _p(density), replicas, _p(r)),
+             "pic_analytic_relaxation")
+        return r
+
     def mlp_forward(self, params: torch.Tensor, x: torch.Tensor, bf16: bool = True):
         self._stream()
         prob = torch.empty(x.shape[0], dtype=torch.float32, device=x.device)
@@ -406,6 +417,12 @@ class Context:
         self._gate_params = params     # the library keeps the pointer
         _chk(lib.pic_gate_config(self._h, _p(params), threshold, k_max, judge_fraction, tolerance,
                                  replicas, int(bf16)), "pic_gate_config")
+
+    def gate_config_analytic(self, threshold: float, k_max: int = 8, judge_fraction: float = 0.01,
+                             tolerance: float = 1e-3, replicas: int = 8):
+        self._gate_params = None
+        _chk(lib.pic_gate_config_analytic(self._h, threshold, k_max, judge_fraction, tolerance,
+                                          replicas), "pic_gate_config_analytic")
 
     def gate_refresh(self, every: int):
         _chk(lib.pic_gate_refresh(self._h, int(every)), "pic_gate_refresh")

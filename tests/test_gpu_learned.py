@@ -380,3 +380,103 @@ def test_trained_gate_gains_over_plain(ctx, tmp_path):
     relax = np.abs(pl["r1"] - pl["r0"])[aniso].mean()
     diff = np.abs(g["r1"] - pl["r1"])[aniso].mean()
     assert diff < 0.03 * relax, (diff, relax)
+
+
+# ---------------------------------------------------------------- analytic gate
+
+
+def test_analytic_relaxation_matches_oracle(ctx):
+    """The moment-based relaxation estimate from the library's FP64 one-pass
+    sums against the oracle's two-pass features: ragged and degenerate cells
+    (0, 1 and 2 members give NaN or a value as the oracle does), densities."""
+    import torch
+    w, cs = sorted_workload(9, [0, 1, 2, 37, 500, 2000, 3000, 777, 4097, 10001], np.float32)
+    dens = np.linspace(0.5, 2.0, w.n_cells)
+    tv = dev(w.v, torch.float32)
+    mom = ctx.cell_moments(tv, dev(cs))
+    for K, d in ((8, None), (2, dens)):
+        r = host(ctx.analytic_relaxation(mom, dt=w.dt, lnL=w.lnL, replicas=K,
+                                         density=None if d is None else dev(d)))
+        ctx.sync()
+        ref = physics.analytic_relaxation(w.v.astype(np.float64), cs, dt=w.dt, lnL=w.lnL,
+                                          replicas=K, density=d)
+        assert np.array_equal(np.isnan(r), np.isnan(ref))
+        ok = ~np.isnan(ref)
+        assert ok.sum() >= 8
+        assert np.allclose(r[ok], ref[ok], rtol=1e-8, atol=0)
+
+
+def test_analytic_gate_decisions_and_steps(ctx):
+    """The analytic gate: its stored score is the estimate over the tolerance
+    from last step's moments, a cell is skipped only when that score is below
+    the threshold (and not judged, and under k_max), and the step equals the
+    oracle run with the gate's own skip / dt_scale decisions."""
+    import torch
+    from paper_2508_06771_amd import piccoll
+    w, cs = sorted_workload(5, [3000] * 24 + [0, 1, 5, 600, 2500, 5000, 9000, 12000], np.float32)
+    ctx.gate_config_analytic(1.0, k_max=3, judge_fraction=0.2, tolerance=1e-3, replicas=2)
+    ctx.gate_reset()
+    ctx.set_mcc(w.sigma0, 1.0, 0.0)
+    fl = piccoll.GATE | piccoll.FUSE_MCC
+    tv, tc, tp = dev(w.v, torch.float32), dev(w.cell_of), dev(w.pid)
+    ctx.coulomb_collide(tv, tc, tp, w.n_cells, dt=w.dt, lnL=w.lnL, seed=1, step=0, flags=fl)
+    _, _, _, mom0 = ctx.gate_state(w.n_cells)
+    q0 = host(ctx.analytic_relaxation(mom0, dt=w.dt, lnL=w.lnL, replicas=2)) / 1e-3
+    ctx.sync()
+    thr = float(np.nanmedian(q0))
+    ctx.gate_config_analytic(thr, k_max=3, judge_fraction=0.2, tolerance=1e-3, replicas=2)
+    k_prev = np.zeros(w.n_cells, np.int32)
+    skipped_any = False
+    try:
+        for step in (1, 2, 3):
+            v_in = host(tv).astype(np.float64)
+            _, _, _, mom_in = ctx.gate_state(w.n_cells)
+            r_in = host(ctx.analytic_relaxation(mom_in, dt=w.dt, lnL=w.lnL, replicas=2))
+            ctx.coulomb_collide(tv, tc, tp, w.n_cells, dt=w.dt, lnL=w.lnL, seed=1, step=step,
+                                flags=fl)
+            skip, k, prob, mom = ctx.gate_state(w.n_cells)
+            ctx.sync()
+            skip, k, prob = host(skip).astype(bool), host(k), host(prob)
+            valid = ~np.isnan(r_in)
+            assert np.allclose(prob[valid], r_in[valid] / 1e-3, rtol=1e-6, atol=0)
+            assert np.all(prob[~valid] == 0.0)
+            want = valid & (prob < np.float32(thr)) & (k_prev < 3)
+            assert not np.any(skip & ~want)
+            assert (want & ~skip).sum() <= 0.5 * max(1, want.sum())   # judged: 20% of cells
+            skipped_any |= bool(skip.any())
+            dts = np.where(skip, 1.0, k_prev + 1.0)
+            assert np.array_equal(k, np.where(skip, k_prev + 1, 0))
+            vr, cr, prr = v_in.copy(), w.cell_of.copy(), w.pid.copy()
+            oracle.step(vr, cr, prr, w.n_cells, dt=w.dt, lnL=w.lnL, seed=1, step=step, mcc=True,
+                        sigma0=w.sigma0, n_neutral=1.0, skip=skip.astype(np.uint8), dt_scale=dts)
+            assert rel_err(host(tv).astype(np.float64), vr) < 1e-5
+            k_prev = k
+        assert skipped_any
+        st = ctx.gate_stats()
+        assert st["steps"] == 4 and st["judged"] > 0
+    finally:
+        ctx.gate_reset()
+
+
+def test_analytic_gate_graph_equals_eager(ctx):
+    import torch
+    from paper_2508_06771_amd import piccoll
+    fl = piccoll.GATE | piccoll.FUSE_MCC
+    w, cs = sorted_workload(7, [3000] * 24 + [0, 1, 5, 600, 2500, 5000, 9000, 12000], np.float32)
+    ctx.set_mcc(w.sigma0, 1.0, 0.0)
+    out = []
+    for graph in (True, False):
+        ctx.gate_config_analytic(1e3, k_max=3, judge_fraction=0.2, tolerance=1e-3, replicas=2)
+        ctx.gate_reset()
+        A = [dev(w.v, torch.float32), dev(w.cell_of), dev(w.pid)]
+        if graph:
+            ctx.run_steps(*A, w.n_cells, dt=w.dt, lnL=w.lnL, seed=2, step0=0, nsteps=5, flags=fl)
+        else:
+            for k in range(5):
+                ctx.coulomb_collide(*A, w.n_cells, dt=w.dt, lnL=w.lnL, seed=2, step=k, flags=fl)
+        ctx.sync()
+        out.append((A[0], ctx.gate_stats()))
+    assert torch.equal(out[0][0], out[1][0])
+    assert out[0][1] == out[1][1]
+    assert out[0][1]["skipped"] > 0
+    ctx.gate_reset()
