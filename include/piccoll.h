@@ -388,6 +388,16 @@ int pic_mlp_grad(pic_ctx *ctx, const float *params, const float *x, const float 
 int pic_mlp_train_step(pic_ctx *ctx, float *params, float *adam_m, float *adam_v, int32_t t,
                        float lr, const float *x, const float *y, int32_t batch, int bf16,
                        float *loss);
+/* One bfloat16 training step in the boundary's short form: feat float[8
+ * batch] (layout of pic_features), label float[batch] (1: r < tolerance),
+ * w_master float[4801] (binary32 master parameters, updated in place),
+ * adam_state float[2 * 4801] (first moments, then second moments; zero before
+ * the first step), loss_out (device, nullable) the batch's mean loss.  The
+ * Adam step count is kept by the context: it restarts at 1 whenever w_master
+ * differs from the previous call's and counts up otherwise.  Same arithmetic
+ * as pic_mlp_train_step with bf16 = 1. */
+int mlp_train_step(pic_ctx *ctx, const void *feat, const float *label, int32_t batch, void *w_master,
+                   void *adam_state, float lr, float *loss_out);
 
 /* Stand-alone gate decision for features feat[8 n_cells] (layout of
  * pic_features): prob = the network (bf16 as in pic_mlp_forward), then
@@ -489,20 +499,32 @@ int pic_kernel_times(pic_ctx *ctx, double *ms, int64_t *count);
 int pic_philox(pic_ctx *ctx, uint64_t seed, uint64_t step, uint32_t domain, uint32_t c3,
                const uint32_t *c0, int64_t n, uint32_t *out);
 
-/* Pairing of storage already in cell order (cell_start from pic_bin_cells):
+/* The pairing of the Coulomb step (partner pairs within each cell's list,
+ * steps CCS3-CCS5 of Table "Coulombic Collision Steps"; the order inside a
+ * cell is random: sorted by (word 0 of the member's domain-0 draw, pid), pairs
+ * (0,1), (2,3), ...; an odd cell's last member is idle) for storage already
+ * in cell order (cell_start from pic_bin_cells):
  * sorted[cell_start[j] + r] = slot of the r-th member of cell j in
- * (key, pid) order; partner[slot] = partner slot or -1 (idle). */
+ * (key, pid) order; partner[slot] = partner slot or -1 (idle).  Device
+ * arrays of n (= cell_start[n_cells]) entries.  PIC_ERR_ARG for NULL arrays
+ * or n_cells < 1. */
 int coulomb_pairs(pic_ctx *ctx, const int32_t *cell_start, const uint32_t *pid,
                   int32_t n_cells, uint64_t seed, uint64_t step, int32_t *sorted,
                   int32_t *partner);
 
 /* Per-cell FP64 raw moment sums of storage in cell order, out[14*j + k]:
  * N, sum vx, vy, vz, sum vx^2, vy^2, vz^2, sum vx vy, vx vz, vy vz,
- * sum |v|^2 vx, |v|^2 vy, |v|^2 vz, sum |v|^4. */
+ * sum |v|^2 vx, |v|^2 vy, |v|^2 vz, sum |v|^4.  The first seven carry each
+ * cell's momentum and energy, which every partner pair of step CCS5 (Table
+ * "Coulombic Collision Steps") conserves; the rest feed the gate's features.
+ * out: device double[14 n_cells].  PIC_ERR_ARG for NULL arrays or
+ * n_cells < 1. */
 int pic_cell_moments(pic_ctx *ctx, int dtype, const void *v, int64_t n,
                      const int32_t *cell_start, int32_t n_cells, double *out);
 
-/* Restores storage to pid order (slot pid[k] receives particle k), i.e. the
+/* Undoes the re-binning (step CCS3 of Table "Coulombic Collision Steps"
+ * moves particles into cell order here, where the paper sorts indices):
+ * restores storage to pid order (slot pid[k] receives particle k), i.e. the
  * caller's original order when pid was 0..n-1.  pid must be a permutation of
  * 0..n-1 (not checked). */
 int pic_unsort(pic_ctx *ctx, int dtype, void *v, uint32_t *pid, int32_t *cell_of, int64_t n);

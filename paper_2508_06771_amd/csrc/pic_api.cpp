@@ -67,6 +67,8 @@ struct pic_ctx {
     double gate_judge_frac = 0.01, gate_tol = 1e-3, gate_max_false = 0.1;
     int gate_mom_every = 1;
     int gate_replicas = 8, gate_bf16 = 1, gate_analytic = 0;
+    void *mlp_w = nullptr;   // mlp_train_step: parameters of the previous call, its step count
+    int32_t mlp_t = 0;
     uint32_t gate_min_judged = 20;
     DevGate *gate_dev = nullptr;
     int32_t gate_M = 0;
@@ -701,6 +703,21 @@ int pic_mlp_train_step(pic_ctx *c, float *params, float *adam_m, float *adam_v, 
     float *grad = scratch + sf;
     RC(launch_mlp_grad(params, x, y, batch, bf16 != 0, scratch, grad, loss, c->stream));
     return launch_adam(params, adam_m, adam_v, grad, t, lr, c->stream);
+}
+
+int mlp_train_step(pic_ctx *c, const void *feat, const float *label, int32_t batch, void *w_master,
+                   void *adam_state, float lr, float *loss_out)
+{
+    if (!c || !w_master || !adam_state) return PIC_ERR_ARG;
+    const int32_t t = (w_master == c->mlp_w && c->mlp_t < INT32_MAX) ? c->mlp_t + 1 : 1;
+    float *m = (float *)adam_state;
+    const int rc = pic_mlp_train_step(c, (float *)w_master, m, m + 4801, t, lr, (const float *)feat,
+                                      label, batch, 1, loss_out);
+    if (rc == PIC_OK) {
+        c->mlp_w = w_master;
+        c->mlp_t = t;
+    }
+    return rc;
 }
 
 int pic_bin_cells(pic_ctx *c, const int32_t *cell_of, int64_t n, int32_t n_cells,

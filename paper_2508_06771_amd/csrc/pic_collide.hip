@@ -847,8 +847,45 @@ __device__ __forceinline__ void lean_round(uint32_t base, uint32_t P, uint32_t n
     }
 }
 
+// The next cell's lines of pid and v are requested while this cell is still
+// being worked on, so that its loads find them in the caches (the last-level
+// cache holds every workgroup's next cell).  The loads go to LDS (a 256-byte
+// sink that nothing reads): they write no register, so nothing waits for them
+// before the next cell's own loads.
+struct LeanNext {
+    int *slot;                 // LDS word receiving the next work item
+    unsigned *head;            // the queue's counter
+    const int32_t *list;
+    uint32_t count;
+    float *sink;               // 64 words of LDS
+};
+
+template <int T>
+__device__ __forceinline__ void prefetch_cell(const CollideArgs &a, int cell, float *sink)
+{
+    const int lo = a.cell_start[cell];
+    const int n = a.cell_start[cell + 1] - lo;
+    if (n <= 0) return;
+    // 128-byte lines of each of the four arrays (one more for a start
+    // inside a line); one dword per line
+    const uint32_t lines = ((uint32_t)n + 31u) / 32u + 1u;
+    for (uint32_t t = threadIdx.x; t < 4u * lines; t += T) {
+        const uint32_t arr = t / lines, l = t - arr * lines;
+        const uint32_t idx = (uint32_t)lo + min(l * 32u, (uint32_t)n - 1u);
+        const float *p = arr == 0 ? (const float *)(a.pid + idx)
+                                  : (const float *)a.v + (size_t)(arr - 1u) * (size_t)a.n + idx;
+        __builtin_amdgcn_global_load_lds((const void *)p, (__attribute__((address_space(3))) void *)sink,
+                                         4, 0, 0);
+    }
+}
+
+// With nx, the pass also takes the next work item from the queue and
+// returns it (every thread reads it after a barrier that follows its write
+// and precedes the pass's end, so the next pass may overwrite the slot);
+// without, it returns 0.
 template <int T, int K, bool MCC>
-__device__ __forceinline__ void lean_pass(const CollideArgs &a, int cell, unsigned char *smem, uint32_t *wtot)
+__device__ __forceinline__ int lean_pass(const CollideArgs &a, int cell, unsigned char *smem, uint32_t *wtot,
+                                         const LeanNext *nx = nullptr)
 {
     typedef LeanGeom<T, K> G;
     constexpr uint32_t P = lean_positions(G::CAP);
@@ -864,9 +901,13 @@ __device__ __forceinline__ void lean_pass(const CollideArgs &a, int cell, unsign
     uint32_t w2[K], w3[K], key[K], pos[K];
     uint32_t cand = 0, multi = 0;
 
+    int next = 0;
     if (n == 0) {
+        if (nx && threadIdx.x == 0) *nx->slot = (int)atomicAdd(nx->head, 1u);
         lds_barrier();   // leave together (see the end of the pass)
-        return;
+        if (nx) next = *nx->slot;
+        lds_barrier();
+        return next;
     }
     // every load of the thread is in flight before the first is used, the
     // ids first (the Philox calls wait for them only).  Members past the end
@@ -886,6 +927,9 @@ __device__ __forceinline__ void lean_pass(const CollideArgs &a, int cell, unsign
             vz[k] = vz_g[ic[k]];
         }
     }
+    // the next work item (issued behind this cell's loads, so waiting for it
+    // costs nothing extra); read after a barrier below
+    if (nx && threadIdx.x == 0) *nx->slot = (int)atomicAdd(nx->head, 1u);
     if (n >= 2) {
         const uint32_t bits = sort_bits(n);
         const uint32_t nb = 1u << bits;
@@ -967,6 +1011,13 @@ __device__ __forceinline__ void lean_pass(const CollideArgs &a, int cell, unsign
         lds_barrier();   // the sort's memory becomes the exchange records
 
         const float C = (float)cell_C(a, cell);
+        // last global loads before the exchange: a later wait for a load (the
+        // density above) would wait for these too, so C is complete first
+        if (nx) {
+            asm volatile("" ::"v"(C));
+            const uint32_t nxt = (uint32_t)*nx->slot;
+            if (nxt < nx->count) prefetch_cell<T>(a, nx->list[nxt], nx->sink);
+        }
         const uint32_t np2 = (uint32_t)n & ~1u;     // positions with a partner
         Rec<float> *rec = (Rec<float> *)smem;
         for (uint32_t base = 0; base < np2; base += P) {
@@ -1013,8 +1064,16 @@ __device__ __forceinline__ void lean_pass(const CollideArgs &a, int cell, unsign
             vz_g[i] = vz[k];
         }
     }
+    // the next item: written by thread 0 before at least one barrier of
+    // this pass when n >= 2 (else one more barrier), read by everyone before
+    // the last one (the next pass writes it only after that)
+    if (nx) {
+        if (n < 2) lds_barrier();
+        next = *nx->slot;
+    }
     // the next cell reuses the LDS; the stores stay in flight into it
     lds_barrier();
+    return next;
 }
 
 template <int T, int K, bool MCC>
@@ -1023,18 +1082,16 @@ __global__ __launch_bounds__(T) void k_collide_lean(CollideArgs a, const int32_t
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint32_t wtot[T / PIC_WAVE];
-    __shared__ int s_item;
+    __shared__ int s_item, s_next;
+    __shared__ float sink[PIC_WAVE];
     if (gated_off(a)) return;
     const uint32_t count = a.dflags->count[cls];
     if (blockIdx.x >= count) return;   // no work for this workgroup (nor a queue atomic)
-    for (;;) {
-        if (threadIdx.x == 0) s_item = (int)atomicAdd(&a.dflags->head[cls], 1u);
-        lds_barrier();
-        const int item = s_item;
-        lds_barrier();
-        if (item >= (int)count) break;
-        lean_pass<T, K, MCC>(a, list[item], smem, wtot);
-    }
+    if (threadIdx.x == 0) s_item = (int)atomicAdd(&a.dflags->head[cls], 1u);
+    lds_barrier();
+    int item = s_item;
+    const LeanNext nx{&s_next, &a.dflags->head[cls], list, count, sink};
+    while (item < (int)count) item = lean_pass<T, K, MCC>(a, list[item], smem, wtot, &nx);
 }
 
 // ------------------------------------------------------------ huge cells

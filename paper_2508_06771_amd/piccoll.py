@@ -84,6 +84,7 @@ def _load():
         "pic_mlp_forward": ([vp, vp, vp, i32, C.c_int, vp], C.c_int),
         "pic_mlp_grad": ([vp, vp, vp, vp, i32, C.c_int, vp, vp], C.c_int),
         "pic_mlp_train_step": ([vp, vp, vp, vp, i32, C.c_float, vp, vp, i32, C.c_int, vp], C.c_int),
+        "mlp_train_step": ([vp, vp, vp, i32, vp, vp, C.c_float, vp], C.c_int),
         "pic_gate_config": ([vp, vp, C.c_float, i32, f64, f64, i32, C.c_int], C.c_int),
         "pic_gate_config_analytic": ([vp, C.c_float, i32, f64, f64, i32], C.c_int),
         "pic_analytic_relaxation": ([vp, vp, i32, f64, f64, vp, i32, vp], C.c_int),
@@ -116,7 +117,9 @@ EXPORTED = ["pic_create", "pic_destroy", "pic_strerror", "pic_sync", "pic_set_st
             "mcc_null_collide", "pic_philox", "coulomb_pairs", "pic_cell_moments", "pic_unsort",
             "pic_time_kernels", "pic_kernel_times", "pic_run_steps", "pic_features",
             "pic_relaxation", "pic_mlp_forward", "pic_mlp_grad", "pic_mlp_train_step",
-            "pic_gate_config", "pic_gate_config_analytic", "pic_analytic_relaxation", "pic_gate_reset", "pic_gate_stats", "pic_gate_state", "pic_autotune",
+            "mlp_train_step", "pic_gate_config", "pic_gate_config_analytic",
+            "pic_analytic_relaxation", "pic_gate_reset", "pic_gate_stats", "pic_gate_state",
+            "pic_autotune",
             "pic_conserve_reset", "pic_gate_refresh", "gate_infer", "pic_set_dsmc", "dsmc_collide",
             "mcc_null_collide_exact", "p2c_sums", "recombine", "coulomb_collide_nanbu",
             "coulomb_collide_triplet", "coulomb_collide_noalloc", "coulomb_collide_weighted", "pic_set_schedule",
@@ -410,6 +413,15 @@ class Context:
         loss = torch.empty(1, dtype=torch.float32, device=x.device)
         _chk(lib.pic_mlp_train_step(self._h, _p(params), _p(m), _p(v), t, lr, _p(x), _p(y),
                                     x.shape[0], int(bf16), _p(loss)), "pic_mlp_train_step")
+        return loss
+
+    def train_step(self, feat, label, w_master, adam_state, lr: float):
+        """mlp_train_step: bfloat16 step, Adam moments in adam_state (2 x 4801),
+        step count kept by the context per w_master."""
+        self._stream()
+        loss = torch.empty(1, dtype=torch.float32, device=feat.device)
+        _chk(lib.mlp_train_step(self._h, _p(feat), _p(label), feat.shape[0], _p(w_master),
+                                _p(adam_state), lr, _p(loss)), "mlp_train_step")
         return loss
 
     def gate_config(self, params, threshold: float, k_max: int = 8, judge_fraction: float = 0.01,

@@ -480,3 +480,27 @@ def test_analytic_gate_graph_equals_eager(ctx):
     assert out[0][1] == out[1][1]
     assert out[0][1]["skipped"] > 0
     ctx.gate_reset()
+
+
+def test_short_form_train_step_counts_adam_steps(ctx):
+    """mlp_train_step equals pic_mlp_train_step (bf16) with t = 1, 2, ... on the
+    same parameters, and restarts at t = 1 for another parameter array."""
+    import torch
+    rng = np.random.default_rng(8)
+    flat = rand_params(9).astype(np.float32)
+    x = dev(rng.standard_normal((700, 8)).astype(np.float32))
+    y = dev((rng.uniform(size=700) < 0.6).astype(np.float32))
+    pa, state = dev(flat), torch.zeros(2 * 4801, device="cuda")
+    pb, m, v = dev(flat), torch.zeros(4801, device="cuda"), torch.zeros(4801, device="cuda")
+    for t in (1, 2, 3):
+        la = ctx.train_step(x, y, pa, state, 2e-3)
+        lb = ctx.mlp_train_step(pb, m, v, t, 2e-3, x, y, bf16=True)
+        ctx.sync()
+        assert torch.equal(pa, pb) and torch.equal(la, lb)
+        assert torch.equal(state[:4801], m) and torch.equal(state[4801:], v)
+    pc, state_c = dev(flat), torch.zeros(2 * 4801, device="cuda")
+    pd, md, vd = dev(flat), torch.zeros(4801, device="cuda"), torch.zeros(4801, device="cuda")
+    ctx.train_step(x, y, pc, state_c, 2e-3)
+    ctx.mlp_train_step(pd, md, vd, 1, 2e-3, x, y, bf16=True)
+    ctx.sync()
+    assert torch.equal(pc, pd)
