@@ -860,6 +860,15 @@ struct LeanNext {
     float *sink;               // 64 words of LDS
 };
 
+// The member count as a value the compiler cannot see through: each phase
+// tests its members against its own copy, so the per-member masks are not
+// kept live (in scalar registers) from one phase to the next.
+__device__ __forceinline__ int opaque(int n)
+{
+    asm volatile("" : "+s"(n));
+    return n;
+}
+
 template <int T>
 __device__ __forceinline__ void prefetch_cell(const CollideArgs &a, int cell, float *sink)
 {
@@ -942,10 +951,11 @@ __device__ __forceinline__ int lean_pass(const CollideArgs &a, int cell, unsigne
             if ((uint32_t)q < per && threadIdx.x + q * T < nb) cnt[threadIdx.x + q * T] = 0u;
         lds_barrier();
         // one Philox call per particle; count its key's bucket
+        const int n1 = opaque(n);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const int i = threadIdx.x + k * T;
-            if (i < n) {
+            if (i < n1) {
                 const W4 w = draw4(a.seed, pos[k], step, 0u, 0u);
                 key[k] = w.x;
                 w2[k] = w.z;
@@ -960,10 +970,11 @@ __device__ __forceinline__ int lean_pass(const CollideArgs &a, int cell, unsigne
         lds_excl_scan<T, G::ROWMAX>(cnt, nb, wtot);
         // slot = bucket start + arrival; members sharing their bucket post
         // their key and index there
+        const int n2 = opaque(n);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const int i = threadIdx.x + k * T;
-            if (i < n) {
+            if (i < n2) {
                 const uint32_t b = key[k] >> (32u - bits);
                 const uint32_t st = cnt[b], en = cnt[b + 1];
                 const uint32_t slot = st + pos[k];
@@ -1022,7 +1033,7 @@ __device__ __forceinline__ int lean_pass(const CollideArgs &a, int cell, unsigne
         Rec<float> *rec = (Rec<float> *)smem;
         for (uint32_t base = 0; base < np2; base += P) {
             if (base) lds_barrier();
-            lean_round<T, K>(base, P, np2, n, C, rec, vx, vy, vz, w2, w3, pos);
+            lean_round<T, K>(base, P, np2, opaque(n), C, rec, vx, vy, vz, w2, w3, pos);
         }
     } else if (MCC) {
         const W4 w = draw4(a.seed, pos[0], step, 0u, 0u);
@@ -1055,10 +1066,11 @@ __device__ __forceinline__ int lean_pass(const CollideArgs &a, int cell, unsigne
             }
         }
     }
+    const int n3 = opaque(n);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int i = threadIdx.x + k * T;
-        if (i < n) {
+        if (i < n3) {
             vx_g[i] = vx[k];
             vy_g[i] = vy[k];
             vz_g[i] = vz[k];
