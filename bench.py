@@ -1016,6 +1016,8 @@ def c2_leg(args, dtype_name):
                       f"as one persistent launch)")
     elif f32 and "class3" in kms:
         dom = ("class3", "k_collide_lean<1024,10,MCC> (cells of 4097..10240 members)")
+    elif not f32 and "class3" in kms and kms["class3"] > kms.get("huge", 0.0):
+        dom = ("class3", "k_collide_lean64<1024,10,MCC> (binary64 cells of 4097..10240 members)")
     elif not f32 and "huge" in kms:
         dom = ("huge", "segmented path of cells beyond 6144 members (k_seg_count, k_seg_scan, "
                        "k_seg_scatter, k_seg_collide, k_seg_fixup)")

@@ -879,9 +879,15 @@ static int step_enqueue(pic_ctx *c, const StepArgs &s, hipStream_t st, const uin
         RC(launch_bin_check(s.cell_of, n, n_cells, cs, c->flags, 0, &c->flags->unsorted, st));
         ktime_end(KT_SORT, st);
     }
-    const ClassCaps caps = c->tuned_valid[dtype] ? c->tuned[dtype] : collide_caps(dtype, c->lds_max);
+    ClassCaps caps = c->tuned_valid[dtype] ? c->tuned[dtype] : collide_caps(dtype, c->lds_max);
     const uint64_t mcc_thr = (s.flags & PIC_FUSE_MCC) ? mcc_threshold(s.dt, c->mcc_sigma0, c->mcc_nn) : 0;
     const bool gate = (s.flags & PIC_GATE) != 0;
+    // the plain binary64 step (no correction, no fused moment sums) runs its
+    // largest class with the lean pass, which holds cells of up to
+    // lean64_cap() members on one workgroup (not with the one-launch schedule)
+    if (dtype == PIC_F64 && !caps.unified && !(s.flags & PIC_CONSERVE_FIX) &&
+        (gate || !(s.flags & PIC_MOMENTS)) && caps.cap[3] < lean64_cap())
+        caps.cap[3] = lean64_cap();
     // cells beyond the LDS classes: several workgroups each, unless the step
     // needs whole-cell sums (conservation correction, fused moments)
     const bool seg_path = !(s.flags & PIC_CONSERVE_FIX) && (gate || !(s.flags & PIC_MOMENTS));

@@ -847,6 +847,109 @@ __device__ __forceinline__ void lean_round(uint32_t base, uint32_t P, uint32_t n
     }
 }
 
+// The member count as a value the compiler cannot see through: each phase
+// tests its members against its own copy, so the per-member masks are not
+// kept live (in scalar registers) from one phase to the next.
+__device__ __forceinline__ int opaque(int n)
+{
+    asm volatile("" : "+s"(n));
+    return n;
+}
+
+// Counting sort of a cell's members by (key, pid) in LDS, shared by the lean
+// passes (n >= 2): one Philox call per member (key, words 2 and 3, the
+// null-collision candidate bit), bucket counts, scan, placement, rank inside
+// shared buckets.  On entry pos[k] holds member k's pid, on return its
+// position in the cell's sorted order.  Contains the barriers; the sort's
+// memory is free after a further barrier.
+template <int T, int K, bool MCC>
+__device__ __forceinline__ void lean_sort(const CollideArgs &a, int n, uint32_t step,
+                                          const uint32_t *pid_c, unsigned char *smem, uint32_t *wtot,
+                                          uint32_t (&w2)[K], uint32_t (&w3)[K], uint32_t (&key)[K],
+                                          uint32_t (&pos)[K], uint32_t &cand, uint32_t &multi)
+{
+    typedef LeanGeom<T, K> G;
+    const uint32_t bits = sort_bits(n);
+    const uint32_t nb = 1u << bits;
+    const uint32_t per = nb >= (uint32_t)T ? nb / (uint32_t)T : 1u;
+    uint32_t *cnt = (uint32_t *)smem;
+    uint32_t *sk = cnt + G::CNT_WORDS;              // keys of members sharing a bucket
+    uint16_t *lst = (uint16_t *)(sk + G::CAP);      // ... and their index in the cell
+#pragma unroll
+    for (int q = 0; q < G::PERMAX; ++q)
+        if ((uint32_t)q < per && threadIdx.x + q * T < nb) cnt[threadIdx.x + q * T] = 0u;
+    lds_barrier();
+    // one Philox call per particle; count its key's bucket
+    const int n1 = opaque(n);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int i = threadIdx.x + k * T;
+        if (i < n1) {
+            const W4 w = draw4(a.seed, pos[k], step, 0u, 0u);
+            key[k] = w.x;
+            w2[k] = w.z;
+            w3[k] = w.w;
+            if (MCC && (uint64_t)w.y < a.mcc_thr) cand |= 1u << k;
+            const uint32_t b = w.x >> (32u - bits);
+            pos[k] = atomicAdd(&cnt[b], 1u);   // arrival rank in the bucket
+        }
+    }
+    lds_barrier();
+    // bucket starts (cnt[nb] = n)
+    lds_excl_scan<T, G::ROWMAX>(cnt, nb, wtot);
+    // slot = bucket start + arrival; members sharing their bucket post
+    // their key and index there
+    const int n2 = opaque(n);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int i = threadIdx.x + k * T;
+        if (i < n2) {
+            const uint32_t b = key[k] >> (32u - bits);
+            const uint32_t st = cnt[b], en = cnt[b + 1];
+            const uint32_t slot = st + pos[k];
+            pos[k] = slot;
+            if (en - st > 1u) {
+                multi |= 1u << k;
+                sk[slot] = key[k];
+                lst[slot] = (uint16_t)i;
+            }
+        }
+    }
+    lds_barrier();
+    // rank inside a shared bucket by (key, pid)
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        if ((multi >> k) & 1u) {
+            const int i = threadIdx.x + k * T;
+            const uint32_t b = key[k] >> (32u - bits);
+            const uint32_t st = cnt[b], en = cnt[b + 1];
+            const uint32_t size = en - st;
+            uint32_t r = 0, tie = 0;
+            // the first four slots without a loop (reads past the bucket
+            // stay inside the sort's memory and are ignored)
+#pragma unroll
+            for (uint32_t j = 0; j < 4; ++j) {
+                const uint32_t kj = sk[st + j];
+                const bool in = j < size;
+                r += (in && kj < key[k]) ? 1u : 0u;
+                tie |= (in && kj == key[k] && st + j != pos[k]) ? 1u : 0u;
+            }
+            for (uint32_t j = st + 4; j < en; ++j) {
+                const uint32_t kj = sk[j];
+                r += kj < key[k] ? 1u : 0u;
+                tie |= (kj == key[k] && j != pos[k]) ? 1u : 0u;
+            }
+            if (tie) {
+                // equal keys (rare): the smaller pid comes first
+                const uint32_t pi = pid_c[i];
+                for (uint32_t j = st; j < en; ++j)
+                    if (j != pos[k] && sk[j] == key[k] && pid_c[lst[j]] < pi) ++r;
+            }
+            pos[k] = st + r;
+        }
+    }
+}
+
 // The next cell's lines of pid and v are requested while this cell is still
 // being worked on, so that its loads find them in the caches (the last-level
 // cache holds every workgroup's next cell).  The loads go to LDS (a 256-byte
@@ -859,15 +962,6 @@ struct LeanNext {
     uint32_t count;
     float *sink;               // 64 words of LDS
 };
-
-// The member count as a value the compiler cannot see through: each phase
-// tests its members against its own copy, so the per-member masks are not
-// kept live (in scalar registers) from one phase to the next.
-__device__ __forceinline__ int opaque(int n)
-{
-    asm volatile("" : "+s"(n));
-    return n;
-}
 
 template <int T>
 __device__ __forceinline__ void prefetch_cell(const CollideArgs &a, int cell, float *sink)
@@ -940,85 +1034,7 @@ __device__ __forceinline__ int lean_pass(const CollideArgs &a, int cell, unsigne
     // costs nothing extra); read after a barrier below
     if (nx && threadIdx.x == 0) *nx->slot = (int)atomicAdd(nx->head, 1u);
     if (n >= 2) {
-        const uint32_t bits = sort_bits(n);
-        const uint32_t nb = 1u << bits;
-        const uint32_t per = nb >= (uint32_t)T ? nb / (uint32_t)T : 1u;
-        uint32_t *cnt = (uint32_t *)smem;
-        uint32_t *sk = cnt + G::CNT_WORDS;              // keys of members sharing a bucket
-        uint16_t *lst = (uint16_t *)(sk + G::CAP);      // ... and their index in the cell
-#pragma unroll
-        for (int q = 0; q < G::PERMAX; ++q)
-            if ((uint32_t)q < per && threadIdx.x + q * T < nb) cnt[threadIdx.x + q * T] = 0u;
-        lds_barrier();
-        // one Philox call per particle; count its key's bucket
-        const int n1 = opaque(n);
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const int i = threadIdx.x + k * T;
-            if (i < n1) {
-                const W4 w = draw4(a.seed, pos[k], step, 0u, 0u);
-                key[k] = w.x;
-                w2[k] = w.z;
-                w3[k] = w.w;
-                if (MCC && (uint64_t)w.y < a.mcc_thr) cand |= 1u << k;
-                const uint32_t b = w.x >> (32u - bits);
-                pos[k] = atomicAdd(&cnt[b], 1u);   // arrival rank in the bucket
-            }
-        }
-        lds_barrier();
-        // bucket starts (cnt[nb] = n)
-        lds_excl_scan<T, G::ROWMAX>(cnt, nb, wtot);
-        // slot = bucket start + arrival; members sharing their bucket post
-        // their key and index there
-        const int n2 = opaque(n);
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const int i = threadIdx.x + k * T;
-            if (i < n2) {
-                const uint32_t b = key[k] >> (32u - bits);
-                const uint32_t st = cnt[b], en = cnt[b + 1];
-                const uint32_t slot = st + pos[k];
-                pos[k] = slot;
-                if (en - st > 1u) {
-                    multi |= 1u << k;
-                    sk[slot] = key[k];
-                    lst[slot] = (uint16_t)i;
-                }
-            }
-        }
-        lds_barrier();
-        // rank inside a shared bucket by (key, pid)
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            if ((multi >> k) & 1u) {
-                const int i = threadIdx.x + k * T;
-                const uint32_t b = key[k] >> (32u - bits);
-                const uint32_t st = cnt[b], en = cnt[b + 1];
-                const uint32_t size = en - st;
-                uint32_t r = 0, tie = 0;
-                // the first four slots without a loop (reads past the bucket
-                // stay inside the sort's memory and are ignored)
-#pragma unroll
-                for (uint32_t j = 0; j < 4; ++j) {
-                    const uint32_t kj = sk[st + j];
-                    const bool in = j < size;
-                    r += (in && kj < key[k]) ? 1u : 0u;
-                    tie |= (in && kj == key[k] && st + j != pos[k]) ? 1u : 0u;
-                }
-                for (uint32_t j = st + 4; j < en; ++j) {
-                    const uint32_t kj = sk[j];
-                    r += kj < key[k] ? 1u : 0u;
-                    tie |= (kj == key[k] && j != pos[k]) ? 1u : 0u;
-                }
-                if (tie) {
-                    // equal keys (rare): the smaller pid comes first
-                    const uint32_t pi = pid_c[i];
-                    for (uint32_t j = st; j < en; ++j)
-                        if (j != pos[k] && sk[j] == key[k] && pid_c[lst[j]] < pi) ++r;
-                }
-                pos[k] = st + r;
-            }
-        }
+        lean_sort<T, K, MCC>(a, n, step, pid_c, smem, wtot, w2, w3, key, pos, cand, multi);
         lds_barrier();   // the sort's memory becomes the exchange records
 
         const float C = (float)cell_C(a, cell);
@@ -1104,6 +1120,243 @@ __global__ __launch_bounds__(T) void k_collide_lean(CollideArgs a, const int32_t
     int item = s_item;
     const LeanNext nx{&s_next, &a.dflags->head[cls], list, count, sink};
     while (item < (int)count) item = lean_pass<T, K, MCC>(a, list[item], smem, wtot, &nx);
+}
+
+// ------------------------------------------------------------ lean pass, binary64
+// The plain binary64 step (optionally with the fused null collisions) for
+// cells of up to T*K members on one workgroup: the lean pass's sort; then
+// every member posts its words 2 and 3 at its sorted position, and the
+// exchange runs in rounds of lean64_positions() sorted positions: the round's
+// members load their velocity and post it at their position, one thread per
+// pair computes the binary64 half change (ta_half, the oracle's order of
+// operations) and writes both members back, the round's members read their
+// record, scatter if they are null-collision candidates, and store it.  No
+// velocity or word is held in registers across a round, which leaves the
+// register file to the binary64 rotation.  The pairs, the rotation and the
+// null collisions are those of cell_pass.
+// Element i of a cell's array as a uniform base plus a 32-bit byte offset
+// (the scalar-base form of the global load and store): the offset is
+// recomputed at each use, so no 64-bit per-member address stays live across
+// the rounds.
+__device__ __forceinline__ double ld_at(const double *base, uint32_t i)
+{
+    return *(const double *)((const char *)base + (size_t)(i * 8u));
+}
+__device__ __forceinline__ void st_at(double *base, uint32_t i, double x)
+{
+    *(double *)((char *)base + (size_t)(i * 8u)) = x;
+}
+
+struct __align__(8) Rec64 {
+    double x, y, z;
+};
+
+template <int T, int K>
+struct Lean64Geom {
+    static constexpr int CAP = T * K;
+    static constexpr size_t WORDS_BYTES = (size_t)CAP * 8;   // words 2 and 3 per position
+    static constexpr uint32_t P =
+        (uint32_t)(((LEAN_LDS_LIMIT - WORDS_BYTES) / sizeof(Rec64)) & ~(size_t)63);
+    static constexpr size_t BYTES = WORDS_BYTES + (size_t)P * sizeof(Rec64);
+};
+
+template <int T, int K>
+__host__ __device__ constexpr size_t lean64_lds_bytes()
+{
+    typedef Lean64Geom<T, K> G;
+    const size_t s = LeanGeom<T, K>::SORT_BYTES;
+    return s > G::BYTES ? s : G::BYTES;
+}
+
+template <int T, int K, bool MCC>
+__device__ __forceinline__ void lean64_pass(const CollideArgs &a, int cell, unsigned char *smem,
+                                            uint32_t *wtot, float *sink)
+{
+    typedef Lean64Geom<T, K> G;
+    constexpr uint32_t P = G::P;
+    const int lo = a.cell_start[cell];
+    const int n = a.cell_start[cell + 1] - lo;
+    const uint32_t step = (uint32_t)read_step(a);
+    double *vx_g = (double *)a.v + lo;
+    double *vy_g = (double *)a.v + a.n + lo;
+    double *vz_g = (double *)a.v + 2 * a.n + lo;
+    const uint32_t *pid_c = a.pid + lo;
+
+    uint32_t pos[K];
+    uint32_t cand = 0;
+    if (n == 0) {
+        lds_barrier();
+        return;
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) pos[k] = pid_c[min((int)threadIdx.x + k * T, n - 1)];
+    // the cell's velocity lines are requested now (into an LDS sink, no
+    // register written), so that the rounds' loads find them cached
+    {
+        const uint32_t lines = ((uint32_t)n + 15u) / 16u + 1u;   // 128-byte lines of doubles
+        for (uint32_t t = threadIdx.x; t < 3u * lines; t += T) {
+            const uint32_t arr = t / lines, l = t - arr * lines;
+            const double *p = (const double *)a.v + (size_t)arr * (size_t)a.n + (uint32_t)lo +
+                              min(l * 16u, (uint32_t)n - 1u);
+            __builtin_amdgcn_global_load_lds((const void *)p, (__attribute__((address_space(3))) void *)sink,
+                                             4, 0, 0);
+        }
+    }
+    uint32_t np2 = 0;
+    if (n >= 2) {
+        {
+            uint32_t w2[K], w3[K], key[K], multi = 0;
+            lean_sort<T, K, MCC>(a, n, step, pid_c, smem, wtot, w2, w3, key, pos, cand, multi);
+            lds_barrier();   // the sort's memory becomes the words and the records
+            uint2 *words = (uint2 *)smem;
+            const int n1 = opaque(n);
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                if ((int)threadIdx.x + k * T < n1) words[pos[k]] = make_uint2(w2[k], w3[k]);
+        }
+        const uint2 *words = (const uint2 *)smem;
+        Rec64 *rec = (Rec64 *)(smem + G::WORDS_BYTES);
+        const double C = cell_C(a, cell);
+        np2 = (uint32_t)n & ~1u;
+        for (uint32_t base = 0; base < np2; base += P) {
+            if (base) lds_barrier();
+            // the thread index as a per-round value the compiler cannot hoist:
+            // each round recomputes its members' offsets instead of keeping
+            // them all live from the kernel's start
+            uint32_t tid = threadIdx.x;
+            asm volatile("" : "+v"(tid));
+            {
+                // loads in two halves, each posted before the next is loaded
+                // (all ten members' velocities at once would not fit beside
+                // the rotation's constants)
+                constexpr int H = (K + 1) / 2;
+#pragma unroll
+                for (int h = 0; h < K; h += H) {
+                    const int n4 = opaque(n);
+                    double x[H], y[H], z[H];
+#pragma unroll
+                    for (int kk = 0; kk < H; ++kk) {
+                        const int k = h + kk;
+                        if (k < K) {
+                            const int i = (int)tid + k * T;
+                            const uint32_t q = pos[k] - base;
+                            if (i < n4 && q < P && pos[k] < np2) {
+                                x[kk] = ld_at(vx_g, (uint32_t)i);
+                                y[kk] = ld_at(vy_g, (uint32_t)i);
+                                z[kk] = ld_at(vz_g, (uint32_t)i);
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int kk = 0; kk < H; ++kk) {
+                        const int k = h + kk;
+                        if (k < K) {
+                            const int i = (int)tid + k * T;
+                            const uint32_t q = pos[k] - base;
+                            if (i < n4 && q < P && pos[k] < np2) rec[q] = Rec64{x[kk], y[kk], z[kk]};
+                        }
+                    }
+                }
+            }
+            lds_barrier();
+            const uint32_t m = min(P, np2 - base) / 2;
+            for (uint32_t j = threadIdx.x; j < m; j += T) {
+                Rec64 A = rec[2 * j], B = rec[2 * j + 1];
+                const uint2 wa = words[base + 2 * j], wb = words[base + 2 * j + 1];
+                double hx, hy, hz;
+                ta_half(A.x - B.x, A.y - B.y, A.z - B.z, C, wa.x, wa.y, wb.x, hx, hy, hz);
+                A.x += hx;
+                A.y += hy;
+                A.z += hz;
+                B.x -= hx;
+                B.y -= hy;
+                B.z -= hz;
+                rec[2 * j] = A;
+                rec[2 * j + 1] = B;
+            }
+            lds_barrier();
+            // the round's members store their record (null-collision
+            // candidates after their scattering, one at a time per lane); the
+            // members' offsets and tests are recomputed, not kept from the posts
+            const int n5 = opaque(n);
+            asm volatile("" : "+v"(tid));
+            uint32_t base5 = base;
+            asm volatile("" : "+s"(base5));
+            uint32_t left = 0;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int i = (int)tid + k * T;
+                const uint32_t q = pos[k] - base5;
+                if (i < n5 && q < P && pos[k] < np2) {
+                    if (MCC && ((cand >> k) & 1u)) {
+                        left |= 1u << k;
+                    } else {
+                        const Rec64 e = rec[q];
+                        st_at(vx_g, (uint32_t)i, e.x);
+                        st_at(vy_g, (uint32_t)i, e.y);
+                        st_at(vz_g, (uint32_t)i, e.z);
+                    }
+                }
+            }
+            if constexpr (MCC) {
+                while (__ballot(left != 0u) != 0ull) {
+                    if (left) {
+                        const int kk = __builtin_ctz(left);
+                        left &= left - 1u;
+                        uint32_t pk = pos[0];
+#pragma unroll
+                        for (int k = 1; k < K; ++k)
+                            if (kk == k) pk = pos[k];
+                        const int i = (int)tid + kk * T;
+                        const Rec64 e = rec[pk - base5];
+                        double x = e.x, y = e.y, z = e.z;
+                        mcc_scatter<double>(x, y, z, pid_c[i], a.seed, step, a.mass_ratio);
+                        st_at(vx_g, (uint32_t)i, x);
+                        st_at(vy_g, (uint32_t)i, y);
+                        st_at(vz_g, (uint32_t)i, z);
+                    }
+                }
+            }
+        }
+    } else if (MCC) {
+        const W4 w = draw4(a.seed, pos[0], step, 0u, 0u);
+        if (threadIdx.x == 0 && (uint64_t)w.y < a.mcc_thr) cand = 1u;
+    }
+    // the member without a partner (odd n) keeps its velocity, apart from
+    // its null collision
+    if constexpr (MCC) {
+        uint32_t left = 0;
+        const int n6 = opaque(n);
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if ((int)threadIdx.x + k * T < n6 && ((cand >> k) & 1u) && (n < 2 || pos[k] >= np2))
+                left |= 1u << k;
+        if (left) {
+            const int kk = __builtin_ctz(left);   // at most one such member per cell
+            const int i = threadIdx.x + kk * T;
+            double x = ld_at(vx_g, (uint32_t)i), y = ld_at(vy_g, (uint32_t)i), z = ld_at(vz_g, (uint32_t)i);
+            mcc_scatter<double>(x, y, z, pid_c[i], a.seed, step, a.mass_ratio);
+            st_at(vx_g, (uint32_t)i, x);
+            st_at(vy_g, (uint32_t)i, y);
+            st_at(vz_g, (uint32_t)i, z);
+        }
+    }
+    lds_barrier();   // the next cell reuses the LDS
+}
+
+template <int T, int K, bool MCC>
+__global__ __launch_bounds__(T) void k_collide_lean64(CollideArgs a, const int32_t *__restrict__ list,
+                                                      int cls)
+{
+    // one cell per workgroup (not persistent: a loop over cells would let
+    // the compiler hoist the rotation's constants and the members' offsets
+    // to the kernel's start and keep them live through every cell)
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ uint32_t wtot[T / PIC_WAVE];
+    __shared__ float sink[PIC_WAVE];
+    if (gated_off(a)) return;
+    if (blockIdx.x >= a.dflags->count[cls]) return;
+    lean64_pass<T, K, MCC>(a, list[blockIdx.x], smem, wtot, sink);
 }
 
 // ------------------------------------------------------------ huge cells
@@ -1794,6 +2047,10 @@ static_assert(Classes<float>::T3 * Classes<float>::K3 == PIC_NOALLOC_MAX_CELL_F3
                   Classes<double>::T3 * Classes<double>::K3 == PIC_NOALLOC_MAX_CELL_F64,
               "the allocation-free step takes the cells of the LDS classes");
 
+// The binary64 lean pass: 1,024 threads of ten members (cells of up to
+// 10,240 members on one workgroup instead of the segmented path).
+constexpr int LEAN64_T = 1024, LEAN64_K = 10;
+
 // Workgroup geometry of one segment of the segmented path: the largest
 // class's (segments of 2,560 members on two 512-thread workgroups per CU
 // were slower: more segments, histograms and edge pairs).
@@ -2187,6 +2444,24 @@ int launch_class_best(const CollideArgs &a, const int32_t *list, int cls, int bl
     }
 }
 
+template <bool MCC>
+int launch_lean64(const CollideArgs &a, const int32_t *list, int cls, int blocks, hipStream_t st)
+{
+    constexpr int T = LEAN64_T, K = LEAN64_K;
+    const size_t lds = lean64_lds_bytes<T, K>();
+    auto kern = k_collide_lean64<T, K, MCC>;
+    static bool attr_done = false;
+    if (!attr_done) {
+        HIP_OK(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        attr_done = true;
+    }
+    ktime_begin(KT_CLASS0 + cls, st);
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(T), lds, st, a, list, cls);
+    ktime_end(KT_CLASS0 + cls, st);
+    HIP_OK(hipGetLastError());
+    return PIC_OK;
+}
+
 SegScratch g_seg;   // set from the workspace before each step's launches
 
 template <typename R, int T, int K, int F>
@@ -2242,9 +2517,21 @@ int launch_all(const CollideArgs &a, const int32_t *lists, int32_t n_cells, int 
                            hs, (const uint8_t *)nullptr);
     ktime_end(KT_HUGE, st);
     HIP_OK(hipGetLastError());
-    if ((live & (1u << 3)) &&
-        (rc = launch_class_best<R, C::T3, C::K3, F>(a, lists + 3 * M, 3, bp[3] * num_cu, st)))
-        return rc;
+    if (live & (1u << 3)) {
+        // binary64 plain steps whose caps widen the largest class: the lean pass
+        bool done = false;
+        if constexpr (std::is_same<R, double>::value && (F & ~F_MCC) == 0) {
+            if (caps.cap[3] > C::T3 * C::K3) {
+                // one workgroup per listed cell (the kernel is not persistent)
+                if ((rc = launch_lean64<(F & F_MCC) != 0>(a, lists + 3 * M, 3, (int)M, st)))
+                    return rc;
+                done = true;
+            }
+        }
+        if (!done &&
+            (rc = launch_class_best<R, C::T3, C::K3, F>(a, lists + 3 * M, 3, bp[3] * num_cu, st)))
+            return rc;
+    }
     if ((live & (1u << 2)) &&
         (rc = launch_class<R, C::T2, C::K2, F>(a, lists + 2 * M, 2, bp[2] * num_cu, st)))
         return rc;
@@ -2412,6 +2699,11 @@ ClassCaps collide_caps(int dtype, size_t)
 }
 
 
+
+int lean64_cap()
+{
+    return LEAN64_T * LEAN64_K;
+}
 
 size_t huge_scratch_bytes(int dtype, int64_t n)
 {

@@ -794,6 +794,9 @@ int launch_collide(int dtype, const CollideArgs &a, const int32_t *lists, int32_
 int launch_deferred(int dtype, const CollideArgs &a, const int32_t *lists, int32_t n_cells,
                     int num_cu, hipStream_t st);
 ClassCaps collide_caps(int dtype, size_t lds_per_block);
+// Largest binary64 class of the plain step when its lean pass takes it (the
+// caps of such steps are widened to it; other binary64 steps keep cap[3]).
+int lean64_cap();
 // Global scratch of the multi-block ("huge") class, indexed by particle slot.
 size_t huge_scratch_bytes(int dtype, int64_t n);
 void set_huge_scratch(int dtype, int64_t n, void *base);

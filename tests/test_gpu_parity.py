@@ -155,6 +155,22 @@ def test_fp64_c1_100_steps(ctx):
 
 
 @pytest.mark.parametrize("mcc", [False, True])
+def test_fp64_step_many_large_cells(ctx, mcc):
+    """Binary64, 600 cells of 4,097..10,240 members (more cells than the GPU has
+    compute units, ragged sizes, odd and even) plus a few small ones: one
+    step from identical input equals the oracle's, every cell."""
+    rng = np.random.default_rng(41)
+    sizes = np.concatenate([rng.integers(4097, 10241, 600), [0, 1, 3, 6144, 6145, 10240]])
+    rng.shuffle(sizes)
+    v = workloads.maxwellian_beam(rng, sizes.astype(np.int64), dtype=np.float64)
+    w = workloads._finish(rng, "f64_large", v, sizes.astype(np.int64), np.float64, mcc=True)
+    vg, cg, pg = run_gpu_step(ctx, w, w.v, "f64", 5, mcc=mcc)
+    vr, cr, pr = run_oracle_step(w, w.v, 5, mcc=mcc)
+    assert np.array_equal(cg, cr) and np.array_equal(pg, pr)
+    assert rel_err(vg, vr) < FP64_TOL, rel_err(vg, vr)
+
+
+@pytest.mark.parametrize("mcc", [False, True])
 def test_fp32_step_c2_small(ctx, mcc):
     """c2 shape at 96 cells x 10,000 (a tile-multiple plus ragged tails via the
     random storage order), one FP32 step from identical input."""
