@@ -1126,7 +1126,7 @@ __global__ __launch_bounds__(T) void k_collide_lean(CollideArgs a, const int32_t
 // The plain binary64 step (optionally with the fused null collisions) for
 // cells of up to T*K members on one workgroup: the lean pass's sort; then
 // every member posts its words 2 and 3 at its sorted position, and the
-// exchange runs in rounds of lean64_positions() sorted positions: the round's
+// exchange runs in rounds of Lean64Geom::P sorted positions: the round's
 // members load their velocity and post it at their position, one thread per
 // pair computes the binary64 half change (ta_half, the oracle's order of
 // operations) and writes both members back, the round's members read their
@@ -1134,6 +1134,7 @@ __global__ __launch_bounds__(T) void k_collide_lean(CollideArgs a, const int32_t
 // velocity or word is held in registers across a round, which leaves the
 // register file to the binary64 rotation.  The pairs, the rotation and the
 // null collisions are those of cell_pass.
+
 // Element i of a cell's array as a uniform base plus a 32-bit byte offset
 // (the scalar-base form of the global load and store): the offset is
 // recomputed at each use, so no 64-bit per-member address stays live across

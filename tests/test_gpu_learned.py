@@ -504,3 +504,41 @@ def test_short_form_train_step_counts_adam_steps(ctx):
     ctx.mlp_train_step(pd, md, vd, 1, 2e-3, x, y, bf16=True)
     ctx.sync()
     assert torch.equal(pc, pd)
+
+
+def test_gated_binary64_large_cells_match_oracle(ctx):
+    """Binary64 gated steps on cells of the binary64 lean pass (4,097..10,240
+    members) and smaller ones: the deferred cells' accumulated time step
+    (dt_scale) and the skips are applied as the oracle applies the gate's own
+    decisions, to 1e-12."""
+    import torch
+    from paper_2508_06771_amd import piccoll
+    w, cs = sorted_workload(12, [6000] * 6 + [9000, 4500, 10240, 3000, 0, 1, 7], np.float64)
+    ctx.gate_config_analytic(1e3, k_max=2, judge_fraction=0.2, tolerance=1e-3, replicas=2)
+    ctx.gate_reset()
+    ctx.set_mcc(w.sigma0, 1.0, 0.0)
+    fl = piccoll.GATE | piccoll.FUSE_MCC
+    tv, tc, tp = dev(w.v, torch.float64), dev(w.cell_of), dev(w.pid)
+    k_prev = np.zeros(w.n_cells, np.int32)
+    try:
+        ctx.coulomb_collide(tv, tc, tp, w.n_cells, dt=w.dt, lnL=w.lnL, seed=3, step=0, flags=fl)
+        ctx.sync()
+        skipped_any = collided_late = False
+        for step in (1, 2, 3, 4):
+            v_in = host(tv).copy()
+            ctx.coulomb_collide(tv, tc, tp, w.n_cells, dt=w.dt, lnL=w.lnL, seed=3, step=step,
+                                flags=fl)
+            skip, k, _, _ = ctx.gate_state(w.n_cells)
+            ctx.sync()
+            skip, k = host(skip).astype(bool), host(k)
+            skipped_any |= bool(skip.any())
+            collided_late |= bool((~skip & (k_prev > 0)).any())
+            dts = np.where(skip, 1.0, k_prev + 1.0)
+            vr, cr, prr = v_in.copy(), w.cell_of.copy(), w.pid.copy()
+            oracle.step(vr, cr, prr, w.n_cells, dt=w.dt, lnL=w.lnL, seed=3, step=step, mcc=True,
+                        sigma0=w.sigma0, n_neutral=1.0, skip=skip.astype(np.uint8), dt_scale=dts)
+            assert rel_err(host(tv), vr) < 1e-12, step
+            k_prev = k
+        assert skipped_any and collided_late
+    finally:
+        ctx.gate_reset()
