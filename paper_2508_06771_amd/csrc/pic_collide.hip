@@ -1124,16 +1124,16 @@ __global__ __launch_bounds__(T) void k_collide_lean(CollideArgs a, const int32_t
 
 // ------------------------------------------------------------ lean pass, binary64
 // The plain binary64 step (optionally with the fused null collisions) for
-// cells of up to T*K members on one workgroup: the lean pass's sort; then
-// every member posts its words 2 and 3 at its sorted position, and the
-// exchange runs in rounds of Lean64Geom::P sorted positions: the round's
-// members load their velocity and post it at their position, one thread per
-// pair computes the binary64 half change (ta_half, the oracle's order of
-// operations) and writes both members back, the round's members read their
-// record, scatter if they are null-collision candidates, and store it.  No
-// velocity or word is held in registers across a round, which leaves the
-// register file to the binary64 rotation.  The pairs, the rotation and the
-// null collisions are those of cell_pass.
+// cells of up to T*K members on one workgroup: the lean pass's sort, then the
+// exchange in rounds of Lean64Geom::P sorted positions (two for a
+// 10,000-member cell): the round's members load their velocity and post it
+// with their words 2 and 3 at their position, one thread per pair computes
+// the binary64 half change (ta_half, the oracle's order of operations) and
+// writes both members back, the round's members read their record, scatter
+// if they are null-collision candidates, and store it.  No velocity is held
+// in registers across a round, which leaves the register file to the
+// binary64 rotation.  The pairs, the rotation and the null collisions are
+// those of cell_pass.
 
 // Element i of a cell's array as a uniform base plus a 32-bit byte offset
 // (the scalar-base form of the global load and store): the offset is
@@ -1148,17 +1148,11 @@ __device__ __forceinline__ void st_at(double *base, uint32_t i, double x)
     *(double *)((char *)base + (size_t)(i * 8u)) = x;
 }
 
-struct __align__(8) Rec64 {
-    double x, y, z;
-};
-
 template <int T, int K>
 struct Lean64Geom {
     static constexpr int CAP = T * K;
-    static constexpr size_t WORDS_BYTES = (size_t)CAP * 8;   // words 2 and 3 per position
-    static constexpr uint32_t P =
-        (uint32_t)(((LEAN_LDS_LIMIT - WORDS_BYTES) / sizeof(Rec64)) & ~(size_t)63);
-    static constexpr size_t BYTES = WORDS_BYTES + (size_t)P * sizeof(Rec64);
+    static constexpr uint32_t P = (uint32_t)((LEAN_LDS_LIMIT / sizeof(Rec<double>)) & ~(size_t)63);
+    static constexpr size_t BYTES = (size_t)P * sizeof(Rec<double>);
 };
 
 template <int T, int K>
@@ -1205,18 +1199,13 @@ __device__ __forceinline__ void lean64_pass(const CollideArgs &a, int cell, unsi
     }
     uint32_t np2 = 0;
     if (n >= 2) {
+        uint32_t w2[K], w3[K];
         {
-            uint32_t w2[K], w3[K], key[K], multi = 0;
+            uint32_t key[K], multi = 0;
             lean_sort<T, K, MCC>(a, n, step, pid_c, smem, wtot, w2, w3, key, pos, cand, multi);
-            lds_barrier();   // the sort's memory becomes the words and the records
-            uint2 *words = (uint2 *)smem;
-            const int n1 = opaque(n);
-#pragma unroll
-            for (int k = 0; k < K; ++k)
-                if ((int)threadIdx.x + k * T < n1) words[pos[k]] = make_uint2(w2[k], w3[k]);
         }
-        const uint2 *words = (const uint2 *)smem;
-        Rec64 *rec = (Rec64 *)(smem + G::WORDS_BYTES);
+        lds_barrier();   // the sort's memory becomes the records
+        Rec<double> *rec = (Rec<double> *)smem;
         const double C = cell_C(a, cell);
         np2 = (uint32_t)n & ~1u;
         for (uint32_t base = 0; base < np2; base += P) {
@@ -1254,7 +1243,15 @@ __device__ __forceinline__ void lean64_pass(const CollideArgs &a, int cell, unsi
                         if (k < K) {
                             const int i = (int)tid + k * T;
                             const uint32_t q = pos[k] - base;
-                            if (i < n4 && q < P && pos[k] < np2) rec[q] = Rec64{x[kk], y[kk], z[kk]};
+                            if (i < n4 && q < P && pos[k] < np2) {
+                                Rec<double> e;
+                                e.x = x[kk];
+                                e.y = y[kk];
+                                e.z = z[kk];
+                                e.w2 = w2[k];
+                                e.pad = w3[k];
+                                rec[q] = e;
+                            }
                         }
                     }
                 }
@@ -1262,10 +1259,9 @@ __device__ __forceinline__ void lean64_pass(const CollideArgs &a, int cell, unsi
             lds_barrier();
             const uint32_t m = min(P, np2 - base) / 2;
             for (uint32_t j = threadIdx.x; j < m; j += T) {
-                Rec64 A = rec[2 * j], B = rec[2 * j + 1];
-                const uint2 wa = words[base + 2 * j], wb = words[base + 2 * j + 1];
+                Rec<double> A = rec[2 * j], B = rec[2 * j + 1];
                 double hx, hy, hz;
-                ta_half(A.x - B.x, A.y - B.y, A.z - B.z, C, wa.x, wa.y, wb.x, hx, hy, hz);
+                ta_half(A.x - B.x, A.y - B.y, A.z - B.z, C, A.w2, A.pad, B.w2, hx, hy, hz);
                 A.x += hx;
                 A.y += hy;
                 A.z += hz;
@@ -1292,7 +1288,7 @@ __device__ __forceinline__ void lean64_pass(const CollideArgs &a, int cell, unsi
                     if (MCC && ((cand >> k) & 1u)) {
                         left |= 1u << k;
                     } else {
-                        const Rec64 e = rec[q];
+                        const Rec<double> e = rec[q];
                         st_at(vx_g, (uint32_t)i, e.x);
                         st_at(vy_g, (uint32_t)i, e.y);
                         st_at(vz_g, (uint32_t)i, e.z);
@@ -1309,7 +1305,7 @@ __device__ __forceinline__ void lean64_pass(const CollideArgs &a, int cell, unsi
                         for (int k = 1; k < K; ++k)
                             if (kk == k) pk = pos[k];
                         const int i = (int)tid + kk * T;
-                        const Rec64 e = rec[pk - base5];
+                        const Rec<double> e = rec[pk - base5];
                         double x = e.x, y = e.y, z = e.z;
                         mcc_scatter<double>(x, y, z, pid_c[i], a.seed, step, a.mass_ratio);
                         st_at(vx_g, (uint32_t)i, x);
