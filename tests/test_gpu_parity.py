@@ -154,18 +154,23 @@ def test_fp64_c1_100_steps(ctx):
     assert err < FP64_TOL, err
 
 
-@pytest.mark.parametrize("mcc", [False, True])
-def test_fp64_step_many_large_cells(ctx, mcc):
+@pytest.mark.parametrize("mcc,dens", [(False, False), (True, False), (True, True)])
+def test_fp64_step_many_large_cells(ctx, mcc, dens):
     """Binary64, 600 cells of 4,097..10,240 members (more cells than the GPU has
-    compute units, ragged sizes, odd and even) plus a few small ones: one
-    step from identical input equals the oracle's, every cell."""
+    compute units, ragged sizes, odd and even: the binary64 lean pass) plus
+    the class boundaries 4,096 / 4,097 / 6,144 / 6,145 / 10,240 / 10,241, a
+    25,000-member cell (segmented path) and tiny ones; optionally per-cell
+    densities: one step from identical input equals the oracle's, every
+    cell."""
     rng = np.random.default_rng(41)
-    sizes = np.concatenate([rng.integers(4097, 10241, 600), [0, 1, 3, 6144, 6145, 10240]])
+    sizes = np.concatenate([rng.integers(4097, 10241, 600),
+                            [0, 1, 3, 4096, 4097, 6144, 6145, 10240, 10241, 25000]])
     rng.shuffle(sizes)
     v = workloads.maxwellian_beam(rng, sizes.astype(np.int64), dtype=np.float64)
     w = workloads._finish(rng, "f64_large", v, sizes.astype(np.int64), np.float64, mcc=True)
-    vg, cg, pg = run_gpu_step(ctx, w, w.v, "f64", 5, mcc=mcc)
-    vr, cr, pr = run_oracle_step(w, w.v, 5, mcc=mcc)
+    density = rng.uniform(0.5, 2.0, sizes.size) if dens else None
+    vg, cg, pg = run_gpu_step(ctx, w, w.v, "f64", 5, mcc=mcc, density=density)
+    vr, cr, pr = run_oracle_step(w, w.v, 5, mcc=mcc, density=density)
     assert np.array_equal(cg, cr) and np.array_equal(pg, pr)
     assert rel_err(vg, vr) < FP64_TOL, rel_err(vg, vr)
 
