@@ -2441,10 +2441,10 @@ int launch_class_best(const CollideArgs &a, const int32_t *list, int cls, int bl
     }
 }
 
-template <bool MCC>
+template <bool MCC, int K = LEAN64_K>
 int launch_lean64(const CollideArgs &a, const int32_t *list, int cls, int blocks, hipStream_t st)
 {
-    constexpr int T = LEAN64_T, K = LEAN64_K;
+    constexpr int T = LEAN64_T;
     const size_t lds = lean64_lds_bytes<T, K>();
     auto kern = k_collide_lean64<T, K, MCC>;
     static bool attr_done = false;
@@ -2529,9 +2529,18 @@ int launch_all(const CollideArgs &a, const int32_t *lists, int32_t n_cells, int 
             (rc = launch_class_best<R, C::T3, C::K3, F>(a, lists + 3 * M, 3, bp[3] * num_cu, st)))
             return rc;
     }
-    if ((live & (1u << 2)) &&
-        (rc = launch_class<R, C::T2, C::K2, F>(a, lists + 2 * M, 2, bp[2] * num_cu, st)))
-        return rc;
+    if (live & (1u << 2)) {
+        bool done = false;
+        if constexpr (std::is_same<R, double>::value && (F & ~F_MCC) == 0) {
+            if (caps.cap[3] > C::T3 * C::K3) {   // the binary64 plain step's lean passes
+                if ((rc = launch_lean64<(F & F_MCC) != 0, C::K2>(a, lists + 2 * M, 2, (int)M, st)))
+                    return rc;
+                done = true;
+            }
+        }
+        if (!done && (rc = launch_class<R, C::T2, C::K2, F>(a, lists + 2 * M, 2, bp[2] * num_cu, st)))
+            return rc;
+    }
     if ((live & (1u << 1)) &&
         (rc = launch_class<R, C::T1, C::K1, F>(a, lists + 1 * M, 1, bp[1] * num_cu, st)))
         return rc;
