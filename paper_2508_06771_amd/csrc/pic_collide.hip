@@ -2538,11 +2538,12 @@ int launch_all(const CollideArgs &a, const int32_t *lists, int32_t n_cells, int 
                 done = true;
             }
         }
-        if (!done && (rc = launch_class<R, C::T2, C::K2, F>(a, lists + 2 * M, 2, bp[2] * num_cu, st)))
+        if (!done &&
+            (rc = launch_class_best<R, C::T2, C::K2, F>(a, lists + 2 * M, 2, bp[2] * num_cu, st)))
             return rc;
     }
     if ((live & (1u << 1)) &&
-        (rc = launch_class<R, C::T1, C::K1, F>(a, lists + 1 * M, 1, bp[1] * num_cu, st)))
+        (rc = launch_class_best<R, C::T1, C::K1, F>(a, lists + 1 * M, 1, bp[1] * num_cu, st)))
         return rc;
     if ((live & (1u << 0)) &&
         (rc = launch_class<R, C::T0, C::K0, F>(a, lists + 0 * M, 0, bp[0] * num_cu, st)))
