@@ -711,57 +711,67 @@ __device__ __forceinline__ uint32_t wave_incl_scan_dpp(uint32_t x)
 }
 
 // Exclusive scan in place of the nb (a power of two) bucket counters, with
-// cnt[nb] = total.  With nb >= T each wave takes a contiguous run of nb / NW
-// counters in rows of 64 (lane l reads word l of the row: no bank conflicts)
-// and scans row by row with a running carry; the waves' totals are then
-// added in order.  Contains the barriers.
-template <int T, int ROWMAX>
-__device__ __forceinline__ void lds_excl_scan(uint32_t *cnt, uint32_t nb, uint32_t *wtot)
+// cnt[nb] = total.  Thread t takes the contiguous run of per = nb / T
+// counters starting at t per (one counter, or none, when nb < T): it sums
+// them, the run totals are scanned across the wave (DPP) and the waves'
+// totals added in order, then it writes its run's starts.  Contains the
+// barriers.
+template <int T, int PERMAX>
+__device__ __forceinline__ void lds_excl_scan_runs(uint32_t *cnt, uint32_t nb, uint32_t *wtot)
 {
     constexpr int NW = T / PIC_WAVE;
     const uint32_t lane = threadIdx.x & (PIC_WAVE - 1), wid = threadIdx.x / PIC_WAVE;
-    if (nb >= (uint32_t)T) {
-        const uint32_t seg = nb / NW, rows = seg / PIC_WAVE;
-        uint32_t *base = cnt + wid * seg + lane;
-        uint32_t x[ROWMAX];
-        uint32_t carry = 0;
+    const uint32_t per = nb >= (uint32_t)T ? nb / (uint32_t)T : (threadIdx.x < nb ? 1u : 0u);
+    uint32_t *run = cnt + threadIdx.x * per;
+    // the run is read twice (its sum, then its starts): no registers held
+    // across the barrier
+    uint32_t s = 0;
+    if (PERMAX >= 4 && per >= 4u) {
 #pragma unroll
-        for (int r = 0; r < ROWMAX; ++r) {
-            if ((uint32_t)r < rows) {
-                const uint32_t v = base[r * PIC_WAVE];
-                const uint32_t inc = wave_incl_scan_dpp(v);
-                x[r] = carry + inc - v;
-                carry += (uint32_t)__builtin_amdgcn_readlane((int)inc, PIC_WAVE - 1);
+        for (int c = 0; c < PERMAX; c += 4)
+            if ((uint32_t)c < per) {
+                const uint4 q = *(const uint4 *)(run + c);
+                s += (q.x + q.y) + (q.z + q.w);
             }
-        }
-        if (lane == 0) wtot[wid] = carry;
-        lds_barrier();
-        uint32_t off = 0, tot = 0;
-#pragma unroll
-        for (int w = 0; w < NW; ++w) {
-            const uint32_t t = wtot[w];
-            off += (uint32_t)w < wid ? t : 0u;
-            tot += t;
-        }
-#pragma unroll
-        for (int r = 0; r < ROWMAX; ++r)
-            if ((uint32_t)r < rows) base[r * PIC_WAVE] = off + x[r];
-        if (threadIdx.x == 0) cnt[nb] = tot;
     } else {
-        const uint32_t v = threadIdx.x < nb ? cnt[threadIdx.x] : 0u;
-        const uint32_t inc = wave_incl_scan_dpp(v);
-        if (lane == PIC_WAVE - 1) wtot[wid] = inc;
-        lds_barrier();
-        uint32_t off = 0, tot = 0;
 #pragma unroll
-        for (int w = 0; w < NW; ++w) {
-            const uint32_t t = wtot[w];
-            off += (uint32_t)w < wid ? t : 0u;
-            tot += t;
-        }
-        if (threadIdx.x < nb) cnt[threadIdx.x] = off + inc - v;
-        if (threadIdx.x == 0) cnt[nb] = tot;
+        for (int c = 0; c < (PERMAX < 4 ? PERMAX : 4); ++c)
+            if ((uint32_t)c < per) s += run[c];
     }
+    const uint32_t inc = wave_incl_scan_dpp(s);
+    if (lane == PIC_WAVE - 1) wtot[wid] = inc;
+    lds_barrier();
+    uint32_t off = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        const uint32_t t = wtot[w];
+        off += (uint32_t)w < wid ? t : 0u;
+        tot += t;
+    }
+    uint32_t r = off + inc - s;
+    if (PERMAX >= 4 && per >= 4u) {
+#pragma unroll
+        for (int c = 0; c < PERMAX; c += 4)
+            if ((uint32_t)c < per) {
+                const uint4 x = *(const uint4 *)(run + c);
+                uint4 q;
+                q.x = r;
+                q.y = q.x + x.x;
+                q.z = q.y + x.y;
+                q.w = q.z + x.z;
+                r = q.w + x.w;
+                *(uint4 *)(run + c) = q;
+            }
+    } else {
+#pragma unroll
+        for (int c = 0; c < (PERMAX < 4 ? PERMAX : 4); ++c)
+            if ((uint32_t)c < per) {
+                const uint32_t x = run[c];
+                run[c] = r;
+                r += x;
+            }
+    }
+    if (threadIdx.x == 0) cnt[nb] = tot;
     lds_barrier();
 }
 
@@ -770,9 +780,8 @@ struct LeanGeom {
     static constexpr int CAP = T * K;
     static constexpr int NBMAX = (int)next_pow2((uint32_t)CAP);
     static constexpr int PERMAX = NBMAX >= T ? NBMAX / T : 1;   // counters per thread
-    static constexpr int ROWMAX = NBMAX >= T ? NBMAX / T : 1;   // scan rows per wave
     static constexpr size_t CNT_WORDS = (size_t)NBMAX + 4;      // counters, starts, end
-    static constexpr size_t SORT_BYTES = CNT_WORDS * 4 + (size_t)CAP * 4 + (size_t)CAP * 2;
+    static constexpr size_t SORT_BYTES = CNT_WORDS * 4 + ((size_t)CAP + 4) * 4 + (size_t)CAP * 2;
 };
 
 // Dynamic LDS the lean pass may use (its static part is below 512 bytes).
@@ -858,23 +867,23 @@ __device__ __forceinline__ int opaque(int n)
 
 // Counting sort of a cell's members by (key, pid) in LDS, shared by the lean
 // passes (n >= 2): one Philox call per member (key, words 2 and 3, the
-// null-collision candidate bit), bucket counts, scan, placement, rank inside
-// shared buckets.  On entry pos[k] holds member k's pid, on return its
-// position in the cell's sorted order.  Contains the barriers; the sort's
-// memory is free after a further barrier.
+// null-collision candidate bit), bucket counts (at least one bucket per
+// member), scan, placement, rank inside the buckets.  On entry pos[k] holds
+// member k's pid, on return its position in the cell's sorted order.
+// Contains the barriers; the sort's memory is free after a further barrier.
 template <int T, int K, bool MCC>
 __device__ __forceinline__ void lean_sort(const CollideArgs &a, int n, uint32_t step,
                                           const uint32_t *pid_c, unsigned char *smem, uint32_t *wtot,
                                           uint32_t (&w2)[K], uint32_t (&w3)[K], uint32_t (&key)[K],
-                                          uint32_t (&pos)[K], uint32_t &cand, uint32_t &multi)
+                                          uint32_t (&pos)[K], uint32_t &cand)
 {
     typedef LeanGeom<T, K> G;
     const uint32_t bits = sort_bits(n);
     const uint32_t nb = 1u << bits;
     const uint32_t per = nb >= (uint32_t)T ? nb / (uint32_t)T : 1u;
     uint32_t *cnt = (uint32_t *)smem;
-    uint32_t *sk = cnt + G::CNT_WORDS;              // keys of members sharing a bucket
-    uint16_t *lst = (uint16_t *)(sk + G::CAP);      // ... and their index in the cell
+    uint32_t *sk = cnt + G::CNT_WORDS;              // keys in sorted-slot order
+    uint16_t *lst = (uint16_t *)(sk + G::CAP + 4);  // ... and their index in the cell
 #pragma unroll
     for (int q = 0; q < G::PERMAX; ++q)
         if ((uint32_t)q < per && threadIdx.x + q * T < nb) cnt[threadIdx.x + q * T] = 0u;
@@ -896,54 +905,56 @@ __device__ __forceinline__ void lean_sort(const CollideArgs &a, int n, uint32_t 
     }
     lds_barrier();
     // bucket starts (cnt[nb] = n)
-    lds_excl_scan<T, G::ROWMAX>(cnt, nb, wtot);
-    // slot = bucket start + arrival; members sharing their bucket post
-    // their key and index there
+    lds_excl_scan_runs<T, G::PERMAX>(cnt, nb, wtot);
+    // slot = bucket start + arrival.  Every member posts its key at its slot
+    // (the three slots past the last hold the largest key), members sharing
+    // their bucket also their index; pos[k] becomes the bucket's start with
+    // its size (15: 15 or more) in the top four bits.
     const int n2 = opaque(n);
+    if (threadIdx.x < 3) sk[n2 + threadIdx.x] = 0xffffffffu;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int i = threadIdx.x + k * T;
         if (i < n2) {
             const uint32_t b = key[k] >> (32u - bits);
-            const uint32_t st = cnt[b], en = cnt[b + 1];
+            const uint32_t st = cnt[b], size = cnt[b + 1] - st;
             const uint32_t slot = st + pos[k];
-            pos[k] = slot;
-            if (en - st > 1u) {
-                multi |= 1u << k;
-                sk[slot] = key[k];
-                lst[slot] = (uint16_t)i;
-            }
+            sk[slot] = key[k];
+            if (size > 1u) lst[slot] = (uint16_t)i;
+            pos[k] = st | (min(size, 15u) << 28);
         }
     }
     lds_barrier();
-    // rank inside a shared bucket by (key, pid)
+    // rank by (key, pid) inside the bucket: the keys below this one among
+    // the four slots from the bucket's start (slots of later buckets hold
+    // larger keys) and the rest of the bucket
+    const int n3 = opaque(n);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        if ((multi >> k) & 1u) {
-            const int i = threadIdx.x + k * T;
-            const uint32_t b = key[k] >> (32u - bits);
-            const uint32_t st = cnt[b], en = cnt[b + 1];
-            const uint32_t size = en - st;
-            uint32_t r = 0, tie = 0;
-            // the first four slots without a loop (reads past the bucket
-            // stay inside the sort's memory and are ignored)
+        const int i = threadIdx.x + k * T;
+        if (i < n3) {
+            const uint32_t st = pos[k] & 0x0fffffffu;
+            uint32_t size = pos[k] >> 28;
+            uint32_t r = 0, e = 0;
 #pragma unroll
             for (uint32_t j = 0; j < 4; ++j) {
                 const uint32_t kj = sk[st + j];
-                const bool in = j < size;
-                r += (in && kj < key[k]) ? 1u : 0u;
-                tie |= (in && kj == key[k] && st + j != pos[k]) ? 1u : 0u;
-            }
-            for (uint32_t j = st + 4; j < en; ++j) {
-                const uint32_t kj = sk[j];
                 r += kj < key[k] ? 1u : 0u;
-                tie |= (kj == key[k] && j != pos[k]) ? 1u : 0u;
+                e += kj == key[k] ? 1u : 0u;
             }
-            if (tie) {
+            if (size > 4u) {
+                if (size == 15u) size = cnt[(key[k] >> (32u - bits)) + 1u] - st;
+                for (uint32_t j = st + 4u; j < st + size; ++j) {
+                    const uint32_t kj = sk[j];
+                    r += kj < key[k] ? 1u : 0u;
+                    e += kj == key[k] ? 1u : 0u;
+                }
+            }
+            if (e > 1u && size > 1u) {
                 // equal keys (rare): the smaller pid comes first
                 const uint32_t pi = pid_c[i];
-                for (uint32_t j = st; j < en; ++j)
-                    if (j != pos[k] && sk[j] == key[k] && pid_c[lst[j]] < pi) ++r;
+                for (uint32_t j = st; j < st + size; ++j)
+                    if (sk[j] == key[k] && pid_c[lst[j]] < pi) ++r;
             }
             pos[k] = st + r;
         }
@@ -1002,7 +1013,7 @@ __device__ __forceinline__ int lean_pass(const CollideArgs &a, int cell, unsigne
 
     float vx[K], vy[K], vz[K];
     uint32_t w2[K], w3[K], key[K], pos[K];
-    uint32_t cand = 0, multi = 0;
+    uint32_t cand = 0;
 
     int next = 0;
     if (n == 0) {
@@ -1034,7 +1045,7 @@ __device__ __forceinline__ int lean_pass(const CollideArgs &a, int cell, unsigne
     // costs nothing extra); read after a barrier below
     if (nx && threadIdx.x == 0) *nx->slot = (int)atomicAdd(nx->head, 1u);
     if (n >= 2) {
-        lean_sort<T, K, MCC>(a, n, step, pid_c, smem, wtot, w2, w3, key, pos, cand, multi);
+        lean_sort<T, K, MCC>(a, n, step, pid_c, smem, wtot, w2, w3, key, pos, cand);
         lds_barrier();   // the sort's memory becomes the exchange records
 
         const float C = (float)cell_C(a, cell);
@@ -1201,8 +1212,8 @@ __device__ __forceinline__ void lean64_pass(const CollideArgs &a, int cell, unsi
     if (n >= 2) {
         uint32_t w2[K], w3[K];
         {
-            uint32_t key[K], multi = 0;
-            lean_sort<T, K, MCC>(a, n, step, pid_c, smem, wtot, w2, w3, key, pos, cand, multi);
+            uint32_t key[K];
+            lean_sort<T, K, MCC>(a, n, step, pid_c, smem, wtot, w2, w3, key, pos, cand);
         }
         lds_barrier();   // the sort's memory becomes the records
         Rec<double> *rec = (Rec<double> *)smem;
