@@ -804,19 +804,23 @@ __host__ __device__ constexpr size_t lean_lds_bytes()
 }
 
 // One exchange round over the sorted positions [base, base + P): members post
-// (velocity, word) at their position, one thread per pair rotates, members
+// (velocity, word) at their position (the unpaired last one too), one thread
+// per pair rotates, null-collision candidates scatter their records, members
 // read their record back.  Contains the barriers.
-template <int T, int K>
+template <int T, int K, bool MCC>
 __device__ __forceinline__ void lean_round(uint32_t base, uint32_t P, uint32_t np2, int n, float C,
                                            Rec<float> *rec, float (&vx)[K], float (&vy)[K],
                                            float (&vz)[K], const uint32_t (&w2)[K],
-                                           const uint32_t (&w3)[K], const uint32_t (&pos)[K])
+                                           const uint32_t (&w3)[K], const uint32_t (&pos)[K],
+                                           uint32_t &cand, int kf, uint32_t cpid,
+                                           const uint32_t *pid_c, const CollideArgs &a,
+                                           uint32_t step)
 {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int i = threadIdx.x + k * T;
         const uint32_t q = pos[k] - base;
-        if (i < n && q < P && pos[k] < np2) {
+        if (i < n && q < P) {
             // first members carry their deviate, second ones word 2
             const float z = ta_z(w2[k], w3[k]);
             Rec<float> e;
@@ -843,11 +847,38 @@ __device__ __forceinline__ void lean_round(uint32_t base, uint32_t P, uint32_t n
         rec[2 * j + 1] = B;
     }
     lds_barrier();
+    // null collisions of this round's candidates, on their own records (each
+    // record is read back by its member's thread only, so no barrier), one
+    // candidate at a time per lane; the pid of the thread's first candidate
+    // (member kf) was kept from the sort
+    if constexpr (MCC) {
+        uint32_t left = cand, later = 0;
+        while (__ballot(left != 0u) != 0ull) {
+            if (left) {
+                const int kk = __builtin_ctz(left);
+                left &= left - 1u;
+                uint32_t pk = pos[0];
+#pragma unroll
+                for (int k = 1; k < K; ++k)
+                    if (kk == k) pk = pos[k];
+                const uint32_t q = pk - base;
+                if (q < P) {
+                    const uint32_t id = kk == kf ? cpid : pid_c[threadIdx.x + kk * T];
+                    Rec<float> e = rec[q];
+                    mcc_scatter<float>(e.x, e.y, e.z, id, a.seed, step, a.mass_ratio);
+                    rec[q] = e;
+                } else {
+                    later |= 1u << kk;
+                }
+            }
+        }
+        cand = later;
+    }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int i = threadIdx.x + k * T;
         const uint32_t q = pos[k] - base;
-        if (i < n && q < P && pos[k] < np2) {
+        if (i < n && q < P) {
             const Rec<float> e = rec[q];
             vx[k] = e.x;
             vy[k] = e.y;
@@ -867,7 +898,8 @@ __device__ __forceinline__ int opaque(int n)
 
 // Counting sort of a cell's members by (key, pid) in LDS, shared by the lean
 // passes (n >= 2): one Philox call per member (key, words 2 and 3, the
-// null-collision candidate bit), bucket counts (at least one bucket per
+// null-collision candidate bit; cpid: the pid of the thread's first
+// candidate), bucket counts (at least one bucket per
 // member), scan, placement, rank inside the buckets.  On entry pos[k] holds
 // member k's pid, on return its position in the cell's sorted order.
 // Contains the barriers; the sort's memory is free after a further barrier.
@@ -875,7 +907,7 @@ template <int T, int K, bool MCC>
 __device__ __forceinline__ void lean_sort(const CollideArgs &a, int n, uint32_t step,
                                           const uint32_t *pid_c, unsigned char *smem, uint32_t *wtot,
                                           uint32_t (&w2)[K], uint32_t (&w3)[K], uint32_t (&key)[K],
-                                          uint32_t (&pos)[K], uint32_t &cand)
+                                          uint32_t (&pos)[K], uint32_t &cand, uint32_t &cpid)
 {
     typedef LeanGeom<T, K> G;
     const uint32_t bits = sort_bits(n);
@@ -898,7 +930,10 @@ __device__ __forceinline__ void lean_sort(const CollideArgs &a, int n, uint32_t 
             key[k] = w.x;
             w2[k] = w.z;
             w3[k] = w.w;
-            if (MCC && (uint64_t)w.y < a.mcc_thr) cand |= 1u << k;
+            if (MCC && (uint64_t)w.y < a.mcc_thr) {
+                if (!cand) cpid = pos[k];
+                cand |= 1u << k;
+            }
             const uint32_t b = w.x >> (32u - bits);
             pos[k] = atomicAdd(&cnt[b], 1u);   // arrival rank in the bucket
         }
@@ -1045,7 +1080,8 @@ __device__ __forceinline__ int lean_pass(const CollideArgs &a, int cell, unsigne
     // costs nothing extra); read after a barrier below
     if (nx && threadIdx.x == 0) *nx->slot = (int)atomicAdd(nx->head, 1u);
     if (n >= 2) {
-        lean_sort<T, K, MCC>(a, n, step, pid_c, smem, wtot, w2, w3, key, pos, cand);
+        uint32_t cpid = 0;
+        lean_sort<T, K, MCC>(a, n, step, pid_c, smem, wtot, w2, w3, key, pos, cand, cpid);
         lds_barrier();   // the sort's memory becomes the exchange records
 
         const float C = (float)cell_C(a, cell);
@@ -1058,41 +1094,20 @@ __device__ __forceinline__ int lean_pass(const CollideArgs &a, int cell, unsigne
         }
         const uint32_t np2 = (uint32_t)n & ~1u;     // positions with a partner
         Rec<float> *rec = (Rec<float> *)smem;
-        for (uint32_t base = 0; base < np2; base += P) {
+        const int kf = cand ? __builtin_ctz(cand) : K;
+        for (uint32_t base = 0; base < (uint32_t)n; base += P) {
             if (base) lds_barrier();
-            lean_round<T, K>(base, P, np2, opaque(n), C, rec, vx, vy, vz, w2, w3, pos);
+            lean_round<T, K, MCC>(base, P, np2, opaque(n), C, rec, vx, vy, vz, w2, w3, pos, cand,
+                                  kf, cpid, pid_c, a, step);
         }
     } else if (MCC) {
         const W4 w = draw4(a.seed, pos[0], step, 0u, 0u);
         if (threadIdx.x == 0 && (uint64_t)w.y < a.mcc_thr) cand = 1u;
     }
 
-    // null collisions, one candidate at a time per lane (as in cell_pass)
-    if constexpr (MCC) {
-        uint32_t left = cand;
-        while (__ballot(left != 0u) != 0ull) {
-            if (left) {
-                const int kk = __builtin_ctz(left);
-                left &= left - 1u;
-                float x = vx[0], y = vy[0], z = vz[0];
-#pragma unroll
-                for (int k = 1; k < K; ++k)
-                    if (kk == k) {
-                        x = vx[k];
-                        y = vy[k];
-                        z = vz[k];
-                    }
-                mcc_scatter<float>(x, y, z, pid_c[threadIdx.x + kk * T], a.seed, step, a.mass_ratio);
-#pragma unroll
-                for (int k = 0; k < K; ++k)
-                    if (kk == k) {
-                        vx[k] = x;
-                        vy[k] = y;
-                        vz[k] = z;
-                    }
-            }
-        }
-    }
+    // null collision of a lone member (n = 1: thread 0's member 0, whose pid
+    // is in pos[0]; the exchange rounds took every candidate of a larger cell)
+    if (MCC && cand) mcc_scatter<float>(vx[0], vy[0], vz[0], pos[0], a.seed, step, a.mass_ratio);
     const int n3 = opaque(n);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -1212,8 +1227,8 @@ __device__ __forceinline__ void lean64_pass(const CollideArgs &a, int cell, unsi
     if (n >= 2) {
         uint32_t w2[K], w3[K];
         {
-            uint32_t key[K];
-            lean_sort<T, K, MCC>(a, n, step, pid_c, smem, wtot, w2, w3, key, pos, cand);
+            uint32_t key[K], cpid = 0;
+            lean_sort<T, K, MCC>(a, n, step, pid_c, smem, wtot, w2, w3, key, pos, cand, cpid);
         }
         lds_barrier();   // the sort's memory becomes the records
         Rec<double> *rec = (Rec<double> *)smem;

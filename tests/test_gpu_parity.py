@@ -194,6 +194,25 @@ def ragged_workload(seed, sizes, dtype=np.float32):
     return workloads._finish(rng, "ragged", v, sizes, dtype, mcc=True)
 
 
+def test_fp32_two_round_cells_dense_mcc(ctx):
+    """Binary32 cells just above what one exchange round of the largest class
+    holds (10,177..10,240 members: two rounds, an odd cell's unpaired member
+    in the second), beside cells of the smaller classes, with a
+    null-collision probability of about 0.33, so that most threads scatter
+    several members, in both rounds, with a mass ratio: one step equals the
+    oracle's, every member."""
+    import dataclasses
+    sizes = [10177, 10239, 10240, 10200, 10178, 9999, 600, 2047, 3001, 4096, 1, 2, 3, 0]
+    w = ragged_workload(13, sizes, np.float32)
+    w = dataclasses.replace(w, n_neutral=w.n_neutral * 40, mass_ratio=1e-3)
+    p_null = oracle.mcc_threshold(w.dt, w.sigma0, w.n_neutral) / 2.0 ** 32
+    assert 0.2 < p_null < 0.5, p_null
+    vg, cg, pg = run_gpu_step(ctx, w, w.v, "f32", 4, mcc=True)
+    vr, cr, pr = run_oracle_step(w, w.v.astype(np.float64), 4, mcc=True)
+    assert np.array_equal(cg, cr) and np.array_equal(pg, pr)
+    assert rel_err(vg, vr) < FP32_TOL, rel_err(vg, vr)
+
+
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 def test_ragged_cells_all_classes(ctx, dtype):
     """Cell sizes spanning every size class, empty and single-member cells and
