@@ -41,10 +41,11 @@ constexpr double PI_D = 3.14159265358979323846;
 // azimuth.  The rotation keeps |u|: u' = u cos T + |u| sin T (cos P e1 + sin P e2).
 // The standard normal deviate of the pair from words 2, 3 of its first member
 // (Box-Muller, cosine branch; the hardware log is base 2 and the cosine takes
-// revolutions).
+// revolutions; the hardware square root, within 1 ulp, where the correctly
+// rounded one costs about 16 more instructions).
 __device__ __forceinline__ float ta_z(uint32_t wa2, uint32_t wa3)
 {
-    return __builtin_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u01f(wa2))) *
+    return __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u01f(wa2))) *
            __builtin_amdgcn_cosf(u01f(wa3));
 }
 
@@ -57,7 +58,7 @@ __device__ __forceinline__ void ta_half_z(float ux, float uy, float uz, float C,
     if (!(uu >= FLT_MIN)) return;   // u = 0 (or below the normal range): no change
     const float rinv = __builtin_amdgcn_rsqf(uu);     // 1 / |u|
     const float um = uu * rinv;                        // |u|
-    const float s = __builtin_sqrtf(C * rinv * rinv * rinv);
+    const float s = __builtin_amdgcn_sqrtf(C * rinv * rinv * rinv);
     const float d = s * z;
     // sin T = 2d / (1 + d^2), 1 - cos T = 2 d^2 / (1 + d^2); for |d| > 1 the
     // same ratios in t = 1/d avoid overflow of d^2.

@@ -153,7 +153,8 @@ __device__ __forceinline__ T nb_omc(T A, T U)
 // ---------------------------------------------------------------------------
 // Elastic isotropic scattering of a null-collision candidate from its domain-1
 // draw w: cos(theta) = 1 - 2 U(w.y), phi = 2 pi U(w.z) (binary32: the hardware
-// sine/cosine take revolutions), |v'|^2 = |v|^2 (1 - 2 (m/M) (1 - vhat.s)).
+// sine/cosine take revolutions, the hardware square root is within 1 ulp),
+// |v'|^2 = |v|^2 (1 - 2 (m/M) (1 - vhat.s)).
 // The cross section sigma0 E^-1/2 gives the speed-independent frequency
 // nu = n_n sigma0 sqrt(2) = nu_max, so the real/null test U(w.x) nu_max < nu
 // always passes and is not evaluated.
@@ -164,14 +165,14 @@ __device__ __forceinline__ void scatter_dir(float &vx, float &vy, float &vz, con
     // no contraction: the fused and the stand-alone step round identically
 #pragma clang fp contract(off)
     const float ct = 1.0f - 2.0f * u01f(w.y);
-    const float st = __builtin_sqrtf(fmaxf(0.0f, 1.0f - ct * ct));
+    const float st = __builtin_amdgcn_sqrtf(fmaxf(0.0f, 1.0f - ct * ct));
     const float up = u01f(w.z);
     const float sx = st * __builtin_amdgcn_cosf(up), sy = st * __builtin_amdgcn_sinf(up), sz = ct;
-    const float sp = __builtin_sqrtf(vx * vx + vy * vy + vz * vz);
+    const float sp = __builtin_amdgcn_sqrtf(vx * vx + vy * vy + vz * vz);
     float scale = sp;
     if (mass_ratio != 0.0 && sp > 0.0f) {
         const float cosx = (vx * sx + vy * sy + vz * sz) / sp;
-        scale = sp * __builtin_sqrtf(1.0f - 2.0f * (float)mass_ratio * (1.0f - cosx));
+        scale = sp * __builtin_amdgcn_sqrtf(1.0f - 2.0f * (float)mass_ratio * (1.0f - cosx));
     }
     vx = scale * sx;
     vy = scale * sy;
