@@ -864,7 +864,14 @@ __device__ __forceinline__ void lean_round(uint32_t base, uint32_t P, uint32_t n
                     if (kk == k) pk = pos[k];
                 const uint32_t q = pk - base;
                 if (q < P) {
-                    const uint32_t id = kk == kf ? cpid : pid_c[threadIdx.x + kk * T];
+                    uint32_t id = cpid;
+                    if (kk != kf) {
+                        // a later candidate (rare): its pid from memory, waited
+                        // for here, so that the common path does not wait for
+                        // the next cell's lines requested above
+                        id = pid_c[threadIdx.x + kk * T];
+                        asm volatile("" ::"v"(id));
+                    }
                     Rec<float> e = rec[q];
                     mcc_scatter<float>(e.x, e.y, e.z, id, a.seed, step, a.mass_ratio);
                     rec[q] = e;
@@ -887,6 +894,10 @@ __device__ __forceinline__ void lean_round(uint32_t base, uint32_t P, uint32_t n
         }
     }
 }
+
+// s_waitcnt operand that waits for vector memory only: vmcnt (bits 3:0 and
+// 15:14) 0, expcnt (6:4) and lgkmcnt (11:8) at their maxima.
+constexpr int WAIT_VMCNT0 = 0x0F70;
 
 // The member count as a value the compiler cannot see through: each phase
 // tests its members against its own copy, so the per-member masks are not
@@ -1109,6 +1120,11 @@ __device__ __forceinline__ int lean_pass(const CollideArgs &a, int cell, unsigne
     // null collision of a lone member (n = 1: thread 0's member 0, whose pid
     // is in pos[0]; the exchange rounds took every candidate of a larger cell)
     if (MCC && cand) mcc_scatter<float>(vx[0], vy[0], vz[0], pos[0], a.seed, step, a.mass_ratio);
+    // one wait for every load still outstanding (the next cell's lines,
+    // requested long before) ahead of the stores: the compiler would otherwise
+    // wait before each member's stores, and each wait drains the stores
+    // before it too
+    if (nx) __builtin_amdgcn_s_waitcnt(WAIT_VMCNT0);
     const int n3 = opaque(n);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
