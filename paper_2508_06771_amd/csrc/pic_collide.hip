@@ -895,6 +895,20 @@ __device__ __forceinline__ void lean_round(uint32_t base, uint32_t P, uint32_t n
     }
 }
 
+// Element i of a cell's array as a uniform base plus a 32-bit byte offset
+// (the scalar-base form of the global load and store): no 64-bit
+// per-member address is formed or kept live.
+template <typename X>
+__device__ __forceinline__ X ld_at(const X *base, uint32_t i)
+{
+    return *(const X *)((const char *)base + (size_t)(i * (uint32_t)sizeof(X)));
+}
+template <typename X>
+__device__ __forceinline__ void st_at(X *base, uint32_t i, X x)
+{
+    *(X *)((char *)base + (size_t)(i * (uint32_t)sizeof(X))) = x;
+}
+
 // s_waitcnt operand that waits for vector memory only: vmcnt (bits 3:0 and
 // 15:14) 0, expcnt (6:4) and lgkmcnt (11:8) at their maxima.
 constexpr int WAIT_VMCNT0 = 0x0F70;
@@ -983,11 +997,15 @@ __device__ __forceinline__ void lean_sort(const CollideArgs &a, int n, uint32_t 
             const uint32_t st = pos[k] & 0x0fffffffu;
             uint32_t size = pos[k] >> 28;
             uint32_t r = 0, e = 0;
+            uint32_t kj[4];
+#pragma unroll
+            for (uint32_t j = 0; j < 4; ++j) kj[j] = sk[st + j];
+            // one wait for the four reads
+            asm volatile("" ::"v"(kj[0]), "v"(kj[1]), "v"(kj[2]), "v"(kj[3]));
 #pragma unroll
             for (uint32_t j = 0; j < 4; ++j) {
-                const uint32_t kj = sk[st + j];
-                r += kj < key[k] ? 1u : 0u;
-                e += kj == key[k] ? 1u : 0u;
+                r += kj[j] < key[k] ? 1u : 0u;
+                e += kj[j] == key[k] ? 1u : 0u;
             }
             if (size > 4u) {
                 if (size == 15u) size = cnt[(key[k] >> (32u - bits)) + 1u] - st;
@@ -1075,17 +1093,17 @@ __device__ __forceinline__ int lean_pass(const CollideArgs &a, int cell, unsigne
     // load the last one instead (ignored): with no branch around the loads the
     // compiler waits for each load by count instead of for all of them.
     {
-        int ic[K];
+        uint32_t ic[K];
 #pragma unroll
-        for (int k = 0; k < K; ++k) ic[k] = min((int)threadIdx.x + k * T, n - 1);
+        for (int k = 0; k < K; ++k) ic[k] = (uint32_t)min((int)threadIdx.x + k * T, n - 1);
 #pragma unroll
-        for (int k = 0; k < K; ++k) pos[k] = pid_c[ic[k]];
+        for (int k = 0; k < K; ++k) pos[k] = ld_at(pid_c, ic[k]);
         asm volatile("" ::: "memory");   // keep the id loads ahead of the velocity loads
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            vx[k] = vx_g[ic[k]];
-            vy[k] = vy_g[ic[k]];
-            vz[k] = vz_g[ic[k]];
+            vx[k] = ld_at((const float *)vx_g, ic[k]);
+            vy[k] = ld_at((const float *)vy_g, ic[k]);
+            vz[k] = ld_at((const float *)vz_g, ic[k]);
         }
     }
     // the next work item (issued behind this cell's loads, so waiting for it
@@ -1178,18 +1196,6 @@ __global__ __launch_bounds__(T) void k_collide_lean(CollideArgs a, const int32_t
 // binary64 rotation.  The pairs, the rotation and the null collisions are
 // those of cell_pass.
 
-// Element i of a cell's array as a uniform base plus a 32-bit byte offset
-// (the scalar-base form of the global load and store): the offset is
-// recomputed at each use, so no 64-bit per-member address stays live across
-// the rounds.
-__device__ __forceinline__ double ld_at(const double *base, uint32_t i)
-{
-    return *(const double *)((const char *)base + (size_t)(i * 8u));
-}
-__device__ __forceinline__ void st_at(double *base, uint32_t i, double x)
-{
-    *(double *)((char *)base + (size_t)(i * 8u)) = x;
-}
 
 template <int T, int K>
 struct Lean64Geom {
