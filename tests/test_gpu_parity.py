@@ -194,6 +194,49 @@ def ragged_workload(seed, sizes, dtype=np.float32):
     return workloads._finish(rng, "ragged", v, sizes, dtype, mcc=True)
 
 
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_crowded_bucket_and_equal_keys(ctx, dtype):
+    """Cells of 10,000, 3,000 and 600 members (binary32: the lean passes of
+    three size classes; binary64: the lean pass at ten and at four members
+    per thread, and the class kernel) whose pids are chosen so that 20
+    members share one sort bucket (past the rank's four unrolled slots and
+    past the 15 its size field holds) and two members have the same 32-bit
+    key (the pid tie-break): one step with null collisions equals the
+    oracle's, every member."""
+    import dataclasses
+    pool = np.arange(400000, dtype=np.uint32)
+    keys = oracle.philox_fill(0, 0, 0, pool)[:, 0]
+    o = np.argsort(keys, kind="stable")
+    dup = np.flatnonzero(keys[o][1:] == keys[o][:-1])
+    assert dup.size >= 3
+    rng = np.random.default_rng(17)
+    used, cells = set(), []
+    for c, n in enumerate((10000, 3000, 600)):
+        bits = int(np.ceil(np.log2(n)))
+        a, b = int(o[dup[c]]), int(o[dup[c] + 1])
+        top = keys >> np.uint32(32 - bits)
+        vals, counts = np.unique(top, return_counts=True)
+        crowd = [int(p) for p in np.flatnonzero(top == vals[np.argmax(counts)])
+                 if int(p) not in used and int(p) not in (a, b)][:20]
+        assert len(crowd) == 20
+        members = [a, b] + crowd
+        used.update(members)
+        fill = [int(p) for p in rng.permutation(pool)[:2 * n] if int(p) not in used][:n - len(members)]
+        used.update(fill)
+        cell = np.array(members + fill, dtype=np.uint32)
+        cells.append(cell[rng.permutation(n)])
+    sizes = np.array([c.size for c in cells], dtype=np.int64)
+    v = workloads.maxwellian_beam(rng, sizes, dtype=np.float32 if dtype == "f32" else np.float64)
+    w = workloads._finish(rng, "crowded", v, sizes, np.float32 if dtype == "f32" else np.float64,
+                          shuffle=False, mcc=True)
+    w = dataclasses.replace(w, pid=np.concatenate(cells))
+    vg, cg, pg = run_gpu_step(ctx, w, w.v, dtype, 0, mcc=True)
+    vr, cr, pr = run_oracle_step(w, w.v.astype(np.float64), 0, mcc=True)
+    assert np.array_equal(cg, cr) and np.array_equal(pg, pr)
+    tol = FP32_TOL if dtype == "f32" else FP64_TOL
+    assert rel_err(vg, vr) < tol, rel_err(vg, vr)
+
+
 def test_fp32_two_round_cells_dense_mcc(ctx):
     """Binary32 cells just above what one exchange round of the largest class
     holds (10,177..10,240 members: two rounds, an odd cell's unpaired member
