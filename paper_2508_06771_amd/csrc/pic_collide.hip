@@ -929,7 +929,7 @@ __device__ __forceinline__ int opaque(int n)
 // member), scan, placement, rank inside the buckets.  On entry pos[k] holds
 // member k's pid, on return its position in the cell's sorted order.
 // Contains the barriers; the sort's memory is free after a further barrier.
-template <int T, int K, bool MCC>
+template <int T, int K, bool MCC, bool CLEAR2 = false>
 __device__ __forceinline__ void lean_sort(const CollideArgs &a, int n, uint32_t step,
                                           const uint32_t *pid_c, unsigned char *smem, uint32_t *wtot,
                                           uint32_t (&w2)[K], uint32_t (&w3)[K], uint32_t (&key)[K],
@@ -942,9 +942,17 @@ __device__ __forceinline__ void lean_sort(const CollideArgs &a, int n, uint32_t 
     uint32_t *cnt = (uint32_t *)smem;
     uint32_t *sk = cnt + G::CNT_WORDS;              // keys in sorted-slot order
     uint16_t *lst = (uint16_t *)(sk + G::CAP + 4);  // ... and their index in the cell
+    // counters cleared two at a time (8-byte writes) in the binary32 pass
+    // (the binary64 pass measured slower with them)
+    if (CLEAR2 && G::PERMAX >= 2 && per >= 2u) {
 #pragma unroll
-    for (int q = 0; q < G::PERMAX; ++q)
-        if ((uint32_t)q < per && threadIdx.x + q * T < nb) cnt[threadIdx.x + q * T] = 0u;
+        for (int q = 0; q < G::PERMAX / 2; ++q)
+            if ((uint32_t)q < per / 2u) *(uint2 *)(cnt + 2 * (threadIdx.x + q * T)) = make_uint2(0u, 0u);
+    } else {
+#pragma unroll
+        for (int q = 0; q < G::PERMAX; ++q)
+            if ((uint32_t)q < per && threadIdx.x + q * T < nb) cnt[threadIdx.x + q * T] = 0u;
+    }
     lds_barrier();
     // one Philox call per particle; count its key's bucket
     const int n1 = opaque(n);
@@ -1111,7 +1119,7 @@ __device__ __forceinline__ int lean_pass(const CollideArgs &a, int cell, unsigne
     if (nx && threadIdx.x == 0) *nx->slot = (int)atomicAdd(nx->head, 1u);
     if (n >= 2) {
         uint32_t cpid = 0;
-        lean_sort<T, K, MCC>(a, n, step, pid_c, smem, wtot, w2, w3, key, pos, cand, cpid);
+        lean_sort<T, K, MCC, true>(a, n, step, pid_c, smem, wtot, w2, w3, key, pos, cand, cpid);
         lds_barrier();   // the sort's memory becomes the exchange records
 
         const float C = (float)cell_C(a, cell);
